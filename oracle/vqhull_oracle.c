@@ -1,0 +1,208 @@
+/*
+ * vqhull_oracle.c -- plain CPU Quickhull, the ground truth that the HIP path is
+ * checked against.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the GPU library, and the GPU library never calls
+ * it.
+ *
+ * What it computes (VQhull paper, Section 2.1, Algorithm 1 "Quickhull
+ * algorithm"): the vertices of the convex hull of a finite planar point set, in
+ * clockwise order, by the recursive partition of Algorithm 1.  Quickhull on
+ * binary64 inputs does not always return the exact hull (Section 5.2, the
+ * Circle dataset: round-off makes near-collinear neighbours look concave), so
+ * this file is the algorithm itself, step by step, with every floating-point
+ * and tie decision fixed:
+ *
+ *   R1  orient(a,b,c) = (a.x-c.x)*(b.y-c.y) - (a.y-c.y)*(b.x-c.x) in binary64,
+ *       round to nearest even, evaluated in exactly this order, with no fused
+ *       multiply-add (this file must be compiled with -ffp-contract=off) and
+ *       gradual underflow.  "u is left of a->b" is orient(a,b,u) > 0: this is
+ *       the displayed left-of inequality of Section 2.1 with both products
+ *       moved to one side (for finite products A > B iff fl(A-B) > 0).
+ *   R2  "right of p->q" at the top level is "left of q->p", orient(q,p,u) > 0,
+ *       which is exactly -orient(p,q,u).
+ *   R3  the distance order of Section 2.1 is realised by the scalar key
+ *       orient(a,b,u) for the edge a->b (|ab| times the signed distance in
+ *       exact arithmetic, so the same order); argmax ties are broken by
+ *       x ascending, then y ascending, then index ascending.
+ *   R4  p is the lexicographic minimum of (x, y, index) and q the
+ *       lexicographic maximum of (x, y), lowest index among equal points.
+ *   R5  a point left of both a->r and r->b (possible only under rounding) goes
+ *       to S1.
+ *   R6  the tests are strict: points on an edge are dropped.
+ *   R7  output order: [p] ++ Hull(S1,p,r1,q) ++ [q] ++ Hull(S2,q,r2,p) with
+ *       Hull(P,a,r,b) = Hull(S1,a,r1,r) ++ [r] ++ Hull(S2,r,r2,b), which is
+ *       clockwise from p with y pointing up.
+ *   R8  n = 0 gives no vertex; all points equal gives [p]; NaN or infinity in
+ *       the input is an error (status 3).
+ *
+ * The recursion is the plain recursive function of Algorithm 1; every call
+ * allocates one buffer for its two subsets and frees it on return.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+#define ORACLE_OK 0
+#define ORACLE_ERR_INVALID_ARGUMENT 1
+#define ORACLE_ERR_OUT_OF_MEMORY 2
+#define ORACLE_ERR_NONFINITE 3
+
+/* R1: the orientation value; positive iff c is strictly left of a->b. */
+double vqhull_oracle_orient(double ax, double ay, double bx, double by, double cx, double cy) {
+  double t1 = ax - cx;
+  double t2 = by - cy;
+  double t3 = ay - cy;
+  double t4 = bx - cx;
+  double m1 = t1 * t2;
+  double m2 = t3 * t4;
+  return m1 - m2;
+}
+
+/* R3: is candidate (k, i) farther than the current best (bk, bi)?  best < 0
+ * means "no best yet". */
+static int farther(const double* x, const double* y, double k, int64_t i, double bk, int64_t bi) {
+  if (bi < 0) return 1;
+  if (k > bk) return 1;
+  if (k < bk) return 0;
+  if (x[i] < x[bi]) return 1;
+  if (x[i] > x[bi]) return 0;
+  if (y[i] < y[bi]) return 1;
+  if (y[i] > y[bi]) return 0;
+  return i < bi;
+}
+
+typedef struct {
+  int64_t* idx;
+  int64_t len;
+} out_list;
+
+/*
+ * One partition step of Algorithm 1 for the triangle (a, r, b): every u of P
+ * left of a->r goes to S1, else every u left of r->b goes to S2, else it is
+ * dropped (R5, R6); r1 and r2 are the farthest points of S1 from a->r and of
+ * S2 from r->b (R3).  S1 is written to s[0..n1) and S2 to s[m-n2..m).
+ */
+static void split(const double* x, const double* y, const int64_t* P, int64_t m, int64_t a, int64_t r, int64_t b,
+                  int64_t* s, int64_t* n1_out, int64_t* n2_out, int64_t* r1_out, int64_t* r2_out) {
+  int64_t n1 = 0, n2 = 0;
+  int64_t r1 = -1, r2 = -1;
+  double k1 = 0.0, k2 = 0.0;
+  for (int64_t j = 0; j < m; ++j) {
+    int64_t u = P[j];
+    double o1 = vqhull_oracle_orient(x[a], y[a], x[r], y[r], x[u], y[u]);
+    if (o1 > 0.0) {
+      s[n1++] = u;
+      if (farther(x, y, o1, u, k1, r1)) {
+        k1 = o1;
+        r1 = u;
+      }
+      continue;
+    }
+    double o2 = vqhull_oracle_orient(x[r], y[r], x[b], y[b], x[u], y[u]);
+    if (o2 > 0.0) {
+      s[m - 1 - n2++] = u;
+      if (farther(x, y, o2, u, k2, r2)) {
+        k2 = o2;
+        r2 = u;
+      }
+    }
+  }
+  *n1_out = n1;
+  *n2_out = n2;
+  *r1_out = r1;
+  *r2_out = r2;
+}
+
+/* Hull(P, a, r, b) of Algorithm 1, appending its vertices in order (R7). */
+static int hull_rec(const double* x, const double* y, const int64_t* P, int64_t m, int64_t a, int64_t r, int64_t b,
+                    out_list* out) {
+  if (m <= 1) { /* base case: return P itself */
+    if (m == 1) out->idx[out->len++] = P[0];
+    return ORACLE_OK;
+  }
+  int64_t* s = (int64_t*)malloc((size_t)m * sizeof(int64_t));
+  if (!s) return ORACLE_ERR_OUT_OF_MEMORY;
+  int64_t n1, n2, r1, r2;
+  split(x, y, P, m, a, r, b, s, &n1, &n2, &r1, &r2);
+  int st = hull_rec(x, y, s, n1, a, r1, r, out);
+  if (st == ORACLE_OK) {
+    out->idx[out->len++] = r;
+    st = hull_rec(x, y, s + (m - n2), n2, r, r2, b, out);
+  }
+  free(s);
+  return st;
+}
+
+/* R4: p = lexmin (x, y, index); q = lexmax (x, y), lowest index among equals. */
+int vqhull_oracle_extremes(const double* x, const double* y, int64_t n, int64_t* p_out, int64_t* q_out) {
+  if (n < 1 || !x || !y || !p_out || !q_out) return ORACLE_ERR_INVALID_ARGUMENT;
+  int64_t p = 0, q = 0;
+  for (int64_t i = 1; i < n; ++i) {
+    if (x[i] < x[p] || (x[i] == x[p] && y[i] < y[p])) p = i;
+    if (x[i] > x[q] || (x[i] == x[q] && y[i] > y[q])) q = i;
+  }
+  *p_out = p;
+  *q_out = q;
+  return ORACLE_OK;
+}
+
+/*
+ * One partition step on an explicit subset: P holds m point indices, (a, r, b)
+ * the triangle.  s must hold m entries; on return S1 = s[0..n1) and
+ * S2 = s[m-n2..m) (each in the scan order of P), and r1 / r2 are the argmax
+ * points (-1 for an empty subset).  The top-level step of Algorithm 1 is
+ * (a, r, b) = (p, q, p).
+ */
+int vqhull_oracle_split(const double* x, const double* y, const int64_t* P, int64_t m, int64_t a, int64_t r,
+                        int64_t b, int64_t* s, int64_t* n1, int64_t* n2, int64_t* r1, int64_t* r2) {
+  if (m < 0 || !x || !y || (m > 0 && (!P || !s)) || !n1 || !n2 || !r1 || !r2) return ORACLE_ERR_INVALID_ARGUMENT;
+  split(x, y, P, m, a, r, b, s, n1, n2, r1, r2);
+  return ORACLE_OK;
+}
+
+/*
+ * Algorithm 1 on all n points: writes the hull vertices (indices into x, y)
+ * in clockwise order from p to out_idx (capacity n) and their number to
+ * *out_count.
+ */
+int vqhull_oracle_hull(const double* x, const double* y, int64_t n, int64_t* out_idx, int64_t* out_count) {
+  if (n < 0 || !out_count || (n > 0 && (!x || !y || !out_idx))) return ORACLE_ERR_INVALID_ARGUMENT;
+  *out_count = 0;
+  if (n == 0) return ORACLE_OK;
+  for (int64_t i = 0; i < n; ++i)
+    if (!isfinite(x[i]) || !isfinite(y[i])) return ORACLE_ERR_NONFINITE;
+
+  int64_t p, q;
+  vqhull_oracle_extremes(x, y, n, &p, &q);
+  out_list out = {out_idx, 0};
+  out.idx[out.len++] = p;
+  if (p == q) { /* every point equals p */
+    *out_count = out.len;
+    return ORACLE_OK;
+  }
+
+  int64_t* all = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+  int64_t* s = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+  if (!all || !s) {
+    free(all);
+    free(s);
+    return ORACLE_ERR_OUT_OF_MEMORY;
+  }
+  for (int64_t i = 0; i < n; ++i) all[i] = i;
+  /* S1 = left of p->q, S2 = left of q->p (R2), r1 / r2 their farthest points:
+   * the partition of the degenerate triangle (p, q, p). */
+  int64_t n1, n2, r1, r2;
+  split(x, y, all, n, p, q, p, s, &n1, &n2, &r1, &r2);
+  free(all);
+  int st = hull_rec(x, y, s, n1, p, r1, q, &out);
+  if (st == ORACLE_OK) {
+    out.idx[out.len++] = q;
+    st = hull_rec(x, y, s + (n - n2), n2, q, r2, p, &out);
+  }
+  free(s);
+  if (st == ORACLE_OK) *out_count = out.len;
+  return st;
+}

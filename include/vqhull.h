@@ -1,0 +1,137 @@
+/*
+ * vqhull.h -- C ABI of the MI355X (gfx950) planar Quickhull library.
+ *
+ * The library computes the vertices of the convex hull of planar point sets,
+ * in clockwise order, by the recursive partition of Quickhull (VQhull paper,
+ * Section 2.1, Algorithm 1): the leftmost point p and rightmost point q split
+ * the points into those left of p->q and those left of q->p; each subset
+ * keeps only the points outside the triangle formed with its farthest point,
+ * recursively.  The pass that dominates the run time -- classify every point of
+ * every live subproblem against two edges, find the farthest point of each
+ * side, and extract the two subsets (Section 3 "Subset Extraction", Section 4
+ * "Bandwidth considerations") -- runs as one fused HIP kernel per level over
+ * all live subproblems.
+ *
+ * Results (what is computed, exactly):
+ *   - orient(a,b,c) = (a.x-c.x)*(b.y-c.y) - (a.y-c.y)*(b.x-c.x), each operation
+ *     rounded to nearest binary64, never fused; "u left of a->b" is
+ *     orient(a,b,u) > 0 (Section 2.1, the left-of inequality).
+ *   - the farthest point of a subset is the maximum of the key orient(a,b,u)
+ *     for its edge a->b; ties go to the smaller x, then the smaller y, then
+ *     the lower index (Section 2.1, the farther-than comparison, read as this
+ *     total order).
+ *   - p = lexicographic minimum of (x, y, index); q = lexicographic maximum of
+ *     (x, y), lowest index among equal points.
+ *   - a point left of both p->r and r->q (possible only under rounding) goes to
+ *     the first subset; points on an edge are dropped.
+ *   - output: [p] ++ Hull(S1,p,r1,q) ++ [q] ++ Hull(S2,q,r2,p) with
+ *     Hull(P,a,r,b) = Hull(S1,a,r1,r) ++ [r] ++ Hull(S2,r,r2,b): clockwise from
+ *     p with y pointing up.  Only the vertices Algorithm 1 emits are listed,
+ *     each once, as 0-based indices into the request's own arrays.
+ *   - n = 0 gives 0 vertices; all points equal gives [p]; all points on one
+ *     line gives [p, q].
+ *   The output depends only on the multiset of (x, y, index) triples, not on
+ *   the order of work inside the GPU, so it is identical from run to run and
+ *   identical for a request alone or inside a batch.
+ *
+ * Conventions:
+ *   - Array arguments are DEVICE pointers on the current HIP device unless
+ *     stated otherwise.  x and y are read-only and must stay unmodified until
+ *     the call's stream work has completed.
+ *   - Calls are stream-ordered.  The hull calls synchronize the given stream
+ *     internally between levels (they read small level counters back to the
+ *     host), so they return after the result has been written; the results are
+ *     then visible to later work on the same stream.
+ *   - The library allocates and keeps its own device workspace (about 40 bytes
+ *     per input point plus small tables), one cache per device, grown on
+ *     demand and guarded by a mutex: concurrent calls from several host
+ *     threads are serialized per device.  vqhull_release_workspace() frees it.
+ *   - Errors detectable on the host return at once with a status and enqueue
+ *     no work.  A NaN or infinity in a request's input is detected on the
+ *     device: that request's count is set to -VQHULL_ERR_NONFINITE and its
+ *     index list is unspecified; the call itself returns VQHULL_OK.
+ */
+#ifndef VQHULL_H
+#define VQHULL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VQHULL_OK = 0,
+  VQHULL_ERR_INVALID_ARGUMENT = 1, /* null pointer, negative size, bad offsets, n >= 2^31 */
+  VQHULL_ERR_OUT_OF_MEMORY = 2,    /* device workspace could not be allocated */
+  VQHULL_ERR_NONFINITE = 3,        /* a NaN or infinity in the input (reported per request) */
+  VQHULL_ERR_HIP = 4               /* a HIP runtime call failed; see vqhull_last_error() */
+} vqhull_status;
+
+/* Stream handle: a hipStream_t passed as an opaque pointer (NULL = the default
+ * stream), so that this header does not need the HIP headers. */
+typedef void* vqhull_stream_t;
+
+/*
+ * Hull of one point set (Algorithm 1 on x[0..n), y[0..n)).
+ *   x, y       device arrays of n binary64 coordinates (structure of arrays).
+ *   n          number of points, 0 <= n < 2^31.
+ *   out_idx    device int64 array with room for n entries (1 if n = 0); on
+ *              return out_idx[0..h) holds the hull vertices, clockwise from p.
+ *   out_count  device int64 scalar: h >= 0, or -VQHULL_ERR_NONFINITE.
+ *   stream     HIP stream the work is ordered on.
+ * Returns VQHULL_OK, or an error status with nothing enqueued.
+ */
+int vqhull_hull(const double* x, const double* y, int64_t n, int64_t* out_idx, int64_t* out_count,
+                vqhull_stream_t stream);
+
+/*
+ * Hulls of nreq independent point sets in one pass (the batched form of
+ * Algorithm 1: every level of every request is processed by the same kernel
+ * launches).
+ *   x, y       device arrays holding all requests back to back.
+ *   offsets    HOST array of nreq+1 non-decreasing int64 values, offsets[0] = 0;
+ *              request i owns x[offsets[i] .. offsets[i+1]).  The total
+ *              offsets[nreq] must be below 2^31.
+ *   nreq       number of requests, >= 0.
+ *   out_idx    device int64 array of offsets[nreq] entries (at least 1);
+ *              request i writes its vertex list to out_idx[offsets[i] ..), as
+ *              indices local to the request (0 .. n_i-1).
+ *   out_counts device int64 array of nreq entries: h_i, or -VQHULL_ERR_NONFINITE.
+ * The result of each request equals that of vqhull_hull on its points alone.
+ */
+int vqhull_hull_batched(const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
+                        int64_t* out_counts, vqhull_stream_t stream);
+
+/* Tuning knobs of the hull kernels (all values are rounded to supported ones). */
+typedef struct {
+  int sweep_block;  /* threads per workgroup of the partition sweep: 256, 512 or 1024 */
+  int sweep_ppt;    /* points per thread of the partition sweep: 8, 16 or 32 */
+  int lds_limit;    /* subproblems of at most this many points finish inside one workgroup: 256..2048 */
+  int reverse_tiles;/* debug: process tiles in reverse order (the result must not change) */
+} vqhull_config;
+
+/* Read / replace the configuration used by later calls (host pointers). */
+int vqhull_get_config(vqhull_config* cfg);
+int vqhull_set_config(const vqhull_config* cfg);
+
+/* Per-level statistics of the last hull call on this device (host pointer,
+ * up to cap entries of 4 int64: live subproblems, points swept, subproblems
+ * finished in LDS, points finished in LDS).  Returns the number of levels. */
+int64_t vqhull_last_level_stats(int64_t* out, int64_t cap);
+
+/* Free the cached device workspace of the current device. */
+int vqhull_release_workspace(void);
+
+/* Human-readable text of a status code (static storage). */
+const char* vqhull_status_string(int status);
+
+/* Text of the last HIP error seen by this thread (static thread-local storage). */
+const char* vqhull_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VQHULL_H */

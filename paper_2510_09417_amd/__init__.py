@@ -1,1 +1,191 @@
-"""MI355X-native planar Quickhull (placeholder; the binding is filled in next)."""
+"""MI355X-native planar Quickhull (the VQhull paper's Algorithm 1 on gfx950).
+
+Thin ctypes binding of ``libvqhull.so``: argument checks and marshalling only;
+every step of the hull runs in the library's HIP kernels.  PyTorch provides the
+device tensors and the current stream.  If the library is not built this
+module raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvqhull.so")
+
+VQHULL_OK = 0
+VQHULL_ERR_INVALID_ARGUMENT = 1
+VQHULL_ERR_OUT_OF_MEMORY = 2
+VQHULL_ERR_NONFINITE = 3
+VQHULL_ERR_HIP = 4
+
+# Symbols that include/vqhull.h declares.
+EXPORTED = (
+    "vqhull_hull", "vqhull_hull_batched", "vqhull_get_config", "vqhull_set_config",
+    "vqhull_last_level_stats", "vqhull_release_workspace", "vqhull_status_string", "vqhull_last_error",
+)
+
+
+class VqhullError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"vqhull status {status}: {message}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("sweep_block", ctypes.c_int), ("sweep_ppt", ctypes.c_int), ("lds_limit", ctypes.c_int),
+                ("reverse_tiles", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load ``libvqhull.so`` (raises FileNotFoundError if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise FileNotFoundError(f"{path} is not built; run `python -m paper_2510_09417_amd.build`")
+        lib = ctypes.CDLL(path)
+        vp, i64, pi64 = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)
+        lib.vqhull_hull.restype = ctypes.c_int
+        lib.vqhull_hull.argtypes = [vp, vp, i64, vp, vp, vp]
+        lib.vqhull_hull_batched.restype = ctypes.c_int
+        lib.vqhull_hull_batched.argtypes = [vp, vp, pi64, i64, vp, vp, vp]
+        lib.vqhull_get_config.restype = ctypes.c_int
+        lib.vqhull_get_config.argtypes = [ctypes.POINTER(Config)]
+        lib.vqhull_set_config.restype = ctypes.c_int
+        lib.vqhull_set_config.argtypes = [ctypes.POINTER(Config)]
+        lib.vqhull_last_level_stats.restype = i64
+        lib.vqhull_last_level_stats.argtypes = [pi64, i64]
+        lib.vqhull_release_workspace.restype = ctypes.c_int
+        lib.vqhull_release_workspace.argtypes = []
+        lib.vqhull_status_string.restype = ctypes.c_char_p
+        lib.vqhull_status_string.argtypes = [ctypes.c_int]
+        lib.vqhull_last_error.restype = ctypes.c_char_p
+        lib.vqhull_last_error.argtypes = []
+        _lib = lib
+        return lib
+
+
+def _check(lib, status: int):
+    if status != VQHULL_OK:
+        msg = lib.vqhull_status_string(status).decode()
+        if status == VQHULL_ERR_HIP:
+            msg += ": " + lib.vqhull_last_error().decode()
+        raise VqhullError(status, msg)
+
+
+def _stream_handle(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_points(x, y):
+    import torch
+
+    if not (isinstance(x, torch.Tensor) and isinstance(y, torch.Tensor)):
+        raise TypeError("x and y must be torch tensors")
+    if x.dtype != torch.float64 or y.dtype != torch.float64:
+        raise TypeError("x and y must be float64")
+    if not (x.is_cuda and y.is_cuda) or x.device != y.device:
+        raise ValueError("x and y must be on the same GPU")
+    if x.dim() != 1 or x.shape != y.shape:
+        raise ValueError("x and y must be 1-D of equal length")
+    if not (x.is_contiguous() and y.is_contiguous()):
+        raise ValueError("x and y must be contiguous")
+
+
+def hull_into(x, y, out_idx, out_count, stream=None) -> None:
+    """vqhull_hull on preallocated device outputs (no allocation, no sync)."""
+    lib = load_library()
+    n = x.numel()
+    st = lib.vqhull_hull(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), n,
+                         ctypes.c_void_p(out_idx.data_ptr()), ctypes.c_void_p(out_count.data_ptr()),
+                         _stream_handle(stream))
+    _check(lib, st)
+
+
+def hull(x, y, stream=None):
+    """Hull vertex indices (int64 tensor on the same GPU), clockwise from the
+    lexicographically smallest point.  Raises VqhullError on a non-finite input."""
+    import torch
+
+    _check_points(x, y)
+    n = x.numel()
+    out = torch.empty(max(n, 1), dtype=torch.int64, device=x.device)
+    cnt = torch.empty(1, dtype=torch.int64, device=x.device)
+    with torch.cuda.device(x.device):
+        hull_into(x, y, out, cnt, stream)
+        h = int(cnt.item())
+    if h < 0:
+        raise VqhullError(-h, "non-finite coordinate in the input")
+    return out[:h]
+
+
+def hull_batched(x, y, offsets, stream=None, check=True):
+    """Hulls of the requests x[offsets[i]:offsets[i+1]] (offsets: host sequence of
+    nreq+1 ints).  Returns (out_idx, counts) device tensors: request i's list is
+    out_idx[offsets[i] : offsets[i] + counts[i]] (indices local to the request)."""
+    import numpy as np
+    import torch
+
+    _check_points(x, y)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    nreq = len(off) - 1
+    if nreq < 0 or (nreq >= 0 and len(off) and off[-1] != x.numel()):
+        raise ValueError("offsets must have nreq+1 entries ending at len(x)")
+    lib = load_library()
+    out = torch.empty(max(x.numel(), 1), dtype=torch.int64, device=x.device)
+    cnt = torch.empty(max(nreq, 1), dtype=torch.int64, device=x.device)
+    with torch.cuda.device(x.device):
+        st = lib.vqhull_hull_batched(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                     off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nreq,
+                                     ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(cnt.data_ptr()),
+                                     _stream_handle(stream))
+    _check(lib, st)
+    return out, cnt[:nreq]
+
+
+def get_config() -> dict:
+    lib = load_library()
+    c = Config()
+    _check(lib, lib.vqhull_get_config(ctypes.byref(c)))
+    return c.as_dict()
+
+
+def set_config(**kw) -> dict:
+    """Update tuning knobs (sweep_block, sweep_ppt, lds_limit, reverse_tiles)."""
+    lib = load_library()
+    c = Config()
+    _check(lib, lib.vqhull_get_config(ctypes.byref(c)))
+    for k, v in kw.items():
+        if k not in c.as_dict():
+            raise KeyError(k)
+        setattr(c, k, int(v))
+    _check(lib, lib.vqhull_set_config(ctypes.byref(c)))
+    return get_config()
+
+
+def level_stats() -> list[dict]:
+    """Per-level statistics of the last call on the current device."""
+    lib = load_library()
+    n = lib.vqhull_last_level_stats(None, 0)
+    buf = (ctypes.c_int64 * (4 * max(n, 1)))()
+    n = lib.vqhull_last_level_stats(buf, n)
+    return [dict(segments=buf[4 * i], swept=buf[4 * i + 1], jobs=buf[4 * i + 2], job_points=buf[4 * i + 3])
+            for i in range(n)]
+
+
+def release_workspace() -> None:
+    lib = load_library()
+    _check(lib, lib.vqhull_release_workspace())

@@ -1,0 +1,196 @@
+// Internal types shared by the host engine and the gfx950 kernels.
+//
+// Data layout in HBM (all positions are "global positions": request i owns
+// positions [off_i, off_i + n_i) of the caller's x/y arrays, of both workspace
+// buffers and of out_idx):
+//   - two ping-pong workspace buffers, each structure-of-arrays
+//     {x: double[N], y: double[N], idx: uint32[N]} (20 bytes per point);
+//     idx is the point's index local to its request;
+//   - per level: a segment table (one row per live subproblem with more points
+//     than the LDS finisher takes), a tile -> segment map, one packed 64-bit
+//     counter per segment and one candidate record per tile;
+//   - a node table (one node per emitted vertex outside the LDS finisher)
+//     from which the clockwise order is assembled at the end.
+#pragma once
+#include <stdint.h>
+
+namespace vqh {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// Source of a finisher job's points.
+enum : uint32_t { kSrcBufA = 0, kSrcBufB = 1, kSrcUser = 2 };
+
+struct Req {
+  uint32_t off;     // global position of the request's point 0
+  uint32_t n;       // number of points
+  uint32_t p, q;    // local indices of the lexicographic extremes
+  int32_t root;     // root node (vertex q), -1 if none
+  uint32_t err;     // set to 1 by a kernel that sees a non-finite coordinate
+  uint32_t tile0;   // first extremes tile of this request
+  uint32_t pad;
+};
+
+// A live subproblem Hull(P, a, r, b): P is the point range [beg, beg + cnt) of
+// the level's input buffer.  At level 0 the input is the caller's arrays and
+// the index of a point is its position minus ibase.
+struct Seg {
+  double ax, ay, rx, ry, bx, by;
+  uint32_t beg, cnt;
+  uint32_t tile0;   // first tile of this segment in the level's tile map
+  uint32_t req;
+  int32_t node;     // node of r
+  uint32_t ibase;
+};
+
+// Farthest-point candidate: key = orient value for the edge, then (x, y, i)
+// break ties.  i == kNone marks "no candidate".
+struct Cand {
+  double k, x, y;
+  uint32_t i, pad;
+};
+
+struct TilePart {
+  Cand c[2];
+};
+
+struct ExtPart {
+  double minx, miny, maxx, maxy;
+  uint32_t mini, maxi;  // local indices (kNone: empty)
+  uint32_t pad[2];
+};
+
+// A subproblem small enough to finish inside one workgroup's LDS.
+struct Job {
+  double ax, ay, rx, ry, bx, by;
+  uint32_t ri;      // local index of r
+  uint32_t beg, cnt;
+  uint32_t src;     // kSrcBufA / kSrcBufB / kSrcUser
+  uint32_t req;
+  int32_t node;     // node of r; receives the size and location of the finished list
+  uint32_t ibase;   // kSrcUser: global position of local index 0
+  uint32_t pad;
+};
+
+struct Node {
+  uint32_t vertex;  // local index of the vertex
+  int32_t c[2];     // child nodes for the S1 / S2 sides, -1 if none
+  uint32_t size;    // vertices in the subtree
+  uint32_t start;   // output position of the subtree's first vertex
+  uint32_t req;
+  uint32_t list;    // finished-in-LDS subtree: global position of its ordered list, else kNone
+  uint32_t lbuf;    // which workspace idx array holds that list (0 = A, 1 = B)
+};
+
+// Counters a planning kernel writes for the host.
+struct Status {
+  uint32_t nseg;        // segments of the next level
+  uint32_t ntiles;      // tiles of the next level
+  uint32_t njobs;       // finisher jobs created by this plan
+  uint32_t nnodes;      // node count after this plan
+  uint32_t swept;       // points in the segments of the next level
+  uint32_t jobpts;      // points in the jobs created
+  uint32_t pad[2];
+};
+
+// ----------------------------------------------------------------- launchers
+struct Workspace;  // host side
+
+struct ExtremesArgs {
+  const double* x;
+  const double* y;
+  const uint32_t* tile_req;  // nullptr: single request 0
+  Req* req;
+  ExtPart* part;
+  uint32_t ntiles;
+};
+
+struct SweepArgs {
+  const double* ix;  // level input (caller arrays at level 0)
+  const double* iy;
+  const uint32_t* ii;  // nullptr at level 0
+  double* ox;
+  double* oy;
+  uint32_t* oi;
+  const Seg* seg;
+  const uint32_t* tile_seg;
+  unsigned long long* ctr;
+  TilePart* part;
+  Req* req;
+  uint32_t ntiles;
+  uint32_t reverse;
+};
+
+struct Plan0Args {
+  Req* req;
+  uint32_t nreq;
+  const ExtPart* epart;
+  Seg* seg_out;
+  unsigned long long* ctr_out;
+  uint32_t* tile_seg_out;
+  Job* jobs;
+  Node* nodes;
+  Status* status;
+  uint32_t tile;
+  uint32_t lds_limit;
+  uint32_t ext_tile;
+};
+
+struct PlanArgs {
+  const Seg* seg;
+  uint32_t nseg;
+  const unsigned long long* ctr;
+  const TilePart* part;
+  Seg* seg_out;
+  unsigned long long* ctr_out;
+  uint32_t* tile_seg_out;
+  Job* jobs;
+  Node* nodes;
+  uint32_t node_base;
+  uint32_t out_buf;  // buffer the children were written to (0 = A, 1 = B)
+  Status* status;
+  uint32_t tile;
+  uint32_t lds_limit;
+};
+
+struct FinishArgs {
+  const Job* jobs;
+  const double* ux;  // caller arrays (root jobs)
+  const double* uy;
+  const double* bx[2];
+  const double* by[2];
+  uint32_t* bi[2];
+  Node* nodes;
+  Req* req;
+};
+
+struct AssembleArgs {
+  Node* nodes;
+  const uint32_t* level_begin;  // node level boundaries, nlevels + 1 entries
+  uint32_t nlevels;
+  Req* req;
+  uint32_t nreq;
+  const uint32_t* lists[2];
+  int64_t* out_idx;
+  int64_t* out_count;
+  uint32_t nnodes;
+};
+
+// Supported sweep shapes.
+bool sweep_shape_supported(int block, int ppt);
+int finish_tmax_for(int lds_limit);
+
+// Launchers (return hipError_t as int).
+int launch_extremes(const ExtremesArgs& a, void* stream);
+int launch_sweep(const SweepArgs& a, bool level0, int block, int ppt, void* stream);
+int launch_plan0(const Plan0Args& a, void* stream);
+int launch_plan(const PlanArgs& a, void* stream);
+int launch_finish(const FinishArgs& a, uint32_t njobs, int tmax, void* stream);
+int launch_assemble(const AssembleArgs& a, void* stream);
+int launch_copy_lists(const AssembleArgs& a, void* stream);
+
+constexpr int kExtBlock = 256;
+constexpr int kExtPPT = 32;
+constexpr uint32_t kExtTile = kExtBlock * kExtPPT;
+
+}  // namespace vqh

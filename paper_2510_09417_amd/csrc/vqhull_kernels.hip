@@ -1,0 +1,1173 @@
+// gfx950 kernels of the planar Quickhull (VQhull paper, Algorithm 1).
+//
+//   k_extremes  leftmost / rightmost point per request (Algorithm 1, first two
+//               steps), reading x only; y is read only to break exact x ties.
+//   k_sweep     the fused partition pass (Section 3, Section 4 "Bandwidth
+//               considerations"): orientation against p->r and r->q, the
+//               farthest point of each side, and extraction of S1 / S2, for
+//               every tile of every live segment of one recursion level.
+//   k_plan0 /   single-workgroup planners: reduce the per-tile results of a
+//   k_plan      level and lay out the next one (breadth-first recursion).
+//   k_finish    one workgroup finishes a whole small subproblem in LDS.
+//   k_assemble  clockwise order from the recursion tree (Algorithm 1's
+//               unions, in the order p, Hull(S1), q, Hull(S2)).
+//
+// Floating point: the orientation value must be bit-identical to the formula
+// evaluated operation by operation, so this file is compiled with
+// -ffp-contract=off and the pragma below; no fused multiply-add may appear.
+#include <hip/hip_runtime.h>
+
+#include "vqhull_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace vqh {
+
+// ------------------------------------------------------------------ helpers
+
+// orient(a, b, c) > 0 iff c is strictly left of a->b (Section 2.1).
+__device__ __forceinline__ double orient(double ax, double ay, double bx, double by, double cx, double cy) {
+  const double t1 = ax - cx;
+  const double t2 = by - cy;
+  const double t3 = ay - cy;
+  const double t4 = bx - cx;
+  const double m1 = t1 * t2;
+  const double m2 = t3 * t4;
+  return m1 - m2;
+}
+
+// Total order of farthest-point candidates: larger key first, then smaller x,
+// smaller y, lower index.  kNone loses to every candidate.
+__device__ __forceinline__ bool better(double k, double x, double y, uint32_t i, const Cand& b) {
+  if (i == kNone) return false;
+  if (b.i == kNone) return true;
+  if (k != b.k) return k > b.k;
+  if (x != b.x) return x < b.x;
+  if (y != b.y) return y < b.y;
+  return i < b.i;
+}
+
+__device__ __forceinline__ bool better(const Cand& a, const Cand& b) { return better(a.k, a.x, a.y, a.i, b); }
+
+__device__ __forceinline__ Cand no_cand() {
+  Cand c;
+  c.k = 0.0;
+  c.x = 0.0;
+  c.y = 0.0;
+  c.i = kNone;
+  c.pad = 0;
+  return c;
+}
+
+__device__ __forceinline__ Cand shfl_xor_cand(const Cand& c, int m) {
+  Cand o;
+  o.k = __shfl_xor(c.k, m, 64);
+  o.x = __shfl_xor(c.x, m, 64);
+  o.y = __shfl_xor(c.y, m, 64);
+  o.i = __shfl_xor(c.i, m, 64);
+  o.pad = __shfl_xor(c.pad, m, 64);
+  return o;
+}
+
+// Every lane ends with the wave's best candidate.
+__device__ __forceinline__ void wave_best(Cand& c) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    Cand o = shfl_xor_cand(c, m);
+    if (better(o, c)) c = o;
+  }
+}
+
+__device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+// Lexicographic order of points by (x, y, position); y is loaded only on an
+// exact x tie.  ia / ib are positions into y.
+__device__ __forceinline__ bool lex_less(double xa, uint32_t ia, double xb, uint32_t ib, const double* y) {
+  if (xa != xb) return xa < xb;
+  const double ya = y[ia], yb = y[ib];
+  if (ya != yb) return ya < yb;
+  return ia < ib;
+}
+
+// Lexicographic maximum by (x, y), lower position among equal points.
+__device__ __forceinline__ bool lex_greater(double xa, uint32_t ia, double xb, uint32_t ib, const double* y) {
+  if (xa != xb) return xa > xb;
+  const double ya = y[ia], yb = y[ib];
+  if (ya != yb) return ya > yb;
+  return ia < ib;
+}
+
+// ------------------------------------------------------------- k_extremes
+
+template <int BLOCK, int PPT>
+__global__ __launch_bounds__(BLOCK) void k_extremes(ExtremesArgs A) {
+  constexpr uint32_t TILE = BLOCK * PPT;
+  constexpr int NW = BLOCK / 64;
+  __shared__ double s_mnx[NW], s_mxx[NW];
+  __shared__ uint32_t s_mni[NW], s_mxi[NW];
+  const uint32_t t = blockIdx.x;
+  const uint32_t r = A.tile_req ? A.tile_req[t] : 0u;
+  const uint32_t off = A.req[r].off, n = A.req[r].n, tile0 = A.req[r].tile0;
+  const uint32_t lo = off + (t - tile0) * TILE;
+  const uint32_t hi = min(off + n, lo + TILE);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+
+  double xs[PPT];
+#pragma unroll
+  for (int v = 0; v < PPT; ++v) {
+    const uint32_t pos = lo + v * BLOCK + tid;
+    xs[v] = pos < hi ? A.x[pos] : 0.0;
+  }
+  double mnx = 0.0, mxx = 0.0;
+  uint32_t mni = kNone, mxi = kNone;
+  bool bad = false;
+#pragma unroll
+  for (int v = 0; v < PPT; ++v) {
+    const uint32_t pos = lo + v * BLOCK + tid;
+    if (pos < hi) {
+      const double xv = xs[v];
+      bad |= !finite(xv);
+      if (mni == kNone || lex_less(xv, pos, mnx, mni, A.y)) {
+        mnx = xv;
+        mni = pos;
+      }
+      if (mxi == kNone || lex_greater(xv, pos, mxx, mxi, A.y)) {
+        mxx = xv;
+        mxi = pos;
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const double ox = __shfl_xor(mnx, m, 64);
+    const uint32_t oi = __shfl_xor(mni, m, 64);
+    if (oi != kNone && (mni == kNone || lex_less(ox, oi, mnx, mni, A.y))) {
+      mnx = ox;
+      mni = oi;
+    }
+    const double gx = __shfl_xor(mxx, m, 64);
+    const uint32_t gi = __shfl_xor(mxi, m, 64);
+    if (gi != kNone && (mxi == kNone || lex_greater(gx, gi, mxx, mxi, A.y))) {
+      mxx = gx;
+      mxi = gi;
+    }
+  }
+  if (__ballot(bad) && lane == 0) A.req[r].err = 1u;
+  if (lane == 0) {
+    s_mnx[w] = mnx;
+    s_mni[w] = mni;
+    s_mxx[w] = mxx;
+    s_mxi[w] = mxi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = 1; i < NW; ++i) {
+      if (s_mni[i] != kNone && (mni == kNone || lex_less(s_mnx[i], s_mni[i], mnx, mni, A.y))) {
+        mnx = s_mnx[i];
+        mni = s_mni[i];
+      }
+      if (s_mxi[i] != kNone && (mxi == kNone || lex_greater(s_mxx[i], s_mxi[i], mxx, mxi, A.y))) {
+        mxx = s_mxx[i];
+        mxi = s_mxi[i];
+      }
+    }
+    ExtPart e;
+    e.minx = mnx;
+    e.maxx = mxx;
+    e.miny = mni != kNone ? A.y[mni] : 0.0;
+    e.maxy = mxi != kNone ? A.y[mxi] : 0.0;
+    e.mini = mni != kNone ? mni - off : kNone;
+    e.maxi = mxi != kNone ? mxi - off : kNone;
+    e.pad[0] = e.pad[1] = 0;
+    A.part[t] = e;
+  }
+}
+
+// ---------------------------------------------------------------- k_sweep
+//
+// One workgroup per tile of BLOCK*PPT consecutive points of one segment.
+// Each thread loads PPT points (striped so that every wave load instruction
+// covers consecutive addresses), classifies them against the segment's
+// triangle (a, r, b), and tracks the farthest point of each side.  Wave
+// ballots give per-wave subset sizes, one packed 64-bit atomic per tile
+// reserves room at the left end (S1) and right end (S2) of the segment's
+// output range, and every wave then writes its survivors as contiguous runs.
+// The order of points inside a subset is irrelevant to the result.
+
+template <int BLOCK, int PPT, bool L0>
+__global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
+  static_assert(PPT <= 32, "class masks are 32-bit");
+  constexpr uint32_t TILE = BLOCK * PPT;
+  constexpr int NW = BLOCK / 64;
+  __shared__ uint32_t s_cnt[2][NW];
+  __shared__ uint32_t s_base[2];
+  __shared__ Cand s_cand[2][NW];
+
+  const uint32_t t = A.reverse ? (A.ntiles - 1u - blockIdx.x) : blockIdx.x;
+  const uint32_t s = A.tile_seg[t];
+  const Seg* sg = A.seg + s;
+  const double ax = sg->ax, ay = sg->ay, rx = sg->rx, ry = sg->ry, bx = sg->bx, by = sg->by;
+  const uint32_t beg = sg->beg, cnt = sg->cnt;
+  const uint32_t lo = beg + (t - sg->tile0) * TILE;
+  const uint32_t hi = min(beg + cnt, lo + TILE);
+  const uint32_t ibase = sg->ibase;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+
+  double px[PPT], py[PPT];
+  uint32_t pi[PPT];
+#pragma unroll
+  for (int v = 0; v < PPT; ++v) {
+    const uint32_t pos = lo + v * BLOCK + tid;
+    const bool ok = pos < hi;
+    px[v] = ok ? A.ix[pos] : 0.0;
+    py[v] = ok ? A.iy[pos] : 0.0;
+    if constexpr (L0) {
+      pi[v] = pos - ibase;
+    } else {
+      pi[v] = ok ? A.ii[pos] : 0u;
+    }
+  }
+
+  uint32_t m1 = 0, m2 = 0;
+  bool bad = false;
+  Cand b1 = no_cand(), b2 = no_cand();
+#pragma unroll
+  for (int v = 0; v < PPT; ++v) {
+    const uint32_t pos = lo + v * BLOCK + tid;
+    const bool ok = pos < hi;
+    const double o1 = orient(ax, ay, rx, ry, px[v], py[v]);
+    const double o2 = orient(rx, ry, bx, by, px[v], py[v]);
+    const bool in1 = ok && (o1 > 0.0);
+    const bool in2 = ok && !in1 && (o2 > 0.0);
+    m1 |= (uint32_t)in1 << v;
+    m2 |= (uint32_t)in2 << v;
+    if (in1 && better(o1, px[v], py[v], pi[v], b1)) {
+      b1.k = o1;
+      b1.x = px[v];
+      b1.y = py[v];
+      b1.i = pi[v];
+    }
+    if (in2 && better(o2, px[v], py[v], pi[v], b2)) {
+      b2.k = o2;
+      b2.x = px[v];
+      b2.y = py[v];
+      b2.i = pi[v];
+    }
+    if constexpr (L0) bad |= ok && !finite(py[v]);
+  }
+
+  uint32_t c1 = 0, c2 = 0;
+#pragma unroll
+  for (int v = 0; v < PPT; ++v) {
+    c1 += __popcll(__ballot((m1 >> v) & 1u));
+    c2 += __popcll(__ballot((m2 >> v) & 1u));
+  }
+  wave_best(b1);
+  wave_best(b2);
+  if (lane == 0) {
+    s_cnt[0][w] = c1;
+    s_cnt[1][w] = c2;
+    s_cand[0][w] = b1;
+    s_cand[1][w] = b2;
+  }
+  if constexpr (L0) {
+    if (__ballot(bad) && lane == 0) A.req[sg->req].err = 1u;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t t1 = 0, t2 = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const uint32_t a = s_cnt[0][i], b = s_cnt[1][i];
+      s_cnt[0][i] = t1;
+      s_cnt[1][i] = t2;
+      t1 += a;
+      t2 += b;
+    }
+    unsigned long long old = 0ull;
+    if (t1 | t2) old = atomicAdd(A.ctr + s, ((unsigned long long)t2 << 32) | (unsigned long long)t1);
+    s_base[0] = beg + (uint32_t)old;
+    s_base[1] = beg + cnt - (uint32_t)(old >> 32) - t2;
+    Cand r1 = s_cand[0][0], r2 = s_cand[1][0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) {
+      if (better(s_cand[0][i], r1)) r1 = s_cand[0][i];
+      if (better(s_cand[1][i], r2)) r2 = s_cand[1][i];
+    }
+    A.part[t].c[0] = r1;
+    A.part[t].c[1] = r2;
+  }
+  __syncthreads();
+  uint32_t o1p = s_base[0] + s_cnt[0][w];
+  uint32_t o2p = s_base[1] + s_cnt[1][w];
+#pragma unroll
+  for (int v = 0; v < PPT; ++v) {
+    const bool in1 = (m1 >> v) & 1u, in2 = (m2 >> v) & 1u;
+    const unsigned long long q1 = __ballot(in1), q2 = __ballot(in2);
+    if (in1 | in2) {
+      const uint32_t dst = in1 ? o1p + lane_rank(q1) : o2p + lane_rank(q2);
+      A.ox[dst] = px[v];
+      A.oy[dst] = py[v];
+      A.oi[dst] = pi[v];
+    }
+    o1p += (uint32_t)__popcll(q1);
+    o2p += (uint32_t)__popcll(q2);
+  }
+}
+
+// --------------------------------------------------------- block utilities
+
+// Exclusive scan of N values per thread across a workgroup of BLOCK threads.
+template <int BLOCK, int N>
+__device__ __forceinline__ void block_scan(const uint32_t (&v)[N], uint32_t (&excl)[N], uint32_t (&total)[N],
+                                           uint32_t (*s_w)[BLOCK / 64]) {
+  constexpr int NW = BLOCK / 64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  uint32_t inc[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) inc[j] = v[j];
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const uint32_t o = __shfl_up(inc[j], d, 64);
+      if (lane >= d) inc[j] += o;
+    }
+  }
+  if (lane == 63) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) s_w[j][w] = inc[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    uint32_t before = 0, all = 0;
+    for (int i = 0; i < NW; ++i) {
+      const uint32_t x = s_w[j][i];
+      if (i < w) before += x;
+      all += x;
+    }
+    excl[j] = before + inc[j] - v[j];
+    total[j] = all;
+  }
+  __syncthreads();
+}
+
+// Best candidate over a workgroup; the result is valid in every thread.
+template <int BLOCK>
+__device__ __forceinline__ Cand block_best(Cand c, Cand* s_c) {
+  constexpr int NW = BLOCK / 64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  wave_best(c);
+  if (lane == 0) s_c[w] = c;
+  __syncthreads();
+  Cand r = s_c[0];
+  for (int i = 1; i < NW; ++i)
+    if (better(s_c[i], r)) r = s_c[i];
+  __syncthreads();
+  return r;
+}
+
+
+// ------------------------------------------------------------------ plans
+//
+// Each side of a partition step (a "child") becomes, by its size: nothing
+// (no point), a leaf vertex (one point: Algorithm 1's base case), a finisher
+// job (2 .. lds_limit points) or a segment of the next sweep level.  Every
+// child with at least one point owns one node of the recursion tree, whose
+// vertex is the child's farthest point.  A root (the top-level triangle
+// (p, q, p) of a request) is always a job or a segment so that its points are
+// read once and checked for non-finite values.
+
+enum : uint32_t { kKindNone = 0, kKindLeaf = 1, kKindJob = 2, kKindSeg = 3 };
+
+struct Child {
+  double ax, ay, rx, ry, bx, by;
+  uint32_t ri, beg, cnt, req;
+  int32_t parent;  // parent node, -1 for a root
+  uint32_t side;
+  uint32_t kind;
+};
+
+constexpr int kPlanBlock = 1024;
+constexpr int kPlanWaves = kPlanBlock / 64;
+constexpr uint32_t kSerialTiles = 32;  // segments with more tiles are reduced by the whole workgroup
+constexpr uint32_t kSerialFill = 16;   // segments with more tiles get their tile map filled by the workgroup
+
+__device__ __forceinline__ uint32_t ceil_div(uint32_t a, uint32_t b) { return (a + b - 1u) / b; }
+
+__device__ __forceinline__ uint32_t child_kind(uint32_t cnt, uint32_t lds_limit) {
+  return cnt == 0u ? kKindNone : cnt == 1u ? kKindLeaf : cnt <= lds_limit ? kKindJob : kKindSeg;
+}
+
+struct PlanShared {
+  uint32_t scan[4][kPlanWaves];
+  uint32_t nodes, jobs, segs, tiles, swept, jobpts;
+  uint32_t nbig, nfill;
+  uint32_t big[kPlanBlock];
+  uint32_t fill[2 * kPlanBlock];  // up to two new segments per thread
+};
+
+// Lay out up to K children per thread (all threads must call).  nid_out gets
+// the node of each child (-1 if none).
+template <int K>
+__device__ void emit_children(const Child (&ch)[K], int32_t (&nid_out)[K], Node* nodes, uint32_t node_base, Job* jobs,
+                              Seg* seg_out, unsigned long long* ctr_out, uint32_t* tile_seg_out, uint32_t src,
+                              uint32_t tile, PlanShared& S) {
+  uint32_t v[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    v[0] += ch[k].kind != kKindNone;
+    v[1] += ch[k].kind == kKindJob;
+    v[2] += ch[k].kind == kKindSeg;
+    v[3] += ch[k].kind == kKindSeg ? ceil_div(ch[k].cnt, tile) : 0u;
+  }
+  uint32_t ex[4], tot[4];
+  block_scan<kPlanBlock, 4>(v, ex, tot, S.scan);
+  const uint32_t nb = S.nodes + ex[0], jb = S.jobs + ex[1], sb = S.segs + ex[2], tb = S.tiles + ex[3];
+  uint32_t dn = 0, dj = 0, ds = 0, dt = 0, swept = 0, jobpts = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const Child& c = ch[k];
+    int32_t nid = -1;
+    if (c.kind != kKindNone) {
+      nid = (int32_t)(node_base + nb + dn++);
+      Node nd;
+      nd.vertex = c.ri;
+      nd.c[0] = -1;
+      nd.c[1] = -1;
+      nd.size = c.kind == kKindLeaf ? 1u : 0u;
+      nd.start = 0;
+      nd.req = c.req;
+      nd.list = kNone;
+      nd.lbuf = 0;
+      nodes[nid] = nd;
+    }
+    nid_out[k] = nid;
+    if (c.parent >= 0) nodes[c.parent].c[c.side] = nid;
+    if (c.kind == kKindJob) {
+      Job j;
+      j.ax = c.ax;
+      j.ay = c.ay;
+      j.rx = c.rx;
+      j.ry = c.ry;
+      j.bx = c.bx;
+      j.by = c.by;
+      j.ri = c.ri;
+      j.beg = c.beg;
+      j.cnt = c.cnt;
+      j.src = src;
+      j.req = c.req;
+      j.node = nid;
+      j.ibase = src == kSrcUser ? c.beg : 0u;
+      j.pad = 0;
+      jobs[jb + dj++] = j;
+      jobpts += c.cnt;
+    } else if (c.kind == kKindSeg) {
+      const uint32_t sid = sb + ds++;
+      const uint32_t nt = ceil_div(c.cnt, tile);
+      const uint32_t t0 = tb + dt;
+      dt += nt;
+      swept += c.cnt;
+      Seg sg;
+      sg.ax = c.ax;
+      sg.ay = c.ay;
+      sg.rx = c.rx;
+      sg.ry = c.ry;
+      sg.bx = c.bx;
+      sg.by = c.by;
+      sg.beg = c.beg;
+      sg.cnt = c.cnt;
+      sg.tile0 = t0;
+      sg.req = c.req;
+      sg.node = nid;
+      sg.ibase = src == kSrcUser ? c.beg : 0u;
+      seg_out[sid] = sg;
+      ctr_out[sid] = 0ull;
+      if (nt <= kSerialFill) {
+        for (uint32_t i = 0; i < nt; ++i) tile_seg_out[t0 + i] = sid;
+      } else {
+        S.fill[atomicAdd(&S.nfill, 1u)] = sid;
+      }
+    }
+  }
+  if (swept) atomicAdd(&S.swept, swept);
+  if (jobpts) atomicAdd(&S.jobpts, jobpts);
+  __syncthreads();
+  const uint32_t nf = S.nfill;
+  for (uint32_t f = 0; f < nf; ++f) {
+    const uint32_t sid = S.fill[f];
+    const uint32_t t0 = seg_out[sid].tile0, nt = ceil_div(seg_out[sid].cnt, tile);
+    for (uint32_t i = threadIdx.x; i < nt; i += kPlanBlock) tile_seg_out[t0 + i] = sid;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    S.nodes += tot[0];
+    S.jobs += tot[1];
+    S.segs += tot[2];
+    S.tiles += tot[3];
+    S.nfill = 0;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void plan_init(PlanShared& S) {
+  if (threadIdx.x == 0) {
+    S.nodes = S.jobs = S.segs = S.tiles = S.swept = S.jobpts = 0;
+    S.nbig = S.nfill = 0;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void plan_status(PlanShared& S, Status* out, uint32_t node_base) {
+  if (threadIdx.x == 0) {
+    Status st;
+    st.nseg = S.segs;
+    st.ntiles = S.tiles;
+    st.njobs = S.jobs;
+    st.nnodes = node_base + S.nodes;
+    st.swept = S.swept;
+    st.jobpts = S.jobpts;
+    st.pad[0] = st.pad[1] = 0;
+    *out = st;
+  }
+}
+
+// Lexicographic extremes of partial records (y is present in the records).
+struct Ext {
+  double mnx, mny, mxx, mxy;
+  uint32_t mni, mxi;
+};
+
+__device__ __forceinline__ void ext_merge(Ext& e, double mnx, double mny, uint32_t mni, double mxx, double mxy,
+                                          uint32_t mxi) {
+  if (mni != kNone &&
+      (e.mni == kNone || mnx < e.mnx || (mnx == e.mnx && (mny < e.mny || (mny == e.mny && mni < e.mni))))) {
+    e.mnx = mnx;
+    e.mny = mny;
+    e.mni = mni;
+  }
+  if (mxi != kNone &&
+      (e.mxi == kNone || mxx > e.mxx || (mxx == e.mxx && (mxy > e.mxy || (mxy == e.mxy && mxi < e.mxi))))) {
+    e.mxx = mxx;
+    e.mxy = mxy;
+    e.mxi = mxi;
+  }
+}
+
+__device__ __forceinline__ Ext no_ext() { return Ext{0.0, 0.0, 0.0, 0.0, kNone, kNone}; }
+
+// Root level: p and q of every request, then the degenerate triangle (p, q, p)
+// of Algorithm 1's top level as a job or a level-0 segment.
+__global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
+  __shared__ PlanShared S;
+  __shared__ Ext s_w[kPlanWaves];
+  __shared__ Ext s_res[kPlanBlock];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  plan_init(S);
+  for (uint32_t base = 0; base < A.nreq; base += kPlanBlock) {
+    const uint32_t i = base + tid;
+    const bool valid = i < A.nreq;
+    Req rq{};
+    Ext e = no_ext();
+    bool big = false;
+    if (valid) {
+      rq = A.req[i];
+      const uint32_t nt = ceil_div(rq.n, A.ext_tile);
+      if (nt <= kSerialTiles) {
+        for (uint32_t k = 0; k < nt; ++k) {
+          const ExtPart p = A.epart[rq.tile0 + k];
+          ext_merge(e, p.minx, p.miny, p.mini, p.maxx, p.maxy, p.maxi);
+        }
+      } else {
+        big = true;
+        S.big[atomicAdd(&S.nbig, 1u)] = (uint32_t)tid;
+      }
+    }
+    __syncthreads();
+    const uint32_t nbig = S.nbig;
+    for (uint32_t b = 0; b < nbig; ++b) {
+      const uint32_t owner = S.big[b];
+      const uint32_t t0 = A.req[base + owner].tile0, nt = ceil_div(A.req[base + owner].n, A.ext_tile);
+      Ext me = no_ext();
+      for (uint32_t k = tid; k < nt; k += kPlanBlock) {
+        const ExtPart p = A.epart[t0 + k];
+        ext_merge(me, p.minx, p.miny, p.mini, p.maxx, p.maxy, p.maxi);
+      }
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) {
+        Ext o;
+        o.mnx = __shfl_xor(me.mnx, m, 64);
+        o.mny = __shfl_xor(me.mny, m, 64);
+        o.mni = __shfl_xor(me.mni, m, 64);
+        o.mxx = __shfl_xor(me.mxx, m, 64);
+        o.mxy = __shfl_xor(me.mxy, m, 64);
+        o.mxi = __shfl_xor(me.mxi, m, 64);
+        ext_merge(me, o.mnx, o.mny, o.mni, o.mxx, o.mxy, o.mxi);
+      }
+      if (lane == 0) s_w[w] = me;
+      __syncthreads();
+      if (tid == 0) {
+        Ext f = no_ext();
+        for (int q = 0; q < kPlanWaves; ++q) ext_merge(f, s_w[q].mnx, s_w[q].mny, s_w[q].mni, s_w[q].mxx, s_w[q].mxy,
+                                                       s_w[q].mxi);
+        s_res[owner] = f;
+      }
+      __syncthreads();
+    }
+    if (big) e = s_res[tid];
+    Child ch[1];
+    ch[0].kind = kKindNone;
+    ch[0].parent = -1;
+    ch[0].side = 0;
+    ch[0].cnt = 0;
+    if (valid && rq.n > 0) {
+      Child& c = ch[0];
+      c.ax = e.mnx;
+      c.ay = e.mny;
+      c.rx = e.mxx;
+      c.ry = e.mxy;
+      c.bx = e.mnx;
+      c.by = e.mny;
+      c.ri = e.mxi;
+      c.beg = rq.off;
+      c.cnt = rq.n;
+      c.req = i;
+      c.kind = rq.n <= A.lds_limit ? kKindJob : kKindSeg;
+    }
+    int32_t nid[1];
+    emit_children<1>(ch, nid, A.nodes, 0u, A.jobs, A.seg_out, A.ctr_out, A.tile_seg_out, kSrcUser, A.tile, S);
+    if (valid) {
+      A.req[i].p = rq.n > 0 ? e.mni : 0u;
+      A.req[i].q = rq.n > 0 ? e.mxi : 0u;
+      A.req[i].root = nid[0];
+    }
+    if (tid == 0) S.nbig = 0;
+    __syncthreads();
+  }
+  plan_status(S, A.status, 0u);
+}
+
+// One recursion level: reduce the per-tile counts and candidates of every
+// segment, then lay out its two children (Algorithm 1: Hull(S1, a, r1, r) and
+// Hull(S2, r, r2, b)).  The children's points already sit at the two ends of
+// the segment's range in the output buffer of the sweep.
+__global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
+  __shared__ PlanShared S;
+  __shared__ Cand s_c[kPlanWaves];
+  __shared__ Cand s_res[kPlanBlock][2];
+  const int tid = threadIdx.x;
+  plan_init(S);
+  for (uint32_t base = 0; base < A.nseg; base += kPlanBlock) {
+    const uint32_t s = base + tid;
+    const bool valid = s < A.nseg;
+    Seg sg{};
+    uint32_t n1 = 0, n2 = 0;
+    Cand r1 = no_cand(), r2 = no_cand();
+    bool big = false;
+    if (valid) {
+      sg = A.seg[s];
+      const unsigned long long c = A.ctr[s];
+      n1 = (uint32_t)c;
+      n2 = (uint32_t)(c >> 32);
+      const uint32_t nt = ceil_div(sg.cnt, A.tile);
+      if (nt <= kSerialTiles) {
+        for (uint32_t k = 0; k < nt; ++k) {
+          const TilePart& p = A.part[sg.tile0 + k];
+          if (better(p.c[0], r1)) r1 = p.c[0];
+          if (better(p.c[1], r2)) r2 = p.c[1];
+        }
+      } else {
+        big = true;
+        S.big[atomicAdd(&S.nbig, 1u)] = (uint32_t)tid;
+      }
+    }
+    __syncthreads();
+    const uint32_t nbig = S.nbig;
+    for (uint32_t b = 0; b < nbig; ++b) {
+      const uint32_t owner = S.big[b];
+      const uint32_t t0 = A.seg[base + owner].tile0, nt = ceil_div(A.seg[base + owner].cnt, A.tile);
+      Cand m1 = no_cand(), m2 = no_cand();
+      for (uint32_t k = tid; k < nt; k += kPlanBlock) {
+        const TilePart& p = A.part[t0 + k];
+        if (better(p.c[0], m1)) m1 = p.c[0];
+        if (better(p.c[1], m2)) m2 = p.c[1];
+      }
+      m1 = block_best<kPlanBlock>(m1, s_c);
+      m2 = block_best<kPlanBlock>(m2, s_c);
+      if (tid == 0) {
+        s_res[owner][0] = m1;
+        s_res[owner][1] = m2;
+      }
+      __syncthreads();
+    }
+    if (big) {
+      r1 = s_res[tid][0];
+      r2 = s_res[tid][1];
+    }
+    Child ch[2];
+    ch[0].kind = ch[1].kind = kKindNone;
+    ch[0].parent = ch[1].parent = -1;
+    ch[0].cnt = ch[1].cnt = 0;
+    if (valid) {
+      Child& c = ch[0];
+      c.ax = sg.ax;
+      c.ay = sg.ay;
+      c.rx = r1.x;
+      c.ry = r1.y;
+      c.bx = sg.rx;
+      c.by = sg.ry;
+      c.ri = r1.i;
+      c.beg = sg.beg;
+      c.cnt = n1;
+      c.req = sg.req;
+      c.parent = sg.node;
+      c.side = 0;
+      c.kind = child_kind(n1, A.lds_limit);
+      Child& d = ch[1];
+      d.ax = sg.rx;
+      d.ay = sg.ry;
+      d.rx = r2.x;
+      d.ry = r2.y;
+      d.bx = sg.bx;
+      d.by = sg.by;
+      d.ri = r2.i;
+      d.beg = sg.beg + sg.cnt - n2;
+      d.cnt = n2;
+      d.req = sg.req;
+      d.parent = sg.node;
+      d.side = 1;
+      d.kind = child_kind(n2, A.lds_limit);
+    }
+    int32_t nid[2];
+    emit_children<2>(ch, nid, A.nodes, A.node_base, A.jobs, A.seg_out, A.ctr_out, A.tile_seg_out, A.out_buf, A.tile, S);
+    if (tid == 0) S.nbig = 0;
+    __syncthreads();
+  }
+  plan_status(S, A.status, A.node_base);
+}
+
+// --------------------------------------------------------------- k_finish
+//
+// One workgroup runs Algorithm 1 to the end on a subproblem (a, r, b) of at
+// most TMAX points, entirely in LDS, breadth-first: every level classifies
+// all live points of all live sub-subproblems at once.  Points are addressed
+// by a local id (< TMAX, plus three ids for a, b and r of the root); the live
+// list holds (sub-subproblem << 16 | local id).  Each level:
+//   1. classify every live point, take a slot in its child with an LDS atomic;
+//   2. scan the child sizes: nodes, next sub-subproblems and their ranges;
+//   3. scatter the points into the next live list (one-point children record
+//      their only point as their vertex);
+//   4. one wave per child with >= 2 points finds its farthest point;
+//   5. create the nodes and the next level's sub-subproblems.
+// The ordered vertex list (in-order over the recursion tree) is written over
+// the job's own index range.
+
+constexpr uint16_t kNone16 = 0xFFFFu;
+
+template <int BLOCK, int TMAX>
+struct FinishShared {
+  double lx[TMAX + 3], ly[TMAX + 3];
+  uint32_t lid[TMAX + 3];
+  uint32_t ord[2][TMAX];
+  uint16_t sa[2][TMAX / 2], sr[2][TMAX / 2], sb[2][TMAX / 2], sbeg[2][TMAX / 2], scnt[2][TMAX / 2],
+      snode[2][TMAX / 2];
+  uint32_t ccnt[TMAX];
+  uint16_t cwin[TMAX], cnode[TMAX], cbase[TMAX], cmap[TMAX];
+  uint16_t nv[TMAX], nc0[TMAX], nc1[TMAX], nsz[TMAX], nst[TMAX];
+  uint16_t lvl[TMAX + 2];
+  uint32_t scan[3][BLOCK / 64];
+  uint32_t nsub, ntot, nnode, nlvl, bad;
+};
+
+template <int BLOCK, int TMAX>
+__global__ __launch_bounds__(BLOCK) void k_finish(FinishArgs A) {
+  constexpr int NW = BLOCK / 64;
+  constexpr int KP = (TMAX + BLOCK - 1) / BLOCK;  // live points per thread per level
+  constexpr int KC = (TMAX + BLOCK - 1) / BLOCK;  // children per thread per level
+  extern __shared__ unsigned char smem_raw[];
+  FinishShared<BLOCK, TMAX>& S = *reinterpret_cast<FinishShared<BLOCK, TMAX>*>(smem_raw);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const Job job = A.jobs[blockIdx.x];
+  const uint32_t cnt = job.cnt;
+  const bool user = job.src == kSrcUser;
+  const double* X = user ? A.ux : A.bx[job.src];
+  const double* Y = user ? A.uy : A.by[job.src];
+  const uint32_t* I = user ? nullptr : A.bi[job.src];
+  uint32_t* out = A.bi[user ? 0 : job.src] + job.beg;
+
+  if (tid == 0) S.bad = 0;
+  __syncthreads();
+  bool bad = false;
+  for (uint32_t l = tid; l < cnt; l += BLOCK) {
+    const uint32_t pos = job.beg + l;
+    const double xv = X[pos], yv = Y[pos];
+    S.lx[l] = xv;
+    S.ly[l] = yv;
+    S.lid[l] = user ? pos - job.ibase : I[pos];
+    S.ord[0][l] = l;
+    if (user) bad |= !finite(xv) || !finite(yv);
+  }
+  if (bad) S.bad = 1;
+  if (tid == 0) {
+    S.lx[cnt] = job.ax;
+    S.ly[cnt] = job.ay;
+    S.lx[cnt + 1] = job.bx;
+    S.ly[cnt + 1] = job.by;
+    S.lx[cnt + 2] = job.rx;
+    S.ly[cnt + 2] = job.ry;
+    S.lid[cnt + 2] = job.ri;
+    S.sa[0][0] = (uint16_t)cnt;
+    S.sb[0][0] = (uint16_t)(cnt + 1);
+    S.sr[0][0] = (uint16_t)(cnt + 2);
+    S.sbeg[0][0] = 0;
+    S.scnt[0][0] = (uint16_t)cnt;
+    S.snode[0][0] = 0;
+    S.nv[0] = (uint16_t)(cnt + 2);
+    S.nc0[0] = kNone16;
+    S.nc1[0] = kNone16;
+    S.nsub = 1;
+    S.ntot = cnt;
+    S.nnode = 1;
+    S.lvl[0] = 0;
+    S.lvl[1] = 1;
+    S.nlvl = 1;
+  }
+  __syncthreads();
+  if (S.bad && tid == 0) A.req[job.req].err = 1u;
+
+  int cb = 0;  // live list buffer / sub-subproblem table of this level
+  while (S.nsub > 0) {
+    const uint32_t nsub = S.nsub, ntot = S.ntot, nch = 2u * nsub;
+    for (uint32_t c = tid; c < nch; c += BLOCK) S.ccnt[c] = 0;
+    __syncthreads();
+    // 1. classify
+    uint32_t chd[KP], slot[KP], pid[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const uint32_t e = tid + k * BLOCK;
+      chd[k] = kNone;
+      slot[k] = 0;
+      pid[k] = 0;
+      if (e < ntot) {
+        const uint32_t ent = S.ord[cb][e];
+        const uint32_t s = ent >> 16, l = ent & 0xFFFFu;
+        const uint32_t a = S.sa[cb][s], r = S.sr[cb][s], b = S.sb[cb][s];
+        const double ux = S.lx[l], uy = S.ly[l];
+        const double o1 = orient(S.lx[a], S.ly[a], S.lx[r], S.ly[r], ux, uy);
+        uint32_t c = kNone;
+        if (o1 > 0.0) {
+          c = 2u * s;
+        } else {
+          const double o2 = orient(S.lx[r], S.ly[r], S.lx[b], S.ly[b], ux, uy);
+          if (o2 > 0.0) c = 2u * s + 1u;
+        }
+        if (c != kNone) slot[k] = atomicAdd(&S.ccnt[c], 1u);
+        chd[k] = c;
+        pid[k] = l;
+      }
+    }
+    __syncthreads();
+    // 2. scan child sizes (children are assigned to threads in contiguous runs)
+    {
+      uint32_t v[3] = {0, 0, 0};
+      const uint32_t c0 = tid * KC;
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        const uint32_t c = c0 + k;
+        if (c < nch) {
+          const uint32_t n = S.ccnt[c];
+          v[0] += n >= 1u;
+          v[1] += n >= 2u;
+          v[2] += n >= 2u ? n : 0u;
+        }
+      }
+      uint32_t ex[3], tot[3];
+      block_scan<BLOCK, 3>(v, ex, tot, S.scan);
+      uint32_t en = S.nnode + ex[0], es = ex[1], ep = ex[2];
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        const uint32_t c = c0 + k;
+        if (c < nch) {
+          const uint32_t n = S.ccnt[c];
+          S.cnode[c] = n >= 1u ? (uint16_t)en : kNone16;
+          S.cmap[c] = n >= 2u ? (uint16_t)es : kNone16;
+          S.cbase[c] = (uint16_t)ep;
+          en += n >= 1u;
+          es += n >= 2u;
+          ep += n >= 2u ? n : 0u;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        S.nnode += tot[0];
+        S.nsub = tot[1];
+        S.ntot = tot[2];
+      }
+    }
+    __syncthreads();
+    // 3. scatter
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const uint32_t c = chd[k];
+      if (c != kNone) {
+        if (S.ccnt[c] >= 2u) {
+          S.ord[cb ^ 1][S.cbase[c] + slot[k]] = ((uint32_t)S.cmap[c] << 16) | pid[k];
+        } else {
+          S.cwin[c] = (uint16_t)pid[k];
+        }
+      }
+    }
+    __syncthreads();
+    // 4. farthest point of every child with >= 2 points (one wave per child)
+    for (uint32_t c = w; c < nch; c += NW) {
+      const uint32_t n = S.ccnt[c];
+      if (n < 2u) continue;
+      const uint32_t s = c >> 1;
+      const uint32_t ea = (c & 1u) ? S.sr[cb][s] : S.sa[cb][s];
+      const uint32_t eb = (c & 1u) ? S.sb[cb][s] : S.sr[cb][s];
+      const double ex0 = S.lx[ea], ey0 = S.ly[ea], ex1 = S.lx[eb], ey1 = S.ly[eb];
+      Cand best = no_cand();
+      const uint32_t b0 = S.cbase[c];
+      for (uint32_t e = lane; e < n; e += 64) {
+        const uint32_t l = S.ord[cb ^ 1][b0 + e] & 0xFFFFu;
+        const double k = orient(ex0, ey0, ex1, ey1, S.lx[l], S.ly[l]);
+        if (better(k, S.lx[l], S.ly[l], S.lid[l], best)) {
+          best.k = k;
+          best.x = S.lx[l];
+          best.y = S.ly[l];
+          best.i = S.lid[l];
+          best.pad = l;
+        }
+      }
+      wave_best(best);  // pad carries the winner's local id
+      if (lane == 0) S.cwin[c] = (uint16_t)best.pad;
+    }
+    __syncthreads();
+    // 5. nodes and next sub-subproblems
+    for (uint32_t c = tid; c < nch; c += BLOCK) {
+      const uint32_t n = S.ccnt[c];
+      const uint32_t s = c >> 1, side = c & 1u;
+      const uint32_t parent = S.snode[cb][s];
+      const uint16_t v = S.cnode[c];
+      if (side) {
+        S.nc1[parent] = v;
+      } else {
+        S.nc0[parent] = v;
+      }
+      if (n >= 1u) {
+        S.nv[v] = S.cwin[c];
+        S.nc0[v] = kNone16;
+        S.nc1[v] = kNone16;
+      }
+      if (n >= 2u) {
+        const uint32_t ns = S.cmap[c];
+        S.sa[cb ^ 1][ns] = side ? S.sr[cb][s] : S.sa[cb][s];
+        S.sb[cb ^ 1][ns] = side ? S.sb[cb][s] : S.sr[cb][s];
+        S.sr[cb ^ 1][ns] = S.cwin[c];
+        S.sbeg[cb ^ 1][ns] = S.cbase[c];
+        S.scnt[cb ^ 1][ns] = (uint16_t)n;
+        S.snode[cb ^ 1][ns] = v;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      S.nlvl += 1;
+      S.lvl[S.nlvl] = (uint16_t)S.nnode;
+    }
+    __syncthreads();
+    cb ^= 1;
+  }
+  // in-order positions: subtree sizes bottom-up, starts top-down
+  const uint32_t nlvl = S.nlvl;
+  for (int L = (int)nlvl - 1; L >= 0; --L) {
+    for (uint32_t v = S.lvl[L] + tid; v < S.lvl[L + 1]; v += BLOCK) {
+      const uint16_t c0 = S.nc0[v], c1 = S.nc1[v];
+      S.nsz[v] = (uint16_t)(1u + (c0 != kNone16 ? S.nsz[c0] : 0u) + (c1 != kNone16 ? S.nsz[c1] : 0u));
+    }
+    __syncthreads();
+  }
+  if (tid == 0) S.nst[0] = 0;
+  __syncthreads();
+  for (uint32_t L = 0; L < nlvl; ++L) {
+    for (uint32_t v = S.lvl[L] + tid; v < S.lvl[L + 1]; v += BLOCK) {
+      const uint16_t c0 = S.nc0[v], c1 = S.nc1[v];
+      const uint32_t pos = S.nst[v] + (c0 != kNone16 ? S.nsz[c0] : 0u);
+      out[pos] = S.lid[S.nv[v]];
+      if (c0 != kNone16) S.nst[c0] = S.nst[v];
+      if (c1 != kNone16) S.nst[c1] = (uint16_t)(pos + 1u);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    Node* nd = A.nodes + job.node;
+    nd->size = S.nsz[0];
+    nd->list = job.beg;
+    nd->lbuf = user ? 0u : job.src;
+  }
+}
+
+// ------------------------------------------------------------- k_assemble
+//
+// Clockwise order of every request: [p] ++ in-order(root), where the root's
+// vertex is q and in-order(v) = in-order(S1 child) ++ [v] ++ in-order(S2
+// child) (Algorithm 1's unions in order).  One workgroup: subtree sizes
+// bottom-up level by level, then output positions top-down.  Subtrees
+// finished in LDS already hold their ordered lists; k_copy_lists moves them.
+
+constexpr int kAsmBlock = 1024;
+
+__global__ __launch_bounds__(kAsmBlock) void k_assemble(AssembleArgs A) {
+  const int tid = threadIdx.x;
+  for (int L = (int)A.nlevels - 1; L >= 0; --L) {
+    for (uint32_t v = A.level_begin[L] + tid; v < A.level_begin[L + 1]; v += kAsmBlock) {
+      Node& nd = A.nodes[v];
+      if (nd.list != kNone) continue;
+      const int32_t c0 = nd.c[0], c1 = nd.c[1];
+      nd.size = 1u + (c0 >= 0 ? A.nodes[c0].size : 0u) + (c1 >= 0 ? A.nodes[c1].size : 0u);
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  for (uint32_t i = tid; i < A.nreq; i += kAsmBlock) {
+    const Req rq = A.req[i];
+    if (rq.root >= 0) A.nodes[rq.root].start = 1u;
+  }
+  __syncthreads();
+  for (uint32_t L = 0; L < A.nlevels; ++L) {
+    for (uint32_t v = A.level_begin[L] + tid; v < A.level_begin[L + 1]; v += kAsmBlock) {
+      const Node nd = A.nodes[v];
+      const Req rq = A.req[nd.req];
+      if (rq.err || rq.p == rq.q) continue;
+      if (nd.list != kNone) continue;
+      const int32_t c0 = nd.c[0], c1 = nd.c[1];
+      const uint32_t pos = nd.start + (c0 >= 0 ? A.nodes[c0].size : 0u);
+      A.out_idx[rq.off + pos] = (int64_t)nd.vertex;
+      if (c0 >= 0) A.nodes[c0].start = nd.start;
+      if (c1 >= 0) A.nodes[c1].start = pos + 1u;
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  for (uint32_t i = tid; i < A.nreq; i += kAsmBlock) {
+    const Req rq = A.req[i];
+    int64_t count;
+    if (rq.err) {
+      count = -3;
+    } else if (rq.n == 0) {
+      count = 0;
+    } else if (rq.p == rq.q) {
+      A.out_idx[rq.off] = (int64_t)rq.p;
+      count = 1;
+    } else {
+      A.out_idx[rq.off] = (int64_t)rq.p;
+      count = 1 + (int64_t)A.nodes[rq.root].size;
+    }
+    A.out_count[i] = count;
+  }
+}
+
+// Copy the ordered lists of LDS-finished subtrees into place (one wave each).
+__global__ __launch_bounds__(256) void k_copy_lists(AssembleArgs A) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = (blockIdx.x * 256u + threadIdx.x) >> 6;
+  const uint32_t nwaves = (gridDim.x * 256u) >> 6;
+  for (uint32_t v = wave; v < A.nnodes; v += nwaves) {
+    const Node nd = A.nodes[v];
+    if (nd.list == kNone) continue;
+    const Req rq = A.req[nd.req];
+    if (rq.err || rq.p == rq.q) continue;
+    const uint32_t* src = A.lists[nd.lbuf] + nd.list;
+    int64_t* dst = A.out_idx + rq.off + nd.start;
+    for (uint32_t e = lane; e < nd.size; e += 64) dst[e] = (int64_t)src[e];
+  }
+}
+
+// -------------------------------------------------------------- launchers
+
+namespace {
+template <int BLOCK, int PPT>
+int sweep_one(const SweepArgs& a, bool level0, hipStream_t st) {
+  if (level0) {
+    hipLaunchKernelGGL((k_sweep<BLOCK, PPT, true>), dim3(a.ntiles), dim3(BLOCK), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_sweep<BLOCK, PPT, false>), dim3(a.ntiles), dim3(BLOCK), 0, st, a);
+  }
+  return (int)hipGetLastError();
+}
+
+template <int BLOCK, int TMAX>
+int finish_one(const FinishArgs& a, uint32_t njobs, hipStream_t st) {
+  const size_t bytes = sizeof(FinishShared<BLOCK, TMAX>);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_finish<BLOCK, TMAX>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return (int)e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_finish<BLOCK, TMAX>), dim3(njobs), dim3(BLOCK), bytes, st, a);
+  return (int)hipGetLastError();
+}
+}  // namespace
+
+bool sweep_shape_supported(int block, int ppt) {
+  return (block == 256 && (ppt == 16 || ppt == 32)) || (block == 512 && (ppt == 8 || ppt == 16)) ||
+         (block == 1024 && ppt == 8);
+}
+
+int finish_tmax_for(int lds_limit) { return lds_limit <= 512 ? 512 : lds_limit <= 1024 ? 1024 : 2048; }
+
+int launch_extremes(const ExtremesArgs& a, void* stream) {
+  if (a.ntiles == 0) return 0;
+  hipLaunchKernelGGL((k_extremes<kExtBlock, kExtPPT>), dim3(a.ntiles), dim3(kExtBlock), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int launch_sweep(const SweepArgs& a, bool level0, int block, int ppt, void* stream) {
+  if (a.ntiles == 0) return 0;
+  hipStream_t st = (hipStream_t)stream;
+  if (block == 256 && ppt == 16) return sweep_one<256, 16>(a, level0, st);
+  if (block == 256 && ppt == 32) return sweep_one<256, 32>(a, level0, st);
+  if (block == 512 && ppt == 8) return sweep_one<512, 8>(a, level0, st);
+  if (block == 512 && ppt == 16) return sweep_one<512, 16>(a, level0, st);
+  if (block == 1024 && ppt == 8) return sweep_one<1024, 8>(a, level0, st);
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_plan0(const Plan0Args& a, void* stream) {
+  hipLaunchKernelGGL(k_plan0, dim3(1), dim3(kPlanBlock), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int launch_plan(const PlanArgs& a, void* stream) {
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanBlock), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int launch_finish(const FinishArgs& a, uint32_t njobs, int tmax, void* stream) {
+  if (njobs == 0) return 0;
+  hipStream_t st = (hipStream_t)stream;
+  if (tmax == 512) return finish_one<256, 512>(a, njobs, st);
+  if (tmax == 1024) return finish_one<256, 1024>(a, njobs, st);
+  if (tmax == 2048) return finish_one<256, 2048>(a, njobs, st);
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_assemble(const AssembleArgs& a, void* stream) {
+  hipLaunchKernelGGL(k_assemble, dim3(1), dim3(kAsmBlock), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int launch_copy_lists(const AssembleArgs& a, void* stream) {
+  if (a.nnodes == 0) return 0;
+  const uint32_t waves = a.nnodes < 65536u ? a.nnodes : 65536u;
+  hipLaunchKernelGGL(k_copy_lists, dim3((waves + 3u) / 4u), dim3(256), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+}  // namespace vqh

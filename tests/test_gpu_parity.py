@@ -1,0 +1,201 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, index
+list for index list (bit-exact), on seeded inputs that span several tiles and
+ragged tails, on the degenerate cases of Algorithm 1, and under every kernel
+shape the library supports (the result must not depend on it)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_09417_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "known_hulls.json")
+
+
+@pytest.fixture(scope="module")
+def vq():
+    import torch
+
+    import paper_2510_09417_amd as vq
+
+    assert torch.cuda.is_available()
+    vq.load_library()
+    vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048, reverse_tiles=0)
+    yield vq
+    vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048, reverse_tiles=0)
+
+
+def gpu_hull(vq, x, y):
+    import torch
+
+    tx = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+    ty = torch.from_numpy(np.ascontiguousarray(y, dtype=np.float64)).cuda()
+    return vq.hull(tx, ty).cpu().numpy()
+
+
+def check(vq, x, y, label=""):
+    want = oracle.hull(x, y)
+    got = gpu_hull(vq, x, y)
+    assert got.dtype == np.int64
+    if not np.array_equal(got, want):
+        k = next((i for i in range(min(len(got), len(want))) if got[i] != want[i]), min(len(got), len(want)))
+        raise AssertionError(f"{label}: gpu h={len(got)} oracle h={len(want)}; first difference at {k}")
+
+
+def _cases():
+    with open(GOLDEN) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _cases(), ids=lambda c: c["name"])
+def test_known_hulls(vq, case):
+    x = np.array(case["x"], dtype=np.float64)
+    y = np.array(case["y"], dtype=np.float64)
+    got = gpu_hull(vq, x, y).tolist()
+    assert got == case["hull"]
+
+
+@pytest.mark.parametrize("dist", list(workloads.DISTRIBUTIONS))
+@pytest.mark.parametrize("n", [3, 100, 2047, 2048, 2049, 4095, 4097, 20_000, 123_457])
+def test_distributions_small(vq, dist, n):
+    x, y = workloads.points(dist, n, seed=n + 17)
+    check(vq, x, y, f"{dist} n={n}")
+
+
+def test_disk_1e6_seed1(vq):
+    """The 10^6-point unit-disk workload (seed 1), bit-exact."""
+    x, y = workloads.workload("disk_1e6")
+    check(vq, x, y, "disk 1e6")
+
+
+@pytest.mark.parametrize("dist", ["square", "circle", "kuzmin"])
+def test_distributions_1e6(vq, dist):
+    x, y = workloads.points(dist, 1_000_000, seed=5)
+    check(vq, x, y, f"{dist} 1e6")
+
+
+def test_lattices(vq):
+    for k in range(60):
+        n = [5, 50, 500, 3000, 9000, 40_000][k % 6]
+        hi = [3, 7, 100, 2**20 - 1][k % 4]
+        x, y = workloads.lattice(n, seed=300 + k, lo=-hi, hi=hi, dup_frac=0.1, collinear_runs=3)
+        check(vq, x, y, f"lattice k={k}")
+
+
+def test_lattice_many_ties_large(vq):
+    """Exactly collinear and duplicated points everywhere, many tiles."""
+    x, y = workloads.lattice(400_000, seed=9, lo=0, hi=15, dup_frac=0.3)
+    check(vq, x, y, "lattice 16x16 4e5")
+
+
+def test_degenerate(vq):
+    for n in (0, 1, 2, 3, 5000, 70_000):
+        check(vq, np.full(n, 3.0), np.full(n, -2.0), f"identical n={n}")
+        t = np.random.default_rng(n).random(n)
+        check(vq, t, 2.0 * t + 1.0, f"collinear n={n}")
+        check(vq, np.zeros(n), t, f"vertical n={n}")
+    check(vq, np.array([0.0, -0.0, 1.0, 0.0]), np.array([-0.0, 0.0, 0.0, 1.0]), "signed zeros")
+
+
+def test_nonfinite_reported(vq):
+    import torch
+
+    for bad in (np.nan, np.inf, -np.inf):
+        for n, where in ((1, 0), (10, 3), (50_000, 49_999), (50_000, 7)):
+            for axis in ("x", "y"):
+                x, y = workloads.points("disk", n, seed=1)
+                (x if axis == "x" else y)[where] = bad
+                with pytest.raises(vq.VqhullError) as e:
+                    gpu_hull(vq, x, y)
+                assert e.value.status == vq.VQHULL_ERR_NONFINITE
+    # the library still works afterwards
+    x, y = workloads.points("disk", 1000, seed=2)
+    check(vq, x, y, "after error")
+    assert torch.cuda.is_available()
+
+
+@pytest.mark.parametrize("shape", [(256, 16), (256, 32), (512, 8), (512, 16), (1024, 8)])
+@pytest.mark.parametrize("lds_limit", [256, 1024, 2048])
+def test_kernel_shapes_do_not_change_result(vq, shape, lds_limit):
+    vq.set_config(sweep_block=shape[0], sweep_ppt=shape[1], lds_limit=lds_limit)
+    try:
+        for dist in workloads.DISTRIBUTIONS:
+            x, y = workloads.points(dist, 300_001, seed=77)
+            check(vq, x, y, f"{dist} {shape} lds={lds_limit}")
+    finally:
+        vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048)
+
+
+def test_reverse_tile_order(vq):
+    vq.set_config(reverse_tiles=1)
+    try:
+        for dist in workloads.DISTRIBUTIONS:
+            x, y = workloads.points(dist, 500_000, seed=78)
+            check(vq, x, y, f"{dist} reversed tiles")
+    finally:
+        vq.set_config(reverse_tiles=0)
+
+
+def test_repeatable(vq):
+    x, y = workloads.points("circle", 400_000, seed=4)
+    a = gpu_hull(vq, x, y)
+    for _ in range(3):
+        assert np.array_equal(gpu_hull(vq, x, y), a)
+
+
+def test_batched_equals_alone(vq):
+    import torch
+
+    rng = np.random.default_rng(12)
+    sizes = [0, 1, 2, 3, 17, 2048, 2049, 5000, 0, 100_000, 7, 40_000, 1]
+    xs, ys = [], []
+    for i, n in enumerate(sizes):
+        x, y = workloads.points(workloads.DISTRIBUTIONS[i % 4], n, seed=[7, i])
+        xs.append(x)
+        ys.append(y)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    X = torch.from_numpy(np.concatenate(xs)).cuda()
+    Y = torch.from_numpy(np.concatenate(ys)).cuda()
+    out, cnt = vq.hull_batched(X, Y, off)
+    out, cnt = out.cpu().numpy(), cnt.cpu().numpy()
+    for i, n in enumerate(sizes):
+        want = oracle.hull(xs[i], ys[i])
+        got = out[off[i]: off[i] + cnt[i]]
+        assert cnt[i] == len(want) and np.array_equal(got, want), f"request {i} (n={n})"
+    assert rng is not None
+
+
+def test_batched_nonfinite_isolated(vq):
+    import torch
+
+    sizes = [1000, 3000, 5000]
+    xs, ys = [], []
+    for i, n in enumerate(sizes):
+        x, y = workloads.points("disk", n, seed=[8, i])
+        xs.append(x)
+        ys.append(y)
+    ys[1][10] = np.nan
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    out, cnt = vq.hull_batched(torch.from_numpy(np.concatenate(xs)).cuda(), torch.from_numpy(np.concatenate(ys)).cuda(),
+                               off)
+    cnt = cnt.cpu().numpy()
+    out = out.cpu().numpy()
+    assert cnt[1] == -vq.VQHULL_ERR_NONFINITE
+    for i in (0, 2):
+        assert np.array_equal(out[off[i]: off[i] + cnt[i]], oracle.hull(xs[i], ys[i]))
+
+
+def test_level0_sweep_sets_via_stats(vq):
+    """Level statistics: the first sweep level covers every point of the request."""
+    x, y = workloads.points("disk", 1_000_000, seed=3)
+    gpu_hull(vq, x, y)
+    st = vq.level_stats()
+    assert st[0]["segments"] == 1 and st[0]["swept"] == 1_000_000
+    # level 1 keeps exactly the points strictly left of p->q or of q->p
+    p, q = oracle.extremes(x, y)
+    s1, s2, _, _ = oracle.split(x, y, np.arange(len(x)), p, q, p)
+    assert st[1]["swept"] + st[1]["job_points"] == len(s1) + len(s2)

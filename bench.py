@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark of the gfx950 Quickhull on one GPU.
+
+One step = the hull of 10^8 uniform unit-disk points plus the hull of 10^8
+uniform unit-square points (seed 2 each; recipe in paper_2510_09417_amd/
+workloads.py), i.e. every kernel of the path (extremes, every sweep level,
+planners, LDS finisher, assembly) over 2e8 points already resident in HBM.
+Prints one JSON line:
+
+  value       whole-step throughput, Gpoints/s (points hulled / wall time);
+  roofline    the level-0 fused sweep (the dominant kernel): algorithmic bytes
+              per launch (16 B read per input point + 20 B written per kept
+              point) over its average duration, from HIP events recorded on the
+              launch stream during the timed steps, against 8 TB/s;
+  cpu_baseline  the CPU oracle (single thread) on one whole step.
+
+Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_level0_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2510_09417_amd", "csrc", "vqhull_kernels.hip")
+METRIC = "Gpoints/s + % HBM peak (1e8 FP64 pts); batched hulls/s + p50/p99 latency"
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic():
+    """Measured HBM bytes per level-0 sweep launch (from rocprofv3 counters), or
+    None when absent or taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n", type=int, default=100_000_000, help="points per dataset (default 1e8)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described "
+              "in DESIGN.md and is not built.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2510_09417_amd as vq
+    from paper_2510_09417_amd import workloads
+
+    vq.load_library()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    names = ("disk_1e8", "square_1e8")
+    data = []
+    for name in names:
+        t0 = time.perf_counter()
+        x, y = workloads.workload(name, n=args.n)
+        data.append((name, x, y))
+        log(f"generated {name} n={len(x)} in {time.perf_counter() - t0:.1f}s")
+    dx = [(torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)) for _, x, y in data]
+    outs = [(torch.empty(len(x), dtype=torch.int64, device=dev), torch.empty(1, dtype=torch.int64, device=dev))
+            for _, x, _ in data]
+    npts = sum(len(x) for _, x, _ in data)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        for (tx, ty), (oi, oc) in zip(dx, outs):
+            vq.hull_into(tx, ty, oi, oc, stream)
+
+    # STREAM-Scale probe (context: achievable HBM bandwidth)
+    a = torch.empty(args.n, dtype=torch.float64, device=dev).uniform_()
+    b = torch.empty_like(a)
+    probe = []
+    for i in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        vq.stream_scale(a, b, 3.0, stream)
+        e1.record(stream)
+        e1.synchronize()
+        if i:
+            probe.append(e0.elapsed_time(e1))
+    del a, b
+    probe_gbs = 16.0 * args.n / (sorted(probe)[len(probe) // 2] * 1e-3) / 1e9
+    log(f"stream-scale probe: {probe_gbs:.0f} GB/s")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    hulls = [int(oc.item()) for _, oc in outs]
+    log(f"hull sizes: {dict(zip(names, hulls))}")
+
+    # timed region: kernel timing events are recorded on the launch stream
+    vq.set_timing(True)
+    sweep0 = []  # (ms, bytes) of every level-0 sweep launch
+    per_kind = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for (tx, ty), (oi, oc) in zip(dx, outs):
+            vq.hull_into(tx, ty, oi, oc, stream)
+            for r in vq.kernel_times():
+                per_kind.setdefault(r["kind"], 0.0)
+                per_kind[r["kind"]] += r["ms"]
+                if r["kind"] == "sweep" and r["level"] == 0:
+                    sweep0.append((r["ms"], 16 * r["points_in"] + 20 * r["points_out"]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    vq.set_timing(False)
+    wall = t1 - t0
+    ms_per_step = 1e3 * wall / args.steps
+    value = npts * args.steps / wall / 1e9
+
+    avg_ms = sum(m for m, _ in sweep0) / len(sweep0)
+    avg_bytes = sum(b for _, b in sweep0) / len(sweep0)
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = load_traffic()
+    roofline = {
+        "bound": "hbm",
+        "kernel": "k_sweep level 0 (fused orient + farthest point + S1/S2 extraction)",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic["bytes_per_launch"] if traffic else None,
+        "bytes_per_launch_alg": int(avg_bytes),
+        "avg_launch_ms": round(avg_ms, 4),
+        "launches": len(sweep0),
+        "stream_scale_gbs": round(probe_gbs, 1),
+        "frac_of_stream_scale": round(achieved / probe_gbs, 4),
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.load()
+        t0 = time.perf_counter()
+        for _, x, y in data:
+            oracle.hull(x, y)
+        tc = time.perf_counter() - t0
+        cpu = {"value": round(npts / tc / 1e9, 5), "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
+               "sample": f"one whole step: {' + '.join(names)} ({npts} points), single-threaded C oracle, "
+                         f"{tc:.2f} s"}
+        log(f"cpu oracle: {tc:.2f}s for one step")
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "Gpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{'+'.join(names)} (uniform disk and unit square, seed 2)",
+                   "points_per_step": npts, "hull_sizes": hulls},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernel_ms_per_step": {k: round(v / args.steps, 4) for k, v in per_kind.items()},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

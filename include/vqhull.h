@@ -110,6 +110,8 @@ typedef struct {
   int sweep_ppt;    /* points per thread of the partition sweep: 8, 16 or 32 */
   int lds_limit;    /* subproblems of at most this many points finish inside one workgroup: 256..2048 */
   int reverse_tiles;/* debug: process tiles in reverse order (the result must not change) */
+  int sweep_persistent; /* 1: the sweep runs as many workgroups as fit on the GPU at once, each
+                           looping over tiles; 0: one workgroup per tile */
 } vqhull_config;
 
 /* Read / replace the configuration used by later calls (host pointers). */
@@ -120,6 +122,40 @@ int vqhull_set_config(const vqhull_config* cfg);
  * up to cap entries of 4 int64: live subproblems, points swept, subproblems
  * finished in LDS, points finished in LDS).  Returns the number of levels. */
 int64_t vqhull_last_level_stats(int64_t* out, int64_t cap);
+
+/* Kernel timing of the last hull call on this device, for benchmarks: when
+ * enabled, HIP events are recorded on the call's stream around every kernel
+ * launch.  Kinds: */
+enum {
+  VQHULL_K_EXTREMES = 0, /* leftmost / rightmost points */
+  VQHULL_K_PLAN0 = 1,    /* root planning */
+  VQHULL_K_SWEEP = 2,    /* fused partition sweep of one level */
+  VQHULL_K_PLAN = 3,     /* planning of one level */
+  VQHULL_K_FINISH = 4,   /* LDS finisher of one level's small subproblems */
+  VQHULL_K_ASSEMBLE = 5  /* clockwise assembly (both kernels) */
+};
+typedef struct {
+  int32_t kind;       /* VQHULL_K_* */
+  int32_t level;      /* recursion level of the launch (0 for the root) */
+  double ms;          /* elapsed time between the events around the launch */
+  int64_t points_in;  /* points the launch reads */
+  int64_t points_out; /* points the launch writes (sweep: |S1| + |S2| over all segments) */
+} vqhull_kernel_time;
+
+/* Enable (1) or disable (0) kernel timing for later calls. */
+int vqhull_set_timing(int enable);
+
+/* Copy up to cap records of the last call (host pointer); returns the count. */
+int64_t vqhull_last_kernel_times(vqhull_kernel_time* out, int64_t cap);
+
+/*
+ * HBM probe for the bandwidth context (the paper reports bandwidth as a share
+ * of the STREAM "Scale" kernel, Section 5.1): out[i] = s * in[i] for
+ * i < n, one read and one write of 8 bytes per element.
+ *   in, out  device arrays of n doubles (must not overlap).
+ * Returns VQHULL_OK or VQHULL_ERR_INVALID_ARGUMENT; stream-ordered, no sync.
+ */
+int vqhull_stream_scale(const double* in, double* out, int64_t n, double s, vqhull_stream_t stream);
 
 /* Free the cached device workspace of the current device. */
 int vqhull_release_workspace(void);

@@ -23,8 +23,11 @@ VQHULL_ERR_HIP = 4
 # Symbols that include/vqhull.h declares.
 EXPORTED = (
     "vqhull_hull", "vqhull_hull_batched", "vqhull_get_config", "vqhull_set_config",
-    "vqhull_last_level_stats", "vqhull_release_workspace", "vqhull_status_string", "vqhull_last_error",
+    "vqhull_last_level_stats", "vqhull_set_timing", "vqhull_last_kernel_times", "vqhull_stream_scale",
+    "vqhull_release_workspace", "vqhull_status_string", "vqhull_last_error",
 )
+
+KERNEL_KINDS = ("extremes", "plan0", "sweep", "plan", "finish", "assemble")
 
 
 class VqhullError(RuntimeError):
@@ -35,10 +38,15 @@ class VqhullError(RuntimeError):
 
 class Config(ctypes.Structure):
     _fields_ = [("sweep_block", ctypes.c_int), ("sweep_ppt", ctypes.c_int), ("lds_limit", ctypes.c_int),
-                ("reverse_tiles", ctypes.c_int)]
+                ("reverse_tiles", ctypes.c_int), ("sweep_persistent", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("level", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("points_in", ctypes.c_int64), ("points_out", ctypes.c_int64)]
 
 
 _lock = threading.Lock()
@@ -65,6 +73,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.vqhull_set_config.argtypes = [ctypes.POINTER(Config)]
         lib.vqhull_last_level_stats.restype = i64
         lib.vqhull_last_level_stats.argtypes = [pi64, i64]
+        lib.vqhull_set_timing.restype = ctypes.c_int
+        lib.vqhull_set_timing.argtypes = [ctypes.c_int]
+        lib.vqhull_last_kernel_times.restype = i64
+        lib.vqhull_last_kernel_times.argtypes = [ctypes.POINTER(KernelTime), i64]
+        lib.vqhull_stream_scale.restype = ctypes.c_int
+        lib.vqhull_stream_scale.argtypes = [vp, vp, i64, ctypes.c_double, vp]
         lib.vqhull_release_workspace.restype = ctypes.c_int
         lib.vqhull_release_workspace.argtypes = []
         lib.vqhull_status_string.restype = ctypes.c_char_p
@@ -164,7 +178,7 @@ def get_config() -> dict:
 
 
 def set_config(**kw) -> dict:
-    """Update tuning knobs (sweep_block, sweep_ppt, lds_limit, reverse_tiles)."""
+    """Update tuning knobs (sweep_block, sweep_ppt, lds_limit, reverse_tiles, sweep_persistent)."""
     lib = load_library()
     c = Config()
     _check(lib, lib.vqhull_get_config(ctypes.byref(c)))
@@ -184,6 +198,33 @@ def level_stats() -> list[dict]:
     n = lib.vqhull_last_level_stats(buf, n)
     return [dict(segments=buf[4 * i], swept=buf[4 * i + 1], jobs=buf[4 * i + 2], job_points=buf[4 * i + 3])
             for i in range(n)]
+
+
+def set_timing(enable: bool) -> None:
+    """Record HIP events around every kernel launch of later calls."""
+    lib = load_library()
+    _check(lib, lib.vqhull_set_timing(1 if enable else 0))
+
+
+def kernel_times() -> list[dict]:
+    """Per-launch timing records of the last call (needs set_timing(True))."""
+    lib = load_library()
+    n = lib.vqhull_last_kernel_times(None, 0)
+    buf = (KernelTime * max(n, 1))()
+    n = lib.vqhull_last_kernel_times(buf, n)
+    return [dict(kind=KERNEL_KINDS[buf[i].kind], level=buf[i].level, ms=buf[i].ms, points_in=buf[i].points_in,
+                 points_out=buf[i].points_out) for i in range(n)]
+
+
+def stream_scale(src, dst, s: float = 3.0, stream=None) -> None:
+    """dst = s * src on the GPU (float64 tensors of equal length): the HBM probe."""
+    import torch
+
+    if src.dtype != torch.float64 or dst.dtype != torch.float64 or src.numel() != dst.numel():
+        raise ValueError("src and dst must be float64 tensors of equal length")
+    lib = load_library()
+    _check(lib, lib.vqhull_stream_scale(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                        src.numel(), float(s), _stream_handle(stream)))
 
 
 def release_workspace() -> None:

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -25,10 +26,18 @@ namespace {
 thread_local std::string g_last_error;
 
 std::mutex g_cfg_mu;
-vqhull_config g_cfg = {512, 8, 2048, 0};
+vqhull_config g_cfg = {512, 8, 2048, 0, 1};
 
 struct LevelStat {
   int64_t segs, swept, jobs, jobpts;
+};
+
+std::atomic<int> g_timing{0};
+
+struct TimedLaunch {
+  int kind, level;
+  int64_t in, out;
+  int ev0, ev1;
 };
 
 template <typename T>
@@ -53,14 +62,20 @@ struct Workspace {
   DevBuf<Job> jobs;
   DevBuf<Node> nodes;
   DevBuf<uint32_t> level_begin;
-  Status* status_dev = nullptr;
-  Status* status_host = nullptr;
+  Status* status_dev = nullptr;   // kStatusRing records
+  Status* status_host = nullptr;  // pinned copies
+  hipEvent_t status_ev[kStatusRing] = {};
   // pinned staging
   Req* h_req = nullptr;
   size_t h_req_cap = 0;
   uint32_t* h_u32 = nullptr;
   size_t h_u32_cap = 0;
   std::vector<LevelStat> stats;
+  // kernel timing
+  std::vector<hipEvent_t> events;
+  int next_event = 0;
+  std::vector<TimedLaunch> launches;
+  std::vector<vqhull_kernel_time> times;
 };
 
 std::mutex g_ws_mu;
@@ -140,8 +155,10 @@ Workspace& workspace_for_current_device() {
   if (it != g_ws.end()) return *it->second;
   Workspace* w = new Workspace();
   w->device = dev;
-  ck(hipMalloc(&w->status_dev, sizeof(Status)), "hipMalloc");
-  ck(hipHostMalloc((void**)&w->status_host, sizeof(Status), hipHostMallocDefault), "hipHostMalloc");
+  ck(hipMalloc(&w->status_dev, kStatusRing * sizeof(Status)), "hipMalloc");
+  ck(hipHostMalloc((void**)&w->status_host, kStatusRing * sizeof(Status), hipHostMallocDefault), "hipHostMalloc");
+  for (int i = 0; i < kStatusRing; ++i)
+    ck(hipEventCreateWithFlags(&w->status_ev[i], hipEventDisableTiming), "hipEventCreateWithFlags");
   g_ws[dev] = w;
   return *w;
 }
@@ -169,6 +186,9 @@ void free_workspace(Workspace* w) {
   if (w->status_host) (void)hipHostFree(w->status_host);
   if (w->h_req) (void)hipHostFree(w->h_req);
   if (w->h_u32) (void)hipHostFree(w->h_u32);
+  for (hipEvent_t e : w->events) (void)hipEventDestroy(e);
+  for (hipEvent_t e : w->status_ev)
+    if (e) (void)hipEventDestroy(e);
   delete w;
 }
 
@@ -179,16 +199,211 @@ vqhull_config sanitized(vqhull_config c) {
   }
   c.lds_limit = std::min(2048, std::max(256, c.lds_limit));
   c.reverse_tiles = c.reverse_tiles ? 1 : 0;
+  c.sweep_persistent = c.sweep_persistent ? 1 : 0;
   return c;
 }
 
-Status read_status(Workspace& w, hipStream_t st) {
-  ck(hipMemcpyAsync(w.status_host, w.status_dev, sizeof(Status), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
-  ck(hipStreamSynchronize(st), "hipStreamSynchronize");
-  return *w.status_host;
+int take_event(Workspace& w) {
+  if (w.next_event == (int)w.events.size()) {
+    hipEvent_t e;
+    ck(hipEventCreate(&e), "hipEventCreate");
+    w.events.push_back(e);
+  }
+  return w.next_event++;
+}
+
+// Launch through f(); with timing enabled, bracket it with events on st.
+template <typename F>
+size_t timed(Workspace& w, bool on, hipStream_t st, int kind, int level, int64_t in, int64_t out, F&& f) {
+  if (!on) {
+    f();
+    return (size_t)-1;
+  }
+  TimedLaunch t{kind, level, in, out, take_event(w), 0};
+  ck(hipEventRecord(w.events[t.ev0], st), "hipEventRecord");
+  f();
+  t.ev1 = take_event(w);
+  ck(hipEventRecord(w.events[t.ev1], st), "hipEventRecord");
+  w.launches.push_back(t);
+  return w.launches.size() - 1;
+}
+
+void collect_times(Workspace& w) {
+  w.times.clear();
+  for (const TimedLaunch& t : w.launches) {
+    float ms = 0.f;
+    ck(hipEventElapsedTime(&ms, w.events[t.ev0], w.events[t.ev1]), "hipEventElapsedTime");
+    w.times.push_back(vqhull_kernel_time{t.kind, t.level, (double)ms, t.in, t.out});
+  }
 }
 
 // The whole hull computation for nreq requests on one stream.
+//
+// Level k's kernels read their work counts from the device status record the
+// previous plan wrote, so the host enqueues level k before it knows them and
+// waits only for the status of level k-1: the GPU never waits for the host
+// between levels.  When a status shows an empty level, the loop stops (the
+// kernels already enqueued for it find no work).
+bool run_once(Workspace& w, const vqhull_config& cfg, const double* x, const double* y, int64_t nreq,
+              int64_t* out_idx, int64_t* out_counts, hipStream_t st, size_t N, const uint32_t* tile_req,
+              size_t ext_tiles, uint64_t tiles0, size_t max_tiles) {
+  const uint32_t tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
+  const uint32_t lds_limit = (uint32_t)cfg.lds_limit;
+  const int tmax = finish_tmax_for(cfg.lds_limit);
+  const uint32_t G_persistent = sweep_grid(cfg.sweep_block, cfg.sweep_ppt);
+  const size_t max_seg = N / (lds_limit + 1) + (size_t)nreq + 2;
+  const bool tm = g_timing.load() != 0;
+
+  ExtremesArgs ea{x, y, tile_req, w.req.p, w.epart.p, (uint32_t)ext_tiles};
+  timed(w, tm, st, VQHULL_K_EXTREMES, 0, (int64_t)N, 0, [&] { ck(launch_extremes(ea, st), "k_extremes"); });
+  Plan0Args pa{};
+  pa.req = w.req.p;
+  pa.nreq = (uint32_t)nreq;
+  pa.epart = w.epart.p;
+  pa.seg_out = w.seg[0].p;
+  pa.ctr_out = w.ctr[0].p;
+  pa.tile_seg_out = w.tile_seg[0].p;
+  pa.jobs = w.jobs.p;
+  pa.nodes = w.nodes.p;
+  pa.node_cap = (uint32_t)std::min<size_t>(w.nodes.cap, 0xFFFFFFFFu);
+  pa.st_out = w.status_dev + 0;
+  pa.tile = tile;
+  pa.lds_limit = lds_limit;
+  pa.ext_tile = kExtTile;
+  timed(w, tm, st, VQHULL_K_PLAN0, 0, nreq, 0, [&] { ck(launch_plan0(pa, st), "k_plan0"); });
+  ck(hipMemcpyAsync(w.status_host + 0, w.status_dev + 0, sizeof(Status), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+  ck(hipEventRecord(w.status_ev[0], st), "hipEventRecord");
+
+  FinishArgs fa{};
+  fa.jobs = w.jobs.p;
+  fa.ux = x;
+  fa.uy = y;
+  for (int k = 0; k < 2; ++k) {
+    fa.bx[k] = w.wx[k];
+    fa.by[k] = w.wy[k];
+    fa.bi[k] = w.wi[k];
+  }
+  fa.req = w.req.p;
+
+  std::vector<Status> known;           // host copies of status[0..]
+  std::vector<size_t> sweep_recs;      // timing records of the sweeps, per level
+  std::vector<size_t> finish_recs;     // timing records of the finisher launches, per level
+  bool overflow = false;
+  int64_t known_nodes = (int64_t)nreq, known_seg = (int64_t)std::min<size_t>((size_t)nreq, max_seg);
+  for (int k = 0;; ++k) {
+    const int slot = k % kStatusRing, next = (k + 1) % kStatusRing;
+    fa.st = w.status_dev + slot;
+    fa.nodes = w.nodes.p;
+    finish_recs.push_back(
+        timed(w, tm, st, VQHULL_K_FINISH, k, 0, 0, [&] { ck(launch_finish(fa, tmax, st), "k_finish"); }));
+
+    SweepArgs sa{};
+    const int in_buf = k == 0 ? -1 : (k - 1) % 2, out_buf = k % 2, cur = k % 2;
+    sa.ix = in_buf < 0 ? x : w.wx[in_buf];
+    sa.iy = in_buf < 0 ? y : w.wy[in_buf];
+    sa.ii = in_buf < 0 ? nullptr : w.wi[in_buf];
+    sa.ox = w.wx[out_buf];
+    sa.oy = w.wy[out_buf];
+    sa.oi = w.wi[out_buf];
+    sa.seg = w.seg[cur].p;
+    sa.tile_seg = w.tile_seg[cur].p;
+    sa.ctr = w.ctr[cur].p;
+    sa.part = w.part.p;
+    sa.req = w.req.p;
+    sa.st = w.status_dev + slot;
+    sa.reverse = (uint32_t)cfg.reverse_tiles;
+    // Grid: persistent, or one workgroup per tile with the tile count bounded
+    // from what the host knows (level 0 exactly; level k from level k-1:
+    // tiles <= ceil(swept(k-1) / tile) + 2 nseg(k-1)); surplus groups exit.
+    uint32_t G = G_persistent;
+    if (!cfg.sweep_persistent) {
+      uint64_t bound = k == 0 ? tiles0
+                              : (known[k - 1].swept + (uint64_t)tile - 1) / tile + 2ull * known[k - 1].nseg + 1;
+      G = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(bound, max_tiles));
+    }
+    sweep_recs.push_back(timed(w, tm, st, VQHULL_K_SWEEP, k, 0, 0, [&] {
+      ck(launch_sweep(sa, in_buf < 0, cfg.sweep_block, cfg.sweep_ppt, G, st), "k_sweep");
+    }));
+
+    // Node capacity for this plan: nodes after it <= nodes(k) + 2 nseg(k), with
+    // nodes(k) <= nodes(k-1) + 2 nseg(k-1) and nseg(k) <= min(2 nseg(k-1), max_seg).
+    const int64_t need = known_nodes + 2 * known_seg + 2 * std::min<int64_t>(2 * known_seg, (int64_t)max_seg) + 16;
+    ensure(w.nodes, (size_t)need, st, true);
+    fa.nodes = w.nodes.p;
+    PlanArgs pl{};
+    pl.seg = w.seg[cur].p;
+    pl.ctr = w.ctr[cur].p;
+    pl.part = w.part.p;
+    pl.st_in = w.status_dev + slot;
+    pl.sweep_grid = G;
+    pl.seg_out = w.seg[cur ^ 1].p;
+    pl.ctr_out = w.ctr[cur ^ 1].p;
+    pl.tile_seg_out = w.tile_seg[cur ^ 1].p;
+    pl.jobs = w.jobs.p;
+    pl.nodes = w.nodes.p;
+    pl.node_cap = (uint32_t)std::min<size_t>(w.nodes.cap, 0xFFFFFFFFu);
+    pl.out_buf = (uint32_t)out_buf;
+    pl.st_out = w.status_dev + next;
+    pl.tile = tile;
+    pl.lds_limit = lds_limit;
+    timed(w, tm, st, VQHULL_K_PLAN, k, 0, 0, [&] { ck(launch_plan(pl, st), "k_plan"); });
+    ck(hipMemcpyAsync(w.status_host + next, w.status_dev + next, sizeof(Status), hipMemcpyDeviceToHost, st),
+       "hipMemcpyAsync");
+    ck(hipEventRecord(w.status_ev[next], st), "hipEventRecord");
+
+    // Wait for the status of level k (written by the previous plan).
+    ck(hipEventSynchronize(w.status_ev[slot]), "hipEventSynchronize");
+    const Status sk = w.status_host[slot];
+    known.push_back(sk);
+    w.stats.push_back({(int64_t)sk.nseg, (int64_t)sk.swept, (int64_t)sk.njobs, (int64_t)sk.jobpts});
+    if (k >= 1 && sweep_recs[k - 1] != (size_t)-1) w.launches[sweep_recs[k - 1]].out = sk.survivors;
+    if (sweep_recs[k] != (size_t)-1) w.launches[sweep_recs[k]].in = sk.swept;
+    if (finish_recs[k] != (size_t)-1) w.launches[finish_recs[k]].in = sk.jobpts;
+    if (sk.overflow) {
+      overflow = true;
+      break;
+    }
+    known_nodes = sk.nnodes;
+    known_seg = sk.nseg;
+    if (sk.nseg == 0) {
+      // Level k had no segment: plan(k) wrote an empty status (its jobs = 0).
+      // The node count after level k is final.
+      break;
+    }
+  }
+  if (overflow) {
+    ck(hipStreamSynchronize(st), "hipStreamSynchronize");
+    return false;
+  }
+
+  // assembly: node level boundaries are the node counts after each plan
+  const size_t nlevels = known.size();
+  ensure(w.level_begin, nlevels + 1, st);
+  ensure_host_u32(w, nlevels + 1);
+  w.h_u32[0] = 0;
+  for (size_t i = 0; i < nlevels; ++i) w.h_u32[i + 1] = known[i].nnodes;
+  ck(hipMemcpyAsync(w.level_begin.p, w.h_u32, (nlevels + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, st),
+     "hipMemcpyAsync");
+  AssembleArgs aa{};
+  aa.nodes = w.nodes.p;
+  aa.level_begin = w.level_begin.p;
+  aa.nlevels = (uint32_t)nlevels;
+  aa.req = w.req.p;
+  aa.nreq = (uint32_t)nreq;
+  aa.lists[0] = w.wi[0];
+  aa.lists[1] = w.wi[1];
+  aa.out_idx = out_idx;
+  aa.out_count = out_counts;
+  aa.nnodes = known.back().nnodes;
+  timed(w, tm, st, VQHULL_K_ASSEMBLE, (int)nlevels, aa.nnodes, 0, [&] {
+    ck(launch_assemble(aa, st), "k_assemble");
+    ck(launch_copy_lists(aa, st), "k_copy_lists");
+  });
+  // The staging buffers are reused by the next call: wait for the copies.
+  ck(hipStreamSynchronize(st), "hipStreamSynchronize");
+  return true;
+}
+
 void run(const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
          int64_t* out_counts, hipStream_t st) {
   vqhull_config cfg;
@@ -198,16 +413,15 @@ void run(const double* x, const double* y, const int64_t* offsets, int64_t nreq,
   }
   const uint32_t tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
   const uint32_t lds_limit = (uint32_t)cfg.lds_limit;
-  const int tmax = finish_tmax_for(cfg.lds_limit);
   const size_t N = (size_t)offsets[nreq];
 
   std::lock_guard<std::mutex> guard(g_ws_mu);
   Workspace& w = workspace_for_current_device();
-  w.stats.clear();
 
   // request table and extremes tile map
   ensure_host_req(w, (size_t)nreq);
   size_t ext_tiles = 0;
+  uint64_t tiles0 = 0;  // level-0 sweep tiles (requests too big for the LDS finisher)
   for (int64_t i = 0; i < nreq; ++i) {
     Req r{};
     r.off = (uint32_t)offsets[i];
@@ -215,10 +429,10 @@ void run(const double* x, const double* y, const int64_t* offsets, int64_t nreq,
     r.root = -1;
     r.tile0 = (uint32_t)ext_tiles;
     ext_tiles += (r.n + kExtTile - 1) / kExtTile;
+    if (r.n > lds_limit) tiles0 += (r.n + tile - 1) / tile;
     w.h_req[i] = r;
   }
   ensure(w.req, (size_t)std::max<int64_t>(nreq, 1), st);
-  ck(hipMemcpyAsync(w.req.p, w.h_req, (size_t)nreq * sizeof(Req), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
   ensure(w.epart, std::max<size_t>(ext_tiles, 1), st);
   const uint32_t* tile_req = nullptr;
   if (nreq > 1 && ext_tiles > 0) {
@@ -245,114 +459,20 @@ void run(const double* x, const double* y, const int64_t* offsets, int64_t nreq,
   }
   ensure(w.part, max_tiles, st);
   ensure(w.jobs, 2 * max_seg + (size_t)nreq, st);
-  ensure(w.nodes, std::max<size_t>((size_t)nreq + 1, 1024), st);
+  ensure(w.nodes, std::max<size_t>(3 * (size_t)nreq + 64, 4096), st);
 
-  // extremes and root plan
-  ExtremesArgs ea{x, y, tile_req, w.req.p, w.epart.p, (uint32_t)ext_tiles};
-  ck(launch_extremes(ea, st), "k_extremes");
-  Plan0Args pa{};
-  pa.req = w.req.p;
-  pa.nreq = (uint32_t)nreq;
-  pa.epart = w.epart.p;
-  pa.seg_out = w.seg[0].p;
-  pa.ctr_out = w.ctr[0].p;
-  pa.tile_seg_out = w.tile_seg[0].p;
-  pa.jobs = w.jobs.p;
-  pa.nodes = w.nodes.p;
-  pa.status = w.status_dev;
-  pa.tile = tile;
-  pa.lds_limit = lds_limit;
-  pa.ext_tile = kExtTile;
-  ck(launch_plan0(pa, st), "k_plan0");
-  Status s = read_status(w, st);
-  w.stats.push_back({(int64_t)s.nseg, (int64_t)s.swept, (int64_t)s.njobs, (int64_t)s.jobpts});
-
-  std::vector<uint32_t> level_begin = {0u, s.nnodes};
-  FinishArgs fa{};
-  fa.jobs = w.jobs.p;
-  fa.ux = x;
-  fa.uy = y;
-  for (int k = 0; k < 2; ++k) {
-    fa.bx[k] = w.wx[k];
-    fa.by[k] = w.wy[k];
-    fa.bi[k] = w.wi[k];
+  for (int attempt = 0;; ++attempt) {
+    ck(hipMemcpyAsync(w.req.p, w.h_req, (size_t)nreq * sizeof(Req), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    w.stats.clear();
+    w.launches.clear();
+    w.next_event = 0;
+    if (run_once(w, cfg, x, y, nreq, out_idx, out_counts, st, N, tile_req, ext_tiles, tiles0, max_tiles)) break;
+    // The node table was too small for a level (not expected with the host's
+    // bound): grow it and start over.
+    ensure(w.nodes, 2 * w.nodes.cap, st);
+    if (attempt > 8) ck(hipErrorOutOfMemory, "node table");
   }
-  fa.nodes = w.nodes.p;
-  fa.req = w.req.p;
-  ck(launch_finish(fa, s.njobs, tmax, st), "k_finish");
-
-  uint32_t nseg = s.nseg, ntiles = s.ntiles, nnodes = s.nnodes;
-  int cur = 0;      // segment table / tile map / counter parity of the current level
-  int in_buf = -1;  // -1: caller arrays (level 0)
-  int out_buf = 0;
-  while (nseg > 0) {
-    SweepArgs sa{};
-    sa.ix = in_buf < 0 ? x : w.wx[in_buf];
-    sa.iy = in_buf < 0 ? y : w.wy[in_buf];
-    sa.ii = in_buf < 0 ? nullptr : w.wi[in_buf];
-    sa.ox = w.wx[out_buf];
-    sa.oy = w.wy[out_buf];
-    sa.oi = w.wi[out_buf];
-    sa.seg = w.seg[cur].p;
-    sa.tile_seg = w.tile_seg[cur].p;
-    sa.ctr = w.ctr[cur].p;
-    sa.part = w.part.p;
-    sa.req = w.req.p;
-    sa.ntiles = ntiles;
-    sa.reverse = (uint32_t)cfg.reverse_tiles;
-    ck(launch_sweep(sa, in_buf < 0, cfg.sweep_block, cfg.sweep_ppt, st), "k_sweep");
-
-    ensure(w.nodes, (size_t)nnodes + 2 * (size_t)nseg, st, true);
-    fa.nodes = w.nodes.p;
-    PlanArgs pl{};
-    pl.seg = w.seg[cur].p;
-    pl.nseg = nseg;
-    pl.ctr = w.ctr[cur].p;
-    pl.part = w.part.p;
-    pl.seg_out = w.seg[cur ^ 1].p;
-    pl.ctr_out = w.ctr[cur ^ 1].p;
-    pl.tile_seg_out = w.tile_seg[cur ^ 1].p;
-    pl.jobs = w.jobs.p;
-    pl.nodes = w.nodes.p;
-    pl.node_base = nnodes;
-    pl.out_buf = (uint32_t)out_buf;
-    pl.status = w.status_dev;
-    pl.tile = tile;
-    pl.lds_limit = lds_limit;
-    ck(launch_plan(pl, st), "k_plan");
-    s = read_status(w, st);
-    w.stats.push_back({(int64_t)s.nseg, (int64_t)s.swept, (int64_t)s.njobs, (int64_t)s.jobpts});
-    ck(launch_finish(fa, s.njobs, tmax, st), "k_finish");
-    nseg = s.nseg;
-    ntiles = s.ntiles;
-    nnodes = s.nnodes;
-    level_begin.push_back(nnodes);
-    cur ^= 1;
-    in_buf = out_buf;
-    out_buf ^= 1;
-  }
-
-  // assembly
-  ensure(w.level_begin, level_begin.size(), st);
-  ensure_host_u32(w, level_begin.size());
-  std::memcpy(w.h_u32, level_begin.data(), level_begin.size() * sizeof(uint32_t));
-  ck(hipMemcpyAsync(w.level_begin.p, w.h_u32, level_begin.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st),
-     "hipMemcpyAsync");
-  AssembleArgs aa{};
-  aa.nodes = w.nodes.p;
-  aa.level_begin = w.level_begin.p;
-  aa.nlevels = (uint32_t)(level_begin.size() - 1);
-  aa.req = w.req.p;
-  aa.nreq = (uint32_t)nreq;
-  aa.lists[0] = w.wi[0];
-  aa.lists[1] = w.wi[1];
-  aa.out_idx = out_idx;
-  aa.out_count = out_counts;
-  aa.nnodes = nnodes;
-  ck(launch_assemble(aa, st), "k_assemble");
-  ck(launch_copy_lists(aa, st), "k_copy_lists");
-  // The staging buffers are reused by the next call: wait for the copies.
-  ck(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (g_timing.load()) collect_times(w);
 }
 
 int guarded(const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
@@ -420,6 +540,32 @@ int64_t vqhull_last_level_stats(int64_t* out, int64_t cap) {
     out[4 * i + 3] = st[i].jobpts;
   }
   return (int64_t)st.size();
+}
+
+int vqhull_stream_scale(const double* in, double* out, int64_t n, double s, vqhull_stream_t stream) {
+  if (n < 0 || (n > 0 && (!in || !out))) return VQHULL_ERR_INVALID_ARGUMENT;
+  const int e = launch_stream_scale(in, out, (uint64_t)n, s, stream);
+  if (e != 0) {
+    g_last_error = std::string("k_stream_scale: ") + hipGetErrorString((hipError_t)e);
+    return VQHULL_ERR_HIP;
+  }
+  return VQHULL_OK;
+}
+
+int vqhull_set_timing(int enable) {
+  g_timing.store(enable ? 1 : 0);
+  return VQHULL_OK;
+}
+
+int64_t vqhull_last_kernel_times(vqhull_kernel_time* out, int64_t cap) {
+  std::lock_guard<std::mutex> guard(g_ws_mu);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  auto it = g_ws.find(dev);
+  if (it == g_ws.end()) return 0;
+  const auto& t = it->second->times;
+  for (int64_t i = 0; i < (int64_t)t.size() && i < cap && out; ++i) out[i] = t[i];
+  return (int64_t)t.size();
 }
 
 int vqhull_release_workspace(void) {

@@ -82,16 +82,21 @@ struct Node {
   uint32_t lbuf;    // which workspace idx array holds that list (0 = A, 1 = B)
 };
 
-// Counters a planning kernel writes for the host.
+// What a planning kernel produces for the level it creates.  The kernels of
+// that level read their work counts from it on the device, so the host can
+// enqueue a level before it knows them; the host reads it back one level later.
 struct Status {
-  uint32_t nseg;        // segments of the next level
-  uint32_t ntiles;      // tiles of the next level
-  uint32_t njobs;       // finisher jobs created by this plan
-  uint32_t nnodes;      // node count after this plan
-  uint32_t swept;       // points in the segments of the next level
+  uint32_t nseg;        // segments of the level
+  uint32_t ntiles;      // sweep tiles of the level
+  uint32_t njobs;       // finisher jobs created by the plan
+  uint32_t nnodes;      // node count after the plan
+  uint32_t swept;       // points in the level's segments
   uint32_t jobpts;      // points in the jobs created
-  uint32_t pad[2];
+  uint32_t survivors;   // points the previous sweep kept (|S1| + |S2| summed over its segments)
+  uint32_t overflow;    // 1 if the node table was too small (nothing was created)
 };
+
+constexpr int kStatusRing = 4;
 
 // ----------------------------------------------------------------- launchers
 struct Workspace;  // host side
@@ -115,9 +120,9 @@ struct SweepArgs {
   const Seg* seg;
   const uint32_t* tile_seg;
   unsigned long long* ctr;
-  TilePart* part;
+  TilePart* part;  // one record per (workgroup, segment) run, at slot tile0 + (tile - tile0) % gridDim
   Req* req;
-  uint32_t ntiles;
+  const Status* st;  // ntiles of this level
   uint32_t reverse;
 };
 
@@ -130,7 +135,8 @@ struct Plan0Args {
   uint32_t* tile_seg_out;
   Job* jobs;
   Node* nodes;
-  Status* status;
+  uint32_t node_cap;
+  Status* st_out;
   uint32_t tile;
   uint32_t lds_limit;
   uint32_t ext_tile;
@@ -138,22 +144,24 @@ struct Plan0Args {
 
 struct PlanArgs {
   const Seg* seg;
-  uint32_t nseg;
   const unsigned long long* ctr;
   const TilePart* part;
+  const Status* st_in;  // the level being planned (nseg, nnodes)
+  uint32_t sweep_grid;  // workgroups of the sweep that produced `part`
   Seg* seg_out;
   unsigned long long* ctr_out;
   uint32_t* tile_seg_out;
   Job* jobs;
   Node* nodes;
-  uint32_t node_base;
+  uint32_t node_cap;
   uint32_t out_buf;  // buffer the children were written to (0 = A, 1 = B)
-  Status* status;
+  Status* st_out;
   uint32_t tile;
   uint32_t lds_limit;
 };
 
 struct FinishArgs {
+  const Status* st;  // njobs
   const Job* jobs;
   const double* ux;  // caller arrays (root jobs)
   const double* uy;
@@ -182,12 +190,15 @@ int finish_tmax_for(int lds_limit);
 
 // Launchers (return hipError_t as int).
 int launch_extremes(const ExtremesArgs& a, void* stream);
-int launch_sweep(const SweepArgs& a, bool level0, int block, int ppt, void* stream);
+int launch_sweep(const SweepArgs& a, bool level0, int block, int ppt, uint32_t grid, void* stream);
+uint32_t sweep_grid(int block, int ppt);   // persistent grid size for a sweep shape
+uint32_t finish_grid(int tmax);            // persistent grid size of the finisher
 int launch_plan0(const Plan0Args& a, void* stream);
 int launch_plan(const PlanArgs& a, void* stream);
-int launch_finish(const FinishArgs& a, uint32_t njobs, int tmax, void* stream);
+int launch_finish(const FinishArgs& a, int tmax, void* stream);
 int launch_assemble(const AssembleArgs& a, void* stream);
 int launch_copy_lists(const AssembleArgs& a, void* stream);
+int launch_stream_scale(const double* in, double* out, uint64_t n, double s, void* stream);
 
 constexpr int kExtBlock = 256;
 constexpr int kExtPPT = 32;

@@ -17,6 +17,8 @@
 // -ffp-contract=off and the pragma below; no fused multiply-add may appear.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "vqhull_internal.h"
 
 #pragma clang fp contract(off)
@@ -189,14 +191,41 @@ __global__ __launch_bounds__(BLOCK) void k_extremes(ExtremesArgs A) {
 
 // ---------------------------------------------------------------- k_sweep
 //
-// One workgroup per tile of BLOCK*PPT consecutive points of one segment.
-// Each thread loads PPT points (striped so that every wave load instruction
-// covers consecutive addresses), classifies them against the segment's
-// triangle (a, r, b), and tracks the farthest point of each side.  Wave
-// ballots give per-wave subset sizes, one packed 64-bit atomic per tile
-// reserves room at the left end (S1) and right end (S2) of the segment's
-// output range, and every wave then writes its survivors as contiguous runs.
-// The order of points inside a subset is irrelevant to the result.
+// Persistent: gridDim.x workgroups walk the level's tiles (BLOCK*PPT
+// consecutive points of one segment each) with stride gridDim.x; the tile
+// count comes from the level's status record.  Per tile, each thread loads PPT
+// points (striped so that every wave load covers consecutive addresses, with
+// non-temporal hints: the data is streamed once), classifies them against the
+// segment's triangle (a, r, b), and keeps the farthest point of each side.
+// Wave ballots give per-wave subset sizes; one packed 64-bit atomic per tile
+// reserves room at the left end (S1) and at the right end (S2) of the
+// segment's output range; every wave then writes its survivors as contiguous
+// runs.  The order of points inside a subset is irrelevant to the result.
+// Farthest-point candidates are kept per thread across the consecutive tiles
+// a workgroup visits in one segment and written once per such run.
+
+template <int NW>
+__device__ __forceinline__ void flush_run(TilePart* part, uint32_t slot, Cand b1, Cand b2, Cand (*s_cand)[NW]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  wave_best(b1);
+  wave_best(b2);
+  if (lane == 0) {
+    s_cand[0][w] = b1;
+    s_cand[1][w] = b2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    Cand r1 = s_cand[0][0], r2 = s_cand[1][0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) {
+      if (better(s_cand[0][i], r1)) r1 = s_cand[0][i];
+      if (better(s_cand[1][i], r2)) r2 = s_cand[1][i];
+    }
+    part[slot].c[0] = r1;
+    part[slot].c[1] = r2;
+  }
+  __syncthreads();
+}
 
 template <int BLOCK, int PPT, bool L0>
 __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
@@ -207,116 +236,132 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
   __shared__ uint32_t s_base[2];
   __shared__ Cand s_cand[2][NW];
 
-  const uint32_t t = A.reverse ? (A.ntiles - 1u - blockIdx.x) : blockIdx.x;
-  const uint32_t s = A.tile_seg[t];
-  const Seg* sg = A.seg + s;
-  const double ax = sg->ax, ay = sg->ay, rx = sg->rx, ry = sg->ry, bx = sg->bx, by = sg->by;
-  const uint32_t beg = sg->beg, cnt = sg->cnt;
-  const uint32_t lo = beg + (t - sg->tile0) * TILE;
-  const uint32_t hi = min(beg + cnt, lo + TILE);
-  const uint32_t ibase = sg->ibase;
+  const uint32_t ntiles = A.st->ntiles;
+  const uint32_t G = gridDim.x;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 
-  double px[PPT], py[PPT];
-  uint32_t pi[PPT];
-#pragma unroll
-  for (int v = 0; v < PPT; ++v) {
-    const uint32_t pos = lo + v * BLOCK + tid;
-    const bool ok = pos < hi;
-    px[v] = ok ? A.ix[pos] : 0.0;
-    py[v] = ok ? A.iy[pos] : 0.0;
-    if constexpr (L0) {
-      pi[v] = pos - ibase;
-    } else {
-      pi[v] = ok ? A.ii[pos] : 0u;
-    }
-  }
-
-  uint32_t m1 = 0, m2 = 0;
-  bool bad = false;
+  uint32_t run_seg = kNone, run_slot = 0;
+  double ax = 0, ay = 0, rx = 0, ry = 0, bx = 0, by = 0;
+  uint32_t beg = 0, cnt = 0, tile0 = 0, ibase = 0, req = 0;
   Cand b1 = no_cand(), b2 = no_cand();
-#pragma unroll
-  for (int v = 0; v < PPT; ++v) {
-    const uint32_t pos = lo + v * BLOCK + tid;
-    const bool ok = pos < hi;
-    const double o1 = orient(ax, ay, rx, ry, px[v], py[v]);
-    const double o2 = orient(rx, ry, bx, by, px[v], py[v]);
-    const bool in1 = ok && (o1 > 0.0);
-    const bool in2 = ok && !in1 && (o2 > 0.0);
-    m1 |= (uint32_t)in1 << v;
-    m2 |= (uint32_t)in2 << v;
-    if (in1 && better(o1, px[v], py[v], pi[v], b1)) {
-      b1.k = o1;
-      b1.x = px[v];
-      b1.y = py[v];
-      b1.i = pi[v];
-    }
-    if (in2 && better(o2, px[v], py[v], pi[v], b2)) {
-      b2.k = o2;
-      b2.x = px[v];
-      b2.y = py[v];
-      b2.i = pi[v];
-    }
-    if constexpr (L0) bad |= ok && !finite(py[v]);
-  }
+  bool bad = false;
 
-  uint32_t c1 = 0, c2 = 0;
-#pragma unroll
-  for (int v = 0; v < PPT; ++v) {
-    c1 += __popcll(__ballot((m1 >> v) & 1u));
-    c2 += __popcll(__ballot((m2 >> v) & 1u));
-  }
-  wave_best(b1);
-  wave_best(b2);
-  if (lane == 0) {
-    s_cnt[0][w] = c1;
-    s_cnt[1][w] = c2;
-    s_cand[0][w] = b1;
-    s_cand[1][w] = b2;
-  }
-  if constexpr (L0) {
-    if (__ballot(bad) && lane == 0) A.req[sg->req].err = 1u;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t t1 = 0, t2 = 0;
-#pragma unroll
-    for (int i = 0; i < NW; ++i) {
-      const uint32_t a = s_cnt[0][i], b = s_cnt[1][i];
-      s_cnt[0][i] = t1;
-      s_cnt[1][i] = t2;
-      t1 += a;
-      t2 += b;
+  for (uint32_t k = blockIdx.x; k < ntiles; k += G) {
+    const uint32_t t = A.reverse ? ntiles - 1u - k : k;
+    const uint32_t s = A.tile_seg[t];
+    if (s != run_seg) {
+      if (run_seg != kNone) flush_run<NW>(A.part, run_slot, b1, b2, s_cand);
+      const Seg* sg = A.seg + s;
+      ax = sg->ax;
+      ay = sg->ay;
+      rx = sg->rx;
+      ry = sg->ry;
+      bx = sg->bx;
+      by = sg->by;
+      beg = sg->beg;
+      cnt = sg->cnt;
+      tile0 = sg->tile0;
+      ibase = sg->ibase;
+      req = sg->req;
+      run_seg = s;
+      run_slot = tile0 + (t - tile0) % G;
+      b1 = no_cand();
+      b2 = no_cand();
     }
-    unsigned long long old = 0ull;
-    if (t1 | t2) old = atomicAdd(A.ctr + s, ((unsigned long long)t2 << 32) | (unsigned long long)t1);
-    s_base[0] = beg + (uint32_t)old;
-    s_base[1] = beg + cnt - (uint32_t)(old >> 32) - t2;
-    Cand r1 = s_cand[0][0], r2 = s_cand[1][0];
+    const uint32_t lo = beg + (t - tile0) * TILE;
+    const uint32_t hi = min(beg + cnt, lo + TILE);
+
+    double px[PPT], py[PPT];
+    uint32_t pi[PPT];
 #pragma unroll
-    for (int i = 1; i < NW; ++i) {
-      if (better(s_cand[0][i], r1)) r1 = s_cand[0][i];
-      if (better(s_cand[1][i], r2)) r2 = s_cand[1][i];
+    for (int v = 0; v < PPT; ++v) {
+      const uint32_t pos = lo + v * BLOCK + tid;
+      const bool ok = pos < hi;
+      px[v] = ok ? __builtin_nontemporal_load(A.ix + pos) : 0.0;
+      py[v] = ok ? __builtin_nontemporal_load(A.iy + pos) : 0.0;
+      if constexpr (L0) {
+        pi[v] = pos - ibase;
+      } else {
+        pi[v] = ok ? __builtin_nontemporal_load(A.ii + pos) : 0u;
+      }
     }
-    A.part[t].c[0] = r1;
-    A.part[t].c[1] = r2;
-  }
-  __syncthreads();
-  uint32_t o1p = s_base[0] + s_cnt[0][w];
-  uint32_t o2p = s_base[1] + s_cnt[1][w];
+
+    uint32_t m1 = 0, m2 = 0;
 #pragma unroll
-  for (int v = 0; v < PPT; ++v) {
-    const bool in1 = (m1 >> v) & 1u, in2 = (m2 >> v) & 1u;
-    const unsigned long long q1 = __ballot(in1), q2 = __ballot(in2);
-    if (in1 | in2) {
-      const uint32_t dst = in1 ? o1p + lane_rank(q1) : o2p + lane_rank(q2);
-      A.ox[dst] = px[v];
-      A.oy[dst] = py[v];
-      A.oi[dst] = pi[v];
+    for (int v = 0; v < PPT; ++v) {
+      const uint32_t pos = lo + v * BLOCK + tid;
+      const bool ok = pos < hi;
+      const double o1 = orient(ax, ay, rx, ry, px[v], py[v]);
+      const double o2 = orient(rx, ry, bx, by, px[v], py[v]);
+      const bool in1 = ok && (o1 > 0.0);
+      const bool in2 = ok && !in1 && (o2 > 0.0);
+      m1 |= (uint32_t)in1 << v;
+      m2 |= (uint32_t)in2 << v;
+      if (in1 && better(o1, px[v], py[v], pi[v], b1)) {
+        b1.k = o1;
+        b1.x = px[v];
+        b1.y = py[v];
+        b1.i = pi[v];
+      }
+      if (in2 && better(o2, px[v], py[v], pi[v], b2)) {
+        b2.k = o2;
+        b2.x = px[v];
+        b2.y = py[v];
+        b2.i = pi[v];
+      }
+      if constexpr (L0) bad |= ok && !finite(py[v]);
     }
-    o1p += (uint32_t)__popcll(q1);
-    o2p += (uint32_t)__popcll(q2);
+
+    uint32_t c1 = 0, c2 = 0;
+#pragma unroll
+    for (int v = 0; v < PPT; ++v) {
+      c1 += __popcll(__ballot((m1 >> v) & 1u));
+      c2 += __popcll(__ballot((m2 >> v) & 1u));
+    }
+    if (lane == 0) {
+      s_cnt[0][w] = c1;
+      s_cnt[1][w] = c2;
+    }
+    if constexpr (L0) {
+      if (__ballot(bad) && lane == 0) A.req[req].err = 1u;
+      bad = false;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t t1 = 0, t2 = 0;
+#pragma unroll
+      for (int i = 0; i < NW; ++i) {
+        const uint32_t a = s_cnt[0][i], b = s_cnt[1][i];
+        s_cnt[0][i] = t1;
+        s_cnt[1][i] = t2;
+        t1 += a;
+        t2 += b;
+      }
+      unsigned long long old = 0ull;
+      if (t1 | t2) old = atomicAdd(A.ctr + s, ((unsigned long long)t2 << 32) | (unsigned long long)t1);
+      s_base[0] = beg + (uint32_t)old;
+      s_base[1] = beg + cnt - (uint32_t)(old >> 32) - t2;
+    }
+    __syncthreads();
+    uint32_t o1p = s_base[0] + s_cnt[0][w];
+    uint32_t o2p = s_base[1] + s_cnt[1][w];
+#pragma unroll
+    for (int v = 0; v < PPT; ++v) {
+      const bool in1 = (m1 >> v) & 1u, in2 = (m2 >> v) & 1u;
+      const unsigned long long q1 = __ballot(in1), q2 = __ballot(in2);
+      if (in1 | in2) {
+        const uint32_t dst = in1 ? o1p + lane_rank(q1) : o2p + lane_rank(q2);
+        A.ox[dst] = px[v];  // plain stores: the L2 merges the partial lines of
+        A.oy[dst] = py[v];  // neighbouring runs before they reach HBM
+        A.oi[dst] = pi[v];
+      }
+      o1p += (uint32_t)__popcll(q1);
+      o2p += (uint32_t)__popcll(q2);
+    }
+    // s_cnt / s_base are rewritten only after the next tile's first barrier,
+    // which every thread reaches after finishing these reads.
   }
+  if (run_seg != kNone) flush_run<NW>(A.part, run_slot, b1, b2, s_cand);
 }
 
 // --------------------------------------------------------- block utilities
@@ -385,18 +430,11 @@ __device__ __forceinline__ Cand block_best(Cand c, Cand* s_c) {
 
 enum : uint32_t { kKindNone = 0, kKindLeaf = 1, kKindJob = 2, kKindSeg = 3 };
 
-struct Child {
-  double ax, ay, rx, ry, bx, by;
-  uint32_t ri, beg, cnt, req;
-  int32_t parent;  // parent node, -1 for a root
-  uint32_t side;
-  uint32_t kind;
-};
-
 constexpr int kPlanBlock = 1024;
 constexpr int kPlanWaves = kPlanBlock / 64;
-constexpr uint32_t kSerialTiles = 32;  // segments with more tiles are reduced by the whole workgroup
-constexpr uint32_t kSerialFill = 16;   // segments with more tiles get their tile map filled by the workgroup
+constexpr uint32_t kSerialRecs = 16;   // segments with more candidate records are reduced by one wave,
+constexpr uint32_t kWaveRecs = 2048;   // and with more than this by the whole workgroup
+constexpr uint32_t kSerialFill = 16;  // segments with more tiles get their tile map filled by the workgroup
 
 __device__ __forceinline__ uint32_t ceil_div(uint32_t a, uint32_t b) { return (a + b - 1u) / b; }
 
@@ -406,97 +444,108 @@ __device__ __forceinline__ uint32_t child_kind(uint32_t cnt, uint32_t lds_limit)
 
 struct PlanShared {
   uint32_t scan[4][kPlanWaves];
-  uint32_t nodes, jobs, segs, tiles, swept, jobpts;
+  uint32_t nodes, jobs, segs, tiles, swept, jobpts, survivors;
   uint32_t nbig, nfill;
   uint32_t big[kPlanBlock];
   uint32_t fill[2 * kPlanBlock];  // up to two new segments per thread
 };
 
-// Lay out up to K children per thread (all threads must call).  nid_out gets
-// the node of each child (-1 if none).
-template <int K>
-__device__ void emit_children(const Child (&ch)[K], int32_t (&nid_out)[K], Node* nodes, uint32_t node_base, Job* jobs,
-                              Seg* seg_out, unsigned long long* ctr_out, uint32_t* tile_seg_out, uint32_t src,
-                              uint32_t tile, PlanShared& S) {
+struct Tri {
+  double ax, ay, rx, ry, bx, by;
+};
+
+// Offsets of this thread's children in the next level's tables.
+struct EmitBase {
+  uint32_t node, job, seg, tile;
+};
+
+__device__ __forceinline__ EmitBase emit_scan(const uint32_t (&kind)[2], const uint32_t (&cnt)[2], uint32_t tile,
+                                              PlanShared& S, uint32_t (&tot)[4]) {
   uint32_t v[4] = {0, 0, 0, 0};
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    v[0] += ch[k].kind != kKindNone;
-    v[1] += ch[k].kind == kKindJob;
-    v[2] += ch[k].kind == kKindSeg;
-    v[3] += ch[k].kind == kKindSeg ? ceil_div(ch[k].cnt, tile) : 0u;
+  for (int k = 0; k < 2; ++k) {
+    v[0] += kind[k] != kKindNone;
+    v[1] += kind[k] == kKindJob;
+    v[2] += kind[k] == kKindSeg;
+    v[3] += kind[k] == kKindSeg ? ceil_div(cnt[k], tile) : 0u;
   }
-  uint32_t ex[4], tot[4];
+  uint32_t ex[4];
   block_scan<kPlanBlock, 4>(v, ex, tot, S.scan);
-  const uint32_t nb = S.nodes + ex[0], jb = S.jobs + ex[1], sb = S.segs + ex[2], tb = S.tiles + ex[3];
-  uint32_t dn = 0, dj = 0, ds = 0, dt = 0, swept = 0, jobpts = 0;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const Child& c = ch[k];
-    int32_t nid = -1;
-    if (c.kind != kKindNone) {
-      nid = (int32_t)(node_base + nb + dn++);
-      Node nd;
-      nd.vertex = c.ri;
-      nd.c[0] = -1;
-      nd.c[1] = -1;
-      nd.size = c.kind == kKindLeaf ? 1u : 0u;
-      nd.start = 0;
-      nd.req = c.req;
-      nd.list = kNone;
-      nd.lbuf = 0;
-      nodes[nid] = nd;
-    }
-    nid_out[k] = nid;
-    if (c.parent >= 0) nodes[c.parent].c[c.side] = nid;
-    if (c.kind == kKindJob) {
-      Job j;
-      j.ax = c.ax;
-      j.ay = c.ay;
-      j.rx = c.rx;
-      j.ry = c.ry;
-      j.bx = c.bx;
-      j.by = c.by;
-      j.ri = c.ri;
-      j.beg = c.beg;
-      j.cnt = c.cnt;
-      j.src = src;
-      j.req = c.req;
-      j.node = nid;
-      j.ibase = src == kSrcUser ? c.beg : 0u;
-      j.pad = 0;
-      jobs[jb + dj++] = j;
-      jobpts += c.cnt;
-    } else if (c.kind == kKindSeg) {
-      const uint32_t sid = sb + ds++;
-      const uint32_t nt = ceil_div(c.cnt, tile);
-      const uint32_t t0 = tb + dt;
-      dt += nt;
-      swept += c.cnt;
-      Seg sg;
-      sg.ax = c.ax;
-      sg.ay = c.ay;
-      sg.rx = c.rx;
-      sg.ry = c.ry;
-      sg.bx = c.bx;
-      sg.by = c.by;
-      sg.beg = c.beg;
-      sg.cnt = c.cnt;
-      sg.tile0 = t0;
-      sg.req = c.req;
-      sg.node = nid;
-      sg.ibase = src == kSrcUser ? c.beg : 0u;
-      seg_out[sid] = sg;
-      ctr_out[sid] = 0ull;
-      if (nt <= kSerialFill) {
-        for (uint32_t i = 0; i < nt; ++i) tile_seg_out[t0 + i] = sid;
-      } else {
-        S.fill[atomicAdd(&S.nfill, 1u)] = sid;
-      }
+  return EmitBase{S.nodes + ex[0], S.jobs + ex[1], S.segs + ex[2], S.tiles + ex[3]};
+}
+
+// Write one child (node, job or segment); advances the running offsets in e.
+__device__ __forceinline__ int32_t emit_one(uint32_t kind, const Tri& tr, uint32_t ri, uint32_t beg, uint32_t cnt,
+                                            uint32_t req, int32_t parent, uint32_t side, uint32_t src,
+                                            uint32_t node_base, uint32_t tile, EmitBase& e, Node* nodes, Job* jobs,
+                                            Seg* seg_out, unsigned long long* ctr_out, uint32_t* tile_seg_out,
+                                            PlanShared& S) {
+  int32_t nid = -1;
+  if (kind != kKindNone) {
+    nid = (int32_t)(node_base + e.node++);
+    Node nd;
+    nd.vertex = ri;
+    nd.c[0] = -1;
+    nd.c[1] = -1;
+    nd.size = kind == kKindLeaf ? 1u : 0u;
+    nd.start = 0;
+    nd.req = req;
+    nd.list = kNone;
+    nd.lbuf = 0;
+    nodes[nid] = nd;
+  }
+  if (parent >= 0) nodes[parent].c[side] = nid;
+  if (kind == kKindJob) {
+    Job j;
+    j.ax = tr.ax;
+    j.ay = tr.ay;
+    j.rx = tr.rx;
+    j.ry = tr.ry;
+    j.bx = tr.bx;
+    j.by = tr.by;
+    j.ri = ri;
+    j.beg = beg;
+    j.cnt = cnt;
+    j.src = src;
+    j.req = req;
+    j.node = nid;
+    j.ibase = src == kSrcUser ? beg : 0u;
+    j.pad = 0;
+    jobs[e.job++] = j;
+    atomicAdd(&S.jobpts, cnt);
+  } else if (kind == kKindSeg) {
+    const uint32_t sid = e.seg++;
+    const uint32_t nt = ceil_div(cnt, tile);
+    const uint32_t t0 = e.tile;
+    e.tile += nt;
+    Seg sg;
+    sg.ax = tr.ax;
+    sg.ay = tr.ay;
+    sg.rx = tr.rx;
+    sg.ry = tr.ry;
+    sg.bx = tr.bx;
+    sg.by = tr.by;
+    sg.beg = beg;
+    sg.cnt = cnt;
+    sg.tile0 = t0;
+    sg.req = req;
+    sg.node = nid;
+    sg.ibase = src == kSrcUser ? beg : 0u;
+    seg_out[sid] = sg;
+    ctr_out[sid] = 0ull;
+    atomicAdd(&S.swept, cnt);
+    if (nt <= kSerialFill) {
+      for (uint32_t i = 0; i < nt; ++i) tile_seg_out[t0 + i] = sid;
+    } else {
+      S.fill[atomicAdd(&S.nfill, 1u)] = sid;
     }
   }
-  if (swept) atomicAdd(&S.swept, swept);
-  if (jobpts) atomicAdd(&S.jobpts, jobpts);
+  return nid;
+}
+
+// Tile maps of the big new segments (whole workgroup), then running totals.
+__device__ __forceinline__ void emit_finish(const uint32_t (&tot)[4], const Seg* seg_out, uint32_t* tile_seg_out,
+                                            uint32_t tile, PlanShared& S) {
   __syncthreads();
   const uint32_t nf = S.nfill;
   for (uint32_t f = 0; f < nf; ++f) {
@@ -511,13 +560,14 @@ __device__ void emit_children(const Child (&ch)[K], int32_t (&nid_out)[K], Node*
     S.segs += tot[2];
     S.tiles += tot[3];
     S.nfill = 0;
+    S.nbig = 0;
   }
   __syncthreads();
 }
 
 __device__ __forceinline__ void plan_init(PlanShared& S) {
   if (threadIdx.x == 0) {
-    S.nodes = S.jobs = S.segs = S.tiles = S.swept = S.jobpts = 0;
+    S.nodes = S.jobs = S.segs = S.tiles = S.swept = S.jobpts = S.survivors = 0;
     S.nbig = S.nfill = 0;
   }
   __syncthreads();
@@ -532,7 +582,17 @@ __device__ __forceinline__ void plan_status(PlanShared& S, Status* out, uint32_t
     st.nnodes = node_base + S.nodes;
     st.swept = S.swept;
     st.jobpts = S.jobpts;
-    st.pad[0] = st.pad[1] = 0;
+    st.survivors = S.survivors;
+    st.overflow = 0;
+    *out = st;
+  }
+}
+
+__device__ __forceinline__ void plan_overflow(Status* out, uint32_t node_base) {
+  if (threadIdx.x == 0) {
+    Status st{};
+    st.nnodes = node_base;
+    st.overflow = 1;
     *out = st;
   }
 }
@@ -561,14 +621,33 @@ __device__ __forceinline__ void ext_merge(Ext& e, double mnx, double mny, uint32
 
 __device__ __forceinline__ Ext no_ext() { return Ext{0.0, 0.0, 0.0, 0.0, kNone, kNone}; }
 
+__device__ __forceinline__ Ext wave_ext(Ext me) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    Ext o;
+    o.mnx = __shfl_xor(me.mnx, m, 64);
+    o.mny = __shfl_xor(me.mny, m, 64);
+    o.mni = __shfl_xor(me.mni, m, 64);
+    o.mxx = __shfl_xor(me.mxx, m, 64);
+    o.mxy = __shfl_xor(me.mxy, m, 64);
+    o.mxi = __shfl_xor(me.mxi, m, 64);
+    ext_merge(me, o.mnx, o.mny, o.mni, o.mxx, o.mxy, o.mxi);
+  }
+  return me;
+}
+
 // Root level: p and q of every request, then the degenerate triangle (p, q, p)
 // of Algorithm 1's top level as a job or a level-0 segment.
 __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
   __shared__ PlanShared S;
-  __shared__ Ext s_w[kPlanWaves];
   __shared__ Ext s_res[kPlanBlock];
+  __shared__ Ext s_w[kPlanWaves];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   plan_init(S);
+  if ((uint64_t)A.nreq > A.node_cap) {
+    plan_overflow(A.st_out, 0u);
+    return;
+  }
   for (uint32_t base = 0; base < A.nreq; base += kPlanBlock) {
     const uint32_t i = base + tid;
     const bool valid = i < A.nreq;
@@ -578,7 +657,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
     if (valid) {
       rq = A.req[i];
       const uint32_t nt = ceil_div(rq.n, A.ext_tile);
-      if (nt <= kSerialTiles) {
+      if (nt <= kSerialRecs) {
         for (uint32_t k = 0; k < nt; ++k) {
           const ExtPart p = A.epart[rq.tile0 + k];
           ext_merge(e, p.minx, p.miny, p.mini, p.maxx, p.maxy, p.maxi);
@@ -590,94 +669,95 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
     }
     __syncthreads();
     const uint32_t nbig = S.nbig;
-    for (uint32_t b = 0; b < nbig; ++b) {
+    for (uint32_t b = w; b < nbig; b += kPlanWaves) {  // one wave per big request
       const uint32_t owner = S.big[b];
       const uint32_t t0 = A.req[base + owner].tile0, nt = ceil_div(A.req[base + owner].n, A.ext_tile);
+      if (nt > kWaveRecs) continue;
+      Ext me = no_ext();
+      for (uint32_t k = lane; k < nt; k += 64) {
+        const ExtPart p = A.epart[t0 + k];
+        ext_merge(me, p.minx, p.miny, p.mini, p.maxx, p.maxy, p.maxi);
+      }
+      me = wave_ext(me);
+      if (lane == 0) s_res[owner] = me;
+    }
+    for (uint32_t b = 0; b < nbig; ++b) {  // the whole workgroup per huge request
+      const uint32_t owner = S.big[b];
+      const uint32_t t0 = A.req[base + owner].tile0, nt = ceil_div(A.req[base + owner].n, A.ext_tile);
+      if (nt <= kWaveRecs) continue;
       Ext me = no_ext();
       for (uint32_t k = tid; k < nt; k += kPlanBlock) {
         const ExtPart p = A.epart[t0 + k];
         ext_merge(me, p.minx, p.miny, p.mini, p.maxx, p.maxy, p.maxi);
       }
-#pragma unroll
-      for (int m = 32; m >= 1; m >>= 1) {
-        Ext o;
-        o.mnx = __shfl_xor(me.mnx, m, 64);
-        o.mny = __shfl_xor(me.mny, m, 64);
-        o.mni = __shfl_xor(me.mni, m, 64);
-        o.mxx = __shfl_xor(me.mxx, m, 64);
-        o.mxy = __shfl_xor(me.mxy, m, 64);
-        o.mxi = __shfl_xor(me.mxi, m, 64);
-        ext_merge(me, o.mnx, o.mny, o.mni, o.mxx, o.mxy, o.mxi);
-      }
+      me = wave_ext(me);
       if (lane == 0) s_w[w] = me;
       __syncthreads();
       if (tid == 0) {
         Ext f = no_ext();
-        for (int q = 0; q < kPlanWaves; ++q) ext_merge(f, s_w[q].mnx, s_w[q].mny, s_w[q].mni, s_w[q].mxx, s_w[q].mxy,
-                                                       s_w[q].mxi);
+        for (int q = 0; q < kPlanWaves; ++q)
+          ext_merge(f, s_w[q].mnx, s_w[q].mny, s_w[q].mni, s_w[q].mxx, s_w[q].mxy, s_w[q].mxi);
         s_res[owner] = f;
       }
       __syncthreads();
     }
+    __syncthreads();
     if (big) e = s_res[tid];
-    Child ch[1];
-    ch[0].kind = kKindNone;
-    ch[0].parent = -1;
-    ch[0].side = 0;
-    ch[0].cnt = 0;
+    uint32_t kind[2] = {kKindNone, kKindNone}, cnt[2] = {0, 0};
     if (valid && rq.n > 0) {
-      Child& c = ch[0];
-      c.ax = e.mnx;
-      c.ay = e.mny;
-      c.rx = e.mxx;
-      c.ry = e.mxy;
-      c.bx = e.mnx;
-      c.by = e.mny;
-      c.ri = e.mxi;
-      c.beg = rq.off;
-      c.cnt = rq.n;
-      c.req = i;
-      c.kind = rq.n <= A.lds_limit ? kKindJob : kKindSeg;
+      kind[0] = rq.n <= A.lds_limit ? kKindJob : kKindSeg;
+      cnt[0] = rq.n;
     }
-    int32_t nid[1];
-    emit_children<1>(ch, nid, A.nodes, 0u, A.jobs, A.seg_out, A.ctr_out, A.tile_seg_out, kSrcUser, A.tile, S);
+    uint32_t tot[4];
+    EmitBase eb = emit_scan(kind, cnt, A.tile, S, tot);
     if (valid) {
+      int32_t nid = -1;
+      if (rq.n > 0) {
+        const Tri tr{e.mnx, e.mny, e.mxx, e.mxy, e.mnx, e.mny};
+        nid = emit_one(kind[0], tr, e.mxi, rq.off, rq.n, i, -1, 0, kSrcUser, 0u, A.tile, eb, A.nodes, A.jobs,
+                       A.seg_out, A.ctr_out, A.tile_seg_out, S);
+      }
       A.req[i].p = rq.n > 0 ? e.mni : 0u;
       A.req[i].q = rq.n > 0 ? e.mxi : 0u;
-      A.req[i].root = nid[0];
+      A.req[i].root = nid;
     }
-    if (tid == 0) S.nbig = 0;
-    __syncthreads();
+    emit_finish(tot, A.seg_out, A.tile_seg_out, A.tile, S);
   }
-  plan_status(S, A.status, 0u);
+  plan_status(S, A.st_out, 0u);
 }
 
-// One recursion level: reduce the per-tile counts and candidates of every
-// segment, then lay out its two children (Algorithm 1: Hull(S1, a, r1, r) and
+// One recursion level: reduce the counts and candidates of every segment,
+// then lay out its two children (Algorithm 1: Hull(S1, a, r1, r) and
 // Hull(S2, r, r2, b)).  The children's points already sit at the two ends of
 // the segment's range in the output buffer of the sweep.
 __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
   __shared__ PlanShared S;
-  __shared__ Cand s_c[kPlanWaves];
   __shared__ Cand s_res[kPlanBlock][2];
-  const int tid = threadIdx.x;
+  __shared__ Cand s_c[kPlanWaves];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   plan_init(S);
-  for (uint32_t base = 0; base < A.nseg; base += kPlanBlock) {
+  const uint32_t nseg = A.st_in->nseg, node_base = A.st_in->nnodes;
+  if ((uint64_t)node_base + 2ull * nseg > A.node_cap) {
+    plan_overflow(A.st_out, node_base);
+    return;
+  }
+  const uint32_t G = A.sweep_grid;
+  for (uint32_t base = 0; base < nseg; base += kPlanBlock) {
     const uint32_t s = base + tid;
-    const bool valid = s < A.nseg;
-    Seg sg{};
-    uint32_t n1 = 0, n2 = 0;
+    const bool valid = s < nseg;
+    uint32_t n1 = 0, n2 = 0, tile0 = 0, nrec = 0;
     Cand r1 = no_cand(), r2 = no_cand();
     bool big = false;
     if (valid) {
-      sg = A.seg[s];
       const unsigned long long c = A.ctr[s];
       n1 = (uint32_t)c;
       n2 = (uint32_t)(c >> 32);
-      const uint32_t nt = ceil_div(sg.cnt, A.tile);
-      if (nt <= kSerialTiles) {
-        for (uint32_t k = 0; k < nt; ++k) {
-          const TilePart& p = A.part[sg.tile0 + k];
+      atomicAdd(&S.survivors, n1 + n2);
+      tile0 = A.seg[s].tile0;
+      nrec = min(G, ceil_div(A.seg[s].cnt, A.tile));
+      if (nrec <= kSerialRecs) {
+        for (uint32_t k = 0; k < nrec; ++k) {
+          const TilePart& p = A.part[tile0 + k];
           if (better(p.c[0], r1)) r1 = p.c[0];
           if (better(p.c[1], r2)) r2 = p.c[1];
         }
@@ -688,11 +768,31 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
     }
     __syncthreads();
     const uint32_t nbig = S.nbig;
-    for (uint32_t b = 0; b < nbig; ++b) {
+    for (uint32_t b = w; b < nbig; b += kPlanWaves) {  // one wave per big segment
       const uint32_t owner = S.big[b];
-      const uint32_t t0 = A.seg[base + owner].tile0, nt = ceil_div(A.seg[base + owner].cnt, A.tile);
+      const uint32_t t0 = A.seg[base + owner].tile0;
+      const uint32_t nr = min(G, ceil_div(A.seg[base + owner].cnt, A.tile));
+      if (nr > kWaveRecs) continue;
       Cand m1 = no_cand(), m2 = no_cand();
-      for (uint32_t k = tid; k < nt; k += kPlanBlock) {
+      for (uint32_t k = lane; k < nr; k += 64) {
+        const TilePart& p = A.part[t0 + k];
+        if (better(p.c[0], m1)) m1 = p.c[0];
+        if (better(p.c[1], m2)) m2 = p.c[1];
+      }
+      wave_best(m1);
+      wave_best(m2);
+      if (lane == 0) {
+        s_res[owner][0] = m1;
+        s_res[owner][1] = m2;
+      }
+    }
+    for (uint32_t b = 0; b < nbig; ++b) {  // the whole workgroup per huge segment
+      const uint32_t owner = S.big[b];
+      const uint32_t t0 = A.seg[base + owner].tile0;
+      const uint32_t nr = min(G, ceil_div(A.seg[base + owner].cnt, A.tile));
+      if (nr <= kWaveRecs) continue;
+      Cand m1 = no_cand(), m2 = no_cand();
+      for (uint32_t k = tid; k < nr; k += kPlanBlock) {
         const TilePart& p = A.part[t0 + k];
         if (better(p.c[0], m1)) m1 = p.c[0];
         if (better(p.c[1], m2)) m2 = p.c[1];
@@ -703,52 +803,31 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
         s_res[owner][0] = m1;
         s_res[owner][1] = m2;
       }
-      __syncthreads();
     }
+    __syncthreads();
     if (big) {
       r1 = s_res[tid][0];
       r2 = s_res[tid][1];
     }
-    Child ch[2];
-    ch[0].kind = ch[1].kind = kKindNone;
-    ch[0].parent = ch[1].parent = -1;
-    ch[0].cnt = ch[1].cnt = 0;
+    uint32_t kind[2] = {kKindNone, kKindNone}, cnt[2] = {n1, n2};
     if (valid) {
-      Child& c = ch[0];
-      c.ax = sg.ax;
-      c.ay = sg.ay;
-      c.rx = r1.x;
-      c.ry = r1.y;
-      c.bx = sg.rx;
-      c.by = sg.ry;
-      c.ri = r1.i;
-      c.beg = sg.beg;
-      c.cnt = n1;
-      c.req = sg.req;
-      c.parent = sg.node;
-      c.side = 0;
-      c.kind = child_kind(n1, A.lds_limit);
-      Child& d = ch[1];
-      d.ax = sg.rx;
-      d.ay = sg.ry;
-      d.rx = r2.x;
-      d.ry = r2.y;
-      d.bx = sg.bx;
-      d.by = sg.by;
-      d.ri = r2.i;
-      d.beg = sg.beg + sg.cnt - n2;
-      d.cnt = n2;
-      d.req = sg.req;
-      d.parent = sg.node;
-      d.side = 1;
-      d.kind = child_kind(n2, A.lds_limit);
+      kind[0] = child_kind(n1, A.lds_limit);
+      kind[1] = child_kind(n2, A.lds_limit);
     }
-    int32_t nid[2];
-    emit_children<2>(ch, nid, A.nodes, A.node_base, A.jobs, A.seg_out, A.ctr_out, A.tile_seg_out, A.out_buf, A.tile, S);
-    if (tid == 0) S.nbig = 0;
-    __syncthreads();
+    uint32_t tot[4];
+    EmitBase eb = emit_scan(kind, cnt, A.tile, S, tot);
+    if (valid) {
+      const Seg sg = A.seg[s];
+      const Tri t1{sg.ax, sg.ay, r1.x, r1.y, sg.rx, sg.ry};
+      emit_one(kind[0], t1, r1.i, sg.beg, n1, sg.req, sg.node, 0, A.out_buf, node_base, A.tile, eb, A.nodes, A.jobs,
+               A.seg_out, A.ctr_out, A.tile_seg_out, S);
+      const Tri t2{sg.rx, sg.ry, r2.x, r2.y, sg.bx, sg.by};
+      emit_one(kind[1], t2, r2.i, sg.beg + sg.cnt - n2, n2, sg.req, sg.node, 1, A.out_buf, node_base, A.tile, eb,
+               A.nodes, A.jobs, A.seg_out, A.ctr_out, A.tile_seg_out, S);
+    }
+    emit_finish(tot, A.seg_out, A.tile_seg_out, A.tile, S);
   }
-  plan_status(S, A.status, A.node_base);
+  plan_status(S, A.st_out, node_base);
 }
 
 // --------------------------------------------------------------- k_finish
@@ -762,37 +841,36 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
 //   2. scan the child sizes: nodes, next sub-subproblems and their ranges;
 //   3. scatter the points into the next live list (one-point children record
 //      their only point as their vertex);
-//   4. one wave per child with >= 2 points finds its farthest point;
+//   4. find the farthest point of every child with >= 2 points (one thread per
+//      small child, one wave per large child);
 //   5. create the nodes and the next level's sub-subproblems.
 // The ordered vertex list (in-order over the recursion tree) is written over
-// the job's own index range.
+// the job's own index range.  Persistent: workgroups loop over the level's jobs.
 
 constexpr uint16_t kNone16 = 0xFFFFu;
+constexpr uint32_t kSmallChild = 32;  // children up to this size are reduced by one thread
 
 template <int BLOCK, int TMAX>
 struct FinishShared {
   double lx[TMAX + 3], ly[TMAX + 3];
   uint32_t lid[TMAX + 3];
   uint32_t ord[2][TMAX];
-  uint16_t sa[2][TMAX / 2], sr[2][TMAX / 2], sb[2][TMAX / 2], sbeg[2][TMAX / 2], scnt[2][TMAX / 2],
-      snode[2][TMAX / 2];
+  uint16_t sa[2][TMAX / 2], sr[2][TMAX / 2], sb[2][TMAX / 2], snode[2][TMAX / 2];
   uint32_t ccnt[TMAX];
   uint16_t cwin[TMAX], cnode[TMAX], cbase[TMAX], cmap[TMAX];
   uint16_t nv[TMAX], nc0[TMAX], nc1[TMAX], nsz[TMAX], nst[TMAX];
   uint16_t lvl[TMAX + 2];
+  uint16_t bigc[TMAX / kSmallChild + 2];
   uint32_t scan[3][BLOCK / 64];
-  uint32_t nsub, ntot, nnode, nlvl, bad;
+  uint32_t nsub, ntot, nnode, nlvl, bad, nbigc;
 };
 
 template <int BLOCK, int TMAX>
-__global__ __launch_bounds__(BLOCK) void k_finish(FinishArgs A) {
+__device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLOCK, TMAX>& S) {
   constexpr int NW = BLOCK / 64;
   constexpr int KP = (TMAX + BLOCK - 1) / BLOCK;  // live points per thread per level
   constexpr int KC = (TMAX + BLOCK - 1) / BLOCK;  // children per thread per level
-  extern __shared__ unsigned char smem_raw[];
-  FinishShared<BLOCK, TMAX>& S = *reinterpret_cast<FinishShared<BLOCK, TMAX>*>(smem_raw);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const Job job = A.jobs[blockIdx.x];
   const uint32_t cnt = job.cnt;
   const bool user = job.src == kSrcUser;
   const double* X = user ? A.ux : A.bx[job.src];
@@ -824,8 +902,6 @@ __global__ __launch_bounds__(BLOCK) void k_finish(FinishArgs A) {
     S.sa[0][0] = (uint16_t)cnt;
     S.sb[0][0] = (uint16_t)(cnt + 1);
     S.sr[0][0] = (uint16_t)(cnt + 2);
-    S.sbeg[0][0] = 0;
-    S.scnt[0][0] = (uint16_t)cnt;
     S.snode[0][0] = 0;
     S.nv[0] = (uint16_t)(cnt + 2);
     S.nc0[0] = kNone16;
@@ -844,6 +920,7 @@ __global__ __launch_bounds__(BLOCK) void k_finish(FinishArgs A) {
   while (S.nsub > 0) {
     const uint32_t nsub = S.nsub, ntot = S.ntot, nch = 2u * nsub;
     for (uint32_t c = tid; c < nch; c += BLOCK) S.ccnt[c] = 0;
+    if (tid == 0) S.nbigc = 0;
     __syncthreads();
     // 1. classify
     uint32_t chd[KP], slot[KP], pid[KP];
@@ -897,6 +974,7 @@ __global__ __launch_bounds__(BLOCK) void k_finish(FinishArgs A) {
           S.cnode[c] = n >= 1u ? (uint16_t)en : kNone16;
           S.cmap[c] = n >= 2u ? (uint16_t)es : kNone16;
           S.cbase[c] = (uint16_t)ep;
+          if (n > kSmallChild) S.bigc[atomicAdd(&S.nbigc, 1u)] = (uint16_t)c;
           en += n >= 1u;
           es += n >= 2u;
           ep += n >= 2u ? n : 0u;
@@ -923,10 +1001,33 @@ __global__ __launch_bounds__(BLOCK) void k_finish(FinishArgs A) {
       }
     }
     __syncthreads();
-    // 4. farthest point of every child with >= 2 points (one wave per child)
-    for (uint32_t c = w; c < nch; c += NW) {
+    // 4. farthest point of every child with >= 2 points
+    for (uint32_t c = tid; c < nch; c += BLOCK) {
       const uint32_t n = S.ccnt[c];
-      if (n < 2u) continue;
+      if (n < 2u || n > kSmallChild) continue;
+      const uint32_t s = c >> 1;
+      const uint32_t ea = (c & 1u) ? S.sr[cb][s] : S.sa[cb][s];
+      const uint32_t eb = (c & 1u) ? S.sb[cb][s] : S.sr[cb][s];
+      const double ex0 = S.lx[ea], ey0 = S.ly[ea], ex1 = S.lx[eb], ey1 = S.ly[eb];
+      Cand best = no_cand();
+      const uint32_t b0 = S.cbase[c];
+      for (uint32_t e = 0; e < n; ++e) {
+        const uint32_t l = S.ord[cb ^ 1][b0 + e] & 0xFFFFu;
+        const double kk = orient(ex0, ey0, ex1, ey1, S.lx[l], S.ly[l]);
+        if (better(kk, S.lx[l], S.ly[l], S.lid[l], best)) {
+          best.k = kk;
+          best.x = S.lx[l];
+          best.y = S.ly[l];
+          best.i = S.lid[l];
+          best.pad = l;
+        }
+      }
+      S.cwin[c] = (uint16_t)best.pad;
+    }
+    const uint32_t nbigc = S.nbigc;
+    for (uint32_t b = w; b < nbigc; b += NW) {
+      const uint32_t c = S.bigc[b];
+      const uint32_t n = S.ccnt[c];
       const uint32_t s = c >> 1;
       const uint32_t ea = (c & 1u) ? S.sr[cb][s] : S.sa[cb][s];
       const uint32_t eb = (c & 1u) ? S.sb[cb][s] : S.sr[cb][s];
@@ -935,9 +1036,9 @@ __global__ __launch_bounds__(BLOCK) void k_finish(FinishArgs A) {
       const uint32_t b0 = S.cbase[c];
       for (uint32_t e = lane; e < n; e += 64) {
         const uint32_t l = S.ord[cb ^ 1][b0 + e] & 0xFFFFu;
-        const double k = orient(ex0, ey0, ex1, ey1, S.lx[l], S.ly[l]);
-        if (better(k, S.lx[l], S.ly[l], S.lid[l], best)) {
-          best.k = k;
+        const double kk = orient(ex0, ey0, ex1, ey1, S.lx[l], S.ly[l]);
+        if (better(kk, S.lx[l], S.ly[l], S.lid[l], best)) {
+          best.k = kk;
           best.x = S.lx[l];
           best.y = S.ly[l];
           best.i = S.lid[l];
@@ -969,8 +1070,6 @@ __global__ __launch_bounds__(BLOCK) void k_finish(FinishArgs A) {
         S.sa[cb ^ 1][ns] = side ? S.sr[cb][s] : S.sa[cb][s];
         S.sb[cb ^ 1][ns] = side ? S.sb[cb][s] : S.sr[cb][s];
         S.sr[cb ^ 1][ns] = S.cwin[c];
-        S.sbeg[cb ^ 1][ns] = S.cbase[c];
-        S.scnt[cb ^ 1][ns] = (uint16_t)n;
         S.snode[cb ^ 1][ns] = v;
       }
     }
@@ -1008,6 +1107,18 @@ __global__ __launch_bounds__(BLOCK) void k_finish(FinishArgs A) {
     nd->size = S.nsz[0];
     nd->list = job.beg;
     nd->lbuf = user ? 0u : job.src;
+  }
+  __syncthreads();  // LDS is reused by the next job
+}
+
+template <int BLOCK, int TMAX>
+__global__ __launch_bounds__(BLOCK) void k_finish(FinishArgs A) {
+  extern __shared__ unsigned char smem_raw[];
+  FinishShared<BLOCK, TMAX>& S = *reinterpret_cast<FinishShared<BLOCK, TMAX>*>(smem_raw);
+  const uint32_t njobs = A.st->njobs;
+  for (uint32_t j = blockIdx.x; j < njobs; j += gridDim.x) {
+    const Job job = A.jobs[j];
+    finish_job<BLOCK, TMAX>(job, A, S);
   }
 }
 
@@ -1087,31 +1198,74 @@ __global__ __launch_bounds__(256) void k_copy_lists(AssembleArgs A) {
   }
 }
 
+// --------------------------------------------------------- k_stream_scale
+// STREAM "Scale" (out = s * in): the achievable-bandwidth yardstick and the
+// known-size kernel that calibrates the byte counters of the profiler.
+__global__ __launch_bounds__(256) void k_stream_scale(const double* __restrict__ in, double* __restrict__ out,
+                                                        uint64_t n, double s) {
+  const uint64_t stride = (uint64_t)gridDim.x * 256u;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < n; i += stride) out[i] = s * in[i];
+}
+
 // -------------------------------------------------------------- launchers
 
 namespace {
 template <int BLOCK, int PPT>
-int sweep_one(const SweepArgs& a, bool level0, hipStream_t st) {
+int sweep_one(const SweepArgs& a, bool level0, uint32_t grid, hipStream_t st) {
   if (level0) {
-    hipLaunchKernelGGL((k_sweep<BLOCK, PPT, true>), dim3(a.ntiles), dim3(BLOCK), 0, st, a);
+    hipLaunchKernelGGL((k_sweep<BLOCK, PPT, true>), dim3(grid), dim3(BLOCK), 0, st, a);
   } else {
-    hipLaunchKernelGGL((k_sweep<BLOCK, PPT, false>), dim3(a.ntiles), dim3(BLOCK), 0, st, a);
+    hipLaunchKernelGGL((k_sweep<BLOCK, PPT, false>), dim3(grid), dim3(BLOCK), 0, st, a);
   }
   return (int)hipGetLastError();
 }
 
+template <int BLOCK, int PPT>
+uint32_t sweep_occupancy_grid() {
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_sweep<BLOCK, PPT, false>, BLOCK, 0) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess || cus < 1)
+    cus = 256;
+  return (uint32_t)(per_cu * cus);
+}
+
 template <int BLOCK, int TMAX>
-int finish_one(const FinishArgs& a, uint32_t njobs, hipStream_t st) {
-  const size_t bytes = sizeof(FinishShared<BLOCK, TMAX>);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_finish<BLOCK, TMAX>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+int finish_attr() {
+  static bool done = false;
+  if (!done) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_finish<BLOCK, TMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)sizeof(FinishShared<BLOCK, TMAX>));
     if (e != hipSuccess) return (int)e;
-    attr_set = true;
+    done = true;
   }
-  hipLaunchKernelGGL((k_finish<BLOCK, TMAX>), dim3(njobs), dim3(BLOCK), bytes, st, a);
+  return 0;
+}
+
+template <int BLOCK, int TMAX>
+int finish_one(const FinishArgs& a, hipStream_t st) {
+  int e = finish_attr<BLOCK, TMAX>();
+  if (e) return e;
+  hipLaunchKernelGGL((k_finish<BLOCK, TMAX>), dim3(finish_grid(TMAX)), dim3(BLOCK), sizeof(FinishShared<BLOCK, TMAX>),
+                     st, a);
   return (int)hipGetLastError();
+}
+
+template <int BLOCK, int TMAX>
+uint32_t finish_occupancy_grid() {
+  if (finish_attr<BLOCK, TMAX>() != 0) return 256;
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_finish<BLOCK, TMAX>, BLOCK,
+                                                   sizeof(FinishShared<BLOCK, TMAX>)) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess || cus < 1)
+    cus = 256;
+  return (uint32_t)(per_cu * cus);
 }
 }  // namespace
 
@@ -1120,7 +1274,31 @@ bool sweep_shape_supported(int block, int ppt) {
          (block == 1024 && ppt == 8);
 }
 
+uint32_t sweep_grid(int block, int ppt) {
+  static uint32_t cache[5] = {0, 0, 0, 0, 0};
+  const int k = block == 256 ? (ppt == 16 ? 0 : 1) : block == 512 ? (ppt == 8 ? 2 : 3) : 4;
+  if (!cache[k]) {
+    if (k == 0) cache[k] = sweep_occupancy_grid<256, 16>();
+    if (k == 1) cache[k] = sweep_occupancy_grid<256, 32>();
+    if (k == 2) cache[k] = sweep_occupancy_grid<512, 8>();
+    if (k == 3) cache[k] = sweep_occupancy_grid<512, 16>();
+    if (k == 4) cache[k] = sweep_occupancy_grid<1024, 8>();
+  }
+  return cache[k];
+}
+
 int finish_tmax_for(int lds_limit) { return lds_limit <= 512 ? 512 : lds_limit <= 1024 ? 1024 : 2048; }
+
+uint32_t finish_grid(int tmax) {
+  static uint32_t cache[3] = {0, 0, 0};
+  const int k = tmax == 512 ? 0 : tmax == 1024 ? 1 : 2;
+  if (!cache[k]) {
+    if (k == 0) cache[k] = finish_occupancy_grid<256, 512>();
+    if (k == 1) cache[k] = finish_occupancy_grid<256, 1024>();
+    if (k == 2) cache[k] = finish_occupancy_grid<256, 2048>();
+  }
+  return cache[k];
+}
 
 int launch_extremes(const ExtremesArgs& a, void* stream) {
   if (a.ntiles == 0) return 0;
@@ -1128,14 +1306,13 @@ int launch_extremes(const ExtremesArgs& a, void* stream) {
   return (int)hipGetLastError();
 }
 
-int launch_sweep(const SweepArgs& a, bool level0, int block, int ppt, void* stream) {
-  if (a.ntiles == 0) return 0;
+int launch_sweep(const SweepArgs& a, bool level0, int block, int ppt, uint32_t grid, void* stream) {
   hipStream_t st = (hipStream_t)stream;
-  if (block == 256 && ppt == 16) return sweep_one<256, 16>(a, level0, st);
-  if (block == 256 && ppt == 32) return sweep_one<256, 32>(a, level0, st);
-  if (block == 512 && ppt == 8) return sweep_one<512, 8>(a, level0, st);
-  if (block == 512 && ppt == 16) return sweep_one<512, 16>(a, level0, st);
-  if (block == 1024 && ppt == 8) return sweep_one<1024, 8>(a, level0, st);
+  if (block == 256 && ppt == 16) return sweep_one<256, 16>(a, level0, grid, st);
+  if (block == 256 && ppt == 32) return sweep_one<256, 32>(a, level0, grid, st);
+  if (block == 512 && ppt == 8) return sweep_one<512, 8>(a, level0, grid, st);
+  if (block == 512 && ppt == 16) return sweep_one<512, 16>(a, level0, grid, st);
+  if (block == 1024 && ppt == 8) return sweep_one<1024, 8>(a, level0, grid, st);
   return (int)hipErrorInvalidValue;
 }
 
@@ -1149,13 +1326,19 @@ int launch_plan(const PlanArgs& a, void* stream) {
   return (int)hipGetLastError();
 }
 
-int launch_finish(const FinishArgs& a, uint32_t njobs, int tmax, void* stream) {
-  if (njobs == 0) return 0;
+int launch_finish(const FinishArgs& a, int tmax, void* stream) {
   hipStream_t st = (hipStream_t)stream;
-  if (tmax == 512) return finish_one<256, 512>(a, njobs, st);
-  if (tmax == 1024) return finish_one<256, 1024>(a, njobs, st);
-  if (tmax == 2048) return finish_one<256, 2048>(a, njobs, st);
+  if (tmax == 512) return finish_one<256, 512>(a, st);
+  if (tmax == 1024) return finish_one<256, 1024>(a, st);
+  if (tmax == 2048) return finish_one<256, 2048>(a, st);
   return (int)hipErrorInvalidValue;
+}
+
+int launch_stream_scale(const double* in, double* out, uint64_t n, double s, void* stream) {
+  if (n == 0) return 0;
+  const uint64_t blocks = std::min<uint64_t>((n + 255u) / 256u, 2048u);
+  hipLaunchKernelGGL(k_stream_scale, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream, in, out, n, s);
+  return (int)hipGetLastError();
 }
 
 int launch_assemble(const AssembleArgs& a, void* stream) {

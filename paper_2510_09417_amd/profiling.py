@@ -1,0 +1,127 @@
+"""Turn rocprofv3 CSV output into the short summaries kept under profiles/.
+
+    python -m paper_2510_09417_amd.profiling stats  <kernel_stats.csv> <out.md> "<command>"
+    python -m paper_2510_09417_amd.profiling traffic <fetch counter_collection.csv> <write counter_collection.csv>
+            <out.json> <out.md> "<fetch command>" "<write command>" [elements of the probe, default 1e8]
+
+``traffic`` calibrates the byte counters on the STREAM-Scale probe kernel, which
+reads and writes exactly 8 bytes per element: factor = known bytes / counted
+bytes, separately for FETCH_SIZE and WRITE_SIZE.  The level-0 sweep's counted
+bytes per dispatch, times those factors, give its measured HBM traffic per
+launch.  The JSON records the hash of the kernel source it was taken on; the
+benchmark ignores it once the source has changed.
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SRC = os.path.join(HERE, "csrc", "vqhull_kernels.hip")
+SWEEP_L0 = "k_sweep<"
+PROBE = "k_stream_scale"
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def short(name: str) -> str:
+    name = name.replace("(vqh::SweepArgs)", "").replace("void ", "")
+    if len(name) > 70:
+        name = name[:67] + "..."
+    return name
+
+
+def stats(path: str, out: str, command: str) -> None:
+    rows = list(csv.DictReader(open(path)))
+    lines = [f"# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
+             "| kernel | calls | avg (us) | min (us) | max (us) | total (ms) | % |", "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} |")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def _per_kernel(path: str, counter: str) -> dict:
+    agg = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        agg.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return agg
+
+
+def _pick(agg: dict, pred) -> list:
+    vals = []
+    for k, v in agg.items():
+        if pred(k):
+            vals += v
+    return vals
+
+
+def traffic(fetch_csv: str, write_csv: str, out_json: str, out_md: str, fetch_cmd: str, write_cmd: str,
+            probe_elems: float = 1e8) -> dict:
+    fa, wa = _per_kernel(fetch_csv, "FETCH_SIZE"), _per_kernel(write_csv, "WRITE_SIZE")
+    is_l0 = lambda k: SWEEP_L0 in k and ", true>" in k
+    is_probe = lambda k: PROBE in k
+    f_probe, w_probe = _pick(fa, is_probe), _pick(wa, is_probe)
+    f_l0, w_l0 = _pick(fa, is_l0), _pick(wa, is_l0)
+    if not (f_probe and w_probe and f_l0 and w_l0):
+        raise SystemExit("missing probe or level-0 sweep dispatches in the counter files")
+    mean = lambda v: sum(v) / len(v)
+    known = 8.0 * probe_elems  # bytes read (and written) by the probe
+    ff = known / (mean(f_probe) * 1024.0)
+    fw = known / (mean(w_probe) * 1024.0)
+    fetch_b = mean(f_l0) * 1024.0 * ff
+    write_b = mean(w_l0) * 1024.0 * fw
+    res = {
+        "kernel": "k_sweep level 0",
+        "bytes_per_launch": int(fetch_b + write_b),
+        "fetch_bytes_per_launch": int(fetch_b),
+        "write_bytes_per_launch": int(write_b),
+        "fetch_size_kib_per_dispatch": round(mean(f_l0), 1),
+        "write_size_kib_per_dispatch": round(mean(w_l0), 1),
+        "probe_fetch_kib": round(mean(f_probe), 1),
+        "probe_write_kib": round(mean(w_probe), 1),
+        "fetch_scale": round(ff, 4),
+        "write_scale": round(fw, 4),
+        "dispatches": len(f_l0),
+        "kernel_source_sha256_16": kernel_source_hash(),
+    }
+    with open(out_json, "w") as f:
+        json.dump(res, f, indent=1)
+    lines = ["# HBM traffic of the level-0 fused sweep (rocprofv3 counters)", "",
+             f"FETCH_SIZE command: `{fetch_cmd}`", "", f"WRITE_SIZE command: `{write_cmd}`", "",
+             "Calibration: the STREAM-Scale probe reads and writes exactly 8 bytes per element "
+             f"({probe_elems:.0f} elements); scale = known bytes / counted bytes.", "",
+             "| quantity | value |", "|---|---|",
+             f"| probe FETCH_SIZE (KiB/dispatch) | {res['probe_fetch_kib']} |",
+             f"| probe WRITE_SIZE (KiB/dispatch) | {res['probe_write_kib']} |",
+             f"| fetch scale | {res['fetch_scale']} |",
+             f"| write scale | {res['write_scale']} |",
+             f"| level-0 sweep FETCH_SIZE (KiB/dispatch, {len(f_l0)} dispatches) | {res['fetch_size_kib_per_dispatch']} |",
+             f"| level-0 sweep WRITE_SIZE (KiB/dispatch) | {res['write_size_kib_per_dispatch']} |",
+             f"| level-0 sweep fetched bytes per launch (scaled) | {res['fetch_bytes_per_launch']} |",
+             f"| level-0 sweep written bytes per launch (scaled) | {res['write_bytes_per_launch']} |",
+             f"| level-0 sweep HBM traffic per launch | {res['bytes_per_launch']} |",
+             f"| kernel source sha256[:16] | `{res['kernel_source_sha256_16']}` |"]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return res
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6], sys.argv[7],
+                float(sys.argv[8]) if len(sys.argv) > 8 else 1e8)
+    else:
+        raise SystemExit(__doc__)

@@ -24,9 +24,9 @@ def vq():
 
     assert torch.cuda.is_available()
     vq.load_library()
-    vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048, reverse_tiles=0)
+    vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048, reverse_tiles=0, sweep_persistent=1)
     yield vq
-    vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048, reverse_tiles=0)
+    vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048, reverse_tiles=0, sweep_persistent=1)
 
 
 def gpu_hull(vq, x, y):
@@ -118,26 +118,28 @@ def test_nonfinite_reported(vq):
     assert torch.cuda.is_available()
 
 
+@pytest.mark.parametrize("persistent", [0, 1])
 @pytest.mark.parametrize("shape", [(256, 16), (256, 32), (512, 8), (512, 16), (1024, 8)])
 @pytest.mark.parametrize("lds_limit", [256, 1024, 2048])
-def test_kernel_shapes_do_not_change_result(vq, shape, lds_limit):
-    vq.set_config(sweep_block=shape[0], sweep_ppt=shape[1], lds_limit=lds_limit)
+def test_kernel_shapes_do_not_change_result(vq, shape, lds_limit, persistent):
+    vq.set_config(sweep_block=shape[0], sweep_ppt=shape[1], lds_limit=lds_limit, sweep_persistent=persistent)
     try:
         for dist in workloads.DISTRIBUTIONS:
             x, y = workloads.points(dist, 300_001, seed=77)
-            check(vq, x, y, f"{dist} {shape} lds={lds_limit}")
+            check(vq, x, y, f"{dist} {shape} lds={lds_limit} persistent={persistent}")
     finally:
-        vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048)
+        vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048, sweep_persistent=1)
 
 
-def test_reverse_tile_order(vq):
-    vq.set_config(reverse_tiles=1)
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_reverse_tile_order(vq, persistent):
+    vq.set_config(reverse_tiles=1, sweep_persistent=persistent)
     try:
         for dist in workloads.DISTRIBUTIONS:
             x, y = workloads.points(dist, 500_000, seed=78)
             check(vq, x, y, f"{dist} reversed tiles")
     finally:
-        vq.set_config(reverse_tiles=0)
+        vq.set_config(reverse_tiles=0, sweep_persistent=1)
 
 
 def test_repeatable(vq):

@@ -1,0 +1,95 @@
+"""The C ABI boundary on the CPU: the library loads, exports every function the
+public header declares, and rejects bad arguments on the host (these calls
+return before any HIP call, so no GPU is needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vqhull.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(vqhull_[a-z_0-9]+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2510_09417_amd as vq
+
+    return vq.load_library()
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for f in ("vqhull_hull", "vqhull_hull_batched", "vqhull_status_string", "vqhull_stream_scale"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), f"{name} declared in include/vqhull.h but not exported"
+
+
+def test_binding_lists_the_same_symbols():
+    import paper_2510_09417_amd as vq
+
+    assert sorted(vq.EXPORTED) == declared_functions()
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    vp = ctypes.c_void_p
+    dummy = vp(0x1000)  # never dereferenced: the checks fail first
+    one = (ctypes.c_int64 * 1)()
+    assert lib.vqhull_hull(dummy, dummy, -1, dummy, dummy, None) == 1
+    assert lib.vqhull_hull(dummy, dummy, 1 << 31, dummy, dummy, None) == 1
+    assert lib.vqhull_hull(None, dummy, 5, dummy, dummy, None) == 1
+    assert lib.vqhull_hull(dummy, dummy, 5, None, dummy, None) == 1
+    assert lib.vqhull_hull(dummy, dummy, 5, dummy, None, None) == 1
+    off = np.array([0, 5, 3], dtype=np.int64)  # decreasing
+    p = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    assert lib.vqhull_hull_batched(dummy, dummy, p, 2, dummy, dummy, None) == 1
+    off2 = np.array([1, 5], dtype=np.int64)  # offsets[0] != 0
+    assert lib.vqhull_hull_batched(dummy, dummy, off2.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1, dummy,
+                                   dummy, None) == 1
+    assert lib.vqhull_hull_batched(dummy, dummy, None, 1, dummy, dummy, None) == 1
+    assert lib.vqhull_hull_batched(dummy, dummy, p, -1, dummy, dummy, None) == 1
+    assert lib.vqhull_stream_scale(dummy, dummy, -1, 2.0, None) == 1
+    assert lib.vqhull_stream_scale(None, dummy, 4, 2.0, None) == 1
+    assert one[0] == 0
+
+
+def test_status_strings(lib):
+    for code in range(5):
+        assert lib.vqhull_status_string(code)
+    assert b"unknown" in lib.vqhull_status_string(99)
+
+
+def test_config_roundtrip_and_sanitizing():
+    import paper_2510_09417_amd as vq
+
+    old = vq.get_config()
+    try:
+        c = vq.set_config(sweep_block=256, sweep_ppt=16, lds_limit=1000, reverse_tiles=5, sweep_persistent=0)
+        assert (c["sweep_block"], c["sweep_ppt"], c["lds_limit"], c["reverse_tiles"], c["sweep_persistent"]) == \
+            (256, 16, 1000, 1, 0)
+        c = vq.set_config(sweep_block=300, sweep_ppt=7, lds_limit=10**6)
+        assert (c["sweep_block"], c["sweep_ppt"], c["lds_limit"]) == (512, 8, 2048)
+    finally:
+        vq.set_config(**old)
+
+
+def test_python_binding_checks():
+    import torch
+
+    import paper_2510_09417_amd as vq
+
+    with pytest.raises(TypeError):
+        vq.hull(torch.zeros(3, dtype=torch.float32), torch.zeros(3, dtype=torch.float32))
+    with pytest.raises(ValueError):
+        vq.hull(torch.zeros(3, dtype=torch.float64), torch.zeros(3, dtype=torch.float64))  # not on a GPU

@@ -1,0 +1,62 @@
+"""GPU parity at the full workload sizes, in the kernel configuration the
+benchmark times: the complete index list of every hull is compared with the
+CPU oracle's (bit-exact).  Inputs: the unit disk and unit square at 10^8
+points (seed 2), the unit circle at 5*10^7 (seed 3) and the Kuzmin disk at
+10^8 (seed 4), drawn by paper_2510_09417_amd.workloads."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_09417_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vq():
+    import torch
+
+    import paper_2510_09417_amd as vq
+
+    assert torch.cuda.is_available()
+    vq.load_library()
+    vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048, reverse_tiles=0, sweep_persistent=1)
+    yield vq
+    vq.release_workspace()
+
+
+@pytest.mark.parametrize("name", ["disk_1e8", "square_1e8", "kuzmin_1e8", "circle_5e7"])
+def test_full_size_bit_exact(vq, name):
+    import torch
+
+    t0 = time.perf_counter()
+    x, y = workloads.workload(name)
+    tx, ty = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    got = vq.hull(tx, ty).cpu().numpy()
+    del tx, ty
+    t1 = time.perf_counter()
+    want = oracle.hull(x, y)
+    t2 = time.perf_counter()
+    print(f"{name}: h={len(want)} gpu+transfer {t1 - t0:.1f}s oracle {t2 - t1:.1f}s", flush=True)
+    assert len(got) == len(want)
+    assert np.array_equal(got, want)
+    # the result is a set of distinct input indices starting at the lexicographic minimum
+    assert got[0] == int(np.lexsort((np.arange(len(x)), y, x))[0])
+
+
+def test_disk_1e6_repeated_and_reversed(vq):
+    """The 10^6-point disk (seed 1) in the benchmark configuration, then with the
+    tile order reversed: the same list both times."""
+    import torch
+
+    x, y = workloads.workload("disk_1e6")
+    want = oracle.hull(x, y)
+    tx, ty = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    assert np.array_equal(vq.hull(tx, ty).cpu().numpy(), want)
+    vq.set_config(reverse_tiles=1)
+    try:
+        assert np.array_equal(vq.hull(tx, ty).cpu().numpy(), want)
+    finally:
+        vq.set_config(reverse_tiles=0)

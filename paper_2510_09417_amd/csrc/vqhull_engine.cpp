@@ -55,7 +55,9 @@ struct Workspace {
   DevBuf<Seg> seg[2];
   DevBuf<unsigned long long> ctr[2];
   DevBuf<uint32_t> tile_seg[2];
-  DevBuf<TilePart> part;
+  DevBuf<TilePart> part, part2;
+  DevBuf<FusedRoot> fr;
+  DevBuf<unsigned long long> jctr;
   DevBuf<ExtPart> epart;
   DevBuf<uint32_t> tile_req;
   DevBuf<Req> req;
@@ -176,6 +178,9 @@ void free_workspace(Workspace* w) {
     f(w->tile_seg[k].p);
   }
   f(w->part.p);
+  f(w->part2.p);
+  f(w->fr.p);
+  f(w->jctr.p);
   f(w->epart.p);
   f(w->tile_req.p);
   f(w->req.p);
@@ -250,7 +255,7 @@ bool run_once(Workspace& w, const vqhull_config& cfg, const double* x, const dou
   const uint32_t tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
   const uint32_t lds_limit = (uint32_t)cfg.lds_limit;
   const int tmax = finish_tmax_for(cfg.lds_limit);
-  const uint32_t G_persistent = sweep_grid(cfg.sweep_block, cfg.sweep_ppt);
+
   const size_t max_seg = N / (lds_limit + 1) + (size_t)nreq + 2;
   const bool tm = g_timing.load() != 0;
 
@@ -290,15 +295,17 @@ bool run_once(Workspace& w, const vqhull_config& cfg, const double* x, const dou
   std::vector<size_t> finish_recs;     // timing records of the finisher launches, per level
   bool overflow = false;
   int64_t known_nodes = (int64_t)nreq, known_seg = (int64_t)std::min<size_t>((size_t)nreq, max_seg);
+  // Level 0 is an argmax-only pass over the roots (sizes and farthest points
+  // of S1 / S2, nothing written); level 1 re-reads the caller's arrays and
+  // classifies every point twice (root triangle, then its child's triangle),
+  // so the top level's subsets are never materialized; levels >= 2 sweep the
+  // workspace.  Finisher jobs of level k run after sweep k (the fused pass
+  // writes the points of level 1's small children).
   for (int k = 0;; ++k) {
     const int slot = k % kStatusRing, next = (k + 1) % kStatusRing;
-    fa.st = w.status_dev + slot;
-    fa.nodes = w.nodes.p;
-    finish_recs.push_back(
-        timed(w, tm, st, VQHULL_K_FINISH, k, 0, 0, [&] { ck(launch_finish(fa, tmax, st), "k_finish"); }));
-
+    const int mode = k == 0 ? kSweepArgmax : k == 1 ? kSweepFused : kSweepLevel;
     SweepArgs sa{};
-    const int in_buf = k == 0 ? -1 : (k - 1) % 2, out_buf = k % 2, cur = k % 2;
+    const int in_buf = k <= 1 ? -1 : (k - 1) % 2, out_buf = k % 2, cur = k % 2;
     sa.ix = in_buf < 0 ? x : w.wx[in_buf];
     sa.iy = in_buf < 0 ? y : w.wy[in_buf];
     sa.ii = in_buf < 0 ? nullptr : w.wi[in_buf];
@@ -306,24 +313,32 @@ bool run_once(Workspace& w, const vqhull_config& cfg, const double* x, const dou
     sa.oy = w.wy[out_buf];
     sa.oi = w.wi[out_buf];
     sa.seg = w.seg[cur].p;
-    sa.tile_seg = w.tile_seg[cur].p;
+    sa.fr = w.fr.p;
+    sa.tile_seg = w.tile_seg[k == 1 ? 0 : cur].p;  // the fused pass walks the roots' tiles again
     sa.ctr = w.ctr[cur].p;
+    sa.jctr = w.jctr.p;
     sa.part = w.part.p;
+    sa.part2 = w.part2.p;
     sa.req = w.req.p;
     sa.st = w.status_dev + slot;
     sa.reverse = (uint32_t)cfg.reverse_tiles;
     // Grid: persistent, or one workgroup per tile with the tile count bounded
-    // from what the host knows (level 0 exactly; level k from level k-1:
-    // tiles <= ceil(swept(k-1) / tile) + 2 nseg(k-1)); surplus groups exit.
-    uint32_t G = G_persistent;
+    // from what the host knows (levels 0 and 1 exactly; level k from level
+    // k-1: tiles <= ceil(swept(k-1) / tile) + 2 nseg(k-1)); surplus groups exit.
+    uint32_t G = sweep_grid(cfg.sweep_block, cfg.sweep_ppt, mode);
     if (!cfg.sweep_persistent) {
-      uint64_t bound = k == 0 ? tiles0
+      uint64_t bound = k <= 1 ? tiles0
                               : (known[k - 1].swept + (uint64_t)tile - 1) / tile + 2ull * known[k - 1].nseg + 1;
       G = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(bound, max_tiles));
     }
     sweep_recs.push_back(timed(w, tm, st, VQHULL_K_SWEEP, k, 0, 0, [&] {
-      ck(launch_sweep(sa, in_buf < 0, cfg.sweep_block, cfg.sweep_ppt, G, st), "k_sweep");
+      ck(launch_sweep(sa, mode, cfg.sweep_block, cfg.sweep_ppt, G, st), "k_sweep");
     }));
+
+    fa.st = w.status_dev + slot;
+    fa.nodes = w.nodes.p;
+    finish_recs.push_back(
+        timed(w, tm, st, VQHULL_K_FINISH, k, 0, 0, [&] { ck(launch_finish(fa, tmax, st), "k_finish"); }));
 
     // Node capacity for this plan: nodes after it <= nodes(k) + 2 nseg(k), with
     // nodes(k) <= nodes(k-1) + 2 nseg(k-1) and nseg(k) <= min(2 nseg(k-1), max_seg).
@@ -334,6 +349,10 @@ bool run_once(Workspace& w, const vqhull_config& cfg, const double* x, const dou
     pl.seg = w.seg[cur].p;
     pl.ctr = w.ctr[cur].p;
     pl.part = w.part.p;
+    pl.part2 = w.part2.p;
+    pl.fuse = k == 0 ? 1u : 0u;
+    pl.fr_out = w.fr.p;
+    pl.jctr_out = w.jctr.p;
     pl.st_in = w.status_dev + slot;
     pl.sweep_grid = G;
     pl.seg_out = w.seg[cur ^ 1].p;
@@ -342,7 +361,7 @@ bool run_once(Workspace& w, const vqhull_config& cfg, const double* x, const dou
     pl.jobs = w.jobs.p;
     pl.nodes = w.nodes.p;
     pl.node_cap = (uint32_t)std::min<size_t>(w.nodes.cap, 0xFFFFFFFFu);
-    pl.out_buf = (uint32_t)out_buf;
+    pl.out_buf = (uint32_t)(k == 0 ? 1 : out_buf);  // level 0's children are written by the fused pass
     pl.st_out = w.status_dev + next;
     pl.tile = tile;
     pl.lds_limit = lds_limit;
@@ -356,8 +375,11 @@ bool run_once(Workspace& w, const vqhull_config& cfg, const double* x, const dou
     const Status sk = w.status_host[slot];
     known.push_back(sk);
     w.stats.push_back({(int64_t)sk.nseg, (int64_t)sk.swept, (int64_t)sk.njobs, (int64_t)sk.jobpts});
-    if (k >= 1 && sweep_recs[k - 1] != (size_t)-1) w.launches[sweep_recs[k - 1]].out = sk.survivors;
-    if (sweep_recs[k] != (size_t)-1) w.launches[sweep_recs[k]].in = sk.swept;
+    // sweep k reads status[k].swept points (the fused pass: the roots' points
+    // again) and writes what plan k counts as survivors (+ pass-through copies)
+    if (k >= 2 && sweep_recs[k - 1] != (size_t)-1) w.launches[sweep_recs[k - 1]].out += sk.survivors;
+    if (sweep_recs[k] != (size_t)-1) w.launches[sweep_recs[k]].in = k == 1 ? known[0].swept : sk.swept;
+    if (k == 1 && sweep_recs[1] != (size_t)-1) w.launches[sweep_recs[1]].out += sk.jobpts;
     if (finish_recs[k] != (size_t)-1) w.launches[finish_recs[k]].in = sk.jobpts;
     if (sk.overflow) {
       overflow = true;
@@ -458,7 +480,10 @@ void run(const double* x, const double* y, const int64_t* offsets, int64_t nreq,
     ensure(w.tile_seg[k], max_tiles, st);
   }
   ensure(w.part, max_tiles, st);
+  ensure(w.part2, max_tiles, st);
+  ensure(w.fr, max_seg, st);
   ensure(w.jobs, 2 * max_seg + (size_t)nreq, st);
+  ensure(w.jctr, 2 * max_seg + (size_t)nreq, st);
   ensure(w.nodes, std::max<size_t>(3 * (size_t)nreq + 64, 4096), st);
 
   for (int attempt = 0;; ++attempt) {

@@ -37,10 +37,29 @@ struct Req {
 struct Seg {
   double ax, ay, rx, ry, bx, by;
   uint32_t beg, cnt;
-  uint32_t tile0;   // first tile of this segment in the level's tile map
+  uint32_t tile0;   // first tile of this segment in the level's tile map (and its first record slot)
   uint32_t req;
   int32_t node;     // node of r
   uint32_t ibase;
+  uint32_t rtiles;  // tiles whose records hold this segment's candidates (0: ceil(cnt / tile))
+  uint32_t rside;   // which record array (fused level: the side of the root it came from)
+};
+
+// The fused pass classifies every point of a root twice: against the root's
+// triangle (p, q, p) and then against the triangle of the child it falls in.
+// A child swept at the next level is "virtual": its points are never written;
+// its own children (the root's grandchildren) are.  A child small enough for
+// the LDS finisher is "pass-through": its points are copied into its range.
+enum : uint32_t { kFuseSkip = 0, kFuseSplit = 1, kFuseCopy = 2 };
+
+struct FusedRoot {
+  double px, py, qx, qy;  // the root triangle (p, q, p)
+  double ax[2], ay[2], rx[2], ry[2], bx[2], by[2];  // child triangles, side 0 = S1, side 1 = S2
+  uint32_t beg[2], cnt[2];  // child ranges in the output buffer
+  uint32_t kind[2];         // kFuse*
+  uint32_t slot[2];         // kFuseSplit: next-level segment id; kFuseCopy: job id
+  uint32_t off, n;          // the root's points in the caller's arrays
+  uint32_t tile0, req;
 };
 
 // Farthest-point candidate: key = orient value for the edge, then (x, y, i)
@@ -110,17 +129,23 @@ struct ExtremesArgs {
   uint32_t ntiles;
 };
 
+// Sweep modes.
+enum : int { kSweepLevel = 0, kSweepArgmax = 1, kSweepFused = 2 };
+
 struct SweepArgs {
-  const double* ix;  // level input (caller arrays at level 0)
+  const double* ix;  // level input (caller arrays for the argmax and fused passes)
   const double* iy;
-  const uint32_t* ii;  // nullptr at level 0
+  const uint32_t* ii;  // level input indices (normal levels)
   double* ox;
   double* oy;
   uint32_t* oi;
-  const Seg* seg;
+  const Seg* seg;       // normal levels and the argmax pass
+  const FusedRoot* fr;  // fused pass
   const uint32_t* tile_seg;
-  unsigned long long* ctr;
-  TilePart* part;  // one record per (workgroup, segment) run, at slot tile0 + (tile - tile0) % gridDim
+  unsigned long long* ctr;   // per segment (normal, argmax) or per next-level segment (fused)
+  unsigned long long* jctr;  // fused pass: per pass-through job
+  TilePart* part;   // records, at slot tile0 + (tile - tile0) % gridDim
+  TilePart* part2;  // fused pass: records of the side-1 children
   Req* req;
   const Status* st;  // ntiles of this level
   uint32_t reverse;
@@ -146,6 +171,10 @@ struct PlanArgs {
   const Seg* seg;
   const unsigned long long* ctr;
   const TilePart* part;
+  const TilePart* part2;   // record array of segments with rside = 1
+  uint32_t fuse;           // 1: plan the roots for the fused pass (children become virtual / pass-through)
+  FusedRoot* fr_out;       // fused roots (fuse = 1)
+  unsigned long long* jctr_out;  // pass-through job counters (fuse = 1)
   const Status* st_in;  // the level being planned (nseg, nnodes)
   uint32_t sweep_grid;  // workgroups of the sweep that produced `part`
   Seg* seg_out;
@@ -190,8 +219,8 @@ int finish_tmax_for(int lds_limit);
 
 // Launchers (return hipError_t as int).
 int launch_extremes(const ExtremesArgs& a, void* stream);
-int launch_sweep(const SweepArgs& a, bool level0, int block, int ppt, uint32_t grid, void* stream);
-uint32_t sweep_grid(int block, int ppt);   // persistent grid size for a sweep shape
+int launch_sweep(const SweepArgs& a, int mode, int block, int ppt, uint32_t grid, void* stream);
+uint32_t sweep_grid(int block, int ppt, int mode);  // persistent grid size for a sweep shape and mode
 uint32_t finish_grid(int tmax);            // persistent grid size of the finisher
 int launch_plan0(const Plan0Args& a, void* stream);
 int launch_plan(const PlanArgs& a, void* stream);

@@ -40,16 +40,30 @@ __device__ __forceinline__ double orient(double ax, double ay, double bx, double
 
 // Total order of farthest-point candidates: larger key first, then smaller x,
 // smaller y, lower index.  kNone loses to every candidate.
+//
+// Written without branches (bitwise operations on the comparison results): the
+// candidate update then lowers to selects.  An equivalent form with early
+// returns was lowered wrongly by the gfx950 backend of the ROCm 7.2 compiler
+// when the key was a negated orientation value: on lanes that already held a
+// candidate the stored key was left unchanged while x, y and the index moved on.
 __device__ __forceinline__ bool better(double k, double x, double y, uint32_t i, const Cand& b) {
-  if (i == kNone) return false;
-  if (b.i == kNone) return true;
-  if (k != b.k) return k > b.k;
-  if (x != b.x) return x < b.x;
-  if (y != b.y) return y < b.y;
-  return i < b.i;
+  const bool tie_y = (y == b.y) & (i < b.i);
+  const bool tie_x = (x == b.x) & ((y < b.y) | tie_y);
+  const bool ord = (k > b.k) | ((k == b.k) & ((x < b.x) | tie_x));
+  return (i != kNone) & ((b.i == kNone) | ord);
 }
 
 __device__ __forceinline__ bool better(const Cand& a, const Cand& b) { return better(a.k, a.x, a.y, a.i, b); }
+
+// c = the better of c and o, field by field through selects.
+__device__ __forceinline__ void keep(Cand& c, const Cand& o) {
+  const bool t = better(o, c);
+  c.k = t ? o.k : c.k;
+  c.x = t ? o.x : c.x;
+  c.y = t ? o.y : c.y;
+  c.i = t ? o.i : c.i;
+  c.pad = t ? o.pad : c.pad;
+}
 
 __device__ __forceinline__ Cand no_cand() {
   Cand c;
@@ -75,8 +89,7 @@ __device__ __forceinline__ Cand shfl_xor_cand(const Cand& c, int m) {
 __device__ __forceinline__ void wave_best(Cand& c) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) {
-    Cand o = shfl_xor_cand(c, m);
-    if (better(o, c)) c = o;
+    keep(c, shfl_xor_cand(c, m));
   }
 }
 
@@ -85,6 +98,20 @@ __device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
 }
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+// Values that are the same in every lane (a segment's triangle and range, read
+// once per run of tiles) are moved to scalar registers: the loads go through
+// the vector memory path, since the compiler cannot prove that the kernel's
+// own stores leave them unchanged, and would otherwise hold them in VGPRs.
+// (The builtin returns a signed int: each half goes back through uint32_t
+// before it is widened.)
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ double uni(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint64_t lo = uni((uint32_t)b);
+  const uint64_t hi = uni((uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, (hi << 32) | lo);
+}
 
 // Lexicographic order of points by (x, y, position); y is loaded only on an
 // exact x tie.  ia / ib are positions into y.
@@ -203,6 +230,132 @@ __global__ __launch_bounds__(BLOCK) void k_extremes(ExtremesArgs A) {
 // runs.  The order of points inside a subset is irrelevant to the result.
 // Farthest-point candidates are kept per thread across the consecutive tiles
 // a workgroup visits in one segment and written once per such run.
+//
+// Modes:
+//   kSweepLevel   one recursion level over the workspace (x, y, index).
+//   kSweepArgmax  the top level over the caller's arrays, without writing any
+//                 point: only the sizes and farthest points of S1 and S2.
+//   kSweepFused   the caller's arrays again: each point is classified against
+//                 the root triangle (p, q, p) and then against the triangle of
+//                 the child it falls in, so the top level's subsets are never
+//                 written or read back.  Children small enough for the LDS
+//                 finisher are copied instead (pass-through).
+
+// Write-run reservation and output for one "stream pair" (left-growing L and
+// right-growing R block of a range [beg, beg + cnt)).
+template <int BLOCK, int PPT, int NW>
+__device__ __forceinline__ void write_pair(uint32_t mL, uint32_t mR, uint32_t beg, uint32_t cnt,
+                                           unsigned long long* ctr, const double (&px)[PPT],
+                                           const double (&py)[PPT], const uint32_t (&pi)[PPT], double* ox,
+                                           double* oy, uint32_t* oi, uint32_t (*s_cnt)[NW], uint32_t* s_base) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  uint32_t c1 = 0, c2 = 0;
+#pragma unroll
+  for (int v = 0; v < PPT; ++v) {
+    c1 += __popcll(__ballot((mL >> v) & 1u));
+    c2 += __popcll(__ballot((mR >> v) & 1u));
+  }
+  if (lane == 0) {
+    s_cnt[0][w] = c1;
+    s_cnt[1][w] = c2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t t1 = 0, t2 = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const uint32_t a = s_cnt[0][i], b = s_cnt[1][i];
+      s_cnt[0][i] = t1;
+      s_cnt[1][i] = t2;
+      t1 += a;
+      t2 += b;
+    }
+    unsigned long long old = 0ull;
+    if (t1 | t2) old = atomicAdd(ctr, ((unsigned long long)t2 << 32) | (unsigned long long)t1);
+    s_base[0] = beg + (uint32_t)old;
+    s_base[1] = beg + cnt - (uint32_t)(old >> 32) - t2;
+  }
+  __syncthreads();
+  uint32_t o1p = s_base[0] + s_cnt[0][w];
+  uint32_t o2p = s_base[1] + s_cnt[1][w];
+#pragma unroll
+  for (int v = 0; v < PPT; ++v) {
+    const bool in1 = (mL >> v) & 1u, in2 = (mR >> v) & 1u;
+    const unsigned long long q1 = __ballot(in1), q2 = __ballot(in2);
+    if (in1 | in2) {
+      const uint32_t dst = in1 ? o1p + lane_rank(q1) : o2p + lane_rank(q2);
+      ox[dst] = px[v];  // plain stores: the L2 merges the partial lines of
+      oy[dst] = py[v];  // neighbouring runs before they reach HBM
+      oi[dst] = pi[v];
+    }
+    o1p += (uint32_t)__popcll(q1);
+    o2p += (uint32_t)__popcll(q2);
+  }
+  // s_cnt / s_base are rewritten only after the next first barrier, which
+  // every thread reaches after finishing these reads.
+}
+
+// Fused pass: one reservation for the four output blocks of a tile (left and
+// right block of each child's range); thread c reserves for child c.
+template <int BLOCK, int PPT, int NW>
+__device__ __forceinline__ void write_quad(const uint32_t (&mL)[2], const uint32_t (&mR)[2], const uint32_t (&beg)[2],
+                                           const uint32_t (&cnt)[2], unsigned long long* ctr0,
+                                           unsigned long long* ctr1, const double (&px)[PPT],
+                                           const double (&py)[PPT], const uint32_t (&pi)[PPT], double* ox,
+                                           double* oy, uint32_t* oi, uint32_t (*s_cnt)[NW], uint32_t* s_base) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  uint32_t c[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int v = 0; v < PPT; ++v) {
+    c[0] += __popcll(__ballot((mL[0] >> v) & 1u));
+    c[1] += __popcll(__ballot((mR[0] >> v) & 1u));
+    c[2] += __popcll(__ballot((mL[1] >> v) & 1u));
+    c[3] += __popcll(__ballot((mR[1] >> v) & 1u));
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s_cnt[q][w] = c[q];
+  }
+  __syncthreads();
+  if (tid < 2) {
+    const int ch = tid;
+    uint32_t t1 = 0, t2 = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const uint32_t a = s_cnt[2 * ch][i], b = s_cnt[2 * ch + 1][i];
+      s_cnt[2 * ch][i] = t1;
+      s_cnt[2 * ch + 1][i] = t2;
+      t1 += a;
+      t2 += b;
+    }
+    unsigned long long old = 0ull;
+    if (t1 | t2) old = atomicAdd(ch ? ctr1 : ctr0, ((unsigned long long)t2 << 32) | (unsigned long long)t1);
+    s_base[2 * ch] = beg[ch] + (uint32_t)old;
+    s_base[2 * ch + 1] = beg[ch] + cnt[ch] - (uint32_t)(old >> 32) - t2;
+  }
+  __syncthreads();
+  uint32_t o[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) o[q] = s_base[q] + s_cnt[q][w];
+#pragma unroll
+  for (int v = 0; v < PPT; ++v) {
+    const bool i0 = (mL[0] >> v) & 1u, i1 = (mR[0] >> v) & 1u, i2 = (mL[1] >> v) & 1u, i3 = (mR[1] >> v) & 1u;
+    const unsigned long long q0 = __ballot(i0), q1 = __ballot(i1), q2 = __ballot(i2), q3 = __ballot(i3);
+    if (i0 | i1 | i2 | i3) {
+      const uint32_t dst = i0   ? o[0] + lane_rank(q0)
+                           : i1 ? o[1] + lane_rank(q1)
+                           : i2 ? o[2] + lane_rank(q2)
+                                : o[3] + lane_rank(q3);
+      ox[dst] = px[v];
+      oy[dst] = py[v];
+      oi[dst] = pi[v];
+    }
+    o[0] += (uint32_t)__popcll(q0);
+    o[1] += (uint32_t)__popcll(q1);
+    o[2] += (uint32_t)__popcll(q2);
+    o[3] += (uint32_t)__popcll(q3);
+  }
+}
 
 template <int NW>
 __device__ __forceinline__ void flush_run(TilePart* part, uint32_t slot, Cand b1, Cand b2, Cand (*s_cand)[NW]) {
@@ -218,8 +371,8 @@ __device__ __forceinline__ void flush_run(TilePart* part, uint32_t slot, Cand b1
     Cand r1 = s_cand[0][0], r2 = s_cand[1][0];
 #pragma unroll
     for (int i = 1; i < NW; ++i) {
-      if (better(s_cand[0][i], r1)) r1 = s_cand[0][i];
-      if (better(s_cand[1][i], r2)) r2 = s_cand[1][i];
+      keep(r1, s_cand[0][i]);
+      keep(r2, s_cand[1][i]);
     }
     part[slot].c[0] = r1;
     part[slot].c[1] = r2;
@@ -227,46 +380,111 @@ __device__ __forceinline__ void flush_run(TilePart* part, uint32_t slot, Cand b1
   __syncthreads();
 }
 
-template <int BLOCK, int PPT, bool L0>
+__device__ __forceinline__ void take(Cand& b, double k, double x, double y, uint32_t i) {
+  const bool t = better(k, x, y, i, b);
+  b.k = t ? k : b.k;
+  b.x = t ? x : b.x;
+  b.y = t ? y : b.y;
+  b.i = t ? i : b.i;
+}
+
+template <int BLOCK, int PPT, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
   static_assert(PPT <= 32, "class masks are 32-bit");
+  constexpr bool USER = MODE != kSweepLevel;  // input = the caller's arrays, index = position - ibase
   constexpr uint32_t TILE = BLOCK * PPT;
   constexpr int NW = BLOCK / 64;
-  __shared__ uint32_t s_cnt[2][NW];
-  __shared__ uint32_t s_base[2];
+  __shared__ uint32_t s_cnt[4][NW];
+  __shared__ uint32_t s_base[4];
   __shared__ Cand s_cand[2][NW];
+  __shared__ uint32_t s_run[2][NW];
 
-  const uint32_t ntiles = A.st->ntiles;
+  const uint32_t ntiles = uni(A.st->ntiles);
   const uint32_t G = gridDim.x;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 
   uint32_t run_seg = kNone, run_slot = 0;
+  // triangle of the segment (root triangle in the fused pass)
   double ax = 0, ay = 0, rx = 0, ry = 0, bx = 0, by = 0;
   uint32_t beg = 0, cnt = 0, tile0 = 0, ibase = 0, req = 0;
-  Cand b1 = no_cand(), b2 = no_cand();
+  // fused pass: the two children
+  double cax[2] = {0, 0}, cay[2] = {0, 0}, crx[2] = {0, 0}, cry[2] = {0, 0}, cbx[2] = {0, 0}, cby[2] = {0, 0};
+  uint32_t cbeg[2] = {0, 0}, ccnt[2] = {0, 0}, ckind[2] = {kFuseSkip, kFuseSkip}, cslot[2] = {0, 0};
+  Cand b1 = no_cand(), b2 = no_cand(), b3 = no_cand(), b4 = no_cand();
+  uint32_t run1 = 0, run2 = 0;  // argmax pass: subset sizes of the current run (per wave)
   bool bad = false;
 
   for (uint32_t k = blockIdx.x; k < ntiles; k += G) {
     const uint32_t t = A.reverse ? ntiles - 1u - k : k;
-    const uint32_t s = A.tile_seg[t];
+    const uint32_t s = uni(A.tile_seg[t]);
     if (s != run_seg) {
-      if (run_seg != kNone) flush_run<NW>(A.part, run_slot, b1, b2, s_cand);
-      const Seg* sg = A.seg + s;
-      ax = sg->ax;
-      ay = sg->ay;
-      rx = sg->rx;
-      ry = sg->ry;
-      bx = sg->bx;
-      by = sg->by;
-      beg = sg->beg;
-      cnt = sg->cnt;
-      tile0 = sg->tile0;
-      ibase = sg->ibase;
-      req = sg->req;
+      if (run_seg != kNone) {
+        if constexpr (MODE == kSweepFused) {
+          flush_run<NW>(A.part, run_slot, b1, b2, s_cand);
+          flush_run<NW>(A.part2, run_slot, b3, b4, s_cand);
+        } else {
+          flush_run<NW>(A.part, run_slot, b1, b2, s_cand);
+        }
+        if constexpr (MODE == kSweepArgmax) {
+          if (lane == 0) {
+            s_run[0][w] = run1;
+            s_run[1][w] = run2;
+          }
+          __syncthreads();
+          if (tid == 0) {
+            uint32_t t1 = 0, t2 = 0;
+            for (int i = 0; i < NW; ++i) {
+              t1 += s_run[0][i];
+              t2 += s_run[1][i];
+            }
+            if (t1 | t2) atomicAdd(A.ctr + run_seg, ((unsigned long long)t2 << 32) | (unsigned long long)t1);
+          }
+          __syncthreads();
+          run1 = run2 = 0;
+        }
+      }
+      if constexpr (MODE == kSweepFused) {
+        const FusedRoot* fr = A.fr + s;
+        ax = uni(fr->px);
+        ay = uni(fr->py);
+        rx = uni(fr->qx);
+        ry = uni(fr->qy);
+        bx = ax;
+        by = ay;
+        beg = uni(fr->off);
+        cnt = uni(fr->n);
+        tile0 = uni(fr->tile0);
+        ibase = beg;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          cax[c] = uni(fr->ax[c]);
+          cay[c] = uni(fr->ay[c]);
+          crx[c] = uni(fr->rx[c]);
+          cry[c] = uni(fr->ry[c]);
+          cbx[c] = uni(fr->bx[c]);
+          cby[c] = uni(fr->by[c]);
+          cbeg[c] = uni(fr->beg[c]);
+          ccnt[c] = uni(fr->cnt[c]);
+          ckind[c] = uni(fr->kind[c]);
+          cslot[c] = uni(fr->slot[c]);
+        }
+      } else {
+        const Seg* sg = A.seg + s;
+        ax = uni(sg->ax);
+        ay = uni(sg->ay);
+        rx = uni(sg->rx);
+        ry = uni(sg->ry);
+        bx = uni(sg->bx);
+        by = uni(sg->by);
+        beg = uni(sg->beg);
+        cnt = uni(sg->cnt);
+        tile0 = uni(sg->tile0);
+        ibase = uni(sg->ibase);
+        req = uni(sg->req);
+      }
       run_seg = s;
       run_slot = tile0 + (t - tile0) % G;
-      b1 = no_cand();
-      b2 = no_cand();
+      b1 = b2 = b3 = b4 = no_cand();
     }
     const uint32_t lo = beg + (t - tile0) * TILE;
     const uint32_t hi = min(beg + cnt, lo + TILE);
@@ -279,89 +497,109 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
       const bool ok = pos < hi;
       px[v] = ok ? __builtin_nontemporal_load(A.ix + pos) : 0.0;
       py[v] = ok ? __builtin_nontemporal_load(A.iy + pos) : 0.0;
-      if constexpr (L0) {
+      if constexpr (USER) {
         pi[v] = pos - ibase;
       } else {
         pi[v] = ok ? __builtin_nontemporal_load(A.ii + pos) : 0u;
       }
     }
 
-    uint32_t m1 = 0, m2 = 0;
+    if constexpr (MODE != kSweepFused) {
+      uint32_t m1 = 0, m2 = 0;
 #pragma unroll
-    for (int v = 0; v < PPT; ++v) {
-      const uint32_t pos = lo + v * BLOCK + tid;
-      const bool ok = pos < hi;
-      const double o1 = orient(ax, ay, rx, ry, px[v], py[v]);
-      const double o2 = orient(rx, ry, bx, by, px[v], py[v]);
-      const bool in1 = ok && (o1 > 0.0);
-      const bool in2 = ok && !in1 && (o2 > 0.0);
-      m1 |= (uint32_t)in1 << v;
-      m2 |= (uint32_t)in2 << v;
-      if (in1 && better(o1, px[v], py[v], pi[v], b1)) {
-        b1.k = o1;
-        b1.x = px[v];
-        b1.y = py[v];
-        b1.i = pi[v];
+      for (int v = 0; v < PPT; ++v) {
+        const uint32_t pos = lo + v * BLOCK + tid;
+        const bool ok = pos < hi;
+        const double o1 = orient(ax, ay, rx, ry, px[v], py[v]);
+        // On the root triangle (p, q, p), orient(q, p, u) is exactly
+        // -orient(p, q, u): the same two rounded products, subtracted the
+        // other way round.
+        const double o2 = MODE == kSweepArgmax ? -o1 : orient(rx, ry, bx, by, px[v], py[v]);
+        const bool in1 = ok && (o1 > 0.0);
+        const bool in2 = ok && !in1 && (o2 > 0.0);
+        m1 |= (uint32_t)in1 << v;
+        m2 |= (uint32_t)in2 << v;
+        if (in1) take(b1, o1, px[v], py[v], pi[v]);
+        if (in2) take(b2, o2, px[v], py[v], pi[v]);
+        if constexpr (MODE == kSweepArgmax) bad |= ok && !finite(py[v]);
       }
-      if (in2 && better(o2, px[v], py[v], pi[v], b2)) {
-        b2.k = o2;
-        b2.x = px[v];
-        b2.y = py[v];
-        b2.i = pi[v];
-      }
-      if constexpr (L0) bad |= ok && !finite(py[v]);
-    }
-
-    uint32_t c1 = 0, c2 = 0;
+      if constexpr (MODE == kSweepArgmax) {
 #pragma unroll
-    for (int v = 0; v < PPT; ++v) {
-      c1 += __popcll(__ballot((m1 >> v) & 1u));
-      c2 += __popcll(__ballot((m2 >> v) & 1u));
-    }
-    if (lane == 0) {
-      s_cnt[0][w] = c1;
-      s_cnt[1][w] = c2;
-    }
-    if constexpr (L0) {
-      if (__ballot(bad) && lane == 0) A.req[req].err = 1u;
-      bad = false;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      uint32_t t1 = 0, t2 = 0;
-#pragma unroll
-      for (int i = 0; i < NW; ++i) {
-        const uint32_t a = s_cnt[0][i], b = s_cnt[1][i];
-        s_cnt[0][i] = t1;
-        s_cnt[1][i] = t2;
-        t1 += a;
-        t2 += b;
+        for (int v = 0; v < PPT; ++v) {
+          run1 += (uint32_t)__popcll(__ballot((m1 >> v) & 1u));
+          run2 += (uint32_t)__popcll(__ballot((m2 >> v) & 1u));
+        }
+        if (__ballot(bad) && lane == 0) A.req[req].err = 1u;
+        bad = false;
+      } else {
+        write_pair<BLOCK, PPT, NW>(m1, m2, beg, cnt, A.ctr + s, px, py, pi, A.ox, A.oy, A.oi, s_cnt, s_base);
       }
-      unsigned long long old = 0ull;
-      if (t1 | t2) old = atomicAdd(A.ctr + s, ((unsigned long long)t2 << 32) | (unsigned long long)t1);
-      s_base[0] = beg + (uint32_t)old;
-      s_base[1] = beg + cnt - (uint32_t)(old >> 32) - t2;
-    }
-    __syncthreads();
-    uint32_t o1p = s_base[0] + s_cnt[0][w];
-    uint32_t o2p = s_base[1] + s_cnt[1][w];
+    } else {
+      // fused: side of the root triangle, then the child's own split (or a copy)
+      uint32_t side0 = 0, side1 = 0;
 #pragma unroll
-    for (int v = 0; v < PPT; ++v) {
-      const bool in1 = (m1 >> v) & 1u, in2 = (m2 >> v) & 1u;
-      const unsigned long long q1 = __ballot(in1), q2 = __ballot(in2);
-      if (in1 | in2) {
-        const uint32_t dst = in1 ? o1p + lane_rank(q1) : o2p + lane_rank(q2);
-        A.ox[dst] = px[v];  // plain stores: the L2 merges the partial lines of
-        A.oy[dst] = py[v];  // neighbouring runs before they reach HBM
-        A.oi[dst] = pi[v];
+      for (int v = 0; v < PPT; ++v) {
+        const uint32_t pos = lo + v * BLOCK + tid;
+        const bool ok = pos < hi;
+        const double o1 = orient(ax, ay, rx, ry, px[v], py[v]);  // root triangle (p, q, p): o2 = -o1
+        side0 |= (uint32_t)(ok && (o1 > 0.0)) << v;
+        side1 |= (uint32_t)(ok && (o1 < 0.0)) << v;
       }
-      o1p += (uint32_t)__popcll(q1);
-      o2p += (uint32_t)__popcll(q2);
+      uint32_t mL[2] = {0, 0}, mR[2] = {0, 0};
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const uint32_t in = c ? side1 : side0;
+        if (ckind[c] == kFuseCopy) {  // uniform branch: the kinds come from the root
+          mL[c] = in;
+        } else if (ckind[c] == kFuseSplit) {
+          const double qax = cax[c], qay = cay[c], qrx = crx[c], qry = cry[c], qbx = cbx[c], qby = cby[c];
+          Cand& bl = c ? b3 : b1;
+          Cand& br = c ? b4 : b2;
+#pragma unroll
+          for (int v = 0; v < PPT; ++v) {
+            if (!((in >> v) & 1u)) continue;
+            const double e1 = orient(qax, qay, qrx, qry, px[v], py[v]);
+            if (e1 > 0.0) {
+              mL[c] |= 1u << v;
+              take(bl, e1, px[v], py[v], pi[v]);
+            } else {
+              const double e2 = orient(qrx, qry, qbx, qby, px[v], py[v]);
+              if (e2 > 0.0) {
+                mR[c] |= 1u << v;
+                take(br, e2, px[v], py[v], pi[v]);
+              }
+            }
+          }
+        }
+      }
+      unsigned long long* c0 = ckind[0] == kFuseSplit ? A.ctr + cslot[0] : A.jctr + cslot[0];
+      unsigned long long* c1 = ckind[1] == kFuseSplit ? A.ctr + cslot[1] : A.jctr + cslot[1];
+      write_quad<BLOCK, PPT, NW>(mL, mR, cbeg, ccnt, c0, c1, px, py, pi, A.ox, A.oy, A.oi, s_cnt, s_base);
     }
-    // s_cnt / s_base are rewritten only after the next tile's first barrier,
-    // which every thread reaches after finishing these reads.
   }
-  if (run_seg != kNone) flush_run<NW>(A.part, run_slot, b1, b2, s_cand);
+  if (run_seg != kNone) {
+    if constexpr (MODE == kSweepFused) {
+      flush_run<NW>(A.part, run_slot, b1, b2, s_cand);
+      flush_run<NW>(A.part2, run_slot, b3, b4, s_cand);
+    } else {
+      flush_run<NW>(A.part, run_slot, b1, b2, s_cand);
+    }
+    if constexpr (MODE == kSweepArgmax) {
+      if (lane == 0) {
+        s_run[0][w] = run1;
+        s_run[1][w] = run2;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t t1 = 0, t2 = 0;
+        for (int i = 0; i < NW; ++i) {
+          t1 += s_run[0][i];
+          t2 += s_run[1][i];
+        }
+        if (t1 | t2) atomicAdd(A.ctr + run_seg, ((unsigned long long)t2 << 32) | (unsigned long long)t1);
+      }
+    }
+  }
 }
 
 // --------------------------------------------------------- block utilities
@@ -412,7 +650,7 @@ __device__ __forceinline__ Cand block_best(Cand c, Cand* s_c) {
   __syncthreads();
   Cand r = s_c[0];
   for (int i = 1; i < NW; ++i)
-    if (better(s_c[i], r)) r = s_c[i];
+    keep(r, s_c[i]);
   __syncthreads();
   return r;
 }
@@ -460,14 +698,14 @@ struct EmitBase {
 };
 
 __device__ __forceinline__ EmitBase emit_scan(const uint32_t (&kind)[2], const uint32_t (&cnt)[2], uint32_t tile,
-                                              PlanShared& S, uint32_t (&tot)[4]) {
+                                              PlanShared& S, uint32_t (&tot)[4], bool virt = false) {
   uint32_t v[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     v[0] += kind[k] != kKindNone;
     v[1] += kind[k] == kKindJob;
     v[2] += kind[k] == kKindSeg;
-    v[3] += kind[k] == kKindSeg ? ceil_div(cnt[k], tile) : 0u;
+    v[3] += (kind[k] == kKindSeg && !virt) ? ceil_div(cnt[k], tile) : 0u;
   }
   uint32_t ex[4];
   block_scan<kPlanBlock, 4>(v, ex, tot, S.scan);
@@ -475,11 +713,19 @@ __device__ __forceinline__ EmitBase emit_scan(const uint32_t (&kind)[2], const u
 }
 
 // Write one child (node, job or segment); advances the running offsets in e.
+// A virtual segment (fused pass) gets no tiles: its candidates are written by
+// the fused pass into the record slots of its root (vrec0, vrtiles, side).
+struct Virt {
+  bool on;
+  uint32_t rec0, rtiles;
+  unsigned long long* jctr_out;
+};
+
 __device__ __forceinline__ int32_t emit_one(uint32_t kind, const Tri& tr, uint32_t ri, uint32_t beg, uint32_t cnt,
                                             uint32_t req, int32_t parent, uint32_t side, uint32_t src,
                                             uint32_t node_base, uint32_t tile, EmitBase& e, Node* nodes, Job* jobs,
                                             Seg* seg_out, unsigned long long* ctr_out, uint32_t* tile_seg_out,
-                                            PlanShared& S) {
+                                            PlanShared& S, const Virt& vt, uint32_t* index_out) {
   int32_t nid = -1;
   if (kind != kKindNone) {
     nid = (int32_t)(node_base + e.node++);
@@ -511,13 +757,38 @@ __device__ __forceinline__ int32_t emit_one(uint32_t kind, const Tri& tr, uint32
     j.node = nid;
     j.ibase = src == kSrcUser ? beg : 0u;
     j.pad = 0;
-    jobs[e.job++] = j;
+    const uint32_t jid = e.job++;
+    jobs[jid] = j;
+    if (vt.on) vt.jctr_out[jid] = 0ull;
+    *index_out = jid;
     atomicAdd(&S.jobpts, cnt);
+  } else if (kind == kKindSeg && vt.on) {
+    const uint32_t sid = e.seg++;
+    Seg sg;
+    sg.ax = tr.ax;
+    sg.ay = tr.ay;
+    sg.rx = tr.rx;
+    sg.ry = tr.ry;
+    sg.bx = tr.bx;
+    sg.by = tr.by;
+    sg.beg = beg;
+    sg.cnt = cnt;
+    sg.tile0 = vt.rec0;
+    sg.req = req;
+    sg.node = nid;
+    sg.ibase = 0u;
+    sg.rtiles = vt.rtiles;
+    sg.rside = side;
+    seg_out[sid] = sg;
+    ctr_out[sid] = 0ull;
+    *index_out = sid;
+    atomicAdd(&S.swept, cnt);
   } else if (kind == kKindSeg) {
     const uint32_t sid = e.seg++;
     const uint32_t nt = ceil_div(cnt, tile);
     const uint32_t t0 = e.tile;
     e.tile += nt;
+    *index_out = sid;
     Seg sg;
     sg.ax = tr.ax;
     sg.ay = tr.ay;
@@ -531,6 +802,8 @@ __device__ __forceinline__ int32_t emit_one(uint32_t kind, const Tri& tr, uint32
     sg.req = req;
     sg.node = nid;
     sg.ibase = src == kSrcUser ? beg : 0u;
+    sg.rtiles = 0u;
+    sg.rside = 0u;
     seg_out[sid] = sg;
     ctr_out[sid] = 0ull;
     atomicAdd(&S.swept, cnt);
@@ -714,8 +987,10 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
       int32_t nid = -1;
       if (rq.n > 0) {
         const Tri tr{e.mnx, e.mny, e.mxx, e.mxy, e.mnx, e.mny};
+        const Virt nov{false, 0u, 0u, nullptr};
+        uint32_t idx = 0;
         nid = emit_one(kind[0], tr, e.mxi, rq.off, rq.n, i, -1, 0, kSrcUser, 0u, A.tile, eb, A.nodes, A.jobs,
-                       A.seg_out, A.ctr_out, A.tile_seg_out, S);
+                       A.seg_out, A.ctr_out, A.tile_seg_out, S, nov, &idx);
       }
       A.req[i].p = rq.n > 0 ? e.mni : 0u;
       A.req[i].q = rq.n > 0 ? e.mxi : 0u;
@@ -754,12 +1029,14 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
       n2 = (uint32_t)(c >> 32);
       atomicAdd(&S.survivors, n1 + n2);
       tile0 = A.seg[s].tile0;
-      nrec = min(G, ceil_div(A.seg[s].cnt, A.tile));
+      const uint32_t rt = A.seg[s].rtiles;
+      nrec = min(G, rt ? rt : ceil_div(A.seg[s].cnt, A.tile));
+      const TilePart* part = A.seg[s].rside ? A.part2 : A.part;
       if (nrec <= kSerialRecs) {
         for (uint32_t k = 0; k < nrec; ++k) {
-          const TilePart& p = A.part[tile0 + k];
-          if (better(p.c[0], r1)) r1 = p.c[0];
-          if (better(p.c[1], r2)) r2 = p.c[1];
+          const TilePart& p = part[tile0 + k];
+          keep(r1, p.c[0]);
+          keep(r2, p.c[1]);
         }
       } else {
         big = true;
@@ -770,14 +1047,16 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
     const uint32_t nbig = S.nbig;
     for (uint32_t b = w; b < nbig; b += kPlanWaves) {  // one wave per big segment
       const uint32_t owner = S.big[b];
-      const uint32_t t0 = A.seg[base + owner].tile0;
-      const uint32_t nr = min(G, ceil_div(A.seg[base + owner].cnt, A.tile));
+      const Seg& so = A.seg[base + owner];
+      const uint32_t t0 = so.tile0;
+      const uint32_t nr = min(G, so.rtiles ? so.rtiles : ceil_div(so.cnt, A.tile));
+      const TilePart* part = so.rside ? A.part2 : A.part;
       if (nr > kWaveRecs) continue;
       Cand m1 = no_cand(), m2 = no_cand();
       for (uint32_t k = lane; k < nr; k += 64) {
-        const TilePart& p = A.part[t0 + k];
-        if (better(p.c[0], m1)) m1 = p.c[0];
-        if (better(p.c[1], m2)) m2 = p.c[1];
+        const TilePart& p = part[t0 + k];
+        keep(m1, p.c[0]);
+        keep(m2, p.c[1]);
       }
       wave_best(m1);
       wave_best(m2);
@@ -788,14 +1067,16 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
     }
     for (uint32_t b = 0; b < nbig; ++b) {  // the whole workgroup per huge segment
       const uint32_t owner = S.big[b];
-      const uint32_t t0 = A.seg[base + owner].tile0;
-      const uint32_t nr = min(G, ceil_div(A.seg[base + owner].cnt, A.tile));
+      const Seg& so = A.seg[base + owner];
+      const uint32_t t0 = so.tile0;
+      const uint32_t nr = min(G, so.rtiles ? so.rtiles : ceil_div(so.cnt, A.tile));
+      const TilePart* part = so.rside ? A.part2 : A.part;
       if (nr <= kWaveRecs) continue;
       Cand m1 = no_cand(), m2 = no_cand();
       for (uint32_t k = tid; k < nr; k += kPlanBlock) {
-        const TilePart& p = A.part[t0 + k];
-        if (better(p.c[0], m1)) m1 = p.c[0];
-        if (better(p.c[1], m2)) m2 = p.c[1];
+        const TilePart& p = part[t0 + k];
+        keep(m1, p.c[0]);
+        keep(m2, p.c[1]);
       }
       m1 = block_best<kPlanBlock>(m1, s_c);
       m2 = block_best<kPlanBlock>(m2, s_c);
@@ -815,19 +1096,53 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
       kind[1] = child_kind(n2, A.lds_limit);
     }
     uint32_t tot[4];
-    EmitBase eb = emit_scan(kind, cnt, A.tile, S, tot);
+    EmitBase eb = emit_scan(kind, cnt, A.tile, S, tot, A.fuse != 0);
     if (valid) {
       const Seg sg = A.seg[s];
+      const uint32_t root_tiles = ceil_div(sg.cnt, A.tile);
+      const Virt vt{A.fuse != 0, sg.tile0, root_tiles, A.jctr_out};
       const Tri t1{sg.ax, sg.ay, r1.x, r1.y, sg.rx, sg.ry};
+      uint32_t i1 = 0, i2 = 0;
       emit_one(kind[0], t1, r1.i, sg.beg, n1, sg.req, sg.node, 0, A.out_buf, node_base, A.tile, eb, A.nodes, A.jobs,
-               A.seg_out, A.ctr_out, A.tile_seg_out, S);
+               A.seg_out, A.ctr_out, A.tile_seg_out, S, vt, &i1);
       const Tri t2{sg.rx, sg.ry, r2.x, r2.y, sg.bx, sg.by};
       emit_one(kind[1], t2, r2.i, sg.beg + sg.cnt - n2, n2, sg.req, sg.node, 1, A.out_buf, node_base, A.tile, eb,
-               A.nodes, A.jobs, A.seg_out, A.ctr_out, A.tile_seg_out, S);
+               A.nodes, A.jobs, A.seg_out, A.ctr_out, A.tile_seg_out, S, vt, &i2);
+      if (A.fuse) {
+        FusedRoot f;
+        f.px = sg.ax;
+        f.py = sg.ay;
+        f.qx = sg.rx;
+        f.qy = sg.ry;
+        const Tri* tt[2] = {&t1, &t2};
+        const uint32_t idx[2] = {i1, i2};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          f.ax[c] = tt[c]->ax;
+          f.ay[c] = tt[c]->ay;
+          f.rx[c] = tt[c]->rx;
+          f.ry[c] = tt[c]->ry;
+          f.bx[c] = tt[c]->bx;
+          f.by[c] = tt[c]->by;
+          f.kind[c] = kind[c] == kKindSeg ? kFuseSplit : kind[c] == kKindJob ? kFuseCopy : kFuseSkip;
+          f.slot[c] = idx[c];
+        }
+        f.beg[0] = sg.beg;
+        f.cnt[0] = n1;
+        f.beg[1] = sg.beg + sg.cnt - n2;
+        f.cnt[1] = n2;
+        f.off = sg.beg;
+        f.n = sg.cnt;
+        f.tile0 = sg.tile0;
+        f.req = sg.req;
+        A.fr_out[s] = f;
+      }
     }
     emit_finish(tot, A.seg_out, A.tile_seg_out, A.tile, S);
   }
   plan_status(S, A.st_out, node_base);
+  // The fused pass walks the roots' tiles again.
+  if (A.fuse && threadIdx.x == 0) A.st_out->ntiles = A.st_in->ntiles;
 }
 
 // --------------------------------------------------------------- k_finish
@@ -1014,13 +1329,13 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
       for (uint32_t e = 0; e < n; ++e) {
         const uint32_t l = S.ord[cb ^ 1][b0 + e] & 0xFFFFu;
         const double kk = orient(ex0, ey0, ex1, ey1, S.lx[l], S.ly[l]);
-        if (better(kk, S.lx[l], S.ly[l], S.lid[l], best)) {
-          best.k = kk;
-          best.x = S.lx[l];
-          best.y = S.ly[l];
-          best.i = S.lid[l];
-          best.pad = l;
-        }
+        Cand o;
+        o.k = kk;
+        o.x = S.lx[l];
+        o.y = S.ly[l];
+        o.i = S.lid[l];
+        o.pad = l;
+        keep(best, o);
       }
       S.cwin[c] = (uint16_t)best.pad;
     }
@@ -1037,13 +1352,13 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
       for (uint32_t e = lane; e < n; e += 64) {
         const uint32_t l = S.ord[cb ^ 1][b0 + e] & 0xFFFFu;
         const double kk = orient(ex0, ey0, ex1, ey1, S.lx[l], S.ly[l]);
-        if (better(kk, S.lx[l], S.ly[l], S.lid[l], best)) {
-          best.k = kk;
-          best.x = S.lx[l];
-          best.y = S.ly[l];
-          best.i = S.lid[l];
-          best.pad = l;
-        }
+        Cand o;
+        o.k = kk;
+        o.x = S.lx[l];
+        o.y = S.ly[l];
+        o.i = S.lid[l];
+        o.pad = l;
+        keep(best, o);
       }
       wave_best(best);  // pad carries the winner's local id
       if (lane == 0) S.cwin[c] = (uint16_t)best.pad;
@@ -1211,19 +1526,21 @@ __global__ __launch_bounds__(256) void k_stream_scale(const double* __restrict__
 
 namespace {
 template <int BLOCK, int PPT>
-int sweep_one(const SweepArgs& a, bool level0, uint32_t grid, hipStream_t st) {
-  if (level0) {
-    hipLaunchKernelGGL((k_sweep<BLOCK, PPT, true>), dim3(grid), dim3(BLOCK), 0, st, a);
+int sweep_one(const SweepArgs& a, int mode, uint32_t grid, hipStream_t st) {
+  if (mode == kSweepArgmax) {
+    hipLaunchKernelGGL((k_sweep<BLOCK, PPT, kSweepArgmax>), dim3(grid), dim3(BLOCK), 0, st, a);
+  } else if (mode == kSweepFused) {
+    hipLaunchKernelGGL((k_sweep<BLOCK, PPT, kSweepFused>), dim3(grid), dim3(BLOCK), 0, st, a);
   } else {
-    hipLaunchKernelGGL((k_sweep<BLOCK, PPT, false>), dim3(grid), dim3(BLOCK), 0, st, a);
+    hipLaunchKernelGGL((k_sweep<BLOCK, PPT, kSweepLevel>), dim3(grid), dim3(BLOCK), 0, st, a);
   }
   return (int)hipGetLastError();
 }
 
-template <int BLOCK, int PPT>
+template <int BLOCK, int PPT, int MODE>
 uint32_t sweep_occupancy_grid() {
   int per_cu = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_sweep<BLOCK, PPT, false>, BLOCK, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_sweep<BLOCK, PPT, MODE>, BLOCK, 0) !=
           hipSuccess ||
       per_cu < 1)
     per_cu = 1;
@@ -1274,17 +1591,23 @@ bool sweep_shape_supported(int block, int ppt) {
          (block == 1024 && ppt == 8);
 }
 
-uint32_t sweep_grid(int block, int ppt) {
-  static uint32_t cache[5] = {0, 0, 0, 0, 0};
+uint32_t sweep_grid(int block, int ppt, int mode) {
+  static uint32_t cache[5][3] = {};
   const int k = block == 256 ? (ppt == 16 ? 0 : 1) : block == 512 ? (ppt == 8 ? 2 : 3) : 4;
-  if (!cache[k]) {
-    if (k == 0) cache[k] = sweep_occupancy_grid<256, 16>();
-    if (k == 1) cache[k] = sweep_occupancy_grid<256, 32>();
-    if (k == 2) cache[k] = sweep_occupancy_grid<512, 8>();
-    if (k == 3) cache[k] = sweep_occupancy_grid<512, 16>();
-    if (k == 4) cache[k] = sweep_occupancy_grid<1024, 8>();
+  if (!cache[k][mode]) {
+#define VQH_GRID(K, B, P)                                                          \
+  if (k == K)                                                                      \
+    cache[k][mode] = mode == kSweepArgmax  ? sweep_occupancy_grid<B, P, kSweepArgmax>() \
+                     : mode == kSweepFused ? sweep_occupancy_grid<B, P, kSweepFused>()  \
+                                           : sweep_occupancy_grid<B, P, kSweepLevel>();
+    VQH_GRID(0, 256, 16)
+    VQH_GRID(1, 256, 32)
+    VQH_GRID(2, 512, 8)
+    VQH_GRID(3, 512, 16)
+    VQH_GRID(4, 1024, 8)
+#undef VQH_GRID
   }
-  return cache[k];
+  return cache[k][mode];
 }
 
 int finish_tmax_for(int lds_limit) { return lds_limit <= 512 ? 512 : lds_limit <= 1024 ? 1024 : 2048; }
@@ -1306,13 +1629,13 @@ int launch_extremes(const ExtremesArgs& a, void* stream) {
   return (int)hipGetLastError();
 }
 
-int launch_sweep(const SweepArgs& a, bool level0, int block, int ppt, uint32_t grid, void* stream) {
+int launch_sweep(const SweepArgs& a, int mode, int block, int ppt, uint32_t grid, void* stream) {
   hipStream_t st = (hipStream_t)stream;
-  if (block == 256 && ppt == 16) return sweep_one<256, 16>(a, level0, grid, st);
-  if (block == 256 && ppt == 32) return sweep_one<256, 32>(a, level0, grid, st);
-  if (block == 512 && ppt == 8) return sweep_one<512, 8>(a, level0, grid, st);
-  if (block == 512 && ppt == 16) return sweep_one<512, 16>(a, level0, grid, st);
-  if (block == 1024 && ppt == 8) return sweep_one<1024, 8>(a, level0, grid, st);
+  if (block == 256 && ppt == 16) return sweep_one<256, 16>(a, mode, grid, st);
+  if (block == 256 && ppt == 32) return sweep_one<256, 32>(a, mode, grid, st);
+  if (block == 512 && ppt == 8) return sweep_one<512, 8>(a, mode, grid, st);
+  if (block == 512 && ppt == 16) return sweep_one<512, 16>(a, mode, grid, st);
+  if (block == 1024 && ppt == 8) return sweep_one<1024, 8>(a, mode, grid, st);
   return (int)hipErrorInvalidValue;
 }
 

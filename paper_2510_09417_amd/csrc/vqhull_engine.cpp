@@ -476,14 +476,14 @@ void run(const double* x, const double* y, const int64_t* offsets, int64_t nreq,
   const size_t max_tiles = N / tile + max_seg + 2;
   for (int k = 0; k < 2; ++k) {
     ensure(w.seg[k], max_seg, st);
-    ensure(w.ctr[k], max_seg, st);
+    ensure(w.ctr[k], max_seg * kCtrStride, st);
     ensure(w.tile_seg[k], max_tiles, st);
   }
   ensure(w.part, max_tiles, st);
   ensure(w.part2, max_tiles, st);
   ensure(w.fr, max_seg, st);
   ensure(w.jobs, 2 * max_seg + (size_t)nreq, st);
-  ensure(w.jctr, 2 * max_seg + (size_t)nreq, st);
+  ensure(w.jctr, (2 * max_seg + (size_t)nreq) * kCtrStride, st);
   ensure(w.nodes, std::max<size_t>(3 * (size_t)nreq + 64, 4096), st);
 
   for (int attempt = 0;; ++attempt) {

@@ -53,8 +53,8 @@ struct Seg {
 enum : uint32_t { kFuseSkip = 0, kFuseSplit = 1, kFuseCopy = 2 };
 
 struct FusedRoot {
-  double px, py, qx, qy;  // the root triangle (p, q, p)
-  double ax[2], ay[2], rx[2], ry[2], bx[2], by[2];  // child triangles, side 0 = S1, side 1 = S2
+  double px, py, qx, qy;  // the root's extreme points p and q
+  double rx[2], ry[2];    // farthest point of each child: child 0 = (p, r1, q) holds S1, child 1 = (q, r2, p) S2
   uint32_t beg[2], cnt[2];  // child ranges in the output buffer
   uint32_t kind[2];         // kFuse*
   uint32_t slot[2];         // kFuseSplit: next-level segment id; kFuseCopy: job id
@@ -116,6 +116,10 @@ struct Status {
 };
 
 constexpr int kStatusRing = 4;
+// Segment and job counters (packed S1 | S2 << 32 reservations) sit one
+// 128-byte line apart: the device-scope atomics of one line are serialised,
+// and the two children of a segment take theirs from every tile.
+constexpr size_t kCtrStride = 16;
 
 // ----------------------------------------------------------------- launchers
 struct Workspace;  // host side

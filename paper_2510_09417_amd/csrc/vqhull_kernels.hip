@@ -222,149 +222,126 @@ __global__ __launch_bounds__(BLOCK) void k_extremes(ExtremesArgs A) {
 // consecutive points of one segment each) with stride gridDim.x; the tile
 // count comes from the level's status record.  Per tile, each thread loads PPT
 // points (striped so that every wave load covers consecutive addresses, with
-// non-temporal hints: the data is streamed once), classifies them against the
-// segment's triangle (a, r, b), and keeps the farthest point of each side.
-// Wave ballots give per-wave subset sizes; one packed 64-bit atomic per tile
-// reserves room at the left end (S1) and at the right end (S2) of the
-// segment's output range; every wave then writes its survivors as contiguous
-// runs.  The order of points inside a subset is irrelevant to the result.
-// Farthest-point candidates are kept per thread across the consecutive tiles
-// a workgroup visits in one segment and written once per such run.
+// non-temporal hints: the data is streamed once), classifies them, and keeps
+// the farthest point of each output subset.  Per-lane bit masks record the
+// subset of every point; their population counts, summed over the wave, give
+// the per-wave subset sizes; one packed 64-bit atomic per output range and
+// tile reserves room at the range's left end (first subset) and right end
+// (second subset); every wave then writes its survivors as contiguous runs
+// (ballot ranks).  The order of points inside a subset is irrelevant to the
+// result.  Farthest-point candidates are kept per thread across the
+// consecutive tiles a workgroup visits in one segment and written once per
+// such run.
+//
+// The orientation values of one point share their coordinate differences:
+// orient(a, b, u) = (a.x - u.x) * (b.y - u.y) - (a.y - u.y) * (b.x - u.x), so
+// a - u, b - u and r - u are formed once and every predicate is the same two
+// rounded products and one rounded difference as the formula evaluated alone.
 //
 // Modes:
-//   kSweepLevel   one recursion level over the workspace (x, y, index).
+//   kSweepLevel   one recursion level over the workspace (x, y, index), each
+//                 segment against its triangle (a, r, b): S1 = left of a->r,
+//                 S2 = left of r->b and not in S1 (Algorithm 1's partition).
 //   kSweepArgmax  the top level over the caller's arrays, without writing any
-//                 point: only the sizes and farthest points of S1 and S2.
+//                 point: only the sizes and farthest points of S1 = left of
+//                 p->q and S2 = left of q->p (orient(q, p, u) is exactly
+//                 -orient(p, q, u)).
 //   kSweepFused   the caller's arrays again: each point is classified against
-//                 the root triangle (p, q, p) and then against the triangle of
-//                 the child it falls in, so the top level's subsets are never
-//                 written or read back.  Children small enough for the LDS
-//                 finisher are copied instead (pass-through).
+//                 p->q and then against the triangle of the child it falls in,
+//                 (p, r1, q) or (q, r2, p), so the top level's subsets are
+//                 never written or read back.  Children small enough for the
+//                 LDS finisher are copied instead (pass-through).
 
-// Write-run reservation and output for one "stream pair" (left-growing L and
-// right-growing R block of a range [beg, beg + cnt)).
-template <int BLOCK, int PPT, int NW>
-__device__ __forceinline__ void write_pair(uint32_t mL, uint32_t mR, uint32_t beg, uint32_t cnt,
-                                           unsigned long long* ctr, const double (&px)[PPT],
-                                           const double (&py)[PPT], const uint32_t (&pi)[PPT], double* ox,
-                                           double* oy, uint32_t* oi, uint32_t (*s_cnt)[NW], uint32_t* s_base) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  uint32_t c1 = 0, c2 = 0;
-#pragma unroll
-  for (int v = 0; v < PPT; ++v) {
-    c1 += __popcll(__ballot((mL >> v) & 1u));
-    c2 += __popcll(__ballot((mR >> v) & 1u));
-  }
-  if (lane == 0) {
-    s_cnt[0][w] = c1;
-    s_cnt[1][w] = c2;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t t1 = 0, t2 = 0;
-#pragma unroll
-    for (int i = 0; i < NW; ++i) {
-      const uint32_t a = s_cnt[0][i], b = s_cnt[1][i];
-      s_cnt[0][i] = t1;
-      s_cnt[1][i] = t2;
-      t1 += a;
-      t2 += b;
-    }
-    unsigned long long old = 0ull;
-    if (t1 | t2) old = atomicAdd(ctr, ((unsigned long long)t2 << 32) | (unsigned long long)t1);
-    s_base[0] = beg + (uint32_t)old;
-    s_base[1] = beg + cnt - (uint32_t)(old >> 32) - t2;
-  }
-  __syncthreads();
-  uint32_t o1p = s_base[0] + s_cnt[0][w];
-  uint32_t o2p = s_base[1] + s_cnt[1][w];
-#pragma unroll
-  for (int v = 0; v < PPT; ++v) {
-    const bool in1 = (mL >> v) & 1u, in2 = (mR >> v) & 1u;
-    const unsigned long long q1 = __ballot(in1), q2 = __ballot(in2);
-    if (in1 | in2) {
-      const uint32_t dst = in1 ? o1p + lane_rank(q1) : o2p + lane_rank(q2);
-      ox[dst] = px[v];  // plain stores: the L2 merges the partial lines of
-      oy[dst] = py[v];  // neighbouring runs before they reach HBM
-      oi[dst] = pi[v];
-    }
-    o1p += (uint32_t)__popcll(q1);
-    o2p += (uint32_t)__popcll(q2);
-  }
-  // s_cnt / s_base are rewritten only after the next first barrier, which
-  // every thread reaches after finishing these reads.
+// Per-thread farthest-point candidate inside a sweep: the key and the position
+// of the point in the level's input arrays.  Coordinates and index are fetched
+// only when a run of tiles is flushed, or when two keys are exactly equal.
+// Members of a subset have keys > 0, so key 0 with position kNone ("none")
+// loses every comparison on the key alone.
+struct Best {
+  double k;
+  uint32_t pos;
+};
+
+__device__ __forceinline__ Best no_best() {
+  Best b;
+  b.k = 0.0;
+  b.pos = kNone;
+  return b;
 }
 
-// Fused pass: one reservation for the four output blocks of a tile (left and
-// right block of each child's range); thread c reserves for child c.
-template <int BLOCK, int PPT, int NW>
-__device__ __forceinline__ void write_quad(const uint32_t (&mL)[2], const uint32_t (&mR)[2], const uint32_t (&beg)[2],
-                                           const uint32_t (&cnt)[2], unsigned long long* ctr0,
-                                           unsigned long long* ctr1, const double (&px)[PPT],
-                                           const double (&py)[PPT], const uint32_t (&pi)[PPT], double* ox,
-                                           double* oy, uint32_t* oi, uint32_t (*s_cnt)[NW], uint32_t* s_base) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  uint32_t c[4] = {0, 0, 0, 0};
+// Ordering of two members with equal keys (the stored one at position b.pos):
+// smaller x, then smaller y, then lower index.  In the caller's arrays the
+// index order is the position order.
+template <bool USER>
+__device__ __forceinline__ bool tie_wins(const SweepArgs& A, double x, double y, uint32_t pos, uint32_t idx,
+                                         uint32_t bpos) {
+  const double bx = A.ix[bpos], by = A.iy[bpos];
+  const uint32_t bi = USER ? bpos : A.ii[bpos];
+  const uint32_t ni = USER ? pos : idx;
+  return (x < bx) | ((x == bx) & ((y < by) | ((y == by) & (ni < bi))));
+}
+
+// Offer NB points (one per candidate slot q, flag in[q], key k[q]) that share
+// the coordinates (x, y) and position pos.  Exact key ties are rare: they take
+// a wave-uniform slow path that fetches the stored candidate's coordinates.
+template <bool USER, int NB>
+__device__ __forceinline__ void offer(Best (&b)[NB], const bool (&in)[NB], const double (&k)[NB], double x, double y,
+                                      uint32_t pos, uint32_t idx, const SweepArgs& A) {
+  bool t[NB], tie[NB];
+  bool any_tie = false;
 #pragma unroll
-  for (int v = 0; v < PPT; ++v) {
-    c[0] += __popcll(__ballot((mL[0] >> v) & 1u));
-    c[1] += __popcll(__ballot((mR[0] >> v) & 1u));
-    c[2] += __popcll(__ballot((mL[1] >> v) & 1u));
-    c[3] += __popcll(__ballot((mR[1] >> v) & 1u));
+  for (int q = 0; q < NB; ++q) {
+    t[q] = in[q] & (k[q] > b[q].k);
+    tie[q] = in[q] & (k[q] == b[q].k);
+    any_tie |= tie[q];
   }
-  if (lane == 0) {
+  if (__builtin_expect(__ballot(any_tie) != 0ull, 0)) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) s_cnt[q][w] = c[q];
+    for (int q = 0; q < NB; ++q)
+      if (tie[q]) t[q] = tie_wins<USER>(A, x, y, pos, idx, b[q].pos);
   }
-  __syncthreads();
-  if (tid < 2) {
-    const int ch = tid;
-    uint32_t t1 = 0, t2 = 0;
 #pragma unroll
-    for (int i = 0; i < NW; ++i) {
-      const uint32_t a = s_cnt[2 * ch][i], b = s_cnt[2 * ch + 1][i];
-      s_cnt[2 * ch][i] = t1;
-      s_cnt[2 * ch + 1][i] = t2;
-      t1 += a;
-      t2 += b;
-    }
-    unsigned long long old = 0ull;
-    if (t1 | t2) old = atomicAdd(ch ? ctr1 : ctr0, ((unsigned long long)t2 << 32) | (unsigned long long)t1);
-    s_base[2 * ch] = beg[ch] + (uint32_t)old;
-    s_base[2 * ch + 1] = beg[ch] + cnt[ch] - (uint32_t)(old >> 32) - t2;
-  }
-  __syncthreads();
-  uint32_t o[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) o[q] = s_base[q] + s_cnt[q][w];
-#pragma unroll
-  for (int v = 0; v < PPT; ++v) {
-    const bool i0 = (mL[0] >> v) & 1u, i1 = (mR[0] >> v) & 1u, i2 = (mL[1] >> v) & 1u, i3 = (mR[1] >> v) & 1u;
-    const unsigned long long q0 = __ballot(i0), q1 = __ballot(i1), q2 = __ballot(i2), q3 = __ballot(i3);
-    if (i0 | i1 | i2 | i3) {
-      const uint32_t dst = i0   ? o[0] + lane_rank(q0)
-                           : i1 ? o[1] + lane_rank(q1)
-                           : i2 ? o[2] + lane_rank(q2)
-                                : o[3] + lane_rank(q3);
-      ox[dst] = px[v];
-      oy[dst] = py[v];
-      oi[dst] = pi[v];
-    }
-    o[0] += (uint32_t)__popcll(q0);
-    o[1] += (uint32_t)__popcll(q1);
-    o[2] += (uint32_t)__popcll(q2);
-    o[3] += (uint32_t)__popcll(q3);
+  for (int q = 0; q < NB; ++q) {
+    b[q].k = t[q] ? k[q] : b[q].k;
+    b[q].pos = t[q] ? pos : b[q].pos;
   }
 }
 
-template <int NW>
-__device__ __forceinline__ void flush_run(TilePart* part, uint32_t slot, Cand b1, Cand b2, Cand (*s_cand)[NW]) {
+template <bool USER>
+__device__ __forceinline__ Cand to_cand(const SweepArgs& A, const Best& b, uint32_t ibase) {
+  Cand c = no_cand();
+  if (b.pos != kNone) {
+    c.k = b.k;
+    c.x = A.ix[b.pos];
+    c.y = A.iy[b.pos];
+    c.i = USER ? b.pos - ibase : A.ii[b.pos];
+  }
+  return c;
+}
+
+// The wave's best candidate.  Only lanes whose key equals the wave's largest
+// key fetch their point (one cache line, not one per lane); several such lanes
+// are ordered by the full tie-break.
+template <bool USER>
+__device__ __forceinline__ Cand wave_cand(const SweepArgs& A, const Best& b, uint32_t ibase) {
+  double kmax = b.k;  // keys are >= 0: no NaN
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) kmax = fmax(kmax, __shfl_xor(kmax, m, 64));
+  Cand c = no_cand();
+  if (b.pos != kNone && b.k == kmax) c = to_cand<USER>(A, b, ibase);
+  wave_best(c);
+  return c;
+}
+
+// Best candidates of a run over the workgroup, written to record slot `slot`.
+template <bool USER, int NW>
+__device__ __forceinline__ void flush_run(const SweepArgs& A, TilePart* part, uint32_t slot, const Best& b1,
+                                          const Best& b2, uint32_t ibase, Cand (*s_cand)[NW]) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  wave_best(b1);
-  wave_best(b2);
+  const Cand c1 = wave_cand<USER>(A, b1, ibase), c2 = wave_cand<USER>(A, b2, ibase);
   if (lane == 0) {
-    s_cand[0][w] = b1;
-    s_cand[1][w] = b2;
+    s_cand[0][w] = c1;
+    s_cand[1][w] = c2;
   }
   __syncthreads();
   if (tid == 0) {
@@ -380,38 +357,147 @@ __device__ __forceinline__ void flush_run(TilePart* part, uint32_t slot, Cand b1
   __syncthreads();
 }
 
-__device__ __forceinline__ void take(Cand& b, double k, double x, double y, uint32_t i) {
-  const bool t = better(k, x, y, i, b);
-  b.k = t ? k : b.k;
-  b.x = t ? x : b.x;
-  b.y = t ? y : b.y;
-  b.i = t ? i : b.i;
+// Sum of a value over the (fully active) wave, returned in a scalar register:
+// an inclusive prefix sum by DPP row shifts 1, 2, 4, 8 (within rows of 16
+// lanes) and row broadcasts of lanes 15 and 31; lane 63 ends with the total.
+// Lanes without a valid source add the zero passed as "old".
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Argmax pass: add a run's subset sizes (per lane) to the segment's counter,
+// one atomic per workgroup.
+template <int NW>
+__device__ __forceinline__ void flush_counts(unsigned long long* ctr, uint32_t run1, uint32_t run2,
+                                             uint32_t (*s_cnt)[NW]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t t1 = wave_sum(run1), t2 = wave_sum(run2);
+  if (lane == 0) {
+    s_cnt[0][w] = t1;
+    s_cnt[1][w] = t2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long a = 0ull, b = 0ull;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      a += s_cnt[0][i];
+      b += s_cnt[1][i];
+    }
+    if (a | b) atomicAdd(ctr, (b << 32) | a);
+  }
+  __syncthreads();
+}
+
+// Reserve room for one tile's survivors and write them.  Stream s goes to the
+// left end (even s) or the right end (odd s) of output range s / 2; thread j
+// reserves range j.  m[s] holds bit v for the thread's v-th point.  Stream
+// sizes per lane are at most 32, so two wave sums share one 32-bit word.
+template <int BLOCK, int PPT, int NS, bool USER>
+__device__ __forceinline__ void write_streams(const uint32_t (&m)[NS], const uint32_t (&beg)[NS / 2],
+                                              const uint32_t (&cnt)[NS / 2], unsigned long long* const (&ctr)[NS / 2],
+                                              const double (&px)[PPT], const double (&py)[PPT],
+                                              const uint32_t (&pi)[PPT], uint32_t idx0, double* ox, double* oy,
+                                              uint32_t* oi, uint32_t (*s_cnt)[BLOCK / 64], uint32_t* s_base) {
+  constexpr int NW = BLOCK / 64;
+  constexpr int NR = NS / 2;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    const uint32_t both = wave_sum((uint32_t)__popc(m[2 * j]) | ((uint32_t)__popc(m[2 * j + 1]) << 16));
+    if (lane == 0) {
+      s_cnt[2 * j][w] = both & 0xFFFFu;
+      s_cnt[2 * j + 1][w] = both >> 16;
+    }
+  }
+  __syncthreads();
+  if (tid < NR) {
+    const int j = tid;
+    uint32_t t1 = 0, t2 = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const uint32_t a = s_cnt[2 * j][i], b = s_cnt[2 * j + 1][i];
+      s_cnt[2 * j][i] = t1;
+      s_cnt[2 * j + 1][i] = t2;
+      t1 += a;
+      t2 += b;
+    }
+    unsigned long long* c = ctr[0];
+    uint32_t b0 = beg[0], n0 = cnt[0];
+    if (NR > 1 && j == 1) {
+      c = ctr[NR - 1];
+      b0 = beg[NR - 1];
+      n0 = cnt[NR - 1];
+    }
+    unsigned long long old = 0ull;
+    if (t1 | t2) old = atomicAdd(c, ((unsigned long long)t2 << 32) | (unsigned long long)t1);
+    s_base[2 * j] = b0 + (uint32_t)old;
+    s_base[2 * j + 1] = b0 + n0 - (uint32_t)(old >> 32) - t2;
+  }
+  __syncthreads();
+  uint32_t o[NS];  // per-wave write offsets (uniform: scalar registers)
+#pragma unroll
+  for (int s = 0; s < NS; ++s) o[s] = uni(s_base[s] + s_cnt[s][w]);
+#pragma unroll
+  for (int v = 0; v < PPT; ++v) {
+    bool in[NS];
+    unsigned long long bal[NS];
+    bool any = false;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      in[s] = (m[s] >> v) & 1u;
+      bal[s] = __ballot(in[s]);
+      any |= in[s];
+    }
+    if (any) {
+      uint32_t dst = o[NS - 1] + lane_rank(bal[NS - 1]);
+#pragma unroll
+      for (int s = NS - 2; s >= 0; --s) dst = in[s] ? o[s] + lane_rank(bal[s]) : dst;
+      ox[dst] = px[v];  // plain stores: the L2 merges the partial lines of
+      oy[dst] = py[v];  // neighbouring runs before they reach HBM
+      oi[dst] = USER ? idx0 + (uint32_t)(v * BLOCK) : pi[v];
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) o[s] += (uint32_t)__popcll(bal[s]);
+  }
+  // s_cnt / s_base are rewritten only after the next first barrier, which
+  // every thread reaches after finishing these reads.
 }
 
 template <int BLOCK, int PPT, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
   static_assert(PPT <= 32, "class masks are 32-bit");
   constexpr bool USER = MODE != kSweepLevel;  // input = the caller's arrays, index = position - ibase
+  constexpr bool FUSED = MODE == kSweepFused;
+  constexpr int NS = FUSED ? 4 : 2;  // output streams (two per output range)
   constexpr uint32_t TILE = BLOCK * PPT;
   constexpr int NW = BLOCK / 64;
-  __shared__ uint32_t s_cnt[4][NW];
-  __shared__ uint32_t s_base[4];
+  __shared__ uint32_t s_cnt[NS][NW];
+  __shared__ uint32_t s_base[NS];
   __shared__ Cand s_cand[2][NW];
-  __shared__ uint32_t s_run[2][NW];
 
   const uint32_t ntiles = uni(A.st->ntiles);
   const uint32_t G = gridDim.x;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 
   uint32_t run_seg = kNone, run_slot = 0;
-  // triangle of the segment (root triangle in the fused pass)
+  // Level: the segment's triangle (a, r, b).  Argmax and fused: p = a, q = r.
   double ax = 0, ay = 0, rx = 0, ry = 0, bx = 0, by = 0;
+  double r1x = 0, r1y = 0, r2x = 0, r2y = 0;  // fused: farthest points of the two children
   uint32_t beg = 0, cnt = 0, tile0 = 0, ibase = 0, req = 0;
-  // fused pass: the two children
-  double cax[2] = {0, 0}, cay[2] = {0, 0}, crx[2] = {0, 0}, cry[2] = {0, 0}, cbx[2] = {0, 0}, cby[2] = {0, 0};
-  uint32_t cbeg[2] = {0, 0}, ccnt[2] = {0, 0}, ckind[2] = {kFuseSkip, kFuseSkip}, cslot[2] = {0, 0};
-  Cand b1 = no_cand(), b2 = no_cand(), b3 = no_cand(), b4 = no_cand();
-  uint32_t run1 = 0, run2 = 0;  // argmax pass: subset sizes of the current run (per wave)
+  uint32_t cbeg[NS / 2] = {}, ccnt[NS / 2] = {};
+  unsigned long long* cctr[NS / 2] = {};
+  bool split0 = false, split1 = false, copy0 = false, copy1 = false;  // fused: kinds of the two children
+  Best b[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) b[s] = no_best();
+  uint32_t run1 = 0, run2 = 0;  // argmax pass: subset sizes of the current run (per lane)
   bool bad = false;
 
   for (uint32_t k = blockIdx.x; k < ntiles; k += G) {
@@ -419,55 +505,39 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
     const uint32_t s = uni(A.tile_seg[t]);
     if (s != run_seg) {
       if (run_seg != kNone) {
-        if constexpr (MODE == kSweepFused) {
-          flush_run<NW>(A.part, run_slot, b1, b2, s_cand);
-          flush_run<NW>(A.part2, run_slot, b3, b4, s_cand);
-        } else {
-          flush_run<NW>(A.part, run_slot, b1, b2, s_cand);
-        }
+        flush_run<USER, NW>(A, A.part, run_slot, b[0], b[1], ibase, s_cand);
+        if constexpr (FUSED) flush_run<USER, NW>(A, A.part2, run_slot, b[2], b[3], ibase, s_cand);
         if constexpr (MODE == kSweepArgmax) {
-          if (lane == 0) {
-            s_run[0][w] = run1;
-            s_run[1][w] = run2;
-          }
-          __syncthreads();
-          if (tid == 0) {
-            uint32_t t1 = 0, t2 = 0;
-            for (int i = 0; i < NW; ++i) {
-              t1 += s_run[0][i];
-              t2 += s_run[1][i];
-            }
-            if (t1 | t2) atomicAdd(A.ctr + run_seg, ((unsigned long long)t2 << 32) | (unsigned long long)t1);
-          }
-          __syncthreads();
+          flush_counts<NW>(A.ctr + (size_t)run_seg * kCtrStride, run1, run2, s_cnt);
           run1 = run2 = 0;
         }
       }
-      if constexpr (MODE == kSweepFused) {
+      if constexpr (FUSED) {
         const FusedRoot* fr = A.fr + s;
         ax = uni(fr->px);
         ay = uni(fr->py);
         rx = uni(fr->qx);
         ry = uni(fr->qy);
-        bx = ax;
-        by = ay;
+        r1x = uni(fr->rx[0]);
+        r1y = uni(fr->ry[0]);
+        r2x = uni(fr->rx[1]);
+        r2y = uni(fr->ry[1]);
         beg = uni(fr->off);
         cnt = uni(fr->n);
         tile0 = uni(fr->tile0);
         ibase = beg;
+        uint32_t kind[2];
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          cax[c] = uni(fr->ax[c]);
-          cay[c] = uni(fr->ay[c]);
-          crx[c] = uni(fr->rx[c]);
-          cry[c] = uni(fr->ry[c]);
-          cbx[c] = uni(fr->bx[c]);
-          cby[c] = uni(fr->by[c]);
           cbeg[c] = uni(fr->beg[c]);
           ccnt[c] = uni(fr->cnt[c]);
-          ckind[c] = uni(fr->kind[c]);
-          cslot[c] = uni(fr->slot[c]);
+          kind[c] = uni(fr->kind[c]);
+          cctr[c] = (kind[c] == kFuseSplit ? A.ctr : A.jctr) + (size_t)uni(fr->slot[c]) * kCtrStride;
         }
+        split0 = kind[0] == kFuseSplit;
+        split1 = kind[1] == kFuseSplit;
+        copy0 = kind[0] == kFuseCopy;
+        copy1 = kind[1] == kFuseCopy;
       } else {
         const Seg* sg = A.seg + s;
         ax = uni(sg->ax);
@@ -481,124 +551,106 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
         tile0 = uni(sg->tile0);
         ibase = uni(sg->ibase);
         req = uni(sg->req);
+        cbeg[0] = beg;
+        ccnt[0] = cnt;
+        cctr[0] = A.ctr + (size_t)s * kCtrStride;
       }
       run_seg = s;
       run_slot = tile0 + (t - tile0) % G;
-      b1 = b2 = b3 = b4 = no_cand();
+#pragma unroll
+      for (int q = 0; q < NS; ++q) b[q] = no_best();
     }
     const uint32_t lo = beg + (t - tile0) * TILE;
     const uint32_t hi = min(beg + cnt, lo + TILE);
 
+    // Loads: positions past the end of the segment re-read its last point
+    // (no branch per load) and are masked out below.
     double px[PPT], py[PPT];
     uint32_t pi[PPT];
 #pragma unroll
     for (int v = 0; v < PPT; ++v) {
-      const uint32_t pos = lo + v * BLOCK + tid;
-      const bool ok = pos < hi;
-      px[v] = ok ? __builtin_nontemporal_load(A.ix + pos) : 0.0;
-      py[v] = ok ? __builtin_nontemporal_load(A.iy + pos) : 0.0;
+      const uint32_t pc = min(lo + v * BLOCK + tid, hi - 1u);
+      px[v] = __builtin_nontemporal_load(A.ix + pc);
+      py[v] = __builtin_nontemporal_load(A.iy + pc);
       if constexpr (USER) {
-        pi[v] = pos - ibase;
+        pi[v] = 0u;
       } else {
-        pi[v] = ok ? __builtin_nontemporal_load(A.ii + pos) : 0u;
+        pi[v] = __builtin_nontemporal_load(A.ii + pc);
       }
     }
 
-    if constexpr (MODE != kSweepFused) {
-      uint32_t m1 = 0, m2 = 0;
+    uint32_t m[NS];
 #pragma unroll
-      for (int v = 0; v < PPT; ++v) {
-        const uint32_t pos = lo + v * BLOCK + tid;
-        const bool ok = pos < hi;
-        const double o1 = orient(ax, ay, rx, ry, px[v], py[v]);
-        // On the root triangle (p, q, p), orient(q, p, u) is exactly
-        // -orient(p, q, u): the same two rounded products, subtracted the
-        // other way round.
-        const double o2 = MODE == kSweepArgmax ? -o1 : orient(rx, ry, bx, by, px[v], py[v]);
-        const bool in1 = ok && (o1 > 0.0);
-        const bool in2 = ok && !in1 && (o2 > 0.0);
-        m1 |= (uint32_t)in1 << v;
-        m2 |= (uint32_t)in2 << v;
-        if (in1) take(b1, o1, px[v], py[v], pi[v]);
-        if (in2) take(b2, o2, px[v], py[v], pi[v]);
-        if constexpr (MODE == kSweepArgmax) bad |= ok && !finite(py[v]);
-      }
-      if constexpr (MODE == kSweepArgmax) {
+    for (int q = 0; q < NS; ++q) m[q] = 0u;
 #pragma unroll
-        for (int v = 0; v < PPT; ++v) {
-          run1 += (uint32_t)__popcll(__ballot((m1 >> v) & 1u));
-          run2 += (uint32_t)__popcll(__ballot((m2 >> v) & 1u));
-        }
-        if (__ballot(bad) && lane == 0) A.req[req].err = 1u;
-        bad = false;
+    for (int v = 0; v < PPT; ++v) {
+      const uint32_t pos = lo + v * BLOCK + tid;
+      const bool ok = pos < hi;
+      const double x = px[v], y = py[v];
+      if constexpr (MODE == kSweepLevel) {
+        const double dax = ax - x, day = ay - y, drx = rx - x, dry = ry - y, dbx = bx - x, dby = by - y;
+        const double o1 = dax * dry - day * drx;  // orient(a, r, u)
+        const double o2 = drx * dby - dry * dbx;  // orient(r, b, u)
+        const bool in1 = ok & (o1 > 0.0);
+        const bool in2 = ok & !in1 & (o2 > 0.0);
+        const bool f[2] = {in1, in2};
+        const double kk[2] = {o1, o2};
+        offer<false, 2>(b, f, kk, x, y, pos, pi[v], A);
+        m[0] |= (uint32_t)in1 << v;
+        m[1] |= (uint32_t)in2 << v;
       } else {
-        write_pair<BLOCK, PPT, NW>(m1, m2, beg, cnt, A.ctr + s, px, py, pi, A.ox, A.oy, A.oi, s_cnt, s_base);
-      }
-    } else {
-      // fused: side of the root triangle, then the child's own split (or a copy)
-      uint32_t side0 = 0, side1 = 0;
-#pragma unroll
-      for (int v = 0; v < PPT; ++v) {
-        const uint32_t pos = lo + v * BLOCK + tid;
-        const bool ok = pos < hi;
-        const double o1 = orient(ax, ay, rx, ry, px[v], py[v]);  // root triangle (p, q, p): o2 = -o1
-        side0 |= (uint32_t)(ok && (o1 > 0.0)) << v;
-        side1 |= (uint32_t)(ok && (o1 < 0.0)) << v;
-      }
-      uint32_t mL[2] = {0, 0}, mR[2] = {0, 0};
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const uint32_t in = c ? side1 : side0;
-        if (ckind[c] == kFuseCopy) {  // uniform branch: the kinds come from the root
-          mL[c] = in;
-        } else if (ckind[c] == kFuseSplit) {
-          const double qax = cax[c], qay = cay[c], qrx = crx[c], qry = cry[c], qbx = cbx[c], qby = cby[c];
-          Cand& bl = c ? b3 : b1;
-          Cand& br = c ? b4 : b2;
-#pragma unroll
-          for (int v = 0; v < PPT; ++v) {
-            if (!((in >> v) & 1u)) continue;
-            const double e1 = orient(qax, qay, qrx, qry, px[v], py[v]);
-            if (e1 > 0.0) {
-              mL[c] |= 1u << v;
-              take(bl, e1, px[v], py[v], pi[v]);
-            } else {
-              const double e2 = orient(qrx, qry, qbx, qby, px[v], py[v]);
-              if (e2 > 0.0) {
-                mR[c] |= 1u << v;
-                take(br, e2, px[v], py[v], pi[v]);
-              }
-            }
-          }
+        const double dpx = ax - x, dpy = ay - y, dqx = rx - x, dqy = ry - y;
+        const double o = dpx * dqy - dpy * dqx;  // orient(p, q, u)
+        const bool s0 = ok & (o > 0.0);
+        const bool s1 = ok & (o < 0.0);
+        if constexpr (MODE == kSweepArgmax) {
+          const bool f[2] = {s0, s1};
+          const double kk[2] = {o, -o};
+          offer<true, 2>(b, f, kk, x, y, pos, 0u, A);
+          m[0] |= (uint32_t)s0 << v;
+          m[1] |= (uint32_t)s1 << v;
+          bad |= ok & !finite(y);
+        } else {
+          // child 0 = (p, r1, q) holds S1, child 1 = (q, r2, p) holds S2.  Both
+          // children are evaluated for every point (no branch on the kinds,
+          // which are uniform); the kind flags mask the results.
+          const double d1x = r1x - x, d1y = r1y - y, d2x = r2x - x, d2y = r2y - y;
+          const double kk[4] = {
+              dpx * d1y - dpy * d1x,  // orient(p, r1, u)
+              d1x * dqy - d1y * dqx,  // orient(r1, q, u)
+              dqx * d2y - dqy * d2x,  // orient(q, r2, u)
+              d2x * dpy - d2y * dpx,  // orient(r2, p, u)
+          };
+          const bool a0 = s0 & split0, a1 = s1 & split1;
+          const bool l0 = kk[0] > 0.0, l1 = kk[2] > 0.0;
+          const bool f[4] = {(bool)(a0 & l0), (bool)(a0 & !l0 & (kk[1] > 0.0)), (bool)(a1 & l1), (bool)(a1 & !l1 & (kk[3] > 0.0))};
+          offer<true, 4>(b, f, kk, x, y, pos, 0u, A);
+          m[0] |= (uint32_t)(f[0] | (s0 & copy0)) << v;
+          m[1] |= (uint32_t)f[1] << v;
+          m[2] |= (uint32_t)(f[2] | (s1 & copy1)) << v;
+          m[3] |= (uint32_t)f[3] << v;
         }
       }
-      unsigned long long* c0 = ckind[0] == kFuseSplit ? A.ctr + cslot[0] : A.jctr + cslot[0];
-      unsigned long long* c1 = ckind[1] == kFuseSplit ? A.ctr + cslot[1] : A.jctr + cslot[1];
-      write_quad<BLOCK, PPT, NW>(mL, mR, cbeg, ccnt, c0, c1, px, py, pi, A.ox, A.oy, A.oi, s_cnt, s_base);
+      // The subset bits are materialised in vector registers point by point:
+      // otherwise the compiler keeps every point's lane masks alive in scalar
+      // registers until the write loop and spills them.
+#pragma unroll
+      for (int q = 0; q < NS; ++q) asm volatile("" : "+v"(m[q]));
+    }
+    if constexpr (MODE == kSweepArgmax) {
+      run1 += (uint32_t)__popc(m[0]);
+      run2 += (uint32_t)__popc(m[1]);
+      if (__ballot(bad) && lane == 0) A.req[req].err = 1u;
+      bad = false;
+    } else {
+      write_streams<BLOCK, PPT, NS, USER>(m, cbeg, ccnt, cctr, px, py, pi, lo + tid - ibase, A.ox, A.oy, A.oi, s_cnt,
+                                          s_base);
     }
   }
   if (run_seg != kNone) {
-    if constexpr (MODE == kSweepFused) {
-      flush_run<NW>(A.part, run_slot, b1, b2, s_cand);
-      flush_run<NW>(A.part2, run_slot, b3, b4, s_cand);
-    } else {
-      flush_run<NW>(A.part, run_slot, b1, b2, s_cand);
-    }
-    if constexpr (MODE == kSweepArgmax) {
-      if (lane == 0) {
-        s_run[0][w] = run1;
-        s_run[1][w] = run2;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        uint32_t t1 = 0, t2 = 0;
-        for (int i = 0; i < NW; ++i) {
-          t1 += s_run[0][i];
-          t2 += s_run[1][i];
-        }
-        if (t1 | t2) atomicAdd(A.ctr + run_seg, ((unsigned long long)t2 << 32) | (unsigned long long)t1);
-      }
-    }
+    flush_run<USER, NW>(A, A.part, run_slot, b[0], b[1], ibase, s_cand);
+    if constexpr (FUSED) flush_run<USER, NW>(A, A.part2, run_slot, b[2], b[3], ibase, s_cand);
+    if constexpr (MODE == kSweepArgmax) flush_counts<NW>(A.ctr + (size_t)run_seg * kCtrStride, run1, run2, s_cnt);
   }
 }
 
@@ -759,7 +811,7 @@ __device__ __forceinline__ int32_t emit_one(uint32_t kind, const Tri& tr, uint32
     j.pad = 0;
     const uint32_t jid = e.job++;
     jobs[jid] = j;
-    if (vt.on) vt.jctr_out[jid] = 0ull;
+    if (vt.on) vt.jctr_out[(size_t)jid * kCtrStride] = 0ull;
     *index_out = jid;
     atomicAdd(&S.jobpts, cnt);
   } else if (kind == kKindSeg && vt.on) {
@@ -780,7 +832,7 @@ __device__ __forceinline__ int32_t emit_one(uint32_t kind, const Tri& tr, uint32
     sg.rtiles = vt.rtiles;
     sg.rside = side;
     seg_out[sid] = sg;
-    ctr_out[sid] = 0ull;
+    ctr_out[(size_t)sid * kCtrStride] = 0ull;
     *index_out = sid;
     atomicAdd(&S.swept, cnt);
   } else if (kind == kKindSeg) {
@@ -805,7 +857,7 @@ __device__ __forceinline__ int32_t emit_one(uint32_t kind, const Tri& tr, uint32
     sg.rtiles = 0u;
     sg.rside = 0u;
     seg_out[sid] = sg;
-    ctr_out[sid] = 0ull;
+    ctr_out[(size_t)sid * kCtrStride] = 0ull;
     atomicAdd(&S.swept, cnt);
     if (nt <= kSerialFill) {
       for (uint32_t i = 0; i < nt; ++i) tile_seg_out[t0 + i] = sid;
@@ -1024,7 +1076,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
     Cand r1 = no_cand(), r2 = no_cand();
     bool big = false;
     if (valid) {
-      const unsigned long long c = A.ctr[s];
+      const unsigned long long c = A.ctr[(size_t)s * kCtrStride];
       n1 = (uint32_t)c;
       n2 = (uint32_t)(c >> 32);
       atomicAdd(&S.survivors, n1 + n2);
@@ -1118,12 +1170,8 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
         const uint32_t idx[2] = {i1, i2};
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          f.ax[c] = tt[c]->ax;
-          f.ay[c] = tt[c]->ay;
           f.rx[c] = tt[c]->rx;
           f.ry[c] = tt[c]->ry;
-          f.bx[c] = tt[c]->bx;
-          f.by[c] = tt[c]->by;
           f.kind[c] = kind[c] == kKindSeg ? kFuseSplit : kind[c] == kKindJob ? kFuseCopy : kFuseSkip;
           f.slot[c] = idx[c];
         }

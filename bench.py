@@ -8,10 +8,12 @@ planners, LDS finisher, assembly) over 2e8 points already resident in HBM.
 Prints one JSON line:
 
   value       whole-step throughput, Gpoints/s (points hulled / wall time);
-  roofline    the level-0 fused sweep (the dominant kernel): algorithmic bytes
-              per launch (16 B read per input point + 20 B written per kept
-              point) over its average duration, from HIP events recorded on the
-              launch stream during the timed steps, against 8 TB/s;
+  roofline    the fused top-level sweep (the dominant kernel: it classifies every
+              input point against p->q and against its child's triangle and
+              writes the grandchild subsets): algorithmic bytes per launch
+              (16 B read per input point + 20 B written per kept point) over its
+              average duration, from HIP events recorded on the launch stream
+              during the timed steps, against 8 TB/s;
   cpu_baseline  the CPU oracle (single thread) on one whole step.
 
 Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2]
@@ -27,7 +29,7 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_level0_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_fused_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2510_09417_amd", "csrc", "vqhull_kernels.hip")
 METRIC = "Gpoints/s + % HBM peak (1e8 FP64 pts); batched hulls/s + p50/p99 latency"
 
@@ -38,7 +40,7 @@ def kernel_source_hash() -> str:
 
 
 def load_traffic():
-    """Measured HBM bytes per level-0 sweep launch (from rocprofv3 counters), or
+    """Measured HBM bytes per fused-sweep launch (from rocprofv3 counters), or
     None when absent or taken on a different kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
@@ -117,7 +119,7 @@ def main() -> int:
 
     # timed region: kernel timing events are recorded on the launch stream
     vq.set_timing(True)
-    sweep0 = []  # (ms, bytes) of every level-0 sweep launch
+    fused, argmax, sweeps = [], [], []  # (ms, algorithmic bytes) per launch
     per_kind = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -127,8 +129,18 @@ def main() -> int:
             for r in vq.kernel_times():
                 per_kind.setdefault(r["kind"], 0.0)
                 per_kind[r["kind"]] += r["ms"]
-                if r["kind"] == "sweep" and r["level"] == 0:
-                    sweep0.append((r["ms"], 16 * r["points_in"] + 20 * r["points_out"]))
+                if r["kind"] != "sweep":
+                    continue
+                # level 0: argmax pass over the caller's arrays (16 B read per point);
+                # level 1: fused pass (16 B read per point, 20 B per kept point);
+                # deeper levels read and write 20 B per point.
+                rd = 16 if r["level"] <= 1 else 20
+                rec = (r["ms"], rd * r["points_in"] + 20 * r["points_out"])
+                sweeps.append(rec)
+                if r["level"] == 0:
+                    argmax.append(rec)
+                elif r["level"] == 1:
+                    fused.append(rec)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     vq.set_timing(False)
@@ -136,13 +148,19 @@ def main() -> int:
     ms_per_step = 1e3 * wall / args.steps
     value = npts * args.steps / wall / 1e9
 
-    avg_ms = sum(m for m, _ in sweep0) / len(sweep0)
-    avg_bytes = sum(b for _, b in sweep0) / len(sweep0)
-    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    def rate(recs):
+        ms = sum(m for m, _ in recs)
+        by = sum(b for _, b in recs)
+        return by / (ms * 1e-3) / 1e9, ms / len(recs), by / len(recs)
+
+    achieved, avg_ms, avg_bytes = rate(fused)
+    a_gbs, a_ms, _ = rate(argmax)
+    s_gbs, _, _ = rate(sweeps)
     traffic = load_traffic()
     roofline = {
         "bound": "hbm",
-        "kernel": "k_sweep level 0 (fused orient + farthest point + S1/S2 extraction)",
+        "kernel": "k_sweep fused pass (orient against p->q and the child triangle, farthest points, "
+                  "extraction of the four grandchild subsets)",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
@@ -150,7 +168,10 @@ def main() -> int:
         "traffic": traffic["bytes_per_launch"] if traffic else None,
         "bytes_per_launch_alg": int(avg_bytes),
         "avg_launch_ms": round(avg_ms, 4),
-        "launches": len(sweep0),
+        "launches": len(fused),
+        "argmax_pass_gbs": round(a_gbs, 1),
+        "argmax_pass_ms": round(a_ms, 4),
+        "all_sweeps_gbs": round(s_gbs, 1),
         "stream_scale_gbs": round(probe_gbs, 1),
         "frac_of_stream_scale": round(achieved / probe_gbs, 4),
     }

@@ -6,9 +6,9 @@
 
 ``traffic`` calibrates the byte counters on the STREAM-Scale probe kernel, which
 reads and writes exactly 8 bytes per element: factor = known bytes / counted
-bytes, separately for FETCH_SIZE and WRITE_SIZE.  The level-0 sweep's counted
-bytes per dispatch, times those factors, give its measured HBM traffic per
-launch.  The JSON records the hash of the kernel source it was taken on; the
+bytes, separately for FETCH_SIZE and WRITE_SIZE.  The fused sweep's counted
+bytes per dispatch (template mode 2 of k_sweep), times those factors, give its
+measured HBM traffic per launch.  The JSON records the hash of the kernel source it was taken on; the
 benchmark ignores it once the source has changed.
 """
 from __future__ import annotations
@@ -21,7 +21,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(HERE, "csrc", "vqhull_kernels.hip")
-SWEEP_L0 = "k_sweep<"
+SWEEP = "k_sweep<"
+FUSED_MODE = ", 2>"  # k_sweep<BLOCK, PPT, MODE>: mode 2 is the fused top-level pass
 PROBE = "k_stream_scale"
 
 
@@ -69,12 +70,12 @@ def _pick(agg: dict, pred) -> list:
 def traffic(fetch_csv: str, write_csv: str, out_json: str, out_md: str, fetch_cmd: str, write_cmd: str,
             probe_elems: float = 1e8) -> dict:
     fa, wa = _per_kernel(fetch_csv, "FETCH_SIZE"), _per_kernel(write_csv, "WRITE_SIZE")
-    is_l0 = lambda k: SWEEP_L0 in k and ", true>" in k
+    is_l0 = lambda k: SWEEP in k and FUSED_MODE in k
     is_probe = lambda k: PROBE in k
     f_probe, w_probe = _pick(fa, is_probe), _pick(wa, is_probe)
     f_l0, w_l0 = _pick(fa, is_l0), _pick(wa, is_l0)
     if not (f_probe and w_probe and f_l0 and w_l0):
-        raise SystemExit("missing probe or level-0 sweep dispatches in the counter files")
+        raise SystemExit("missing probe or fused sweep dispatches in the counter files")
     mean = lambda v: sum(v) / len(v)
     known = 8.0 * probe_elems  # bytes read (and written) by the probe
     ff = known / (mean(f_probe) * 1024.0)
@@ -82,7 +83,7 @@ def traffic(fetch_csv: str, write_csv: str, out_json: str, out_md: str, fetch_cm
     fetch_b = mean(f_l0) * 1024.0 * ff
     write_b = mean(w_l0) * 1024.0 * fw
     res = {
-        "kernel": "k_sweep level 0",
+        "kernel": "k_sweep fused pass",
         "bytes_per_launch": int(fetch_b + write_b),
         "fetch_bytes_per_launch": int(fetch_b),
         "write_bytes_per_launch": int(write_b),
@@ -97,7 +98,7 @@ def traffic(fetch_csv: str, write_csv: str, out_json: str, out_md: str, fetch_cm
     }
     with open(out_json, "w") as f:
         json.dump(res, f, indent=1)
-    lines = ["# HBM traffic of the level-0 fused sweep (rocprofv3 counters)", "",
+    lines = ["# HBM traffic of the fused top-level sweep (rocprofv3 counters)", "",
              f"FETCH_SIZE command: `{fetch_cmd}`", "", f"WRITE_SIZE command: `{write_cmd}`", "",
              "Calibration: the STREAM-Scale probe reads and writes exactly 8 bytes per element "
              f"({probe_elems:.0f} elements); scale = known bytes / counted bytes.", "",
@@ -106,11 +107,11 @@ def traffic(fetch_csv: str, write_csv: str, out_json: str, out_md: str, fetch_cm
              f"| probe WRITE_SIZE (KiB/dispatch) | {res['probe_write_kib']} |",
              f"| fetch scale | {res['fetch_scale']} |",
              f"| write scale | {res['write_scale']} |",
-             f"| level-0 sweep FETCH_SIZE (KiB/dispatch, {len(f_l0)} dispatches) | {res['fetch_size_kib_per_dispatch']} |",
-             f"| level-0 sweep WRITE_SIZE (KiB/dispatch) | {res['write_size_kib_per_dispatch']} |",
-             f"| level-0 sweep fetched bytes per launch (scaled) | {res['fetch_bytes_per_launch']} |",
-             f"| level-0 sweep written bytes per launch (scaled) | {res['write_bytes_per_launch']} |",
-             f"| level-0 sweep HBM traffic per launch | {res['bytes_per_launch']} |",
+             f"| fused sweep FETCH_SIZE (KiB/dispatch, {len(f_l0)} dispatches) | {res['fetch_size_kib_per_dispatch']} |",
+             f"| fused sweep WRITE_SIZE (KiB/dispatch) | {res['write_size_kib_per_dispatch']} |",
+             f"| fused sweep fetched bytes per launch (scaled) | {res['fetch_bytes_per_launch']} |",
+             f"| fused sweep written bytes per launch (scaled) | {res['write_bytes_per_launch']} |",
+             f"| fused sweep HBM traffic per launch | {res['bytes_per_launch']} |",
              f"| kernel source sha256[:16] | `{res['kernel_source_sha256_16']}` |"]
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")

@@ -166,6 +166,88 @@ const char* vqhull_status_string(int status);
 /* Text of the last HIP error seen by this thread (static thread-local storage). */
 const char* vqhull_last_error(void);
 
+/*
+ * Continuous-batching server: the served form of the batched hull.
+ *
+ * Requests are submitted one at a time, each with its own device arrays, and
+ * queue in arrival order.  The server runs `lanes` batch lanes; each has its
+ * own HIP stream, device workspace and batch buffers, allocated once at
+ * creation, and a host thread that repeatedly takes the oldest pending
+ * requests that fit the lane (at most lane_points points and lane_requests
+ * requests; admission by the lane's device memory), gathers them into one
+ * batch, runs the batched hull on it (vqhull_hull_batched semantics), and
+ * writes every request's vertex list and count to that request's buffers.
+ * Requests that arrive while batches are on the GPU are taken by the next lane
+ * that frees up, so the work of different batches overlaps on the device.
+ * Each request's result is identical to vqhull_hull on its points alone.
+ *
+ * Device memory per lane is about 64 + 40 bytes per lane point plus small
+ * tables.  All functions are thread-safe.  Host pointers: cfg, out, ticket,
+ * tickets, info, stats.  Times are seconds on the host's steady clock since
+ * the server's creation.
+ */
+typedef struct vqhull_server vqhull_server; /* opaque */
+
+typedef struct {
+  int32_t lanes;         /* concurrent batches (1..8), one HIP stream each */
+  int32_t reserved;      /* must be 0 */
+  int64_t lane_points;   /* points per batch (1 .. 2^31-1); also the largest request */
+  int64_t lane_requests; /* requests per batch (1 .. 2^24) */
+} vqhull_server_config;
+
+typedef struct {
+  int64_t n;        /* points of the request */
+  int64_t batch;    /* batch that computed it (-1 while pending or running) */
+  int32_t lane;     /* lane that took it (-1 while pending) */
+  int32_t status;   /* VQHULL_OK or the request's error (meaningful once done) */
+  int32_t done;     /* 1 once the results are in the caller's buffers */
+  int32_t reserved;
+  double t_submit;  /* when vqhull_server_submit accepted it */
+  double t_start;   /* when a lane took it into a batch */
+  double t_done;    /* when its batch finished (results written) */
+} vqhull_ticket_info;
+
+typedef struct {
+  int64_t submitted, completed, failed, batches, points, pending;
+  double busy_seconds; /* summed wall time of all batches over all lanes */
+  double now;          /* the server clock when the statistics were taken */
+} vqhull_server_counters;
+
+/* Create a server on the current device; VQHULL_ERR_INVALID_ARGUMENT for a
+ * configuration out of range, VQHULL_ERR_OUT_OF_MEMORY if the lanes do not fit. */
+int vqhull_server_create(const vqhull_server_config* cfg, vqhull_server** out);
+
+/*
+ * Queue one request.  x, y: device arrays of n binary64 coordinates, 0 <= n <=
+ * lane_points; out_idx: device int64 array with room for n entries (may be
+ * NULL when n = 0); out_count: device int64 scalar, receives h or
+ * -VQHULL_ERR_NONFINITE.  The caller keeps all four valid and x, y unmodified
+ * until the request is done.  *ticket receives the request's id (0, 1, 2, ...
+ * in submission order).  Returns at once; no HIP call is made.
+ */
+int vqhull_server_submit(vqhull_server* s, const double* x, const double* y, int64_t n, int64_t* out_idx,
+                         int64_t* out_count, int64_t* ticket);
+
+/* Block until the request is done; returns its status (VQHULL_OK,
+ * VQHULL_ERR_NONFINITE, ...) or VQHULL_ERR_INVALID_ARGUMENT for an unknown ticket. */
+int vqhull_server_wait(vqhull_server* s, int64_t ticket);
+
+/* Completed tickets not returned by an earlier poll, oldest first, up to cap;
+ * returns how many were written (a negative status on bad arguments). */
+int64_t vqhull_server_poll(vqhull_server* s, int64_t* tickets, int64_t cap);
+
+/* Block until every submitted request is done. */
+int vqhull_server_drain(vqhull_server* s);
+
+/* Timing and placement of one request. */
+int vqhull_server_ticket_info(vqhull_server* s, int64_t ticket, vqhull_ticket_info* info);
+
+/* Server-wide counters. */
+int vqhull_server_stats(vqhull_server* s, vqhull_server_counters* stats);
+
+/* Finish the queued requests, stop the lanes and free the server. */
+int vqhull_server_destroy(vqhull_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,6 +25,8 @@ EXPORTED = (
     "vqhull_hull", "vqhull_hull_batched", "vqhull_get_config", "vqhull_set_config",
     "vqhull_last_level_stats", "vqhull_set_timing", "vqhull_last_kernel_times", "vqhull_stream_scale",
     "vqhull_release_workspace", "vqhull_status_string", "vqhull_last_error",
+    "vqhull_server_create", "vqhull_server_submit", "vqhull_server_wait", "vqhull_server_poll",
+    "vqhull_server_drain", "vqhull_server_ticket_info", "vqhull_server_stats", "vqhull_server_destroy",
 )
 
 KERNEL_KINDS = ("extremes", "plan0", "sweep", "plan", "finish", "assemble")
@@ -47,6 +49,23 @@ class Config(ctypes.Structure):
 class KernelTime(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("level", ctypes.c_int32), ("ms", ctypes.c_double),
                 ("points_in", ctypes.c_int64), ("points_out", ctypes.c_int64)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_int32), ("reserved", ctypes.c_int32), ("lane_points", ctypes.c_int64),
+                ("lane_requests", ctypes.c_int64)]
+
+
+class TicketInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("batch", ctypes.c_int64), ("lane", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("done", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("points", ctypes.c_int64), ("pending", ctypes.c_int64),
+                ("busy_seconds", ctypes.c_double), ("now", ctypes.c_double)]
 
 
 _lock = threading.Lock()
@@ -85,6 +104,23 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.vqhull_status_string.argtypes = [ctypes.c_int]
         lib.vqhull_last_error.restype = ctypes.c_char_p
         lib.vqhull_last_error.argtypes = []
+        ci = ctypes.c_int
+        lib.vqhull_server_create.restype = ci
+        lib.vqhull_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+        lib.vqhull_server_submit.restype = ci
+        lib.vqhull_server_submit.argtypes = [vp, vp, vp, i64, vp, vp, pi64]
+        lib.vqhull_server_wait.restype = ci
+        lib.vqhull_server_wait.argtypes = [vp, i64]
+        lib.vqhull_server_poll.restype = i64
+        lib.vqhull_server_poll.argtypes = [vp, pi64, i64]
+        lib.vqhull_server_drain.restype = ci
+        lib.vqhull_server_drain.argtypes = [vp]
+        lib.vqhull_server_ticket_info.restype = ci
+        lib.vqhull_server_ticket_info.argtypes = [vp, i64, ctypes.POINTER(TicketInfo)]
+        lib.vqhull_server_stats.restype = ci
+        lib.vqhull_server_stats.argtypes = [vp, ctypes.POINTER(ServerCounters)]
+        lib.vqhull_server_destroy.restype = ci
+        lib.vqhull_server_destroy.argtypes = [vp]
         _lib = lib
         return lib
 
@@ -230,3 +266,69 @@ def stream_scale(src, dst, s: float = 3.0, stream=None) -> None:
 def release_workspace() -> None:
     lib = load_library()
     _check(lib, lib.vqhull_release_workspace())
+
+
+class Server:
+    """Continuous-batching hull server (vqhull_server_*): requests are queued
+    as they are submitted and computed in batches by ``lanes`` concurrent batch
+    lanes; see include/vqhull.h.  The caller keeps each request's tensors alive
+    until the request is done (``wait``, ``drain`` or ``poll``)."""
+
+    def __init__(self, lanes: int = 2, lane_points: int = 1 << 24, lane_requests: int = 4096):
+        self._lib = load_library()
+        cfg = ServerConfig(lanes, 0, lane_points, lane_requests)
+        h = ctypes.c_void_p()
+        _check(self._lib, self._lib.vqhull_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.lane_points = lane_points
+
+    def submit(self, x, y, out_idx, out_count) -> int:
+        """Queue the hull of (x, y) into out_idx (int64, >= len(x) entries) and
+        out_count (int64 scalar tensor); returns the request's ticket."""
+        import torch
+
+        _check_points(x, y)
+        if out_idx.dtype != torch.int64 or out_count.dtype != torch.int64 or not out_idx.is_cuda:
+            raise TypeError("out_idx and out_count must be int64 GPU tensors")
+        if out_idx.numel() < x.numel():
+            raise ValueError("out_idx needs room for len(x) entries")
+        t = ctypes.c_int64()
+        _check(self._lib, self._lib.vqhull_server_submit(
+            self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), x.numel(),
+            ctypes.c_void_p(out_idx.data_ptr()), ctypes.c_void_p(out_count.data_ptr()), ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int) -> int:
+        """Block until the request is done; returns its status (0 = ok)."""
+        return self._lib.vqhull_server_wait(self._h, ticket)
+
+    def poll(self, cap: int = 4096) -> list:
+        buf = (ctypes.c_int64 * cap)()
+        k = self._lib.vqhull_server_poll(self._h, buf, cap)
+        if k < 0:
+            _check(self._lib, -k)
+        return list(buf[:k])
+
+    def drain(self) -> None:
+        _check(self._lib, self._lib.vqhull_server_drain(self._h))
+
+    def info(self, ticket: int) -> dict:
+        ti = TicketInfo()
+        _check(self._lib, self._lib.vqhull_server_ticket_info(self._h, ticket, ctypes.byref(ti)))
+        return {k: getattr(ti, k) for k, _ in TicketInfo._fields_ if k != "reserved"}
+
+    def stats(self) -> dict:
+        c = ServerCounters()
+        _check(self._lib, self._lib.vqhull_server_stats(self._h, ctypes.byref(c)))
+        return {k: getattr(c, k) for k, _ in ServerCounters._fields_}
+
+    def close(self) -> None:
+        if self._h:
+            _check(self._lib, self._lib.vqhull_server_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvqhull.so")
-SOURCES = ["vqhull_kernels.hip", "vqhull_engine.cpp"]
+SOURCES = ["vqhull_kernels.hip", "vqhull_engine.cpp", "vqhull_server.cpp"]
 ARCH = "gfx950"
 
 # -ffp-contract=off: the orientation predicate must never be fused into FMA.

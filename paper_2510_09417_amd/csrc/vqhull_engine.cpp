@@ -46,7 +46,15 @@ struct DevBuf {
   size_t cap = 0;
 };
 
-struct Workspace {
+}  // namespace
+
+namespace vqh {
+
+// One hull computation at a time runs on a context: device workspace, pinned
+// staging, the status ring and timing records.  The public entry points use
+// one context per device; the batching server owns one per lane.
+struct Context {
+  std::mutex mu;
   int device = -1;
   size_t cap_pts = 0;
   double* wx[2] = {nullptr, nullptr};
@@ -80,8 +88,12 @@ struct Workspace {
   std::vector<vqhull_kernel_time> times;
 };
 
+}  // namespace vqh
+
+namespace {
+
 std::mutex g_ws_mu;
-std::map<int, Workspace*> g_ws;
+std::map<int, Context*> g_ws;
 
 struct HipFail {
   hipError_t e;
@@ -111,7 +123,7 @@ void ensure(DevBuf<T>& b, size_t n, hipStream_t st, bool keep = false) {
   b.cap = cap;
 }
 
-void ensure_points(Workspace& w, size_t n, hipStream_t st) {
+void ensure_points(Context& w, size_t n, hipStream_t st) {
   if (n <= w.cap_pts) return;
   ck(hipStreamSynchronize(st), "hipStreamSynchronize");
   for (int k = 0; k < 2; ++k) {
@@ -130,7 +142,7 @@ void ensure_points(Workspace& w, size_t n, hipStream_t st) {
   w.cap_pts = n;
 }
 
-void ensure_host_req(Workspace& w, size_t n) {
+void ensure_host_req(Context& w, size_t n) {
   if (n <= w.h_req_cap) return;
   if (w.h_req) ck(hipHostFree(w.h_req), "hipHostFree");
   w.h_req = nullptr;
@@ -140,7 +152,7 @@ void ensure_host_req(Workspace& w, size_t n) {
   w.h_req_cap = cap;
 }
 
-void ensure_host_u32(Workspace& w, size_t n) {
+void ensure_host_u32(Context& w, size_t n) {
   if (n <= w.h_u32_cap) return;
   if (w.h_u32) ck(hipHostFree(w.h_u32), "hipHostFree");
   w.h_u32 = nullptr;
@@ -150,22 +162,31 @@ void ensure_host_u32(Workspace& w, size_t n) {
   w.h_u32_cap = cap;
 }
 
-Workspace& workspace_for_current_device() {
+Context* new_context() {
   int dev = 0;
   ck(hipGetDevice(&dev), "hipGetDevice");
-  auto it = g_ws.find(dev);
-  if (it != g_ws.end()) return *it->second;
-  Workspace* w = new Workspace();
+  Context* w = new Context();
   w->device = dev;
   ck(hipMalloc(&w->status_dev, kStatusRing * sizeof(Status)), "hipMalloc");
   ck(hipHostMalloc((void**)&w->status_host, kStatusRing * sizeof(Status), hipHostMallocDefault), "hipHostMalloc");
   for (int i = 0; i < kStatusRing; ++i)
     ck(hipEventCreateWithFlags(&w->status_ev[i], hipEventDisableTiming), "hipEventCreateWithFlags");
+  return w;
+}
+
+// The default context of the current device (created on first use).
+Context& default_context() {
+  std::lock_guard<std::mutex> guard(g_ws_mu);
+  int dev = 0;
+  ck(hipGetDevice(&dev), "hipGetDevice");
+  auto it = g_ws.find(dev);
+  if (it != g_ws.end()) return *it->second;
+  Context* w = new_context();
   g_ws[dev] = w;
   return *w;
 }
 
-void free_workspace(Workspace* w) {
+void free_workspace(Context* w) {
   auto f = [](void* p) {
     if (p) (void)hipFree(p);
   };
@@ -208,7 +229,7 @@ vqhull_config sanitized(vqhull_config c) {
   return c;
 }
 
-int take_event(Workspace& w) {
+int take_event(Context& w) {
   if (w.next_event == (int)w.events.size()) {
     hipEvent_t e;
     ck(hipEventCreate(&e), "hipEventCreate");
@@ -219,7 +240,7 @@ int take_event(Workspace& w) {
 
 // Launch through f(); with timing enabled, bracket it with events on st.
 template <typename F>
-size_t timed(Workspace& w, bool on, hipStream_t st, int kind, int level, int64_t in, int64_t out, F&& f) {
+size_t timed(Context& w, bool on, hipStream_t st, int kind, int level, int64_t in, int64_t out, F&& f) {
   if (!on) {
     f();
     return (size_t)-1;
@@ -233,7 +254,7 @@ size_t timed(Workspace& w, bool on, hipStream_t st, int kind, int level, int64_t
   return w.launches.size() - 1;
 }
 
-void collect_times(Workspace& w) {
+void collect_times(Context& w) {
   w.times.clear();
   for (const TimedLaunch& t : w.launches) {
     float ms = 0.f;
@@ -249,7 +270,7 @@ void collect_times(Workspace& w) {
 // waits only for the status of level k-1: the GPU never waits for the host
 // between levels.  When a status shows an empty level, the loop stops (the
 // kernels already enqueued for it find no work).
-bool run_once(Workspace& w, const vqhull_config& cfg, const double* x, const double* y, int64_t nreq,
+bool run_once(Context& w, const vqhull_config& cfg, const double* x, const double* y, int64_t nreq,
               int64_t* out_idx, int64_t* out_counts, hipStream_t st, size_t N, const uint32_t* tile_req,
               size_t ext_tiles, uint64_t tiles0, size_t max_tiles) {
   const uint32_t tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
@@ -426,19 +447,48 @@ bool run_once(Workspace& w, const vqhull_config& cfg, const double* x, const dou
   return true;
 }
 
-void run(const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
-         int64_t* out_counts, hipStream_t st) {
-  vqhull_config cfg;
-  {
-    std::lock_guard<std::mutex> g(g_cfg_mu);
-    cfg = sanitized(g_cfg);
+vqhull_config current_config() {
+  std::lock_guard<std::mutex> g(g_cfg_mu);
+  return sanitized(g_cfg);
+}
+
+// Device capacity for batches of up to N points in nreq requests.
+struct Caps {
+  size_t max_seg, max_tiles;
+};
+
+Caps reserve(Context& w, const vqhull_config& cfg, size_t N, size_t nreq, size_t ext_tiles, hipStream_t st) {
+  const uint32_t tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
+  const uint32_t lds_limit = (uint32_t)cfg.lds_limit;
+  ensure(w.req, std::max<size_t>(nreq, 1), st);
+  ensure(w.epart, std::max<size_t>(ext_tiles, 1), st);
+  ensure_points(w, std::max<size_t>(N, 1), st);
+  Caps c;
+  c.max_seg = N / (lds_limit + 1) + nreq + 2;
+  c.max_tiles = N / tile + c.max_seg + 2;
+  for (int k = 0; k < 2; ++k) {
+    ensure(w.seg[k], c.max_seg, st);
+    ensure(w.ctr[k], c.max_seg * kCtrStride, st);
+    ensure(w.tile_seg[k], c.max_tiles, st);
   }
+  ensure(w.part, c.max_tiles, st);
+  ensure(w.part2, c.max_tiles, st);
+  ensure(w.fr, c.max_seg, st);
+  ensure(w.jobs, 2 * c.max_seg + nreq, st);
+  ensure(w.jctr, (2 * c.max_seg + nreq) * kCtrStride, st);
+  ensure(w.nodes, std::max<size_t>(3 * nreq + 64, 4096), st);
+  return c;
+}
+
+void run(Context& w, const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
+         int64_t* out_counts, hipStream_t st) {
+  const vqhull_config cfg = current_config();
   const uint32_t tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
   const uint32_t lds_limit = (uint32_t)cfg.lds_limit;
   const size_t N = (size_t)offsets[nreq];
 
-  std::lock_guard<std::mutex> guard(g_ws_mu);
-  Workspace& w = workspace_for_current_device();
+  std::lock_guard<std::mutex> guard(w.mu);
+  ck(hipSetDevice(w.device), "hipSetDevice");
 
   // request table and extremes tile map
   ensure_host_req(w, (size_t)nreq);
@@ -454,8 +504,7 @@ void run(const double* x, const double* y, const int64_t* offsets, int64_t nreq,
     if (r.n > lds_limit) tiles0 += (r.n + tile - 1) / tile;
     w.h_req[i] = r;
   }
-  ensure(w.req, (size_t)std::max<int64_t>(nreq, 1), st);
-  ensure(w.epart, std::max<size_t>(ext_tiles, 1), st);
+  const Caps caps = reserve(w, cfg, N, (size_t)nreq, ext_tiles, st);
   const uint32_t* tile_req = nullptr;
   if (nreq > 1 && ext_tiles > 0) {
     ensure_host_u32(w, ext_tiles);
@@ -470,28 +519,12 @@ void run(const double* x, const double* y, const int64_t* offsets, int64_t nreq,
     tile_req = w.tile_req.p;
   }
 
-  // capacities
-  ensure_points(w, std::max<size_t>(N, 1), st);
-  const size_t max_seg = N / (lds_limit + 1) + (size_t)nreq + 2;
-  const size_t max_tiles = N / tile + max_seg + 2;
-  for (int k = 0; k < 2; ++k) {
-    ensure(w.seg[k], max_seg, st);
-    ensure(w.ctr[k], max_seg * kCtrStride, st);
-    ensure(w.tile_seg[k], max_tiles, st);
-  }
-  ensure(w.part, max_tiles, st);
-  ensure(w.part2, max_tiles, st);
-  ensure(w.fr, max_seg, st);
-  ensure(w.jobs, 2 * max_seg + (size_t)nreq, st);
-  ensure(w.jctr, (2 * max_seg + (size_t)nreq) * kCtrStride, st);
-  ensure(w.nodes, std::max<size_t>(3 * (size_t)nreq + 64, 4096), st);
-
   for (int attempt = 0;; ++attempt) {
     ck(hipMemcpyAsync(w.req.p, w.h_req, (size_t)nreq * sizeof(Req), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
     w.stats.clear();
     w.launches.clear();
     w.next_event = 0;
-    if (run_once(w, cfg, x, y, nreq, out_idx, out_counts, st, N, tile_req, ext_tiles, tiles0, max_tiles)) break;
+    if (run_once(w, cfg, x, y, nreq, out_idx, out_counts, st, N, tile_req, ext_tiles, tiles0, caps.max_tiles)) break;
     // The node table was too small for a level (not expected with the host's
     // bound): grow it and start over.
     ensure(w.nodes, 2 * w.nodes.cap, st);
@@ -500,12 +533,12 @@ void run(const double* x, const double* y, const int64_t* offsets, int64_t nreq,
   if (g_timing.load()) collect_times(w);
 }
 
-int guarded(const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
-            int64_t* out_counts, vqhull_stream_t stream) {
+template <typename F>
+int guard_status(F&& f) {
   try {
-    run(x, y, offsets, nreq, out_idx, out_counts, (hipStream_t)stream);
-  } catch (const HipFail& f) {
-    return f.e == hipErrorOutOfMemory ? VQHULL_ERR_OUT_OF_MEMORY : VQHULL_ERR_HIP;
+    f();
+  } catch (const HipFail& e) {
+    return e.e == hipErrorOutOfMemory ? VQHULL_ERR_OUT_OF_MEMORY : VQHULL_ERR_HIP;
   } catch (const std::bad_alloc&) {
     g_last_error = "host allocation failed";
     return VQHULL_ERR_OUT_OF_MEMORY;
@@ -513,7 +546,54 @@ int guarded(const double* x, const double* y, const int64_t* offsets, int64_t nr
   return VQHULL_OK;
 }
 
+int guarded(const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
+            int64_t* out_counts, vqhull_stream_t stream) {
+  return guard_status([&] { run(default_context(), x, y, offsets, nreq, out_idx, out_counts, (hipStream_t)stream); });
+}
+
 }  // namespace
+
+namespace vqh {
+
+int context_create(Context** out) {
+  return guard_status([&] { *out = new_context(); });
+}
+
+void context_destroy(Context* c) {
+  if (!c) return;
+  {
+    std::lock_guard<std::mutex> guard(c->mu);
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+  }
+  free_workspace(c);
+}
+
+int context_reserve(Context* c, int64_t npoints, int64_t nreq, void* stream) {
+  return guard_status([&] {
+    std::lock_guard<std::mutex> guard(c->mu);
+    ck(hipSetDevice(c->device), "hipSetDevice");
+    const vqhull_config cfg = current_config();
+    hipStream_t st = (hipStream_t)stream;
+    const size_t ext_tiles = (size_t)npoints / kExtTile + (size_t)nreq;
+    reserve(*c, cfg, (size_t)npoints, (size_t)nreq, ext_tiles, st);
+    ensure(c->tile_req, ext_tiles, st);
+    ensure(c->nodes, (size_t)npoints + 3 * (size_t)nreq + 64, st);
+    ensure_host_req(*c, (size_t)nreq);
+    ensure_host_u32(*c, ext_tiles);
+    ck(hipStreamSynchronize(st), "hipStreamSynchronize");
+  });
+}
+
+int context_run(Context* c, const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
+                int64_t* out_counts, void* stream) {
+  if (nreq == 0) return VQHULL_OK;
+  return guard_status([&] { run(*c, x, y, offsets, nreq, out_idx, out_counts, (hipStream_t)stream); });
+}
+
+const char* context_last_error() { return g_last_error.c_str(); }
+
+}  // namespace vqh
 
 extern "C" {
 
@@ -552,11 +632,12 @@ int vqhull_set_config(const vqhull_config* cfg) {
 }
 
 int64_t vqhull_last_level_stats(int64_t* out, int64_t cap) {
-  std::lock_guard<std::mutex> guard(g_ws_mu);
+  std::lock_guard<std::mutex> guard(g_ws_mu);  // the default context of the current device
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   auto it = g_ws.find(dev);
   if (it == g_ws.end()) return 0;
+  std::lock_guard<std::mutex> cguard(it->second->mu);
   const auto& st = it->second->stats;
   for (int64_t i = 0; i < (int64_t)st.size() && i < cap && out; ++i) {
     out[4 * i + 0] = st[i].segs;
@@ -588,6 +669,7 @@ int64_t vqhull_last_kernel_times(vqhull_kernel_time* out, int64_t cap) {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   auto it = g_ws.find(dev);
   if (it == g_ws.end()) return 0;
+  std::lock_guard<std::mutex> cguard(it->second->mu);
   const auto& t = it->second->times;
   for (int64_t i = 0; i < (int64_t)t.size() && i < cap && out; ++i) out[i] = t[i];
   return (int64_t)t.size();
@@ -599,9 +681,13 @@ int vqhull_release_workspace(void) {
   if (hipGetDevice(&dev) != hipSuccess) return VQHULL_ERR_HIP;
   auto it = g_ws.find(dev);
   if (it == g_ws.end()) return VQHULL_OK;
-  if (hipDeviceSynchronize() != hipSuccess) return VQHULL_ERR_HIP;
-  free_workspace(it->second);
+  Context* c = it->second;
+  {
+    std::lock_guard<std::mutex> cguard(c->mu);
+    if (hipDeviceSynchronize() != hipSuccess) return VQHULL_ERR_HIP;
+  }
   g_ws.erase(it);
+  free_workspace(c);
   return VQHULL_OK;
 }
 

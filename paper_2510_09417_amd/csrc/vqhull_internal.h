@@ -122,7 +122,18 @@ constexpr int kStatusRing = 4;
 constexpr size_t kCtrStride = 16;
 
 // ----------------------------------------------------------------- launchers
-struct Workspace;  // host side
+// Host engine contexts (vqhull_engine.cpp): one hull computation at a time
+// runs on a context (device workspace, pinned staging, status ring).  Status
+// values are VQHULL_*; streams are hipStream_t.
+struct Context;
+int context_create(Context** out);  // on the current device
+void context_destroy(Context* c);
+// Allocate the workspace for batches of up to npoints points in nreq requests.
+int context_reserve(Context* c, int64_t npoints, int64_t nreq, void* stream);
+// vqhull_hull_batched on this context (arguments already validated).
+int context_run(Context* c, const double* x, const double* y, const int64_t* offsets, int64_t nreq,
+                int64_t* out_idx, int64_t* out_counts, void* stream);
+const char* context_last_error();  // of the calling thread
 
 struct ExtremesArgs {
   const double* x;
@@ -232,6 +243,25 @@ int launch_finish(const FinishArgs& a, int tmax, void* stream);
 int launch_assemble(const AssembleArgs& a, void* stream);
 int launch_copy_lists(const AssembleArgs& a, void* stream);
 int launch_stream_scale(const double* in, double* out, uint64_t n, double s, void* stream);
+
+// Batching server: a request as the caller handed it in, placed at batch
+// offset off; a chunk is at most kServeChunk consecutive points of a request
+// (every request with n > 0 has ceil(n / kServeChunk) chunks, n = 0 has one).
+constexpr uint32_t kServeChunk = 4096;
+struct ServedReq {
+  const double* x;
+  const double* y;
+  int64_t* out_idx;
+  int64_t* out_count;
+  uint64_t off, n;
+};
+struct ServedChunk {
+  uint32_t req, beg;
+};
+int launch_gather(const ServedReq* reqs, const ServedChunk* chunks, uint32_t nchunks, double* dx, double* dy,
+                  void* stream);
+int launch_scatter(const ServedReq* reqs, const ServedChunk* chunks, uint32_t nchunks, const int64_t* idx,
+                   const int64_t* counts, void* stream);
 
 constexpr int kExtBlock = 256;
 constexpr int kExtPPT = 32;

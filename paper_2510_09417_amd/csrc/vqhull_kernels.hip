@@ -1570,6 +1570,35 @@ __global__ __launch_bounds__(256) void k_stream_scale(const double* __restrict__
   for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < n; i += stride) out[i] = s * in[i];
 }
 
+// ------------------------------------------------------ k_gather / k_scatter
+// Batching server: requests arrive as separate device arrays.  k_gather packs
+// them into one batch (request i at [off_i, off_i + n_i) of the staging
+// arrays); k_scatter copies each request's count and vertex list from the
+// batch output to the caller's buffers.  One workgroup per chunk of at most
+// kServeChunk points of one request, so a large request spreads over many
+// workgroups and a small one costs one.
+__global__ __launch_bounds__(256) void k_gather(const ServedReq* __restrict__ reqs, const ServedChunk* __restrict__ chunks,
+                                                double* __restrict__ dx, double* __restrict__ dy) {
+  const ServedChunk c = chunks[blockIdx.x];
+  const ServedReq r = reqs[c.req];
+  const uint64_t m = min((uint64_t)kServeChunk, (uint64_t)r.n - c.beg);
+  for (uint64_t j = threadIdx.x; j < m; j += 256) {
+    dx[r.off + c.beg + j] = __builtin_nontemporal_load(r.x + c.beg + j);
+    dy[r.off + c.beg + j] = __builtin_nontemporal_load(r.y + c.beg + j);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scatter(const ServedReq* __restrict__ reqs, const ServedChunk* __restrict__ chunks,
+                                                 const int64_t* __restrict__ idx, const int64_t* __restrict__ counts) {
+  const ServedChunk c = chunks[blockIdx.x];
+  const ServedReq r = reqs[c.req];
+  const int64_t cnt = counts[c.req];
+  if (c.beg == 0 && threadIdx.x == 0) *r.out_count = cnt;
+  if (cnt <= (int64_t)c.beg) return;  // also a negative (error) count
+  const uint64_t m = min((uint64_t)kServeChunk, (uint64_t)cnt - c.beg);
+  for (uint64_t j = threadIdx.x; j < m; j += 256) r.out_idx[c.beg + j] = idx[r.off + c.beg + j];
+}
+
 // -------------------------------------------------------------- launchers
 
 namespace {
@@ -1721,6 +1750,20 @@ int launch_copy_lists(const AssembleArgs& a, void* stream) {
   if (a.nnodes == 0) return 0;
   const uint32_t waves = a.nnodes < 65536u ? a.nnodes : 65536u;
   hipLaunchKernelGGL(k_copy_lists, dim3((waves + 3u) / 4u), dim3(256), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int launch_gather(const ServedReq* reqs, const ServedChunk* chunks, uint32_t nchunks, double* dx, double* dy,
+                  void* stream) {
+  if (nchunks == 0) return 0;
+  hipLaunchKernelGGL(k_gather, dim3(nchunks), dim3(256), 0, (hipStream_t)stream, reqs, chunks, dx, dy);
+  return (int)hipGetLastError();
+}
+
+int launch_scatter(const ServedReq* reqs, const ServedChunk* chunks, uint32_t nchunks, const int64_t* idx,
+                   const int64_t* counts, void* stream) {
+  if (nchunks == 0) return 0;
+  hipLaunchKernelGGL(k_scatter, dim3(nchunks), dim3(256), 0, (hipStream_t)stream, reqs, chunks, idx, counts);
   return (int)hipGetLastError();
 }
 

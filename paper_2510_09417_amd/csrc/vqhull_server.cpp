@@ -1,0 +1,354 @@
+// Continuous-batching hull server (C ABI in include/vqhull.h).
+//
+// Requests (device arrays owned by the caller) enter a FIFO.  The server runs
+// `lanes` batch lanes, each with its own HIP stream, engine context and
+// pre-allocated batch buffers, and a host thread that loops:
+//   take the oldest pending requests that fit the lane (points and request
+//   count), gather them into the lane's staging arrays (one kernel), run the
+//   batched hull on the lane's context, scatter every request's vertex list
+//   and count into the caller's buffers (one kernel), then mark the requests
+//   done.
+// A request that arrives while batches are on the GPU is taken by the next
+// lane that frees up, so work of different batches overlaps on the device;
+// admission is by the lane's fixed device memory, sized once at creation, so
+// serving allocates nothing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/vqhull.h"
+#include "vqhull_internal.h"
+
+using namespace vqh;
+
+namespace {
+
+struct Ticket {
+  ServedReq r{};
+  int64_t n = 0;
+  double t_submit = 0, t_start = 0, t_done = 0;
+  int64_t batch = -1;
+  int32_t lane = -1;
+  int32_t status = VQHULL_OK;
+  bool done = false;
+};
+
+struct Lane {
+  int index = 0;
+  Context* ctx = nullptr;
+  hipStream_t st = nullptr;
+  std::thread th;
+  // device batch buffers
+  double* sx = nullptr;
+  double* sy = nullptr;
+  int64_t* sidx = nullptr;
+  int64_t* scnt = nullptr;
+  ServedReq* d_reqs = nullptr;
+  ServedChunk* d_chunks = nullptr;
+  // pinned host tables
+  ServedReq* h_reqs = nullptr;
+  ServedChunk* h_chunks = nullptr;
+  int64_t* h_off = nullptr;
+  int64_t* h_cnt = nullptr;
+};
+
+}  // namespace
+
+struct vqhull_server {
+  vqhull_server_config cfg{};
+  int device = 0;
+  int64_t max_chunks = 0;
+  std::chrono::steady_clock::time_point t0;
+  std::vector<Lane*> lanes;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<int64_t> pending;      // ticket ids, FIFO
+  std::vector<Ticket> tickets;      // by id
+  std::deque<int64_t> unpolled;     // completed, not yet returned by poll
+  bool stopping = false;
+  int64_t batches = 0, completed = 0, points = 0, failed = 0;
+  double busy = 0;  // summed batch wall time over lanes
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+namespace {
+
+int hip_status(hipError_t e) { return e == hipErrorOutOfMemory ? VQHULL_ERR_OUT_OF_MEMORY : VQHULL_ERR_HIP; }
+
+void free_lane(Lane* L) {
+  auto f = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  auto h = [](void* p) {
+    if (p) (void)hipHostFree(p);
+  };
+  if (L->st) (void)hipStreamSynchronize(L->st);
+  f(L->sx);
+  f(L->sy);
+  f(L->sidx);
+  f(L->scnt);
+  f(L->d_reqs);
+  f(L->d_chunks);
+  h(L->h_reqs);
+  h(L->h_chunks);
+  h(L->h_off);
+  h(L->h_cnt);
+  context_destroy(L->ctx);
+  if (L->st) (void)hipStreamDestroy(L->st);
+  delete L;
+}
+
+int make_lane(vqhull_server* s, int index, Lane** out) {
+  Lane* L = new Lane();
+  L->index = index;
+  const size_t P = (size_t)s->cfg.lane_points, R = (size_t)s->cfg.lane_requests, C = (size_t)s->max_chunks;
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t r) {
+    if (e == hipSuccess && r != hipSuccess) e = r;
+  };
+  chk(hipStreamCreateWithFlags(&L->st, hipStreamNonBlocking));
+  chk(hipMalloc(&L->sx, std::max<size_t>(P, 1) * sizeof(double)));
+  chk(hipMalloc(&L->sy, std::max<size_t>(P, 1) * sizeof(double)));
+  chk(hipMalloc(&L->sidx, std::max<size_t>(P, 1) * sizeof(int64_t)));
+  chk(hipMalloc(&L->scnt, R * sizeof(int64_t)));
+  chk(hipMalloc(&L->d_reqs, R * sizeof(ServedReq)));
+  chk(hipMalloc(&L->d_chunks, C * sizeof(ServedChunk)));
+  chk(hipHostMalloc((void**)&L->h_reqs, R * sizeof(ServedReq), hipHostMallocDefault));
+  chk(hipHostMalloc((void**)&L->h_chunks, C * sizeof(ServedChunk), hipHostMallocDefault));
+  chk(hipHostMalloc((void**)&L->h_off, (R + 1) * sizeof(int64_t), hipHostMallocDefault));
+  chk(hipHostMalloc((void**)&L->h_cnt, R * sizeof(int64_t), hipHostMallocDefault));
+  if (e != hipSuccess) {
+    free_lane(L);
+    return hip_status(e);
+  }
+  int st = context_create(&L->ctx);
+  if (st == VQHULL_OK) st = context_reserve(L->ctx, (int64_t)P, (int64_t)R, L->st);
+  if (st != VQHULL_OK) {
+    free_lane(L);
+    return st;
+  }
+  *out = L;
+  return VQHULL_OK;
+}
+
+// Run one batch on lane L (the requests as copied from their tickets under the
+// server lock); returns a VQHULL status for the batch.
+int run_batch(Lane* L, const std::vector<ServedReq>& reqs) {
+  const size_t nreq = reqs.size();
+  size_t nch = 0;
+  int64_t off = 0;
+  for (size_t i = 0; i < nreq; ++i) {
+    ServedReq r = reqs[i];
+    r.off = (uint64_t)off;
+    L->h_reqs[i] = r;
+    L->h_off[i] = off;
+    const uint64_t nc = r.n > 0 ? (r.n + kServeChunk - 1) / kServeChunk : 1;
+    for (uint64_t c = 0; c < nc; ++c) L->h_chunks[nch++] = ServedChunk{(uint32_t)i, (uint32_t)(c * kServeChunk)};
+    off += (int64_t)r.n;
+  }
+  L->h_off[nreq] = off;
+  hipError_t e = hipMemcpyAsync(L->d_reqs, L->h_reqs, nreq * sizeof(ServedReq), hipMemcpyHostToDevice, L->st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(L->d_chunks, L->h_chunks, nch * sizeof(ServedChunk), hipMemcpyHostToDevice, L->st);
+  if (e == hipSuccess) e = (hipError_t)launch_gather(L->d_reqs, L->d_chunks, (uint32_t)nch, L->sx, L->sy, L->st);
+  if (e != hipSuccess) return hip_status(e);
+  const int st = context_run(L->ctx, L->sx, L->sy, L->h_off, (int64_t)nreq, L->sidx, L->scnt, L->st);
+  if (st != VQHULL_OK) return st;
+  e = (hipError_t)launch_scatter(L->d_reqs, L->d_chunks, (uint32_t)nch, L->sidx, L->scnt, L->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(L->h_cnt, L->scnt, nreq * sizeof(int64_t), hipMemcpyDeviceToHost, L->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->st);
+  return e == hipSuccess ? VQHULL_OK : hip_status(e);
+}
+
+void lane_loop(vqhull_server* s, Lane* L) {
+  (void)hipSetDevice(s->device);
+  std::vector<int64_t> ids;
+  std::vector<ServedReq> reqs;
+  for (;;) {
+    ids.clear();
+    reqs.clear();
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_work.wait(lk, [&] { return s->stopping || !s->pending.empty(); });
+      if (s->pending.empty()) return;  // stopping, nothing left
+      int64_t pts = 0;
+      while (!s->pending.empty() && (int64_t)ids.size() < s->cfg.lane_requests) {
+        const Ticket& t = s->tickets[(size_t)s->pending.front()];
+        if (!ids.empty() && pts + t.n > s->cfg.lane_points) break;
+        pts += t.n;
+        ids.push_back(s->pending.front());
+        reqs.push_back(t.r);
+        s->pending.pop_front();
+      }
+      const double ts = s->now();
+      for (int64_t id : ids) {
+        s->tickets[(size_t)id].t_start = ts;
+        s->tickets[(size_t)id].lane = L->index;
+      }
+    }
+    const double tb = s->now();
+    const int st = run_batch(L, reqs);
+    const double te = s->now();
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      const int64_t b = s->batches++;
+      s->busy += te - tb;
+      for (size_t i = 0; i < ids.size(); ++i) {
+        Ticket& t = s->tickets[(size_t)ids[i]];
+        t.batch = b;
+        t.t_done = te;
+        if (st != VQHULL_OK)
+          t.status = st;
+        else if (L->h_cnt[i] < 0)
+          t.status = (int32_t)(-L->h_cnt[i]);
+        else
+          t.status = VQHULL_OK;
+        if (t.status != VQHULL_OK) ++s->failed;
+        t.done = true;
+        s->points += t.n;
+        ++s->completed;
+        s->unpolled.push_back(ids[i]);
+      }
+    }
+    s->cv_done.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int vqhull_server_create(const vqhull_server_config* cfg, vqhull_server** out) {
+  if (!cfg || !out) return VQHULL_ERR_INVALID_ARGUMENT;
+  if (cfg->lanes < 1 || cfg->lanes > 8 || cfg->lane_points < 1 || cfg->lane_points >= (int64_t(1) << 31) ||
+      cfg->lane_requests < 1 || cfg->lane_requests > (int64_t(1) << 24))
+    return VQHULL_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  vqhull_server* s = new vqhull_server();
+  s->cfg = *cfg;
+  s->t0 = std::chrono::steady_clock::now();
+  s->max_chunks = cfg->lane_points / kServeChunk + cfg->lane_requests + 1;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return VQHULL_ERR_HIP;
+  }
+  for (int i = 0; i < cfg->lanes; ++i) {
+    Lane* L = nullptr;
+    const int st = make_lane(s, i, &L);
+    if (st != VQHULL_OK) {
+      for (Lane* l : s->lanes) free_lane(l);
+      delete s;
+      return st;
+    }
+    s->lanes.push_back(L);
+  }
+  for (Lane* L : s->lanes) L->th = std::thread(lane_loop, s, L);
+  *out = s;
+  return VQHULL_OK;
+}
+
+int vqhull_server_submit(vqhull_server* s, const double* x, const double* y, int64_t n, int64_t* out_idx,
+                         int64_t* out_count, int64_t* ticket) {
+  if (!s || !ticket || !out_count || n < 0 || n > s->cfg.lane_points) return VQHULL_ERR_INVALID_ARGUMENT;
+  if (n > 0 && (!x || !y || !out_idx)) return VQHULL_ERR_INVALID_ARGUMENT;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping) return VQHULL_ERR_INVALID_ARGUMENT;
+    Ticket t;
+    t.r.x = x;
+    t.r.y = y;
+    t.r.out_idx = out_idx;
+    t.r.out_count = out_count;
+    t.r.n = (uint64_t)n;
+    t.n = n;
+    t.t_submit = s->now();
+    *ticket = (int64_t)s->tickets.size();
+    s->tickets.push_back(t);
+    s->pending.push_back(*ticket);
+  }
+  s->cv_work.notify_one();
+  return VQHULL_OK;
+}
+
+int vqhull_server_wait(vqhull_server* s, int64_t ticket) {
+  if (!s) return VQHULL_ERR_INVALID_ARGUMENT;
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (ticket < 0 || ticket >= (int64_t)s->tickets.size()) return VQHULL_ERR_INVALID_ARGUMENT;
+  s->cv_done.wait(lk, [&] { return s->tickets[(size_t)ticket].done; });
+  return s->tickets[(size_t)ticket].status;
+}
+
+int64_t vqhull_server_poll(vqhull_server* s, int64_t* tickets, int64_t cap) {
+  if (!s || cap < 0 || (cap > 0 && !tickets)) return -VQHULL_ERR_INVALID_ARGUMENT;
+  std::lock_guard<std::mutex> lk(s->mu);
+  int64_t k = 0;
+  while (k < cap && !s->unpolled.empty()) {
+    tickets[k++] = s->unpolled.front();
+    s->unpolled.pop_front();
+  }
+  return k;
+}
+
+int vqhull_server_drain(vqhull_server* s) {
+  if (!s) return VQHULL_ERR_INVALID_ARGUMENT;
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->completed == (int64_t)s->tickets.size(); });
+  return VQHULL_OK;
+}
+
+int vqhull_server_ticket_info(vqhull_server* s, int64_t ticket, vqhull_ticket_info* out) {
+  if (!s || !out) return VQHULL_ERR_INVALID_ARGUMENT;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (ticket < 0 || ticket >= (int64_t)s->tickets.size()) return VQHULL_ERR_INVALID_ARGUMENT;
+  const Ticket& t = s->tickets[(size_t)ticket];
+  out->n = t.n;
+  out->batch = t.batch;
+  out->lane = t.lane;
+  out->status = t.status;
+  out->done = t.done ? 1 : 0;
+  out->t_submit = t.t_submit;
+  out->t_start = t.t_start;
+  out->t_done = t.t_done;
+  return VQHULL_OK;
+}
+
+int vqhull_server_stats(vqhull_server* s, vqhull_server_counters* out) {
+  if (!s || !out) return VQHULL_ERR_INVALID_ARGUMENT;
+  std::lock_guard<std::mutex> lk(s->mu);
+  out->submitted = (int64_t)s->tickets.size();
+  out->completed = s->completed;
+  out->failed = s->failed;
+  out->batches = s->batches;
+  out->points = s->points;
+  out->pending = (int64_t)s->pending.size();
+  out->busy_seconds = s->busy;
+  out->now = s->now();
+  return VQHULL_OK;
+}
+
+int vqhull_server_destroy(vqhull_server* s) {
+  if (!s) return VQHULL_ERR_INVALID_ARGUMENT;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stopping = true;
+  }
+  s->cv_work.notify_all();
+  for (Lane* L : s->lanes)
+    if (L->th.joinable()) L->th.join();
+  for (Lane* L : s->lanes) free_lane(L);
+  delete s;
+  return VQHULL_OK;
+}
+
+}  // extern "C"

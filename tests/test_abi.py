@@ -93,3 +93,25 @@ def test_python_binding_checks():
         vq.hull(torch.zeros(3, dtype=torch.float32), torch.zeros(3, dtype=torch.float32))
     with pytest.raises(ValueError):
         vq.hull(torch.zeros(3, dtype=torch.float64), torch.zeros(3, dtype=torch.float64))  # not on a GPU
+
+
+def test_server_arguments_rejected_on_host(lib):
+    import paper_2510_09417_amd as vq
+
+    vq.load_library()
+    vp = ctypes.c_void_p
+    h = vp()
+    assert lib.vqhull_server_create(None, ctypes.byref(h)) == 1
+    for lanes, pts, reqs in ((0, 1000, 10), (9, 1000, 10), (1, 0, 10), (1, 1 << 31, 10), (1, 1000, 0),
+                             (1, 1000, (1 << 24) + 1)):
+        cfg = vq.ServerConfig(lanes, 0, pts, reqs)
+        assert lib.vqhull_server_create(ctypes.byref(cfg), ctypes.byref(h)) == 1
+    t = ctypes.c_int64()
+    dummy = vp(0x1000)
+    assert lib.vqhull_server_submit(None, dummy, dummy, 5, dummy, dummy, ctypes.byref(t)) == 1
+    assert lib.vqhull_server_wait(None, 0) == 1
+    assert lib.vqhull_server_poll(None, None, 0) == -1
+    assert lib.vqhull_server_drain(None) == 1
+    assert lib.vqhull_server_ticket_info(None, 0, None) == 1
+    assert lib.vqhull_server_stats(None, None) == 1
+    assert lib.vqhull_server_destroy(None) == 1

@@ -1,0 +1,148 @@
+"""GPU tests of the continuous-batching server (vqhull_server_*, the served
+form of the batched hull): every request's result is bit-exact against the
+CPU oracle and identical to the same request computed alone by vqhull_hull,
+whatever batch it lands in; requests submitted while batches run are admitted
+by the next free lane; errors stay with their request."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_09417_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vq():
+    import torch
+
+    import paper_2510_09417_amd as vq
+
+    assert torch.cuda.is_available()
+    vq.load_library()
+    vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048, reverse_tiles=0, sweep_persistent=1)
+    return vq
+
+
+def _requests(nreq, max_n, seed):
+    sizes, dists, _ = workloads.served_plan(nreq, seed=seed)
+    sizes = np.minimum(sizes, max_n)
+    return [(i, int(sizes[i]), int(dists[i])) for i in range(nreq)]
+
+
+def _device(x, y):
+    import torch
+
+    return torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+
+
+def test_mix_matches_oracle_and_alone(vq):
+    import torch
+
+    reqs = _requests(240, 150_000, seed=11)
+    reqs += [(240, 0, 0), (241, 1, 1), (242, 2, 2), (243, 3, 3), (244, 2049, 0)]
+    data = []
+    for i, n, d in reqs:
+        x, y = workloads.served_request(i, n, d, seed=11)
+        tx, ty = _device(x, y)
+        data.append((x, y, tx, ty, torch.empty(max(n, 1), dtype=torch.int64, device="cuda"),
+                     torch.empty(1, dtype=torch.int64, device="cuda")))
+    torch.cuda.synchronize()
+    with vq.Server(lanes=3, lane_points=1 << 19, lane_requests=48) as srv:
+        tickets = []
+        for k, (_, _, tx, ty, oi, oc) in enumerate(data):
+            tickets.append(srv.submit(tx, ty, oi, oc))
+            if k % 40 == 39:
+                time.sleep(0.002)  # later requests arrive while batches run
+        for t in tickets:
+            assert srv.wait(t) == vq.VQHULL_OK
+        st = srv.stats()
+        infos = [srv.info(t) for t in tickets]
+    assert st["completed"] == len(reqs) and st["failed"] == 0 and st["batches"] >= 4
+    lanes = {inf["lane"] for inf in infos}
+    assert len(lanes) >= 2, "only one lane was used"
+    for inf in infos:
+        assert inf["done"] == 1 and inf["t_submit"] <= inf["t_start"] <= inf["t_done"]
+    for (x, y, tx, ty, oi, oc), (i, n, d) in zip(data, reqs):
+        h = int(oc.item())
+        got = oi[:h].cpu().numpy()
+        want = oracle.hull(x, y)
+        assert np.array_equal(got, want), f"request {i} n={n} {workloads.DISTRIBUTIONS[d]}"
+        alone = vq.hull(tx, ty).cpu().numpy()
+        assert np.array_equal(got, alone)
+
+
+def test_submit_from_several_threads_and_poll(vq):
+    import torch
+
+    reqs = _requests(96, 60_000, seed=12)
+    data = {}
+    for i, n, d in reqs:
+        x, y = workloads.served_request(i, n, d, seed=12)
+        tx, ty = _device(x, y)
+        data[i] = (x, y, tx, ty, torch.empty(max(n, 1), dtype=torch.int64, device="cuda"),
+                   torch.empty(1, dtype=torch.int64, device="cuda"))
+    torch.cuda.synchronize()
+    tickets = {}
+    lock = threading.Lock()
+    with vq.Server(lanes=2, lane_points=1 << 18, lane_requests=16) as srv:
+        def worker(part):
+            for i in part:
+                _, _, tx, ty, oi, oc = data[i]
+                t = srv.submit(tx, ty, oi, oc)
+                with lock:
+                    tickets[t] = i
+
+        ths = [threading.Thread(target=worker, args=([i for i, _, _ in reqs][k::4],)) for k in range(4)]
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join()
+        srv.drain()
+        seen = srv.poll(cap=1000)
+        assert sorted(seen) == sorted(tickets) and srv.poll() == []
+    for t, i in tickets.items():
+        x, y, _, _, oi, oc = data[i]
+        assert np.array_equal(oi[:int(oc.item())].cpu().numpy(), oracle.hull(x, y)), f"request {i}"
+
+
+def test_nonfinite_request_is_isolated(vq):
+    import torch
+
+    outs = []
+    with vq.Server(lanes=1, lane_points=1 << 16, lane_requests=8) as srv:
+        tks = []
+        for k in range(3):
+            x, y = workloads.points("disk", 5000, seed=[13, k])
+            if k == 1:
+                y[77] = np.nan
+            tx, ty = _device(x, y)
+            oi = torch.empty(5000, dtype=torch.int64, device="cuda")
+            oc = torch.empty(1, dtype=torch.int64, device="cuda")
+            outs.append((x, y, tx, ty, oi, oc))
+            tks.append(srv.submit(tx, ty, oi, oc))
+        status = [srv.wait(t) for t in tks]
+    assert status == [vq.VQHULL_OK, vq.VQHULL_ERR_NONFINITE, vq.VQHULL_OK]
+    assert int(outs[1][5].item()) == -vq.VQHULL_ERR_NONFINITE
+    for k in (0, 2):
+        x, y, _, _, oi, oc = outs[k]
+        assert np.array_equal(oi[:int(oc.item())].cpu().numpy(), oracle.hull(x, y))
+
+
+def test_request_larger_than_a_lane_is_rejected(vq):
+    import torch
+
+    x, y = _device(*workloads.points("square", 5000, seed=14))
+    oi = torch.empty(5000, dtype=torch.int64, device="cuda")
+    oc = torch.empty(1, dtype=torch.int64, device="cuda")
+    with vq.Server(lanes=1, lane_points=4096, lane_requests=4) as srv:
+        with pytest.raises(vq.VqhullError) as e:
+            srv.submit(x, y, oi, oc)
+        assert e.value.status == vq.VQHULL_ERR_INVALID_ARGUMENT
+        t = srv.submit(x[:4096], y[:4096], oi, oc)  # exactly a lane fits
+        assert srv.wait(t) == vq.VQHULL_OK
+        xs, ys = x[:4096].cpu().numpy(), y[:4096].cpu().numpy()
+        assert np.array_equal(oi[:int(oc.item())].cpu().numpy(), oracle.hull(xs, ys))

@@ -15,6 +15,13 @@ Prints one JSON line:
               average duration, from HIP events recorded on the launch stream
               during the timed steps, against 8 TB/s;
   cpu_baseline  the CPU oracle (single thread) on one whole step.
+  served      the served mix (65,536 requests, sizes log-uniform in [16, 10^6],
+              disk / square / circle / Kuzmin in equal shares, drawn on the GPU):
+              hulls/s with every request submitted at once; p50 / p99 latency
+              (submit to results written) under Poisson arrivals at half that
+              rate; the plain path (one vqhull_hull call per request) on a
+              time-boxed prefix of the same mix; and a check that served results
+              equal the plain path's on a sample.
 
 Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2]
 """
@@ -56,12 +63,131 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
+def percentile(v, q):
+    v = sorted(v)
+    return v[min(len(v) - 1, int(q * len(v)))]
+
+
+def served_benchmark(vq, workloads, torch, nreq: int, lanes: int) -> dict:
+    """The served mix through vqhull_server_*, against the plain per-request path."""
+    import numpy as np
+
+    sizes, dists, _ = workloads.served_plan(nreq)
+    total = int(sizes.sum())
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    X = torch.empty(total, dtype=torch.float64, device=dev)
+    Y = torch.empty(total, dtype=torch.float64, device=dev)
+    OUT = torch.empty(total, dtype=torch.int64, device=dev)
+    CNT = torch.empty(nreq, dtype=torch.int64, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(workloads.SERVED_SEED)
+    for d, name in enumerate(workloads.DISTRIBUTIONS):  # one draw per distribution, split into requests
+        idx = np.nonzero(dists == d)[0]
+        for lo in range(0, len(idx), 4096):
+            part = idx[lo:lo + 4096]
+            m = int(sizes[part].sum())
+            bx = torch.empty(m, dtype=torch.float64, device=dev)
+            by = torch.empty(m, dtype=torch.float64, device=dev)
+            workloads.device_points_into(name, bx, by, gen)
+            k = 0
+            for i in part:
+                n = int(sizes[i])
+                X[off[i]:off[i] + n].copy_(bx[k:k + n])
+                Y[off[i]:off[i] + n].copy_(by[k:k + n])
+                k += n
+    torch.cuda.synchronize()
+    log(f"served mix: {nreq} requests, {total} points, generated in {time.perf_counter() - t0:.1f}s")
+    # device addresses of every request's arrays (float64 / int64: 8 bytes per entry)
+    px = X.data_ptr() + 8 * off[:-1]
+    py = Y.data_ptr() + 8 * off[:-1]
+    po = OUT.data_ptr() + 8 * off[:-1]
+    pc = CNT.data_ptr() + 8 * np.arange(nreq, dtype=np.int64)
+    lane_points = 1 << 25
+
+    def run(arrivals):
+        """Submit request i at arrivals[i] seconds (all that are due in one call)."""
+        srv = vq.Server(lanes=lanes, lane_points=lane_points, lane_requests=8192)
+        try:
+            m = len(arrivals)
+            first = None
+            i = 0
+            t_start = time.perf_counter()
+            while i < m:
+                now = time.perf_counter() - t_start
+                j = int(np.searchsorted(arrivals, now, side="right"))
+                if j <= i:
+                    continue
+                t = srv.submit_pointers(px[i:j], py[i:j], sizes[i:j], po[i:j], pc[i:j])
+                first = t if first is None else first
+                i = j
+            srv.drain()
+            infos = [srv.info(first + k) for k in range(m)]
+            st = srv.stats()
+        finally:
+            srv.close()
+        return infos, st
+
+    # warm-up (lane allocation, first launches)
+    run(np.zeros(min(nreq, 256)))
+    infos, st = run(np.zeros(nreq))
+    t_first = min(i["t_submit"] for i in infos)
+    t_last = max(i["t_done"] for i in infos)
+    thr = nreq / (t_last - t_first)
+    bad = sum(1 for i in infos if i["status"] != 0)
+    log(f"served throughput: {thr:.0f} hulls/s over {st['batches']} batches")
+    counts_served = CNT.cpu().numpy().copy()
+
+    # latency under Poisson arrivals at half the measured throughput
+    nlat = min(nreq, 16384)
+    g = np.random.default_rng(workloads.SERVED_SEED + 1)
+    arr = np.cumsum(-np.log1p(-g.random(nlat)) / (0.5 * thr))
+    linfos, lst = run(arr)
+    lat = [1e3 * (i["t_done"] - i["t_submit"]) for i in linfos]
+
+    # plain path: one synchronous vqhull_hull per request, time-boxed
+    stream = torch.cuda.current_stream()
+    oi = torch.empty(1 << 20, dtype=torch.int64, device=dev)
+    oc = torch.empty(1, dtype=torch.int64, device=dev)
+    plain_lat, same = [], 0
+    tp0 = time.perf_counter()
+    i = 0
+    while i < nreq and time.perf_counter() - tp0 < 15.0:
+        a = time.perf_counter()
+        vq.hull_into(X[off[i]:off[i + 1]], Y[off[i]:off[i + 1]], oi, oc, stream)
+        h = int(oc.item())
+        plain_lat.append(1e3 * (time.perf_counter() - a))
+        if i < 512:
+            same += int(h == counts_served[i] and torch.equal(oi[:max(h, 0)], OUT[off[i]:off[i] + max(h, 0)]))
+        i += 1
+    plain_thr = len(plain_lat) / (time.perf_counter() - tp0)
+    checked = min(i, 512)
+    log(f"plain path: {plain_thr:.0f} hulls/s over {len(plain_lat)} requests; served == plain on {same}/{checked}")
+    return {
+        "workload": f"{nreq} requests, sizes log-uniform in [16, 1e6] (seed {workloads.SERVED_SEED}), "
+                    f"disk/square/circle/kuzmin, {total} points, drawn on the GPU",
+        "lanes": lanes, "lane_points": lane_points,
+        "hulls_per_s": round(thr, 1),
+        "gpoints_per_s": round(total / (t_last - t_first) / 1e9, 3),
+        "batches": st["batches"], "failed": bad,
+        "latency_load_hulls_per_s": round(0.5 * thr, 1), "latency_requests": nlat,
+        "p50_ms": round(percentile(lat, 0.50), 3), "p99_ms": round(percentile(lat, 0.99), 3),
+        "plain_hulls_per_s": round(plain_thr, 1), "plain_requests": len(plain_lat),
+        "plain_p50_ms": round(percentile(plain_lat, 0.50), 3), "plain_p99_ms": round(percentile(plain_lat, 0.99), 3),
+        "served_equals_plain": f"{same}/{checked}",
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=65536)
+    ap.add_argument("--served-lanes", type=int, default=4)
     ap.add_argument("--n", type=int, default=100_000_000, help="points per dataset (default 1e8)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -176,6 +302,12 @@ def main() -> int:
         "frac_of_stream_scale": round(achieved / probe_gbs, 4),
     }
 
+    served = None
+    if not args.no_served:
+        del dx, outs
+        torch.cuda.empty_cache()
+        served = served_benchmark(vq, workloads, torch, args.served_requests, args.served_lanes)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -208,6 +340,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernel_ms_per_step": {k: round(v / args.steps, 4) for k, v in per_kind.items()},
+        "served": served,
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -228,6 +228,17 @@ int vqhull_server_create(const vqhull_server_config* cfg, vqhull_server** out);
 int vqhull_server_submit(vqhull_server* s, const double* x, const double* y, int64_t n, int64_t* out_idx,
                          int64_t* out_count, int64_t* ticket);
 
+/*
+ * Queue count requests at once, in array order (same rules as
+ * vqhull_server_submit per request).  x, y, n, out_idx, out_count are HOST
+ * arrays of count entries (x[i], y[i], out_idx[i], out_count[i] being device
+ * pointers); the requests get tickets *first_ticket .. *first_ticket+count-1.
+ * All requests are checked before any is queued.
+ */
+int vqhull_server_submit_batch(vqhull_server* s, int64_t count, const double* const* x, const double* const* y,
+                               const int64_t* n, int64_t* const* out_idx, int64_t* const* out_count,
+                               int64_t* first_ticket);
+
 /* Block until the request is done; returns its status (VQHULL_OK,
  * VQHULL_ERR_NONFINITE, ...) or VQHULL_ERR_INVALID_ARGUMENT for an unknown ticket. */
 int vqhull_server_wait(vqhull_server* s, int64_t ticket);

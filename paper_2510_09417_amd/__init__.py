@@ -25,7 +25,7 @@ EXPORTED = (
     "vqhull_hull", "vqhull_hull_batched", "vqhull_get_config", "vqhull_set_config",
     "vqhull_last_level_stats", "vqhull_set_timing", "vqhull_last_kernel_times", "vqhull_stream_scale",
     "vqhull_release_workspace", "vqhull_status_string", "vqhull_last_error",
-    "vqhull_server_create", "vqhull_server_submit", "vqhull_server_wait", "vqhull_server_poll",
+    "vqhull_server_create", "vqhull_server_submit", "vqhull_server_submit_batch", "vqhull_server_wait", "vqhull_server_poll",
     "vqhull_server_drain", "vqhull_server_ticket_info", "vqhull_server_stats", "vqhull_server_destroy",
 )
 
@@ -109,6 +109,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.vqhull_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
         lib.vqhull_server_submit.restype = ci
         lib.vqhull_server_submit.argtypes = [vp, vp, vp, i64, vp, vp, pi64]
+        lib.vqhull_server_submit_batch.restype = ci
+        lib.vqhull_server_submit_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, pi64]
         lib.vqhull_server_wait.restype = ci
         lib.vqhull_server_wait.argtypes = [vp, i64]
         lib.vqhull_server_poll.restype = i64
@@ -296,6 +298,23 @@ class Server:
         _check(self._lib, self._lib.vqhull_server_submit(
             self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), x.numel(),
             ctypes.c_void_p(out_idx.data_ptr()), ctypes.c_void_p(out_count.data_ptr()), ctypes.byref(t)))
+        return t.value
+
+    def submit_pointers(self, x_ptrs, y_ptrs, sizes, out_ptrs, count_ptrs) -> int:
+        """Queue len(sizes) requests given as numpy int64 arrays of device
+        addresses (x, y, out_idx, out_count per request) and sizes, with one
+        library call; returns the first ticket (the others follow in order).
+        The caller guarantees the addresses (float64 / int64 device buffers)."""
+        import numpy as np
+
+        arrs = [np.ascontiguousarray(a, dtype=np.int64) for a in (x_ptrs, y_ptrs, sizes, out_ptrs, count_ptrs)]
+        k = len(arrs[2])
+        if any(len(a) != k for a in arrs):
+            raise ValueError("all arrays need one entry per request")
+        t = ctypes.c_int64()
+        ptr = lambda a: ctypes.c_void_p(a.ctypes.data)
+        _check(self._lib, self._lib.vqhull_server_submit_batch(self._h, k, *[ptr(a) for a in arrs],
+                                                                ctypes.byref(t)))
         return t.value
 
     def wait(self, ticket: int) -> int:

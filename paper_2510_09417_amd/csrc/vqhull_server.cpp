@@ -281,6 +281,37 @@ int vqhull_server_submit(vqhull_server* s, const double* x, const double* y, int
   return VQHULL_OK;
 }
 
+int vqhull_server_submit_batch(vqhull_server* s, int64_t count, const double* const* x, const double* const* y,
+                               const int64_t* n, int64_t* const* out_idx, int64_t* const* out_count,
+                               int64_t* first_ticket) {
+  if (!s || !first_ticket || count < 0) return VQHULL_ERR_INVALID_ARGUMENT;
+  if (count > 0 && (!x || !y || !n || !out_idx || !out_count)) return VQHULL_ERR_INVALID_ARGUMENT;
+  for (int64_t i = 0; i < count; ++i) {
+    if (!out_count[i] || n[i] < 0 || n[i] > s->cfg.lane_points) return VQHULL_ERR_INVALID_ARGUMENT;
+    if (n[i] > 0 && (!x[i] || !y[i] || !out_idx[i])) return VQHULL_ERR_INVALID_ARGUMENT;
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping) return VQHULL_ERR_INVALID_ARGUMENT;
+    const double now = s->now();
+    *first_ticket = (int64_t)s->tickets.size();
+    for (int64_t i = 0; i < count; ++i) {
+      Ticket t;
+      t.r.x = x[i];
+      t.r.y = y[i];
+      t.r.out_idx = out_idx[i];
+      t.r.out_count = out_count[i];
+      t.r.n = (uint64_t)n[i];
+      t.n = n[i];
+      t.t_submit = now;
+      s->pending.push_back((int64_t)s->tickets.size());
+      s->tickets.push_back(t);
+    }
+  }
+  s->cv_work.notify_all();
+  return VQHULL_OK;
+}
+
 int vqhull_server_wait(vqhull_server* s, int64_t ticket) {
   if (!s) return VQHULL_ERR_INVALID_ARGUMENT;
   std::unique_lock<std::mutex> lk(s->mu);

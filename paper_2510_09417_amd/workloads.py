@@ -143,3 +143,37 @@ def served_plan(nreq: int = SERVED_REQUESTS, rate: float = 1.0, seed: int = SERV
 def served_request(i: int, n: int, dist_index: int, seed: int = SERVED_SEED):
     """Points of request ``i`` of the served mix."""
     return points(DISTRIBUTIONS[dist_index], int(n), [seed, int(i)])
+
+
+def device_points_into(dist: str, x, y, generator) -> None:
+    """Fill the float64 GPU tensors x and y (same length) with points of
+    ``dist`` drawn on the device from a seeded torch generator: the same
+    formulas as ``points`` with the device's random numbers (used where host
+    generation would take too long, e.g. the full served mix)."""
+    import torch
+
+    n = x.numel()
+    if n == 0:
+        return
+    u1 = torch.rand(n, dtype=torch.float64, device=x.device, generator=generator)
+    u2 = torch.rand(n, dtype=torch.float64, device=x.device, generator=generator)
+    if dist == "square":
+        x.copy_(u1)
+        y.copy_(u2)
+        return
+    if dist == "circle":
+        theta = u1.mul_(2.0 * math.pi)
+        torch.cos(theta, out=x)
+        torch.sin(theta, out=y)
+        return
+    if dist == "disk":
+        r = u1.sqrt_()
+    elif dist == "kuzmin":
+        r = u1.neg_().add_(1.0).square_().reciprocal_().sub_(1.0).sqrt_()
+    else:
+        raise ValueError(f"unknown distribution {dist!r}")
+    theta = u2.mul_(2.0 * math.pi)
+    torch.cos(theta, out=x)
+    torch.sin(theta, out=y)
+    x.mul_(r)
+    y.mul_(r)

@@ -109,6 +109,7 @@ def test_server_arguments_rejected_on_host(lib):
     t = ctypes.c_int64()
     dummy = vp(0x1000)
     assert lib.vqhull_server_submit(None, dummy, dummy, 5, dummy, dummy, ctypes.byref(t)) == 1
+    assert lib.vqhull_server_submit_batch(None, 1, dummy, dummy, dummy, dummy, dummy, ctypes.byref(t)) == 1
     assert lib.vqhull_server_wait(None, 0) == 1
     assert lib.vqhull_server_poll(None, None, 0) == -1
     assert lib.vqhull_server_drain(None) == 1

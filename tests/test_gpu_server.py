@@ -146,3 +146,31 @@ def test_request_larger_than_a_lane_is_rejected(vq):
         assert srv.wait(t) == vq.VQHULL_OK
         xs, ys = x[:4096].cpu().numpy(), y[:4096].cpu().numpy()
         assert np.array_equal(oi[:int(oc.item())].cpu().numpy(), oracle.hull(xs, ys))
+
+
+def test_submit_pointers_batch_path(vq):
+    """The one-call submission of many requests (device addresses in host
+    arrays), as the benchmark uses it, on requests packed in one buffer."""
+    import torch
+
+    reqs = _requests(150, 40_000, seed=15)
+    xs, ys = [], []
+    for i, n, d in reqs:
+        x, y = workloads.served_request(i, n, d, seed=15)
+        xs.append(x)
+        ys.append(y)
+    sizes = np.array([n for _, n, _ in reqs], dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    X = torch.from_numpy(np.concatenate(xs)).cuda()
+    Y = torch.from_numpy(np.concatenate(ys)).cuda()
+    OUT = torch.full((int(off[-1]),), -7, dtype=torch.int64, device="cuda")
+    CNT = torch.full((len(reqs),), -7, dtype=torch.int64, device="cuda")
+    with vq.Server(lanes=2, lane_points=1 << 18, lane_requests=32) as srv:
+        first = srv.submit_pointers(X.data_ptr() + 8 * off[:-1], Y.data_ptr() + 8 * off[:-1], sizes,
+                                    OUT.data_ptr() + 8 * off[:-1], CNT.data_ptr() + 8 * np.arange(len(reqs)))
+        srv.drain()
+        assert [srv.info(first + k)["status"] for k in range(len(reqs))] == [0] * len(reqs)
+    cnt = CNT.cpu().numpy()
+    out = OUT.cpu().numpy()
+    for k in range(len(reqs)):
+        assert np.array_equal(out[off[k]:off[k] + cnt[k]], oracle.hull(xs[k], ys[k])), f"request {k}"

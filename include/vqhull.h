@@ -118,6 +118,26 @@ typedef struct {
 int vqhull_get_config(vqhull_config* cfg);
 int vqhull_set_config(const vqhull_config* cfg);
 
+/*
+ * Autotuner: compute the hull of x[0..n) (device arrays, 1 <= n < 2^31) under
+ * every supported configuration -- sweep shapes 256x16, 256x32, 512x8, 512x16,
+ * 1024x8; LDS thresholds 512, 1024, 2048; persistent or one workgroup per tile
+ * -- timing `repeats` runs of each (median wall time, after one warm-up run)
+ * and checking that each result equals the first configuration's.  *best
+ * receives the fastest configuration whose result is equal; up to cap entries
+ * (host array) receive the table and *count the number of configurations
+ * tried.  The library's current configuration is not changed.  Allocates
+ * 8 n + 8 bytes of device memory for the duration of the call.
+ */
+typedef struct {
+  vqhull_config cfg;
+  double ms;          /* median wall time of one hull call */
+  int32_t same_result;/* 1 if the index list equals the first configuration's */
+  int32_t reserved;
+} vqhull_tune_entry;
+int vqhull_autotune(const double* x, const double* y, int64_t n, int32_t repeats, vqhull_tune_entry* entries,
+                    int64_t cap, int64_t* count, vqhull_config* best, vqhull_stream_t stream);
+
 /* Per-level statistics of the last hull call on this device (host pointer,
  * up to cap entries of 4 int64: live subproblems, points swept, subproblems
  * finished in LDS, points finished in LDS).  Returns the number of levels. */

@@ -22,7 +22,7 @@ VQHULL_ERR_HIP = 4
 
 # Symbols that include/vqhull.h declares.
 EXPORTED = (
-    "vqhull_hull", "vqhull_hull_batched", "vqhull_get_config", "vqhull_set_config",
+    "vqhull_hull", "vqhull_hull_batched", "vqhull_get_config", "vqhull_set_config", "vqhull_autotune",
     "vqhull_last_level_stats", "vqhull_set_timing", "vqhull_last_kernel_times", "vqhull_stream_scale",
     "vqhull_release_workspace", "vqhull_status_string", "vqhull_last_error",
     "vqhull_server_create", "vqhull_server_submit", "vqhull_server_submit_batch", "vqhull_server_wait", "vqhull_server_poll",
@@ -44,6 +44,11 @@ class Config(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("cfg", Config), ("ms", ctypes.c_double), ("same_result", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class KernelTime(ctypes.Structure):
@@ -90,6 +95,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.vqhull_get_config.argtypes = [ctypes.POINTER(Config)]
         lib.vqhull_set_config.restype = ctypes.c_int
         lib.vqhull_set_config.argtypes = [ctypes.POINTER(Config)]
+        lib.vqhull_autotune.restype = ctypes.c_int
+        lib.vqhull_autotune.argtypes = [vp, vp, i64, ctypes.c_int32, ctypes.POINTER(TuneEntry), i64, pi64,
+                                        ctypes.POINTER(Config), vp]
         lib.vqhull_last_level_stats.restype = i64
         lib.vqhull_last_level_stats.argtypes = [pi64, i64]
         lib.vqhull_set_timing.restype = ctypes.c_int
@@ -268,6 +276,23 @@ def stream_scale(src, dst, s: float = 3.0, stream=None) -> None:
 def release_workspace() -> None:
     lib = load_library()
     _check(lib, lib.vqhull_release_workspace())
+
+
+def autotune_table(x, y, repeats: int = 3, stream=None):
+    """Run vqhull_autotune on (x, y): returns (best config dict, list of
+    {config, ms, same_result}).  The library's configuration is unchanged."""
+    _check_points(x, y)
+    lib = load_library()
+    cap = 64
+    entries = (TuneEntry * cap)()
+    count = ctypes.c_int64()
+    best = Config()
+    _check(lib, lib.vqhull_autotune(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), x.numel(),
+                                    repeats, entries, cap, ctypes.byref(count), ctypes.byref(best),
+                                    _stream_handle(stream)))
+    table = [{"config": entries[i].cfg.as_dict(), "ms": entries[i].ms, "same_result": bool(entries[i].same_result)}
+             for i in range(min(count.value, cap))]
+    return best.as_dict(), table
 
 
 class Server:

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -480,9 +481,8 @@ Caps reserve(Context& w, const vqhull_config& cfg, size_t N, size_t nreq, size_t
   return c;
 }
 
-void run(Context& w, const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
-         int64_t* out_counts, hipStream_t st) {
-  const vqhull_config cfg = current_config();
+void run(Context& w, const vqhull_config& cfg, const double* x, const double* y, const int64_t* offsets, int64_t nreq,
+         int64_t* out_idx, int64_t* out_counts, hipStream_t st) {
   const uint32_t tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
   const uint32_t lds_limit = (uint32_t)cfg.lds_limit;
   const size_t N = (size_t)offsets[nreq];
@@ -548,7 +548,9 @@ int guard_status(F&& f) {
 
 int guarded(const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
             int64_t* out_counts, vqhull_stream_t stream) {
-  return guard_status([&] { run(default_context(), x, y, offsets, nreq, out_idx, out_counts, (hipStream_t)stream); });
+  return guard_status([&] {
+    run(default_context(), current_config(), x, y, offsets, nreq, out_idx, out_counts, (hipStream_t)stream);
+  });
 }
 
 }  // namespace
@@ -588,7 +590,8 @@ int context_reserve(Context* c, int64_t npoints, int64_t nreq, void* stream) {
 int context_run(Context* c, const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
                 int64_t* out_counts, void* stream) {
   if (nreq == 0) return VQHULL_OK;
-  return guard_status([&] { run(*c, x, y, offsets, nreq, out_idx, out_counts, (hipStream_t)stream); });
+  return guard_status(
+      [&] { run(*c, current_config(), x, y, offsets, nreq, out_idx, out_counts, (hipStream_t)stream); });
 }
 
 const char* context_last_error() { return g_last_error.c_str(); }
@@ -615,6 +618,66 @@ int vqhull_hull_batched(const double* x, const double* y, const int64_t* offsets
   if (offsets[nreq] >= (int64_t(1) << 31)) return VQHULL_ERR_INVALID_ARGUMENT;
   if (offsets[nreq] > 0 && (!x || !y)) return VQHULL_ERR_INVALID_ARGUMENT;
   return guarded(x, y, offsets, nreq, out_idx, out_counts, stream);
+}
+
+int vqhull_autotune(const double* x, const double* y, int64_t n, int32_t repeats, vqhull_tune_entry* entries,
+                    int64_t cap, int64_t* count, vqhull_config* best, vqhull_stream_t stream) {
+  if (n < 1 || n >= (int64_t(1) << 31) || !x || !y || repeats < 1 || repeats > 100 || !count || !best ||
+      cap < 0 || (cap > 0 && !entries))
+    return VQHULL_ERR_INVALID_ARGUMENT;
+  static const int shapes[][2] = {{256, 16}, {256, 32}, {512, 8}, {512, 16}, {1024, 8}};
+  static const int lds_limits[] = {512, 1024, 2048};
+  std::vector<vqhull_config> cands;
+  for (const auto& sh : shapes)
+    for (int lds : lds_limits)
+      for (int pers = 1; pers >= 0; --pers) cands.push_back(sanitized(vqhull_config{sh[0], sh[1], lds, 0, pers}));
+  hipStream_t st = (hipStream_t)stream;
+  int64_t* d_idx = nullptr;
+  int64_t* d_cnt = nullptr;
+  int status = guard_status([&] {
+    ck(hipMalloc(&d_idx, (size_t)n * sizeof(int64_t)), "hipMalloc");
+    ck(hipMalloc(&d_cnt, sizeof(int64_t)), "hipMalloc");
+  });
+  std::vector<int64_t> ref, cur;
+  int64_t ref_cnt = 0;
+  double best_ms = 1e300;
+  int64_t k = 0;
+  const int64_t offsets[2] = {0, n};
+  for (size_t c = 0; c < cands.size() && status == VQHULL_OK; ++c) {
+    std::vector<double> ms;
+    int64_t cnt = 0;
+    status = guard_status([&] {
+      Context& w = default_context();
+      for (int r = 0; r <= repeats; ++r) {  // the first run warms up
+        ck(hipStreamSynchronize(st), "hipStreamSynchronize");
+        const auto t0 = std::chrono::steady_clock::now();
+        run(w, cands[c], x, y, offsets, 1, d_idx, d_cnt, st);  // returns after the result is written
+        const auto t1 = std::chrono::steady_clock::now();
+        if (r) ms.push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
+      }
+      ck(hipMemcpy(&cnt, d_cnt, sizeof(int64_t), hipMemcpyDeviceToHost), "hipMemcpy");
+      cur.assign((size_t)std::max<int64_t>(cnt, 0), 0);
+      if (cnt > 0) ck(hipMemcpy(cur.data(), d_idx, (size_t)cnt * sizeof(int64_t), hipMemcpyDeviceToHost), "hipMemcpy");
+    });
+    if (status != VQHULL_OK) break;
+    std::sort(ms.begin(), ms.end());
+    const double med = ms[ms.size() / 2];
+    if (c == 0) {
+      ref = cur;
+      ref_cnt = cnt;
+    }
+    const bool same = cnt == ref_cnt && cur == ref;
+    if (k < cap) entries[k] = vqhull_tune_entry{cands[c], med, same ? 1 : 0, 0};
+    ++k;
+    if (same && med < best_ms) {
+      best_ms = med;
+      *best = cands[c];
+    }
+  }
+  if (d_idx) (void)hipFree(d_idx);
+  if (d_cnt) (void)hipFree(d_cnt);
+  *count = k;
+  return status;
 }
 
 int vqhull_get_config(vqhull_config* cfg) {

@@ -1220,12 +1220,14 @@ struct FinishShared {
   uint32_t ord[2][TMAX];
   uint16_t sa[2][TMAX / 2], sr[2][TMAX / 2], sb[2][TMAX / 2], snode[2][TMAX / 2];
   uint32_t ccnt[TMAX];
+  unsigned long long cmax[TMAX];  // largest key of each child (bits of a positive double)
+  uint32_t ctie[TMAX];            // points of each child that reach that key
   uint16_t cwin[TMAX], cnode[TMAX], cbase[TMAX], cmap[TMAX];
   uint16_t nv[TMAX], nc0[TMAX], nc1[TMAX], nsz[TMAX], nst[TMAX];
   uint16_t lvl[TMAX + 2];
   uint16_t bigc[TMAX / kSmallChild + 2];
   uint32_t scan[3][BLOCK / 64];
-  uint32_t nsub, ntot, nnode, nlvl, bad, nbigc;
+  uint32_t nsub, ntot, nnode, nlvl, bad, nbigc, anytie;
 };
 
 template <int BLOCK, int TMAX>
@@ -1282,17 +1284,28 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
   int cb = 0;  // live list buffer / sub-subproblem table of this level
   while (S.nsub > 0) {
     const uint32_t nsub = S.nsub, ntot = S.ntot, nch = 2u * nsub;
-    for (uint32_t c = tid; c < nch; c += BLOCK) S.ccnt[c] = 0;
-    if (tid == 0) S.nbigc = 0;
+    for (uint32_t c = tid; c < nch; c += BLOCK) {
+      S.ccnt[c] = 0;
+      S.cmax[c] = 0ull;
+      S.ctie[c] = 0;
+    }
+    if (tid == 0) {
+      S.nbigc = 0;
+      S.anytie = 0;
+    }
     __syncthreads();
-    // 1. classify
+    // 1. classify; the key of a point in its child (the orientation value that
+    //    put it there, > 0) also enters the child's maximum: for positive
+    //    doubles the bit patterns order like the values.
     uint32_t chd[KP], slot[KP], pid[KP];
+    unsigned long long kb[KP];
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       const uint32_t e = tid + k * BLOCK;
       chd[k] = kNone;
       slot[k] = 0;
       pid[k] = 0;
+      kb[k] = 0ull;
       if (e < ntot) {
         const uint32_t ent = S.ord[cb][e];
         const uint32_t s = ent >> 16, l = ent & 0xFFFFu;
@@ -1300,13 +1313,22 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
         const double ux = S.lx[l], uy = S.ly[l];
         const double o1 = orient(S.lx[a], S.ly[a], S.lx[r], S.ly[r], ux, uy);
         uint32_t c = kNone;
+        double key = 0.0;
         if (o1 > 0.0) {
           c = 2u * s;
+          key = o1;
         } else {
           const double o2 = orient(S.lx[r], S.ly[r], S.lx[b], S.ly[b], ux, uy);
-          if (o2 > 0.0) c = 2u * s + 1u;
+          if (o2 > 0.0) {
+            c = 2u * s + 1u;
+            key = o2;
+          }
         }
-        if (c != kNone) slot[k] = atomicAdd(&S.ccnt[c], 1u);
+        if (c != kNone) {
+          slot[k] = atomicAdd(&S.ccnt[c], 1u);
+          kb[k] = __builtin_bit_cast(unsigned long long, key);
+          atomicMax(&S.cmax[c], kb[k]);
+        }
         chd[k] = c;
         pid[k] = l;
       }
@@ -1351,23 +1373,33 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
       }
     }
     __syncthreads();
-    // 3. scatter
+    // 3. scatter; the point holding its child's largest key is the child's
+    //    farthest point unless another point of the child has the same key
+    //    (then the full order decides below).
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       const uint32_t c = chd[k];
       if (c != kNone) {
         if (S.ccnt[c] >= 2u) {
           S.ord[cb ^ 1][S.cbase[c] + slot[k]] = ((uint32_t)S.cmap[c] << 16) | pid[k];
+          if (kb[k] == S.cmax[c]) {
+            if (atomicAdd(&S.ctie[c], 1u) == 0u)
+              S.cwin[c] = (uint16_t)pid[k];
+            else
+              S.anytie = 1u;
+          }
         } else {
           S.cwin[c] = (uint16_t)pid[k];
         }
       }
     }
     __syncthreads();
-    // 4. farthest point of every child with >= 2 points
+    // 4. children whose largest key is shared by several points: farthest
+    //    point by the full order (key, then x, y, index)
+    if (S.anytie) {
     for (uint32_t c = tid; c < nch; c += BLOCK) {
       const uint32_t n = S.ccnt[c];
-      if (n < 2u || n > kSmallChild) continue;
+      if (n < 2u || n > kSmallChild || S.ctie[c] < 2u) continue;
       const uint32_t s = c >> 1;
       const uint32_t ea = (c & 1u) ? S.sr[cb][s] : S.sa[cb][s];
       const uint32_t eb = (c & 1u) ? S.sb[cb][s] : S.sr[cb][s];
@@ -1390,6 +1422,7 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
     const uint32_t nbigc = S.nbigc;
     for (uint32_t b = w; b < nbigc; b += NW) {
       const uint32_t c = S.bigc[b];
+      if (S.ctie[c] < 2u) continue;
       const uint32_t n = S.ccnt[c];
       const uint32_t s = c >> 1;
       const uint32_t ea = (c & 1u) ? S.sr[cb][s] : S.sa[cb][s];
@@ -1412,6 +1445,7 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
       if (lane == 0) S.cwin[c] = (uint16_t)best.pad;
     }
     __syncthreads();
+    }
     // 5. nodes and next sub-subproblems
     for (uint32_t c = tid; c < nch; c += BLOCK) {
       const uint32_t n = S.ccnt[c];
@@ -1627,6 +1661,9 @@ uint32_t sweep_occupancy_grid() {
   return (uint32_t)(per_cu * cus);
 }
 
+// Workgroup size of the LDS finisher per job capacity.
+constexpr int kFinishBlock512 = 256, kFinishBlock1024 = 256, kFinishBlock2048 = 512;
+
 template <int BLOCK, int TMAX>
 int finish_attr() {
   static bool done = false;
@@ -1693,9 +1730,9 @@ uint32_t finish_grid(int tmax) {
   static uint32_t cache[3] = {0, 0, 0};
   const int k = tmax == 512 ? 0 : tmax == 1024 ? 1 : 2;
   if (!cache[k]) {
-    if (k == 0) cache[k] = finish_occupancy_grid<256, 512>();
-    if (k == 1) cache[k] = finish_occupancy_grid<256, 1024>();
-    if (k == 2) cache[k] = finish_occupancy_grid<256, 2048>();
+    if (k == 0) cache[k] = finish_occupancy_grid<kFinishBlock512, 512>();
+    if (k == 1) cache[k] = finish_occupancy_grid<kFinishBlock1024, 1024>();
+    if (k == 2) cache[k] = finish_occupancy_grid<kFinishBlock2048, 2048>();
   }
   return cache[k];
 }
@@ -1728,9 +1765,9 @@ int launch_plan(const PlanArgs& a, void* stream) {
 
 int launch_finish(const FinishArgs& a, int tmax, void* stream) {
   hipStream_t st = (hipStream_t)stream;
-  if (tmax == 512) return finish_one<256, 512>(a, st);
-  if (tmax == 1024) return finish_one<256, 1024>(a, st);
-  if (tmax == 2048) return finish_one<256, 2048>(a, st);
+  if (tmax == 512) return finish_one<kFinishBlock512, 512>(a, st);
+  if (tmax == 1024) return finish_one<kFinishBlock1024, 1024>(a, st);
+  if (tmax == 2048) return finish_one<kFinishBlock2048, 2048>(a, st);
   return (int)hipErrorInvalidValue;
 }
 

@@ -264,7 +264,7 @@ int launch_scatter(const ServedReq* reqs, const ServedChunk* chunks, uint32_t nc
                    const int64_t* counts, void* stream);
 
 constexpr int kExtBlock = 256;
-constexpr int kExtPPT = 32;
+constexpr int kExtPPT = 16;
 constexpr uint32_t kExtTile = kExtBlock * kExtPPT;
 
 }  // namespace vqh

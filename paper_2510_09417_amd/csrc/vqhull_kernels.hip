@@ -145,28 +145,48 @@ __global__ __launch_bounds__(BLOCK) void k_extremes(ExtremesArgs A) {
   const uint32_t hi = min(off + n, lo + TILE);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 
+  // Positions past the request's end read NaN, which no comparison selects.
   double xs[PPT];
 #pragma unroll
   for (int v = 0; v < PPT; ++v) {
     const uint32_t pos = lo + v * BLOCK + tid;
-    xs[v] = pos < hi ? A.x[pos] : 0.0;
+    xs[v] = pos < hi ? __builtin_nontemporal_load(A.x + pos) : __builtin_nan("");
   }
-  double mnx = 0.0, mxx = 0.0;
+  // Branch-free first pass on x alone: a thread's positions increase with v,
+  // so the first strict minimum (maximum) is the lexicographic one unless a
+  // later point has exactly the same x; such ties are flagged and that
+  // thread's points are taken again with the full order (y, then position).
+  double mnx = __builtin_inf(), mxx = -__builtin_inf();
   uint32_t mni = kNone, mxi = kNone;
-  bool bad = false;
+  bool bad = false, tmin = false, tmax = false;
 #pragma unroll
   for (int v = 0; v < PPT; ++v) {
     const uint32_t pos = lo + v * BLOCK + tid;
-    if (pos < hi) {
-      const double xv = xs[v];
-      bad |= !finite(xv);
-      if (mni == kNone || lex_less(xv, pos, mnx, mni, A.y)) {
-        mnx = xv;
-        mni = pos;
-      }
-      if (mxi == kNone || lex_greater(xv, pos, mxx, mxi, A.y)) {
-        mxx = xv;
-        mxi = pos;
+    const double xv = xs[v];
+    bad |= (pos < hi) & !finite(xv);
+    const bool lt = xv < mnx, gt = xv > mxx;
+    tmin = lt ? false : (tmin | (xv == mnx));
+    tmax = gt ? false : (tmax | (xv == mxx));
+    mnx = lt ? xv : mnx;
+    mni = lt ? pos : mni;
+    mxx = gt ? xv : mxx;
+    mxi = gt ? pos : mxi;
+  }
+  if (__builtin_expect(__ballot(tmin | tmax) != 0ull, 0)) {
+    if (tmin | tmax) {
+      mni = mxi = kNone;
+      for (int v = 0; v < PPT; ++v) {
+        const uint32_t pos = lo + v * BLOCK + tid;
+        if (pos >= hi) break;
+        const double xv = xs[v];
+        if (mni == kNone || lex_less(xv, pos, mnx, mni, A.y)) {
+          mnx = xv;
+          mni = pos;
+        }
+        if (mxi == kNone || lex_greater(xv, pos, mxx, mxi, A.y)) {
+          mxx = xv;
+          mxi = pos;
+        }
       }
     }
   }

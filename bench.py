@@ -170,7 +170,8 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int) -> dict:
         "lanes": lanes, "lane_points": lane_points,
         "hulls_per_s": round(thr, 1),
         "gpoints_per_s": round(total / (t_last - t_first) / 1e9, 3),
-        "batches": st["batches"], "failed": bad,
+        "batches": st["batches"], "graph_batches": st["graph_batches"], "plain_batches": st["plain_batches"],
+        "failed": bad,
         "latency_load_hulls_per_s": round(0.5 * thr, 1), "latency_requests": nlat,
         "p50_ms": round(percentile(lat, 0.50), 3), "p99_ms": round(percentile(lat, 0.99), 3),
         "plain_hulls_per_s": round(plain_thr, 1), "plain_requests": len(plain_lat),

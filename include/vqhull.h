@@ -210,7 +210,10 @@ typedef struct vqhull_server vqhull_server; /* opaque */
 
 typedef struct {
   int32_t lanes;         /* concurrent batches (1..8), one HIP stream each */
-  int32_t reserved;      /* must be 0 */
+  int32_t graph_levels;  /* 0: plain launches; L in 1..64: each lane captures its whole batch step
+                            (table copies, gather, extremes, L recursion levels, assembly, scatter)
+                            once as a hipGraph and replays it for every batch; a batch whose
+                            recursion is deeper than L is computed again with plain launches */
   int64_t lane_points;   /* points per batch (1 .. 2^31-1); also the largest request */
   int64_t lane_requests; /* requests per batch (1 .. 2^24) */
 } vqhull_server_config;
@@ -231,6 +234,8 @@ typedef struct {
   int64_t submitted, completed, failed, batches, points, pending;
   double busy_seconds; /* summed wall time of all batches over all lanes */
   double now;          /* the server clock when the statistics were taken */
+  int64_t graph_batches; /* batches finished by one replay of a lane's graph */
+  int64_t plain_batches; /* batches computed with plain launches */
 } vqhull_server_counters;
 
 /* Create a server on the current device; VQHULL_ERR_INVALID_ARGUMENT for a

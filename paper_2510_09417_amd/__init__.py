@@ -57,7 +57,7 @@ class KernelTime(ctypes.Structure):
 
 
 class ServerConfig(ctypes.Structure):
-    _fields_ = [("lanes", ctypes.c_int32), ("reserved", ctypes.c_int32), ("lane_points", ctypes.c_int64),
+    _fields_ = [("lanes", ctypes.c_int32), ("graph_levels", ctypes.c_int32), ("lane_points", ctypes.c_int64),
                 ("lane_requests", ctypes.c_int64)]
 
 
@@ -70,7 +70,8 @@ class TicketInfo(ctypes.Structure):
 class ServerCounters(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("batches", ctypes.c_int64), ("points", ctypes.c_int64), ("pending", ctypes.c_int64),
-                ("busy_seconds", ctypes.c_double), ("now", ctypes.c_double)]
+                ("busy_seconds", ctypes.c_double), ("now", ctypes.c_double), ("graph_batches", ctypes.c_int64),
+                ("plain_batches", ctypes.c_int64)]
 
 
 _lock = threading.Lock()
@@ -301,9 +302,9 @@ class Server:
     lanes; see include/vqhull.h.  The caller keeps each request's tensors alive
     until the request is done (``wait``, ``drain`` or ``poll``)."""
 
-    def __init__(self, lanes: int = 2, lane_points: int = 1 << 24, lane_requests: int = 4096):
+    def __init__(self, lanes: int = 2, lane_points: int = 1 << 24, lane_requests: int = 4096, graph_levels: int = 20):
         self._lib = load_library()
-        cfg = ServerConfig(lanes, 0, lane_points, lane_requests)
+        cfg = ServerConfig(lanes, graph_levels, lane_points, lane_requests)
         h = ctypes.c_void_p()
         _check(self._lib, self._lib.vqhull_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -72,7 +72,9 @@ struct Context {
   DevBuf<Req> req;
   DevBuf<Job> jobs;
   DevBuf<Node> nodes;
-  DevBuf<uint32_t> level_begin;
+  BatchCounts* counts_dev = nullptr;   // the batch's counts (device copy)
+  BatchCounts* counts_host = nullptr;  // pinned source of that copy
+  DevBuf<uint32_t> level_nodes;        // node count after each level (written by the planners)
   Status* status_dev = nullptr;   // kStatusRing records
   Status* status_host = nullptr;  // pinned copies
   hipEvent_t status_ev[kStatusRing] = {};
@@ -109,9 +111,14 @@ inline void ck(hipError_t e, const char* what) {
 
 inline void ck(int e, const char* what) { ck((hipError_t)e, what); }
 
+// Bumped whenever a workspace buffer moves: launch sequences captured in a
+// graph hold buffer addresses and must be captured again.
+std::atomic<uint64_t> g_alloc_gen{0};
+
 template <typename T>
 void ensure(DevBuf<T>& b, size_t n, hipStream_t st, bool keep = false) {
   if (n <= b.cap) return;
+  g_alloc_gen.fetch_add(1);
   size_t cap = std::max<size_t>(n, b.cap + b.cap / 2);
   T* p = nullptr;
   ck(hipMalloc(&p, cap * sizeof(T)), "hipMalloc");
@@ -126,6 +133,7 @@ void ensure(DevBuf<T>& b, size_t n, hipStream_t st, bool keep = false) {
 
 void ensure_points(Context& w, size_t n, hipStream_t st) {
   if (n <= w.cap_pts) return;
+  g_alloc_gen.fetch_add(1);
   ck(hipStreamSynchronize(st), "hipStreamSynchronize");
   for (int k = 0; k < 2; ++k) {
     if (w.wx[k]) ck(hipFree(w.wx[k]), "hipFree");
@@ -169,6 +177,8 @@ Context* new_context() {
   Context* w = new Context();
   w->device = dev;
   ck(hipMalloc(&w->status_dev, kStatusRing * sizeof(Status)), "hipMalloc");
+  ck(hipMalloc(&w->counts_dev, sizeof(BatchCounts)), "hipMalloc");
+  ck(hipHostMalloc((void**)&w->counts_host, sizeof(BatchCounts), hipHostMallocDefault), "hipHostMalloc");
   ck(hipHostMalloc((void**)&w->status_host, kStatusRing * sizeof(Status), hipHostMallocDefault), "hipHostMalloc");
   for (int i = 0; i < kStatusRing; ++i)
     ck(hipEventCreateWithFlags(&w->status_ev[i], hipEventDisableTiming), "hipEventCreateWithFlags");
@@ -208,8 +218,10 @@ void free_workspace(Context* w) {
   f(w->req.p);
   f(w->jobs.p);
   f(w->nodes.p);
-  f(w->level_begin.p);
   f(w->status_dev);
+  f(w->counts_dev);
+  f(w->level_nodes.p);
+  if (w->counts_host) (void)hipHostFree(w->counts_host);
   if (w->status_host) (void)hipHostFree(w->status_host);
   if (w->h_req) (void)hipHostFree(w->h_req);
   if (w->h_u32) (void)hipHostFree(w->h_u32);
@@ -264,6 +276,99 @@ void collect_times(Context& w) {
   }
 }
 
+int sweep_mode(int k) { return k == 0 ? kSweepArgmax : k == 1 ? kSweepFused : kSweepLevel; }
+
+// Arguments of level k's kernels (buffers by the parity of k, status slot k mod
+// the ring size).  Level 0 is an argmax-only pass over the roots (sizes and
+// farthest points of S1 / S2, nothing written); level 1 re-reads the caller's
+// arrays and classifies every point twice (root triangle, then its child's
+// triangle), so the top level's subsets are never materialized; levels >= 2
+// sweep the workspace.
+SweepArgs sweep_args(Context& w, const vqhull_config& cfg, int k, const double* x, const double* y) {
+  SweepArgs sa{};
+  const int in_buf = k <= 1 ? -1 : (k - 1) % 2, out_buf = k % 2, cur = k % 2;
+  sa.ix = in_buf < 0 ? x : w.wx[in_buf];
+  sa.iy = in_buf < 0 ? y : w.wy[in_buf];
+  sa.ii = in_buf < 0 ? nullptr : w.wi[in_buf];
+  sa.ox = w.wx[out_buf];
+  sa.oy = w.wy[out_buf];
+  sa.oi = w.wi[out_buf];
+  sa.seg = w.seg[cur].p;
+  sa.fr = w.fr.p;
+  sa.tile_seg = w.tile_seg[k == 1 ? 0 : cur].p;  // the fused pass walks the roots' tiles again
+  sa.ctr = w.ctr[cur].p;
+  sa.jctr = w.jctr.p;
+  sa.part = w.part.p;
+  sa.part2 = w.part2.p;
+  sa.req = w.req.p;
+  sa.st = w.status_dev + k % kStatusRing;
+  sa.reverse = (uint32_t)cfg.reverse_tiles;
+  return sa;
+}
+
+FinishArgs finish_args(Context& w, const double* x, const double* y, int k) {
+  FinishArgs fa{};
+  fa.jobs = w.jobs.p;
+  fa.ux = x;
+  fa.uy = y;
+  for (int b = 0; b < 2; ++b) {
+    fa.bx[b] = w.wx[b];
+    fa.by[b] = w.wy[b];
+    fa.bi[b] = w.wi[b];
+  }
+  fa.req = w.req.p;
+  fa.st = w.status_dev + k % kStatusRing;
+  fa.nodes = w.nodes.p;
+  return fa;
+}
+
+PlanArgs plan_args(Context& w, const vqhull_config& cfg, int k, uint32_t G) {
+  const int cur = k % 2;
+  PlanArgs pl{};
+  pl.seg = w.seg[cur].p;
+  pl.ctr = w.ctr[cur].p;
+  pl.part = w.part.p;
+  pl.part2 = w.part2.p;
+  pl.fuse = k == 0 ? 1u : 0u;
+  pl.fr_out = w.fr.p;
+  pl.jctr_out = w.jctr.p;
+  pl.st_in = w.status_dev + k % kStatusRing;
+  pl.sweep_grid = G;
+  pl.seg_out = w.seg[cur ^ 1].p;
+  pl.ctr_out = w.ctr[cur ^ 1].p;
+  pl.tile_seg_out = w.tile_seg[cur ^ 1].p;
+  pl.jobs = w.jobs.p;
+  pl.nodes = w.nodes.p;
+  pl.node_cap = (uint32_t)std::min<size_t>(w.nodes.cap, 0xFFFFFFFFu);
+  pl.out_buf = (uint32_t)(k == 0 ? 1 : k % 2);  // level 0's children are written by the fused pass
+  pl.st_out = w.status_dev + (k + 1) % kStatusRing;
+  pl.tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
+  pl.lds_limit = (uint32_t)cfg.lds_limit;
+  pl.level_nodes = w.level_nodes.p;
+  pl.level = (uint32_t)k;
+  pl.counts = w.counts_dev;
+  return pl;
+}
+
+Plan0Args plan0_args(Context& w, const vqhull_config& cfg) {
+  Plan0Args pa{};
+  pa.req = w.req.p;
+  pa.counts = w.counts_dev;
+  pa.level_nodes = w.level_nodes.p;
+  pa.epart = w.epart.p;
+  pa.seg_out = w.seg[0].p;
+  pa.ctr_out = w.ctr[0].p;
+  pa.tile_seg_out = w.tile_seg[0].p;
+  pa.jobs = w.jobs.p;
+  pa.nodes = w.nodes.p;
+  pa.node_cap = (uint32_t)std::min<size_t>(w.nodes.cap, 0xFFFFFFFFu);
+  pa.st_out = w.status_dev + 0;
+  pa.tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
+  pa.lds_limit = (uint32_t)cfg.lds_limit;
+  pa.ext_tile = kExtTile;
+  return pa;
+}
+
 // The whole hull computation for nreq requests on one stream.
 //
 // Level k's kernels read their work counts from the device status record the
@@ -281,69 +386,25 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
   const size_t max_seg = N / (lds_limit + 1) + (size_t)nreq + 2;
   const bool tm = g_timing.load() != 0;
 
-  ExtremesArgs ea{x, y, tile_req, w.req.p, w.epart.p, (uint32_t)ext_tiles};
+  ExtremesArgs ea{x, y, tile_req, w.req.p, w.epart.p, w.counts_dev, (uint32_t)ext_tiles};
   timed(w, tm, st, VQHULL_K_EXTREMES, 0, (int64_t)N, 0, [&] { ck(launch_extremes(ea, st), "k_extremes"); });
-  Plan0Args pa{};
-  pa.req = w.req.p;
-  pa.nreq = (uint32_t)nreq;
-  pa.epart = w.epart.p;
-  pa.seg_out = w.seg[0].p;
-  pa.ctr_out = w.ctr[0].p;
-  pa.tile_seg_out = w.tile_seg[0].p;
-  pa.jobs = w.jobs.p;
-  pa.nodes = w.nodes.p;
-  pa.node_cap = (uint32_t)std::min<size_t>(w.nodes.cap, 0xFFFFFFFFu);
-  pa.st_out = w.status_dev + 0;
-  pa.tile = tile;
-  pa.lds_limit = lds_limit;
-  pa.ext_tile = kExtTile;
+  ensure(w.level_nodes, 16, st, true);
+  const Plan0Args pa = plan0_args(w, cfg);
   timed(w, tm, st, VQHULL_K_PLAN0, 0, nreq, 0, [&] { ck(launch_plan0(pa, st), "k_plan0"); });
   ck(hipMemcpyAsync(w.status_host + 0, w.status_dev + 0, sizeof(Status), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
   ck(hipEventRecord(w.status_ev[0], st), "hipEventRecord");
-
-  FinishArgs fa{};
-  fa.jobs = w.jobs.p;
-  fa.ux = x;
-  fa.uy = y;
-  for (int k = 0; k < 2; ++k) {
-    fa.bx[k] = w.wx[k];
-    fa.by[k] = w.wy[k];
-    fa.bi[k] = w.wi[k];
-  }
-  fa.req = w.req.p;
 
   std::vector<Status> known;           // host copies of status[0..]
   std::vector<size_t> sweep_recs;      // timing records of the sweeps, per level
   std::vector<size_t> finish_recs;     // timing records of the finisher launches, per level
   bool overflow = false;
   int64_t known_nodes = (int64_t)nreq, known_seg = (int64_t)std::min<size_t>((size_t)nreq, max_seg);
-  // Level 0 is an argmax-only pass over the roots (sizes and farthest points
-  // of S1 / S2, nothing written); level 1 re-reads the caller's arrays and
-  // classifies every point twice (root triangle, then its child's triangle),
-  // so the top level's subsets are never materialized; levels >= 2 sweep the
-  // workspace.  Finisher jobs of level k run after sweep k (the fused pass
-  // writes the points of level 1's small children).
+  // Finisher jobs of level k run after sweep k (the fused pass writes the
+  // points of level 1's small children).
   for (int k = 0;; ++k) {
     const int slot = k % kStatusRing, next = (k + 1) % kStatusRing;
-    const int mode = k == 0 ? kSweepArgmax : k == 1 ? kSweepFused : kSweepLevel;
-    SweepArgs sa{};
-    const int in_buf = k <= 1 ? -1 : (k - 1) % 2, out_buf = k % 2, cur = k % 2;
-    sa.ix = in_buf < 0 ? x : w.wx[in_buf];
-    sa.iy = in_buf < 0 ? y : w.wy[in_buf];
-    sa.ii = in_buf < 0 ? nullptr : w.wi[in_buf];
-    sa.ox = w.wx[out_buf];
-    sa.oy = w.wy[out_buf];
-    sa.oi = w.wi[out_buf];
-    sa.seg = w.seg[cur].p;
-    sa.fr = w.fr.p;
-    sa.tile_seg = w.tile_seg[k == 1 ? 0 : cur].p;  // the fused pass walks the roots' tiles again
-    sa.ctr = w.ctr[cur].p;
-    sa.jctr = w.jctr.p;
-    sa.part = w.part.p;
-    sa.part2 = w.part2.p;
-    sa.req = w.req.p;
-    sa.st = w.status_dev + slot;
-    sa.reverse = (uint32_t)cfg.reverse_tiles;
+    const int mode = sweep_mode(k);
+    const SweepArgs sa = sweep_args(w, cfg, k, x, y);
     // Grid: persistent, or one workgroup per tile with the tile count bounded
     // from what the host knows (levels 0 and 1 exactly; level k from level
     // k-1: tiles <= ceil(swept(k-1) / tile) + 2 nseg(k-1)); surplus groups exit.
@@ -357,36 +418,18 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
       ck(launch_sweep(sa, mode, cfg.sweep_block, cfg.sweep_ppt, G, st), "k_sweep");
     }));
 
-    fa.st = w.status_dev + slot;
-    fa.nodes = w.nodes.p;
+    const FinishArgs fa = finish_args(w, x, y, k);
     finish_recs.push_back(
         timed(w, tm, st, VQHULL_K_FINISH, k, 0, 0, [&] { ck(launch_finish(fa, tmax, st), "k_finish"); }));
 
     // Node capacity for this plan: nodes after it <= nodes(k) + 2 nseg(k), with
     // nodes(k) <= nodes(k-1) + 2 nseg(k-1) and nseg(k) <= min(2 nseg(k-1), max_seg).
+    // (The finisher above took its pointer already: it only reads nodes its
+    // plan created, which the copy on growth preserves.)
     const int64_t need = known_nodes + 2 * known_seg + 2 * std::min<int64_t>(2 * known_seg, (int64_t)max_seg) + 16;
     ensure(w.nodes, (size_t)need, st, true);
-    fa.nodes = w.nodes.p;
-    PlanArgs pl{};
-    pl.seg = w.seg[cur].p;
-    pl.ctr = w.ctr[cur].p;
-    pl.part = w.part.p;
-    pl.part2 = w.part2.p;
-    pl.fuse = k == 0 ? 1u : 0u;
-    pl.fr_out = w.fr.p;
-    pl.jctr_out = w.jctr.p;
-    pl.st_in = w.status_dev + slot;
-    pl.sweep_grid = G;
-    pl.seg_out = w.seg[cur ^ 1].p;
-    pl.ctr_out = w.ctr[cur ^ 1].p;
-    pl.tile_seg_out = w.tile_seg[cur ^ 1].p;
-    pl.jobs = w.jobs.p;
-    pl.nodes = w.nodes.p;
-    pl.node_cap = (uint32_t)std::min<size_t>(w.nodes.cap, 0xFFFFFFFFu);
-    pl.out_buf = (uint32_t)(k == 0 ? 1 : out_buf);  // level 0's children are written by the fused pass
-    pl.st_out = w.status_dev + next;
-    pl.tile = tile;
-    pl.lds_limit = lds_limit;
+    ensure(w.level_nodes, (size_t)k + 3, st, true);
+    const PlanArgs pl = plan_args(w, cfg, k, G);
     timed(w, tm, st, VQHULL_K_PLAN, k, 0, 0, [&] { ck(launch_plan(pl, st), "k_plan"); });
     ck(hipMemcpyAsync(w.status_host + next, w.status_dev + next, sizeof(Status), hipMemcpyDeviceToHost, st),
        "hipMemcpyAsync");
@@ -420,26 +463,21 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
     return false;
   }
 
-  // assembly: node level boundaries are the node counts after each plan
+  // assembly: node level boundaries are the node counts after each plan,
+  // recorded on the device by the planners
   const size_t nlevels = known.size();
-  ensure(w.level_begin, nlevels + 1, st);
-  ensure_host_u32(w, nlevels + 1);
-  w.h_u32[0] = 0;
-  for (size_t i = 0; i < nlevels; ++i) w.h_u32[i + 1] = known[i].nnodes;
-  ck(hipMemcpyAsync(w.level_begin.p, w.h_u32, (nlevels + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, st),
-     "hipMemcpyAsync");
   AssembleArgs aa{};
   aa.nodes = w.nodes.p;
-  aa.level_begin = w.level_begin.p;
+  aa.level_begin = w.level_nodes.p;
   aa.nlevels = (uint32_t)nlevels;
   aa.req = w.req.p;
-  aa.nreq = (uint32_t)nreq;
+  aa.counts = w.counts_dev;
   aa.lists[0] = w.wi[0];
   aa.lists[1] = w.wi[1];
   aa.out_idx = out_idx;
   aa.out_count = out_counts;
-  aa.nnodes = known.back().nnodes;
-  timed(w, tm, st, VQHULL_K_ASSEMBLE, (int)nlevels, aa.nnodes, 0, [&] {
+  aa.max_nodes = known.back().nnodes;
+  timed(w, tm, st, VQHULL_K_ASSEMBLE, (int)nlevels, aa.max_nodes, 0, [&] {
     ck(launch_assemble(aa, st), "k_assemble");
     ck(launch_copy_lists(aa, st), "k_copy_lists");
   });
@@ -519,6 +557,11 @@ void run(Context& w, const vqhull_config& cfg, const double* x, const double* y,
     tile_req = w.tile_req.p;
   }
 
+  w.counts_host->nreq = (uint32_t)nreq;
+  w.counts_host->ext_tiles = (uint32_t)ext_tiles;
+  w.counts_host->overflow = 0;
+  w.counts_host->pad = 0;
+  ck(hipMemcpyAsync(w.counts_dev, w.counts_host, sizeof(BatchCounts), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
   for (int attempt = 0;; ++attempt) {
     ck(hipMemcpyAsync(w.req.p, w.h_req, (size_t)nreq * sizeof(Req), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
     w.stats.clear();
@@ -595,6 +638,108 @@ int context_run(Context* c, const double* x, const double* y, const int64_t* off
 }
 
 const char* context_last_error() { return g_last_error.c_str(); }
+
+uint64_t allocation_generation() { return g_alloc_gen.load(); }
+
+int context_reserve_fixed(Context* c, int64_t npoints, int64_t nreq, int levels, void* stream) {
+  int st = context_reserve(c, npoints, nreq, stream);
+  if (st != VQHULL_OK) return st;
+  return guard_status([&] {
+    std::lock_guard<std::mutex> guard(c->mu);
+    ck(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    ensure(c->level_nodes, (size_t)levels + 3, s);
+    // grid sizes are cached on the host here, before any capture
+    const vqhull_config cfg = current_config();
+    for (int m = 0; m < 3; ++m) (void)sweep_grid(cfg.sweep_block, cfg.sweep_ppt, m);
+    (void)finish_grid(finish_tmax_for(cfg.lds_limit));
+    ck(hipStreamSynchronize(s), "hipStreamSynchronize");
+  });
+}
+
+int context_stage(Context* c, const int64_t* offsets, int64_t nreq) {
+  std::lock_guard<std::mutex> guard(c->mu);
+  const vqhull_config cfg = current_config();
+  const uint32_t tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
+  const size_t N = (size_t)offsets[nreq];
+  if (nreq < 1 || N > c->cap_pts || (size_t)nreq > c->req.cap || (size_t)nreq > c->h_req_cap)
+    return VQHULL_ERR_INVALID_ARGUMENT;
+  size_t ext_tiles = 0;
+  for (int64_t i = 0; i < nreq; ++i) {
+    Req r{};
+    r.off = (uint32_t)offsets[i];
+    r.n = (uint32_t)(offsets[i + 1] - offsets[i]);
+    r.root = -1;
+    r.tile0 = (uint32_t)ext_tiles;
+    ext_tiles += (r.n + kExtTile - 1) / kExtTile;
+    c->h_req[i] = r;
+  }
+  (void)tile;
+  if (ext_tiles > c->tile_req.cap || ext_tiles > c->h_u32_cap || ext_tiles > c->epart.cap)
+    return VQHULL_ERR_INVALID_ARGUMENT;
+  size_t t = 0;
+  for (int64_t i = 0; i < nreq; ++i) {
+    const size_t nt = (c->h_req[i].n + kExtTile - 1) / kExtTile;
+    for (size_t k = 0; k < nt; ++k) c->h_u32[t++] = (uint32_t)i;
+  }
+  c->counts_host->nreq = (uint32_t)nreq;
+  c->counts_host->ext_tiles = (uint32_t)ext_tiles;
+  c->counts_host->overflow = 0;
+  c->counts_host->pad = 0;
+  return VQHULL_OK;
+}
+
+int context_enqueue_fixed(Context* c, const double* x, const double* y, int64_t* out_idx, int64_t* out_counts,
+                          int levels, void* stream) {
+  return guard_status([&] {
+    std::lock_guard<std::mutex> guard(c->mu);
+    Context& w = *c;
+    const vqhull_config cfg = current_config();
+    if (!cfg.sweep_persistent || levels < 1 || w.level_nodes.cap < (size_t)levels + 3)
+      ck(hipErrorInvalidValue, "fixed launch sequence");
+    hipStream_t st = (hipStream_t)stream;
+    const int tmax = finish_tmax_for(cfg.lds_limit);
+    const size_t nreq_cap = std::min(w.req.cap, w.h_req_cap);
+    const size_t tiles_cap = std::min(std::min(w.tile_req.cap, w.h_u32_cap), w.epart.cap);
+    ck(hipMemcpyAsync(w.req.p, w.h_req, nreq_cap * sizeof(Req), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    ck(hipMemcpyAsync(w.tile_req.p, w.h_u32, tiles_cap * sizeof(uint32_t), hipMemcpyHostToDevice, st),
+       "hipMemcpyAsync");
+    ck(hipMemcpyAsync(w.counts_dev, w.counts_host, sizeof(BatchCounts), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    const ExtremesArgs ea{x, y, w.tile_req.p, w.req.p, w.epart.p, w.counts_dev, (uint32_t)tiles_cap};
+    ck(launch_extremes(ea, st), "k_extremes");
+    ck(launch_plan0(plan0_args(w, cfg), st), "k_plan0");
+    for (int k = 0; k < levels; ++k) {
+      const int mode = sweep_mode(k);
+      const uint32_t G = sweep_grid(cfg.sweep_block, cfg.sweep_ppt, mode);
+      ck(launch_sweep(sweep_args(w, cfg, k, x, y), mode, cfg.sweep_block, cfg.sweep_ppt, G, st), "k_sweep");
+      ck(launch_finish(finish_args(w, x, y, k), tmax, st), "k_finish");
+      ck(launch_plan(plan_args(w, cfg, k, G), st), "k_plan");
+    }
+    const int last = levels % kStatusRing;
+    ck(hipMemcpyAsync(w.status_host + last, w.status_dev + last, sizeof(Status), hipMemcpyDeviceToHost, st),
+       "hipMemcpyAsync");
+    ck(hipMemcpyAsync(w.counts_host, w.counts_dev, sizeof(BatchCounts), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    AssembleArgs aa{};
+    aa.nodes = w.nodes.p;
+    aa.level_begin = w.level_nodes.p;
+    aa.nlevels = (uint32_t)levels + 1u;
+    aa.req = w.req.p;
+    aa.counts = w.counts_dev;
+    aa.lists[0] = w.wi[0];
+    aa.lists[1] = w.wi[1];
+    aa.out_idx = out_idx;
+    aa.out_count = out_counts;
+    aa.max_nodes = (uint32_t)std::min<size_t>(w.nodes.cap, 0xFFFFFFFFu);
+    ck(launch_assemble(aa, st), "k_assemble");
+    ck(launch_copy_lists(aa, st), "k_copy_lists");
+  });
+}
+
+bool context_fixed_done(Context* c, int levels) {
+  std::lock_guard<std::mutex> guard(c->mu);
+  const Status& s = c->status_host[levels % kStatusRing];
+  return s.nseg == 0 && s.njobs == 0 && s.overflow == 0 && c->counts_host->overflow == 0;
+}
 
 }  // namespace vqh
 

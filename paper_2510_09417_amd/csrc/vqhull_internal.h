@@ -135,13 +135,40 @@ int context_run(Context* c, const double* x, const double* y, const int64_t* off
                 int64_t* out_idx, int64_t* out_counts, void* stream);
 const char* context_last_error();  // of the calling thread
 
+// Fixed launch sequence for graph capture.  context_stage fills the
+// context's pinned tables for a batch (host only); context_enqueue_fixed
+// enqueues copies of those tables and `levels` recursion levels with grids
+// sized for the reserved capacity (context_reserve with the same levels):
+// no allocation, no host wait, the same launches for every batch.  Once the
+// stream has finished, context_fixed_done says whether the recursion ended
+// within `levels` levels without a table overflow; if not, the batch must be
+// recomputed with context_run.
+int context_reserve_fixed(Context* c, int64_t npoints, int64_t nreq, int levels, void* stream);
+int context_stage(Context* c, const int64_t* offsets, int64_t nreq);
+int context_enqueue_fixed(Context* c, const double* x, const double* y, int64_t* out_idx, int64_t* out_counts,
+                          int levels, void* stream);
+bool context_fixed_done(Context* c, int levels);
+// Changes whenever any context's workspace buffer is reallocated.
+uint64_t allocation_generation();
+
+// Counts that depend on the batch.  The kernels read them from device memory,
+// so one launch sequence (grids sized for the largest batch) serves every
+// batch; workgroups past a count exit at once.
+struct BatchCounts {
+  uint32_t nreq;       // requests
+  uint32_t ext_tiles;  // tiles of the extremes pass
+  uint32_t overflow;   // set by a planner whose node table was too small
+  uint32_t pad;
+};
+
 struct ExtremesArgs {
   const double* x;
   const double* y;
   const uint32_t* tile_req;  // nullptr: single request 0
   Req* req;
   ExtPart* part;
-  uint32_t ntiles;
+  const BatchCounts* counts;
+  uint32_t ntiles;  // grid (>= counts->ext_tiles)
 };
 
 // Sweep modes.
@@ -168,7 +195,8 @@ struct SweepArgs {
 
 struct Plan0Args {
   Req* req;
-  uint32_t nreq;
+  BatchCounts* counts;
+  uint32_t* level_nodes;  // node count after each level: [0] = 0, [1] = after the roots
   const ExtPart* epart;
   Seg* seg_out;
   unsigned long long* ctr_out;
@@ -202,6 +230,9 @@ struct PlanArgs {
   Status* st_out;
   uint32_t tile;
   uint32_t lds_limit;
+  uint32_t* level_nodes;  // [level + 2] = node count after this plan
+  uint32_t level;
+  BatchCounts* counts;    // overflow flag
 };
 
 struct FinishArgs {
@@ -218,14 +249,14 @@ struct FinishArgs {
 
 struct AssembleArgs {
   Node* nodes;
-  const uint32_t* level_begin;  // node level boundaries, nlevels + 1 entries
+  const uint32_t* level_begin;  // node level boundaries, nlevels + 1 entries (device)
   uint32_t nlevels;
   Req* req;
-  uint32_t nreq;
+  const BatchCounts* counts;
   const uint32_t* lists[2];
   int64_t* out_idx;
   int64_t* out_count;
-  uint32_t nnodes;
+  uint32_t max_nodes;  // bound on level_begin[nlevels] (sizes k_copy_lists' grid)
 };
 
 // Supported sweep shapes.
@@ -258,10 +289,11 @@ struct ServedReq {
 struct ServedChunk {
   uint32_t req, beg;
 };
-int launch_gather(const ServedReq* reqs, const ServedChunk* chunks, uint32_t nchunks, double* dx, double* dy,
-                  void* stream);
-int launch_scatter(const ServedReq* reqs, const ServedChunk* chunks, uint32_t nchunks, const int64_t* idx,
-                   const int64_t* counts, void* stream);
+// grid workgroups, of which the first *nchunks (device) have a chunk.
+int launch_gather(const ServedReq* reqs, const ServedChunk* chunks, const uint32_t* nchunks, uint32_t grid, double* dx,
+                  double* dy, void* stream);
+int launch_scatter(const ServedReq* reqs, const ServedChunk* chunks, const uint32_t* nchunks, uint32_t grid,
+                   const int64_t* idx, const int64_t* counts, void* stream);
 
 constexpr int kExtBlock = 256;
 constexpr int kExtPPT = 16;

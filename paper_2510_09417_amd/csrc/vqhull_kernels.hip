@@ -139,6 +139,7 @@ __global__ __launch_bounds__(BLOCK) void k_extremes(ExtremesArgs A) {
   __shared__ double s_mnx[NW], s_mxx[NW];
   __shared__ uint32_t s_mni[NW], s_mxi[NW];
   const uint32_t t = blockIdx.x;
+  if (t >= A.counts->ext_tiles) return;
   const uint32_t r = A.tile_req ? A.tile_req[t] : 0u;
   const uint32_t off = A.req[r].off, n = A.req[r].n, tile0 = A.req[r].tile0;
   const uint32_t lo = off + (t - tile0) * TILE;
@@ -918,8 +919,9 @@ __device__ __forceinline__ void plan_init(PlanShared& S) {
   __syncthreads();
 }
 
-__device__ __forceinline__ void plan_status(PlanShared& S, Status* out, uint32_t node_base) {
+__device__ __forceinline__ void plan_status(PlanShared& S, Status* out, uint32_t node_base, uint32_t* level_nodes) {
   if (threadIdx.x == 0) {
+    *level_nodes = node_base + S.nodes;
     Status st;
     st.nseg = S.segs;
     st.ntiles = S.tiles;
@@ -933,8 +935,11 @@ __device__ __forceinline__ void plan_status(PlanShared& S, Status* out, uint32_t
   }
 }
 
-__device__ __forceinline__ void plan_overflow(Status* out, uint32_t node_base) {
+__device__ __forceinline__ void plan_overflow(Status* out, uint32_t node_base, uint32_t* level_nodes,
+                                              BatchCounts* counts) {
   if (threadIdx.x == 0) {
+    *level_nodes = node_base;
+    counts->overflow = 1u;
     Status st{};
     st.nnodes = node_base;
     st.overflow = 1;
@@ -989,13 +994,15 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
   __shared__ Ext s_w[kPlanWaves];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   plan_init(S);
-  if ((uint64_t)A.nreq > A.node_cap) {
-    plan_overflow(A.st_out, 0u);
+  const uint32_t nreq = A.counts->nreq;
+  if ((uint64_t)nreq > A.node_cap) {
+    if (threadIdx.x == 0) A.level_nodes[0] = 0u;
+    plan_overflow(A.st_out, 0u, A.level_nodes + 1, A.counts);
     return;
   }
-  for (uint32_t base = 0; base < A.nreq; base += kPlanBlock) {
+  for (uint32_t base = 0; base < nreq; base += kPlanBlock) {
     const uint32_t i = base + tid;
-    const bool valid = i < A.nreq;
+    const bool valid = i < nreq;
     Req rq{};
     Ext e = no_ext();
     bool big = false;
@@ -1070,7 +1077,8 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
     }
     emit_finish(tot, A.seg_out, A.tile_seg_out, A.tile, S);
   }
-  plan_status(S, A.st_out, 0u);
+  if (threadIdx.x == 0) A.level_nodes[0] = 0u;
+  plan_status(S, A.st_out, 0u, A.level_nodes + 1);
 }
 
 // One recursion level: reduce the counts and candidates of every segment,
@@ -1085,7 +1093,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
   plan_init(S);
   const uint32_t nseg = A.st_in->nseg, node_base = A.st_in->nnodes;
   if ((uint64_t)node_base + 2ull * nseg > A.node_cap) {
-    plan_overflow(A.st_out, node_base);
+    plan_overflow(A.st_out, node_base, A.level_nodes + A.level + 2u, A.counts);
     return;
   }
   const uint32_t G = A.sweep_grid;
@@ -1208,7 +1216,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
     }
     emit_finish(tot, A.seg_out, A.tile_seg_out, A.tile, S);
   }
-  plan_status(S, A.st_out, node_base);
+  plan_status(S, A.st_out, node_base, A.level_nodes + A.level + 2u);
   // The fused pass walks the roots' tiles again.
   if (A.fuse && threadIdx.x == 0) A.st_out->ntiles = A.st_in->ntiles;
 }
@@ -1561,7 +1569,8 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble(AssembleArgs A) {
     __threadfence_block();
     __syncthreads();
   }
-  for (uint32_t i = tid; i < A.nreq; i += kAsmBlock) {
+  const uint32_t nreq = A.counts->nreq;
+  for (uint32_t i = tid; i < nreq; i += kAsmBlock) {
     const Req rq = A.req[i];
     if (rq.root >= 0) A.nodes[rq.root].start = 1u;
   }
@@ -1581,7 +1590,7 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble(AssembleArgs A) {
     __threadfence_block();
     __syncthreads();
   }
-  for (uint32_t i = tid; i < A.nreq; i += kAsmBlock) {
+  for (uint32_t i = tid; i < nreq; i += kAsmBlock) {
     const Req rq = A.req[i];
     int64_t count;
     if (rq.err) {
@@ -1604,7 +1613,8 @@ __global__ __launch_bounds__(256) void k_copy_lists(AssembleArgs A) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = (blockIdx.x * 256u + threadIdx.x) >> 6;
   const uint32_t nwaves = (gridDim.x * 256u) >> 6;
-  for (uint32_t v = wave; v < A.nnodes; v += nwaves) {
+  const uint32_t nnodes = A.level_begin[A.nlevels];
+  for (uint32_t v = wave; v < nnodes; v += nwaves) {
     const Node nd = A.nodes[v];
     if (nd.list == kNone) continue;
     const Req rq = A.req[nd.req];
@@ -1632,7 +1642,9 @@ __global__ __launch_bounds__(256) void k_stream_scale(const double* __restrict__
 // kServeChunk points of one request, so a large request spreads over many
 // workgroups and a small one costs one.
 __global__ __launch_bounds__(256) void k_gather(const ServedReq* __restrict__ reqs, const ServedChunk* __restrict__ chunks,
-                                                double* __restrict__ dx, double* __restrict__ dy) {
+                                                const uint32_t* __restrict__ nchunks, double* __restrict__ dx,
+                                                double* __restrict__ dy) {
+  if (blockIdx.x >= *nchunks) return;
   const ServedChunk c = chunks[blockIdx.x];
   const ServedReq r = reqs[c.req];
   const uint64_t m = min((uint64_t)kServeChunk, (uint64_t)r.n - c.beg);
@@ -1643,7 +1655,9 @@ __global__ __launch_bounds__(256) void k_gather(const ServedReq* __restrict__ re
 }
 
 __global__ __launch_bounds__(256) void k_scatter(const ServedReq* __restrict__ reqs, const ServedChunk* __restrict__ chunks,
-                                                 const int64_t* __restrict__ idx, const int64_t* __restrict__ counts) {
+                                                 const uint32_t* __restrict__ nchunks, const int64_t* __restrict__ idx,
+                                                 const int64_t* __restrict__ counts) {
+  if (blockIdx.x >= *nchunks) return;
   const ServedChunk c = chunks[blockIdx.x];
   const ServedReq r = reqs[c.req];
   const int64_t cnt = counts[c.req];
@@ -1804,23 +1818,23 @@ int launch_assemble(const AssembleArgs& a, void* stream) {
 }
 
 int launch_copy_lists(const AssembleArgs& a, void* stream) {
-  if (a.nnodes == 0) return 0;
-  const uint32_t waves = a.nnodes < 65536u ? a.nnodes : 65536u;
+  if (a.max_nodes == 0) return 0;
+  const uint32_t waves = a.max_nodes < 65536u ? a.max_nodes : 65536u;
   hipLaunchKernelGGL(k_copy_lists, dim3((waves + 3u) / 4u), dim3(256), 0, (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 
-int launch_gather(const ServedReq* reqs, const ServedChunk* chunks, uint32_t nchunks, double* dx, double* dy,
-                  void* stream) {
-  if (nchunks == 0) return 0;
-  hipLaunchKernelGGL(k_gather, dim3(nchunks), dim3(256), 0, (hipStream_t)stream, reqs, chunks, dx, dy);
+int launch_gather(const ServedReq* reqs, const ServedChunk* chunks, const uint32_t* nchunks, uint32_t grid, double* dx,
+                  double* dy, void* stream) {
+  if (grid == 0) return 0;
+  hipLaunchKernelGGL(k_gather, dim3(grid), dim3(256), 0, (hipStream_t)stream, reqs, chunks, nchunks, dx, dy);
   return (int)hipGetLastError();
 }
 
-int launch_scatter(const ServedReq* reqs, const ServedChunk* chunks, uint32_t nchunks, const int64_t* idx,
-                   const int64_t* counts, void* stream) {
-  if (nchunks == 0) return 0;
-  hipLaunchKernelGGL(k_scatter, dim3(nchunks), dim3(256), 0, (hipStream_t)stream, reqs, chunks, idx, counts);
+int launch_scatter(const ServedReq* reqs, const ServedChunk* chunks, const uint32_t* nchunks, uint32_t grid,
+                   const int64_t* idx, const int64_t* counts, void* stream) {
+  if (grid == 0) return 0;
+  hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(256), 0, (hipStream_t)stream, reqs, chunks, nchunks, idx, counts);
   return (int)hipGetLastError();
 }
 

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -58,6 +59,15 @@ struct Lane {
   ServedChunk* h_chunks = nullptr;
   int64_t* h_off = nullptr;
   int64_t* h_cnt = nullptr;
+  uint32_t* d_nchunks = nullptr;
+  uint32_t* h_nchunks = nullptr;
+  // the batch step as one hipGraph (graph_levels > 0)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t graph_gen = 0;
+  vqhull_config graph_cfg{};
+  bool graph_broken = false;
+  std::atomic<int64_t> graph_batches{0}, fallback_batches{0};
 };
 
 }  // namespace
@@ -94,6 +104,10 @@ void free_lane(Lane* L) {
     if (p) (void)hipHostFree(p);
   };
   if (L->st) (void)hipStreamSynchronize(L->st);
+  if (L->exec) (void)hipGraphExecDestroy(L->exec);
+  if (L->graph) (void)hipGraphDestroy(L->graph);
+  f(L->d_nchunks);
+  h(L->h_nchunks);
   f(L->sx);
   f(L->sy);
   f(L->sidx);
@@ -128,12 +142,17 @@ int make_lane(vqhull_server* s, int index, Lane** out) {
   chk(hipHostMalloc((void**)&L->h_chunks, C * sizeof(ServedChunk), hipHostMallocDefault));
   chk(hipHostMalloc((void**)&L->h_off, (R + 1) * sizeof(int64_t), hipHostMallocDefault));
   chk(hipHostMalloc((void**)&L->h_cnt, R * sizeof(int64_t), hipHostMallocDefault));
+  chk(hipMalloc(&L->d_nchunks, sizeof(uint32_t)));
+  chk(hipHostMalloc((void**)&L->h_nchunks, sizeof(uint32_t), hipHostMallocDefault));
   if (e != hipSuccess) {
     free_lane(L);
     return hip_status(e);
   }
   int st = context_create(&L->ctx);
-  if (st == VQHULL_OK) st = context_reserve(L->ctx, (int64_t)P, (int64_t)R, L->st);
+  if (st == VQHULL_OK)
+    st = s->cfg.graph_levels > 0
+             ? context_reserve_fixed(L->ctx, (int64_t)P, (int64_t)R, s->cfg.graph_levels, L->st)
+             : context_reserve(L->ctx, (int64_t)P, (int64_t)R, L->st);
   if (st != VQHULL_OK) {
     free_lane(L);
     return st;
@@ -142,9 +161,53 @@ int make_lane(vqhull_server* s, int index, Lane** out) {
   return VQHULL_OK;
 }
 
+bool same_config(const vqhull_config& a, const vqhull_config& b) {
+  return a.sweep_block == b.sweep_block && a.sweep_ppt == b.sweep_ppt && a.lds_limit == b.lds_limit &&
+         a.reverse_tiles == b.reverse_tiles && a.sweep_persistent == b.sweep_persistent;
+}
+
+// Capture the lane's whole batch step (table copies, gather, the fixed
+// sequence of `levels` recursion levels, assembly, scatter, count copy) as
+// one graph.  Every count the kernels need is read from device memory, so the
+// graph serves every batch; it is captured again when the library's
+// configuration changes or a workspace buffer has moved.
+bool capture_graph(vqhull_server* s, Lane* L, const vqhull_config& cfg) {
+  if (L->exec) (void)hipGraphExecDestroy(L->exec);
+  if (L->graph) (void)hipGraphDestroy(L->graph);
+  L->exec = nullptr;
+  L->graph = nullptr;
+  const size_t R = (size_t)s->cfg.lane_requests, C = (size_t)s->max_chunks;
+  const uint64_t gen = allocation_generation();
+  if (hipStreamBeginCapture(L->st, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+  bool ok = hipMemcpyAsync(L->d_reqs, L->h_reqs, R * sizeof(ServedReq), hipMemcpyHostToDevice, L->st) == hipSuccess;
+  ok = ok && hipMemcpyAsync(L->d_chunks, L->h_chunks, C * sizeof(ServedChunk), hipMemcpyHostToDevice, L->st) ==
+                 hipSuccess;
+  ok = ok && hipMemcpyAsync(L->d_nchunks, L->h_nchunks, sizeof(uint32_t), hipMemcpyHostToDevice, L->st) == hipSuccess;
+  ok = ok && launch_gather(L->d_reqs, L->d_chunks, L->d_nchunks, (uint32_t)C, L->sx, L->sy, L->st) == 0;
+  ok = ok && context_enqueue_fixed(L->ctx, L->sx, L->sy, L->sidx, L->scnt, s->cfg.graph_levels, L->st) == VQHULL_OK;
+  ok = ok && launch_scatter(L->d_reqs, L->d_chunks, L->d_nchunks, (uint32_t)C, L->sidx, L->scnt, L->st) == 0;
+  ok = ok && hipMemcpyAsync(L->h_cnt, L->scnt, R * sizeof(int64_t), hipMemcpyDeviceToHost, L->st) == hipSuccess;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(L->st, &g);
+  if (!ok || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return false;
+  }
+  if (hipGraphInstantiate(&L->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    L->exec = nullptr;
+    return false;
+  }
+  L->graph = g;
+  L->graph_gen = gen;
+  L->graph_cfg = cfg;
+  return true;
+}
+
 // Run one batch on lane L (the requests as copied from their tickets under the
 // server lock); returns a VQHULL status for the batch.
-int run_batch(Lane* L, const std::vector<ServedReq>& reqs) {
+int run_batch(vqhull_server* s, Lane* L, const std::vector<ServedReq>& reqs) {
   const size_t nreq = reqs.size();
   size_t nch = 0;
   int64_t off = 0;
@@ -158,14 +221,39 @@ int run_batch(Lane* L, const std::vector<ServedReq>& reqs) {
     off += (int64_t)r.n;
   }
   L->h_off[nreq] = off;
+  *L->h_nchunks = (uint32_t)nch;
+
+  if (s->cfg.graph_levels > 0 && !L->graph_broken) {
+    vqhull_config cfg;
+    (void)vqhull_get_config(&cfg);
+    if (cfg.sweep_persistent && context_stage(L->ctx, L->h_off, (int64_t)nreq) == VQHULL_OK) {
+      if (!L->exec || L->graph_gen != allocation_generation() || !same_config(cfg, L->graph_cfg)) {
+        if (!capture_graph(s, L, cfg)) L->graph_broken = true;  // this lane stays on the plain path
+      }
+      if (L->exec) {
+        hipError_t e = hipGraphLaunch(L->exec, L->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(L->st);
+        if (e != hipSuccess) return hip_status(e);
+        if (context_fixed_done(L->ctx, s->cfg.graph_levels)) {
+          ++L->graph_batches;
+          return VQHULL_OK;
+        }
+        // deeper recursion than captured, or a full table: compute again below
+      }
+    }
+  }
+
+  ++L->fallback_batches;
   hipError_t e = hipMemcpyAsync(L->d_reqs, L->h_reqs, nreq * sizeof(ServedReq), hipMemcpyHostToDevice, L->st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(L->d_chunks, L->h_chunks, nch * sizeof(ServedChunk), hipMemcpyHostToDevice, L->st);
-  if (e == hipSuccess) e = (hipError_t)launch_gather(L->d_reqs, L->d_chunks, (uint32_t)nch, L->sx, L->sy, L->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(L->d_nchunks, L->h_nchunks, sizeof(uint32_t), hipMemcpyHostToDevice, L->st);
+  if (e == hipSuccess)
+    e = (hipError_t)launch_gather(L->d_reqs, L->d_chunks, L->d_nchunks, (uint32_t)nch, L->sx, L->sy, L->st);
   if (e != hipSuccess) return hip_status(e);
   const int st = context_run(L->ctx, L->sx, L->sy, L->h_off, (int64_t)nreq, L->sidx, L->scnt, L->st);
   if (st != VQHULL_OK) return st;
-  e = (hipError_t)launch_scatter(L->d_reqs, L->d_chunks, (uint32_t)nch, L->sidx, L->scnt, L->st);
+  e = (hipError_t)launch_scatter(L->d_reqs, L->d_chunks, L->d_nchunks, (uint32_t)nch, L->sidx, L->scnt, L->st);
   if (e == hipSuccess) e = hipMemcpyAsync(L->h_cnt, L->scnt, nreq * sizeof(int64_t), hipMemcpyDeviceToHost, L->st);
   if (e == hipSuccess) e = hipStreamSynchronize(L->st);
   return e == hipSuccess ? VQHULL_OK : hip_status(e);
@@ -198,7 +286,7 @@ void lane_loop(vqhull_server* s, Lane* L) {
       }
     }
     const double tb = s->now();
-    const int st = run_batch(L, reqs);
+    const int st = run_batch(s, L, reqs);
     const double te = s->now();
     {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -232,7 +320,8 @@ extern "C" {
 int vqhull_server_create(const vqhull_server_config* cfg, vqhull_server** out) {
   if (!cfg || !out) return VQHULL_ERR_INVALID_ARGUMENT;
   if (cfg->lanes < 1 || cfg->lanes > 8 || cfg->lane_points < 1 || cfg->lane_points >= (int64_t(1) << 31) ||
-      cfg->lane_requests < 1 || cfg->lane_requests > (int64_t(1) << 24))
+      cfg->lane_requests < 1 || cfg->lane_requests > (int64_t(1) << 24) || cfg->graph_levels < 0 ||
+      cfg->graph_levels > 64)
     return VQHULL_ERR_INVALID_ARGUMENT;
   *out = nullptr;
   vqhull_server* s = new vqhull_server();
@@ -365,6 +454,12 @@ int vqhull_server_stats(vqhull_server* s, vqhull_server_counters* out) {
   out->pending = (int64_t)s->pending.size();
   out->busy_seconds = s->busy;
   out->now = s->now();
+  out->graph_batches = 0;
+  out->plain_batches = 0;
+  for (const Lane* L : s->lanes) {
+    out->graph_batches += L->graph_batches.load();
+    out->plain_batches += L->fallback_batches.load();
+  }
   return VQHULL_OK;
 }
 

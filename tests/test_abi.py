@@ -102,9 +102,9 @@ def test_server_arguments_rejected_on_host(lib):
     vp = ctypes.c_void_p
     h = vp()
     assert lib.vqhull_server_create(None, ctypes.byref(h)) == 1
-    for lanes, pts, reqs in ((0, 1000, 10), (9, 1000, 10), (1, 0, 10), (1, 1 << 31, 10), (1, 1000, 0),
-                             (1, 1000, (1 << 24) + 1)):
-        cfg = vq.ServerConfig(lanes, 0, pts, reqs)
+    for lanes, pts, reqs, lv in ((0, 1000, 10, 0), (9, 1000, 10, 0), (1, 0, 10, 0), (1, 1 << 31, 10, 0),
+                                 (1, 1000, 0, 0), (1, 1000, (1 << 24) + 1, 0), (1, 1000, 10, -1), (1, 1000, 10, 65)):
+        cfg = vq.ServerConfig(lanes, lv, pts, reqs)
         assert lib.vqhull_server_create(ctypes.byref(cfg), ctypes.byref(h)) == 1
     t = ctypes.c_int64()
     dummy = vp(0x1000)

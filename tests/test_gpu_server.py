@@ -174,3 +174,48 @@ def test_submit_pointers_batch_path(vq):
     out = OUT.cpu().numpy()
     for k in range(len(reqs)):
         assert np.array_equal(out[off[k]:off[k] + cnt[k]], oracle.hull(xs[k], ys[k])), f"request {k}"
+
+
+def _run_server(vq, data, **kw):
+    import torch
+
+    outs = []
+    with vq.Server(**kw) as srv:
+        tks = []
+        for x, y, tx, ty in data:
+            oi = torch.full((max(len(x), 1),), -5, dtype=torch.int64, device="cuda")
+            oc = torch.full((1,), -5, dtype=torch.int64, device="cuda")
+            outs.append((oi, oc))
+            tks.append(srv.submit(tx, ty, oi, oc))
+        for t in tks:
+            assert srv.wait(t) == vq.VQHULL_OK
+        st = srv.stats()
+    return [oi[:int(oc.item())].cpu().numpy() for oi, oc in outs], st
+
+
+def test_graph_lanes_equal_plain_lanes(vq):
+    """The captured batch step (one hipGraph replay per batch) and plain
+    launches give the same lists; the graph is replayed for many batches."""
+    data = []
+    for i, n, d in _requests(120, 80_000, seed=16):
+        x, y = workloads.served_request(i, n, d, seed=16)
+        data.append((x, y) + _device(x, y))
+    got_g, st_g = _run_server(vq, data, lanes=2, lane_points=1 << 18, lane_requests=24, graph_levels=20)
+    got_p, st_p = _run_server(vq, data, lanes=2, lane_points=1 << 18, lane_requests=24, graph_levels=0)
+    assert st_g["graph_batches"] >= 4 and st_p["graph_batches"] == 0 and st_p["plain_batches"] == st_p["batches"]
+    for k, ((x, y, _, _), a, b) in enumerate(zip(data, got_g, got_p)):
+        want = oracle.hull(x, y)
+        assert np.array_equal(a, want) and np.array_equal(b, want), f"request {k}"
+
+
+def test_graph_falls_back_when_recursion_is_deeper(vq):
+    """A lane captured with 2 levels cannot finish a large circle inside the
+    graph: the batch is computed again with plain launches, bit-exact."""
+    data = []
+    for k, (dist, n) in enumerate((("circle", 300_000), ("disk", 50_000), ("circle", 9_000))):
+        x, y = workloads.points(dist, n, seed=[17, k])
+        data.append((x, y) + _device(x, y))
+    got, st = _run_server(vq, data, lanes=1, lane_points=1 << 19, lane_requests=2, graph_levels=2)
+    assert st["plain_batches"] >= 1
+    for (x, y, _, _), a in zip(data, got):
+        assert np.array_equal(a, oracle.hull(x, y))

@@ -76,7 +76,8 @@ struct Context {
   BatchCounts* counts_host = nullptr;  // pinned source of that copy
   DevBuf<uint32_t> level_nodes;        // node count after each level (written by the planners)
   Status* status_dev = nullptr;   // kStatusRing records
-  Status* status_host = nullptr;  // pinned copies
+  Status* status_host = nullptr;  // pinned copies, written by the planners
+  Status* status_host_dev = nullptr;  // device view of status_host
   hipEvent_t status_ev[kStatusRing] = {};
   // pinned staging
   Req* h_req = nullptr;
@@ -179,7 +180,8 @@ Context* new_context() {
   ck(hipMalloc(&w->status_dev, kStatusRing * sizeof(Status)), "hipMalloc");
   ck(hipMalloc(&w->counts_dev, sizeof(BatchCounts)), "hipMalloc");
   ck(hipHostMalloc((void**)&w->counts_host, sizeof(BatchCounts), hipHostMallocDefault), "hipHostMalloc");
-  ck(hipHostMalloc((void**)&w->status_host, kStatusRing * sizeof(Status), hipHostMallocDefault), "hipHostMalloc");
+  ck(hipHostMalloc((void**)&w->status_host, kStatusRing * sizeof(Status), hipHostMallocMapped), "hipHostMalloc");
+  ck(hipHostGetDevicePointer((void**)&w->status_host_dev, w->status_host, 0), "hipHostGetDevicePointer");
   for (int i = 0; i < kStatusRing; ++i)
     ck(hipEventCreateWithFlags(&w->status_ev[i], hipEventDisableTiming), "hipEventCreateWithFlags");
   return w;
@@ -342,6 +344,7 @@ PlanArgs plan_args(Context& w, const vqhull_config& cfg, int k, uint32_t G) {
   pl.node_cap = (uint32_t)std::min<size_t>(w.nodes.cap, 0xFFFFFFFFu);
   pl.out_buf = (uint32_t)(k == 0 ? 1 : k % 2);  // level 0's children are written by the fused pass
   pl.st_out = w.status_dev + (k + 1) % kStatusRing;
+  pl.st_host = w.status_host_dev + (k + 1) % kStatusRing;
   pl.tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
   pl.lds_limit = (uint32_t)cfg.lds_limit;
   pl.level_nodes = w.level_nodes.p;
@@ -363,6 +366,7 @@ Plan0Args plan0_args(Context& w, const vqhull_config& cfg) {
   pa.nodes = w.nodes.p;
   pa.node_cap = (uint32_t)std::min<size_t>(w.nodes.cap, 0xFFFFFFFFu);
   pa.st_out = w.status_dev + 0;
+  pa.st_host = w.status_host_dev + 0;
   pa.tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
   pa.lds_limit = (uint32_t)cfg.lds_limit;
   pa.ext_tile = kExtTile;
@@ -391,7 +395,6 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
   ensure(w.level_nodes, 16, st, true);
   const Plan0Args pa = plan0_args(w, cfg);
   timed(w, tm, st, VQHULL_K_PLAN0, 0, nreq, 0, [&] { ck(launch_plan0(pa, st), "k_plan0"); });
-  ck(hipMemcpyAsync(w.status_host + 0, w.status_dev + 0, sizeof(Status), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
   ck(hipEventRecord(w.status_ev[0], st), "hipEventRecord");
 
   std::vector<Status> known;           // host copies of status[0..]
@@ -431,8 +434,6 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
     ensure(w.level_nodes, (size_t)k + 3, st, true);
     const PlanArgs pl = plan_args(w, cfg, k, G);
     timed(w, tm, st, VQHULL_K_PLAN, k, 0, 0, [&] { ck(launch_plan(pl, st), "k_plan"); });
-    ck(hipMemcpyAsync(w.status_host + next, w.status_dev + next, sizeof(Status), hipMemcpyDeviceToHost, st),
-       "hipMemcpyAsync");
     ck(hipEventRecord(w.status_ev[next], st), "hipEventRecord");
 
     // Wait for the status of level k (written by the previous plan).

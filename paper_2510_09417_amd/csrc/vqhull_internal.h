@@ -205,6 +205,7 @@ struct Plan0Args {
   Node* nodes;
   uint32_t node_cap;
   Status* st_out;
+  Status* st_host;  // pinned host copy of *st_out (device view), or null
   uint32_t tile;
   uint32_t lds_limit;
   uint32_t ext_tile;
@@ -228,6 +229,7 @@ struct PlanArgs {
   uint32_t node_cap;
   uint32_t out_buf;  // buffer the children were written to (0 = A, 1 = B)
   Status* st_out;
+  Status* st_host;   // pinned host copy of *st_out (device view), or null
   uint32_t tile;
   uint32_t lds_limit;
   uint32_t* level_nodes;  // [level + 2] = node count after this plan
@@ -297,6 +299,7 @@ int launch_scatter(const ServedReq* reqs, const ServedChunk* chunks, const uint3
 
 constexpr int kExtBlock = 256;
 constexpr int kExtPPT = 16;
-constexpr uint32_t kExtTile = kExtBlock * kExtPPT;
+constexpr int kExtIter = 4;
+constexpr uint32_t kExtTile = kExtBlock * kExtPPT * kExtIter;
 
 }  // namespace vqh

@@ -132,9 +132,12 @@ __device__ __forceinline__ bool lex_greater(double xa, uint32_t ia, double xb, u
 
 // ------------------------------------------------------------- k_extremes
 
-template <int BLOCK, int PPT>
+// One workgroup per tile of ITER * BLOCK * PPT consecutive points of one
+// request (ITER sub-tiles taken in order), one partial record per tile.
+template <int BLOCK, int PPT, int ITER>
 __global__ __launch_bounds__(BLOCK) void k_extremes(ExtremesArgs A) {
-  constexpr uint32_t TILE = BLOCK * PPT;
+  constexpr uint32_t SUB = BLOCK * PPT;
+  constexpr uint32_t TILE = SUB * ITER;
   constexpr int NW = BLOCK / 64;
   __shared__ double s_mnx[NW], s_mxx[NW];
   __shared__ uint32_t s_mni[NW], s_mxi[NW];
@@ -146,40 +149,43 @@ __global__ __launch_bounds__(BLOCK) void k_extremes(ExtremesArgs A) {
   const uint32_t hi = min(off + n, lo + TILE);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 
-  // Positions past the request's end read NaN, which no comparison selects.
-  double xs[PPT];
-#pragma unroll
-  for (int v = 0; v < PPT; ++v) {
-    const uint32_t pos = lo + v * BLOCK + tid;
-    xs[v] = pos < hi ? __builtin_nontemporal_load(A.x + pos) : __builtin_nan("");
-  }
-  // Branch-free first pass on x alone: a thread's positions increase with v,
-  // so the first strict minimum (maximum) is the lexicographic one unless a
-  // later point has exactly the same x; such ties are flagged and that
-  // thread's points are taken again with the full order (y, then position).
+  // Branch-free first pass on x alone: a thread's positions increase with
+  // (sub-tile, v), so the first strict minimum (maximum) is the lexicographic
+  // one unless a later point has exactly the same x; such ties are flagged
+  // and that thread's points are taken again with the full order (y, then
+  // position).  Positions past the request's end read NaN, which no
+  // comparison selects.
   double mnx = __builtin_inf(), mxx = -__builtin_inf();
   uint32_t mni = kNone, mxi = kNone;
   bool bad = false, tmin = false, tmax = false;
+  for (int it = 0; it < ITER; ++it) {
+    const uint32_t slo = lo + (uint32_t)it * SUB;
+    if (slo >= hi) break;  // uniform
+    double xs[PPT];
 #pragma unroll
-  for (int v = 0; v < PPT; ++v) {
-    const uint32_t pos = lo + v * BLOCK + tid;
-    const double xv = xs[v];
-    bad |= (pos < hi) & !finite(xv);
-    const bool lt = xv < mnx, gt = xv > mxx;
-    tmin = lt ? false : (tmin | (xv == mnx));
-    tmax = gt ? false : (tmax | (xv == mxx));
-    mnx = lt ? xv : mnx;
-    mni = lt ? pos : mni;
-    mxx = gt ? xv : mxx;
-    mxi = gt ? pos : mxi;
+    for (int v = 0; v < PPT; ++v) {
+      const uint32_t pos = slo + v * BLOCK + tid;
+      xs[v] = pos < hi ? __builtin_nontemporal_load(A.x + pos) : __builtin_nan("");
+    }
+#pragma unroll
+    for (int v = 0; v < PPT; ++v) {
+      const uint32_t pos = slo + v * BLOCK + tid;
+      const double xv = xs[v];
+      bad |= (pos < hi) & !finite(xv);
+      const bool lt = xv < mnx, gt = xv > mxx;
+      tmin = lt ? false : (tmin | (xv == mnx));
+      tmax = gt ? false : (tmax | (xv == mxx));
+      mnx = lt ? xv : mnx;
+      mni = lt ? pos : mni;
+      mxx = gt ? xv : mxx;
+      mxi = gt ? pos : mxi;
+    }
   }
   if (__builtin_expect(__ballot(tmin | tmax) != 0ull, 0)) {
     if (tmin | tmax) {
       mni = mxi = kNone;
-      for (int v = 0; v < PPT; ++v) {
-        const uint32_t pos = lo + v * BLOCK + tid;
-        if (pos >= hi) break;
-        const double xv = xs[v];
+      for (uint32_t pos = lo + tid; pos < hi; pos += BLOCK) {
+        const double xv = A.x[pos];
         if (mni == kNone || lex_less(xv, pos, mnx, mni, A.y)) {
           mnx = xv;
           mni = pos;
@@ -729,6 +735,25 @@ __device__ __forceinline__ Cand block_best(Cand c, Cand* s_c) {
 }
 
 
+// Visit records first, first + stride, ... below n with U loads in flight
+// per thread (the records of a level were written by other compute units, so
+// each load is a full memory round trip).
+template <int U, typename Rec, typename F>
+__device__ __forceinline__ void strided_visit(const Rec* rec, uint32_t first, uint32_t n, uint32_t stride, F&& f) {
+  for (uint32_t k = first; k < n; k += U * stride) {
+    Rec r[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const uint32_t kj = k + (uint32_t)j * stride;
+      if (kj < n) r[j] = rec[kj];
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (k + (uint32_t)j * stride < n) f(r[j]);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ plans
 //
 // Each side of a partition step (a "child") becomes, by its size: nothing
@@ -741,7 +766,7 @@ __device__ __forceinline__ Cand block_best(Cand c, Cand* s_c) {
 
 enum : uint32_t { kKindNone = 0, kKindLeaf = 1, kKindJob = 2, kKindSeg = 3 };
 
-constexpr int kPlanBlock = 1024;
+constexpr int kPlanBlock = 512;
 constexpr int kPlanWaves = kPlanBlock / 64;
 constexpr uint32_t kSerialRecs = 16;   // segments with more candidate records are reduced by one wave,
 constexpr uint32_t kWaveRecs = 2048;   // and with more than this by the whole workgroup
@@ -919,31 +944,44 @@ __device__ __forceinline__ void plan_init(PlanShared& S) {
   __syncthreads();
 }
 
-__device__ __forceinline__ void plan_status(PlanShared& S, Status* out, uint32_t node_base, uint32_t* level_nodes) {
+// The status record goes to the device ring (read by the next level's
+// kernels) and, when host_out is set, straight to the host's pinned copy (read
+// by the host after the event that follows this kernel), so no copy is
+// enqueued per level.
+__device__ __forceinline__ void put_status(const Status& st, Status* out, Status* host_out) {
+  *out = st;
+  if (host_out) {
+    *host_out = st;
+    __threadfence_system();
+  }
+}
+
+__device__ __forceinline__ void plan_status(PlanShared& S, Status* out, Status* host_out, uint32_t node_base,
+                                            uint32_t* level_nodes, uint32_t ntiles) {
   if (threadIdx.x == 0) {
     *level_nodes = node_base + S.nodes;
     Status st;
     st.nseg = S.segs;
-    st.ntiles = S.tiles;
+    st.ntiles = ntiles;
     st.njobs = S.jobs;
     st.nnodes = node_base + S.nodes;
     st.swept = S.swept;
     st.jobpts = S.jobpts;
     st.survivors = S.survivors;
     st.overflow = 0;
-    *out = st;
+    put_status(st, out, host_out);
   }
 }
 
-__device__ __forceinline__ void plan_overflow(Status* out, uint32_t node_base, uint32_t* level_nodes,
-                                              BatchCounts* counts) {
+__device__ __forceinline__ void plan_overflow(Status* out, Status* host_out, uint32_t node_base,
+                                              uint32_t* level_nodes, BatchCounts* counts) {
   if (threadIdx.x == 0) {
     *level_nodes = node_base;
     counts->overflow = 1u;
     Status st{};
     st.nnodes = node_base;
     st.overflow = 1;
-    *out = st;
+    put_status(st, out, host_out);
   }
 }
 
@@ -997,7 +1035,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
   const uint32_t nreq = A.counts->nreq;
   if ((uint64_t)nreq > A.node_cap) {
     if (threadIdx.x == 0) A.level_nodes[0] = 0u;
-    plan_overflow(A.st_out, 0u, A.level_nodes + 1, A.counts);
+    plan_overflow(A.st_out, A.st_host, 0u, A.level_nodes + 1, A.counts);
     return;
   }
   for (uint32_t base = 0; base < nreq; base += kPlanBlock) {
@@ -1010,10 +1048,8 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
       rq = A.req[i];
       const uint32_t nt = ceil_div(rq.n, A.ext_tile);
       if (nt <= kSerialRecs) {
-        for (uint32_t k = 0; k < nt; ++k) {
-          const ExtPart p = A.epart[rq.tile0 + k];
-          ext_merge(e, p.minx, p.miny, p.mini, p.maxx, p.maxy, p.maxi);
-        }
+        strided_visit<4>(A.epart + rq.tile0, 0u, nt, 1u,
+                         [&](const ExtPart& p) { ext_merge(e, p.minx, p.miny, p.mini, p.maxx, p.maxy, p.maxi); });
       } else {
         big = true;
         S.big[atomicAdd(&S.nbig, 1u)] = (uint32_t)tid;
@@ -1026,10 +1062,8 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
       const uint32_t t0 = A.req[base + owner].tile0, nt = ceil_div(A.req[base + owner].n, A.ext_tile);
       if (nt > kWaveRecs) continue;
       Ext me = no_ext();
-      for (uint32_t k = lane; k < nt; k += 64) {
-        const ExtPart p = A.epart[t0 + k];
-        ext_merge(me, p.minx, p.miny, p.mini, p.maxx, p.maxy, p.maxi);
-      }
+      strided_visit<4>(A.epart + t0, (uint32_t)lane, nt, 64u,
+                       [&](const ExtPart& p) { ext_merge(me, p.minx, p.miny, p.mini, p.maxx, p.maxy, p.maxi); });
       me = wave_ext(me);
       if (lane == 0) s_res[owner] = me;
     }
@@ -1038,10 +1072,8 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
       const uint32_t t0 = A.req[base + owner].tile0, nt = ceil_div(A.req[base + owner].n, A.ext_tile);
       if (nt <= kWaveRecs) continue;
       Ext me = no_ext();
-      for (uint32_t k = tid; k < nt; k += kPlanBlock) {
-        const ExtPart p = A.epart[t0 + k];
-        ext_merge(me, p.minx, p.miny, p.mini, p.maxx, p.maxy, p.maxi);
-      }
+      strided_visit<4>(A.epart + t0, (uint32_t)tid, nt, (uint32_t)kPlanBlock,
+                       [&](const ExtPart& p) { ext_merge(me, p.minx, p.miny, p.mini, p.maxx, p.maxy, p.maxi); });
       me = wave_ext(me);
       if (lane == 0) s_w[w] = me;
       __syncthreads();
@@ -1078,7 +1110,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
     emit_finish(tot, A.seg_out, A.tile_seg_out, A.tile, S);
   }
   if (threadIdx.x == 0) A.level_nodes[0] = 0u;
-  plan_status(S, A.st_out, 0u, A.level_nodes + 1);
+  plan_status(S, A.st_out, A.st_host, 0u, A.level_nodes + 1, S.tiles);
 }
 
 // One recursion level: reduce the counts and candidates of every segment,
@@ -1093,7 +1125,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
   plan_init(S);
   const uint32_t nseg = A.st_in->nseg, node_base = A.st_in->nnodes;
   if ((uint64_t)node_base + 2ull * nseg > A.node_cap) {
-    plan_overflow(A.st_out, node_base, A.level_nodes + A.level + 2u, A.counts);
+    plan_overflow(A.st_out, A.st_host, node_base, A.level_nodes + A.level + 2u, A.counts);
     return;
   }
   const uint32_t G = A.sweep_grid;
@@ -1113,11 +1145,10 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
       nrec = min(G, rt ? rt : ceil_div(A.seg[s].cnt, A.tile));
       const TilePart* part = A.seg[s].rside ? A.part2 : A.part;
       if (nrec <= kSerialRecs) {
-        for (uint32_t k = 0; k < nrec; ++k) {
-          const TilePart& p = part[tile0 + k];
+        strided_visit<4>(part + tile0, 0u, nrec, 1u, [&](const TilePart& p) {
           keep(r1, p.c[0]);
           keep(r2, p.c[1]);
-        }
+        });
       } else {
         big = true;
         S.big[atomicAdd(&S.nbig, 1u)] = (uint32_t)tid;
@@ -1133,11 +1164,10 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
       const TilePart* part = so.rside ? A.part2 : A.part;
       if (nr > kWaveRecs) continue;
       Cand m1 = no_cand(), m2 = no_cand();
-      for (uint32_t k = lane; k < nr; k += 64) {
-        const TilePart& p = part[t0 + k];
+      strided_visit<4>(part + t0, (uint32_t)lane, nr, 64u, [&](const TilePart& p) {
         keep(m1, p.c[0]);
         keep(m2, p.c[1]);
-      }
+      });
       wave_best(m1);
       wave_best(m2);
       if (lane == 0) {
@@ -1153,11 +1183,10 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
       const TilePart* part = so.rside ? A.part2 : A.part;
       if (nr <= kWaveRecs) continue;
       Cand m1 = no_cand(), m2 = no_cand();
-      for (uint32_t k = tid; k < nr; k += kPlanBlock) {
-        const TilePart& p = part[t0 + k];
+      strided_visit<4>(part + t0, (uint32_t)tid, nr, (uint32_t)kPlanBlock, [&](const TilePart& p) {
         keep(m1, p.c[0]);
         keep(m2, p.c[1]);
-      }
+      });
       m1 = block_best<kPlanBlock>(m1, s_c);
       m2 = block_best<kPlanBlock>(m2, s_c);
       if (tid == 0) {
@@ -1216,9 +1245,8 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
     }
     emit_finish(tot, A.seg_out, A.tile_seg_out, A.tile, S);
   }
-  plan_status(S, A.st_out, node_base, A.level_nodes + A.level + 2u);
   // The fused pass walks the roots' tiles again.
-  if (A.fuse && threadIdx.x == 0) A.st_out->ntiles = A.st_in->ntiles;
+  plan_status(S, A.st_out, A.st_host, node_base, A.level_nodes + A.level + 2u, A.fuse ? A.st_in->ntiles : S.tiles);
 }
 
 // --------------------------------------------------------------- k_finish
@@ -1773,7 +1801,7 @@ uint32_t finish_grid(int tmax) {
 
 int launch_extremes(const ExtremesArgs& a, void* stream) {
   if (a.ntiles == 0) return 0;
-  hipLaunchKernelGGL((k_extremes<kExtBlock, kExtPPT>), dim3(a.ntiles), dim3(kExtBlock), 0, (hipStream_t)stream, a);
+  hipLaunchKernelGGL((k_extremes<kExtBlock, kExtPPT, kExtIter>), dim3(a.ntiles), dim3(kExtBlock), 0, (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 

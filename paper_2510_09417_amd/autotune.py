@@ -84,6 +84,52 @@ def tune(x, y, repeats: int = 3, path: str | None = None) -> dict:
     return entry
 
 
+# The configuration space of the tuner (the same as the library's single-hull
+# tuner): sweep shapes, LDS-finisher thresholds, persistent grid or not.
+SHAPES = ((256, 16), (256, 32), (512, 8), (512, 16), (1024, 8))
+LDS_LIMITS = (512, 1024, 2048)
+
+
+def tune_batched(x, y, offsets, repeats: int = 3, stream=None, persistent=(1, 0)) -> tuple[dict, list[dict]]:
+    """Tune the batched path on one representative batch: times
+    ``hull_batched(x, y, offsets)`` (median of ``repeats`` runs after a warm-up)
+    under every configuration (grid modes limited to ``persistent``: the
+    server's graph-captured batches need persistent sweeps) and checks that
+    each gives the same index lists and counts as the first.  Returns (fastest
+    equal configuration, table); the library configuration is restored
+    afterwards."""
+    import torch
+
+    import paper_2510_09417_amd as vq
+
+    saved = vq.get_config()
+    table, ref, best = [], None, None
+    try:
+        for blk, ppt in SHAPES:
+            for lds in LDS_LIMITS:
+                for pers in persistent:
+                    cfg = vq.set_config(sweep_block=blk, sweep_ppt=ppt, lds_limit=lds, sweep_persistent=pers)
+                    out, cnt = vq.hull_batched(x, y, offsets, stream=stream)
+                    torch.cuda.synchronize()
+                    times = []
+                    for _ in range(max(1, repeats)):
+                        t0 = time.perf_counter()
+                        out, cnt = vq.hull_batched(x, y, offsets, stream=stream)
+                        torch.cuda.synchronize()
+                        times.append(time.perf_counter() - t0)
+                    res = (out.cpu().numpy(), cnt.cpu().numpy())
+                    if ref is None:
+                        ref = res
+                    same = bool((res[0] == ref[0]).all() and (res[1] == ref[1]).all())
+                    ms = 1e3 * sorted(times)[len(times) // 2]
+                    table.append({"config": cfg, "ms": ms, "same_result": same})
+                    if same and (best is None or ms < best["ms"]):
+                        best = table[-1]
+    finally:
+        vq.set_config(**saved)
+    return best["config"], table
+
+
 def apply(n: int, path: str | None = None) -> dict | None:
     """Set the library configuration tuned for size n on this GPU; returns it,
     or None (configuration unchanged) when nothing is cached for this GPU."""

@@ -50,3 +50,33 @@ def test_autotune_same_result_everywhere(tmp_path):
         assert np.array_equal(vq.hull(tx, ty).cpu().numpy(), oracle.hull(x, y))
     finally:
         vq.set_config(**before)
+
+
+@pytest.mark.gpu
+def test_tune_batched_same_result_everywhere():
+    import torch
+
+    import oracle
+    import paper_2510_09417_amd as vq
+    from paper_2510_09417_amd import workloads
+
+    vq.load_library()
+    before = vq.get_config()
+    parts = [workloads.points(d, n, seed=30 + k) for k, (d, n) in
+             enumerate([("disk", 40_000), ("circle", 5_001), ("square", 17), ("kuzmin", 120_000), ("circle", 3_000)])]
+    x = np.concatenate([p[0] for p in parts])
+    y = np.concatenate([p[1] for p in parts])
+    off = np.concatenate([[0], np.cumsum([len(p[0]) for p in parts])]).astype(np.int64)
+    tx, ty = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    best, table = autotune.tune_batched(tx, ty, off, repeats=1)
+    assert vq.get_config() == before  # tuning leaves the configuration alone
+    assert len(table) == 30 and all(r["same_result"] for r in table)
+    assert best in [r["config"] for r in table]
+    try:
+        vq.set_config(**best)
+        out, cnt = vq.hull_batched(tx, ty, off)
+        out, cnt = out.cpu().numpy(), cnt.cpu().numpy()
+        for i, (px, py) in enumerate(parts):
+            assert np.array_equal(out[off[i]:off[i] + cnt[i]], oracle.hull(px, py))
+    finally:
+        vq.set_config(**before)

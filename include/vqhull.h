@@ -150,8 +150,9 @@ enum {
   VQHULL_K_EXTREMES = 0, /* leftmost / rightmost points */
   VQHULL_K_PLAN0 = 1,    /* root planning */
   VQHULL_K_SWEEP = 2,    /* fused partition sweep of one level */
-  VQHULL_K_PLAN = 3,     /* planning of one level */
-  VQHULL_K_FINISH = 4,   /* LDS finisher of one level's small subproblems */
+  VQHULL_K_PLAN = 3,     /* planning of one level, in one launch with the LDS finisher of that
+                            level's small subproblems (workgroup 0 plans, the others finish) */
+  VQHULL_K_FINISH = 4,   /* reserved: no launch is a finisher alone */
   VQHULL_K_ASSEMBLE = 5  /* clockwise assembly (both kernels) */
 };
 typedef struct {

@@ -29,7 +29,7 @@ EXPORTED = (
     "vqhull_server_drain", "vqhull_server_ticket_info", "vqhull_server_stats", "vqhull_server_destroy",
 )
 
-KERNEL_KINDS = ("extremes", "plan0", "sweep", "plan", "finish", "assemble")
+KERNEL_KINDS = ("extremes", "plan0", "sweep", "finish_plan", "finish", "assemble")
 
 
 class VqhullError(RuntimeError):

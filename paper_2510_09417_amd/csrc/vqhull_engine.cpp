@@ -66,11 +66,11 @@ struct Context {
   DevBuf<uint32_t> tile_seg[2];
   DevBuf<TilePart> part, part2;
   DevBuf<FusedRoot> fr;
-  DevBuf<unsigned long long> jctr;
+  DevBuf<unsigned long long> jctr[2];  // by level parity, like the job tables
   DevBuf<ExtPart> epart;
   DevBuf<uint32_t> tile_req;
   DevBuf<Req> req;
-  DevBuf<Job> jobs;
+  DevBuf<Job> jobs[2];  // level k's jobs in jobs[k % 2] (the planner of level k writes the other)
   DevBuf<Node> nodes;
   BatchCounts* counts_dev = nullptr;   // the batch's counts (device copy)
   BatchCounts* counts_host = nullptr;  // pinned source of that copy
@@ -214,11 +214,13 @@ void free_workspace(Context* w) {
   f(w->part.p);
   f(w->part2.p);
   f(w->fr.p);
-  f(w->jctr.p);
+  f(w->jctr[0].p);
+  f(w->jctr[1].p);
   f(w->epart.p);
   f(w->tile_req.p);
   f(w->req.p);
-  f(w->jobs.p);
+  f(w->jobs[0].p);
+  f(w->jobs[1].p);
   f(w->nodes.p);
   f(w->status_dev);
   f(w->counts_dev);
@@ -299,7 +301,7 @@ SweepArgs sweep_args(Context& w, const vqhull_config& cfg, int k, const double* 
   sa.fr = w.fr.p;
   sa.tile_seg = w.tile_seg[k == 1 ? 0 : cur].p;  // the fused pass walks the roots' tiles again
   sa.ctr = w.ctr[cur].p;
-  sa.jctr = w.jctr.p;
+  sa.jctr = w.jctr[k & 1].p;
   sa.part = w.part.p;
   sa.part2 = w.part2.p;
   sa.req = w.req.p;
@@ -310,7 +312,7 @@ SweepArgs sweep_args(Context& w, const vqhull_config& cfg, int k, const double* 
 
 FinishArgs finish_args(Context& w, const double* x, const double* y, int k) {
   FinishArgs fa{};
-  fa.jobs = w.jobs.p;
+  fa.jobs = w.jobs[k & 1].p;
   fa.ux = x;
   fa.uy = y;
   for (int b = 0; b < 2; ++b) {
@@ -333,13 +335,13 @@ PlanArgs plan_args(Context& w, const vqhull_config& cfg, int k, uint32_t G) {
   pl.part2 = w.part2.p;
   pl.fuse = k == 0 ? 1u : 0u;
   pl.fr_out = w.fr.p;
-  pl.jctr_out = w.jctr.p;
+  pl.jctr_out = w.jctr[(k + 1) & 1].p;
   pl.st_in = w.status_dev + k % kStatusRing;
   pl.sweep_grid = G;
   pl.seg_out = w.seg[cur ^ 1].p;
   pl.ctr_out = w.ctr[cur ^ 1].p;
   pl.tile_seg_out = w.tile_seg[cur ^ 1].p;
-  pl.jobs = w.jobs.p;
+  pl.jobs = w.jobs[(k + 1) & 1].p;
   pl.nodes = w.nodes.p;
   pl.node_cap = (uint32_t)std::min<size_t>(w.nodes.cap, 0xFFFFFFFFu);
   pl.out_buf = (uint32_t)(k == 0 ? 1 : k % 2);  // level 0's children are written by the fused pass
@@ -362,7 +364,7 @@ Plan0Args plan0_args(Context& w, const vqhull_config& cfg) {
   pa.seg_out = w.seg[0].p;
   pa.ctr_out = w.ctr[0].p;
   pa.tile_seg_out = w.tile_seg[0].p;
-  pa.jobs = w.jobs.p;
+  pa.jobs = w.jobs[0].p;
   pa.nodes = w.nodes.p;
   pa.node_cap = (uint32_t)std::min<size_t>(w.nodes.cap, 0xFFFFFFFFu);
   pa.st_out = w.status_dev + 0;
@@ -399,11 +401,11 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
 
   std::vector<Status> known;           // host copies of status[0..]
   std::vector<size_t> sweep_recs;      // timing records of the sweeps, per level
-  std::vector<size_t> finish_recs;     // timing records of the finisher launches, per level
+  std::vector<size_t> finish_recs;     // timing records of the finisher + planner launches, per level
   bool overflow = false;
   int64_t known_nodes = (int64_t)nreq, known_seg = (int64_t)std::min<size_t>((size_t)nreq, max_seg);
   // Finisher jobs of level k run after sweep k (the fused pass writes the
-  // points of level 1's small children).
+  // points of level 1's small children), in the same launch as plan k.
   for (int k = 0;; ++k) {
     const int slot = k % kStatusRing, next = (k + 1) % kStatusRing;
     const int mode = sweep_mode(k);
@@ -421,19 +423,17 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
       ck(launch_sweep(sa, mode, cfg.sweep_block, cfg.sweep_ppt, G, st), "k_sweep");
     }));
 
-    const FinishArgs fa = finish_args(w, x, y, k);
-    finish_recs.push_back(
-        timed(w, tm, st, VQHULL_K_FINISH, k, 0, 0, [&] { ck(launch_finish(fa, tmax, st), "k_finish"); }));
-
     // Node capacity for this plan: nodes after it <= nodes(k) + 2 nseg(k), with
     // nodes(k) <= nodes(k-1) + 2 nseg(k-1) and nseg(k) <= min(2 nseg(k-1), max_seg).
-    // (The finisher above took its pointer already: it only reads nodes its
-    // plan created, which the copy on growth preserves.)
+    // A grown table is copied on the stream before the launch below, which
+    // takes the new pointer for both its planner and its finisher.
     const int64_t need = known_nodes + 2 * known_seg + 2 * std::min<int64_t>(2 * known_seg, (int64_t)max_seg) + 16;
     ensure(w.nodes, (size_t)need, st, true);
     ensure(w.level_nodes, (size_t)k + 3, st, true);
+    const FinishArgs fa = finish_args(w, x, y, k);
     const PlanArgs pl = plan_args(w, cfg, k, G);
-    timed(w, tm, st, VQHULL_K_PLAN, k, 0, 0, [&] { ck(launch_plan(pl, st), "k_plan"); });
+    finish_recs.push_back(timed(w, tm, st, VQHULL_K_PLAN, k, 0, 0,
+                                [&] { ck(launch_finish_plan(fa, pl, tmax, st), "k_finish_plan"); }));
     ck(hipEventRecord(w.status_ev[next], st), "hipEventRecord");
 
     // Wait for the status of level k (written by the previous plan).
@@ -514,8 +514,10 @@ Caps reserve(Context& w, const vqhull_config& cfg, size_t N, size_t nreq, size_t
   ensure(w.part, c.max_tiles, st);
   ensure(w.part2, c.max_tiles, st);
   ensure(w.fr, c.max_seg, st);
-  ensure(w.jobs, 2 * c.max_seg + nreq, st);
-  ensure(w.jctr, (2 * c.max_seg + nreq) * kCtrStride, st);
+  for (int k = 0; k < 2; ++k) {
+    ensure(w.jobs[k], 2 * c.max_seg + nreq, st);
+    ensure(w.jctr[k], (2 * c.max_seg + nreq) * kCtrStride, st);
+  }
   ensure(w.nodes, std::max<size_t>(3 * nreq + 64, 4096), st);
   return c;
 }
@@ -713,8 +715,7 @@ int context_enqueue_fixed(Context* c, const double* x, const double* y, int64_t*
       const int mode = sweep_mode(k);
       const uint32_t G = sweep_grid(cfg.sweep_block, cfg.sweep_ppt, mode);
       ck(launch_sweep(sweep_args(w, cfg, k, x, y), mode, cfg.sweep_block, cfg.sweep_ppt, G, st), "k_sweep");
-      ck(launch_finish(finish_args(w, x, y, k), tmax, st), "k_finish");
-      ck(launch_plan(plan_args(w, cfg, k, G), st), "k_plan");
+      ck(launch_finish_plan(finish_args(w, x, y, k), plan_args(w, cfg, k, G), tmax, st), "k_finish_plan");
     }
     const int last = levels % kStatusRing;
     ck(hipMemcpyAsync(w.status_host + last, w.status_dev + last, sizeof(Status), hipMemcpyDeviceToHost, st),

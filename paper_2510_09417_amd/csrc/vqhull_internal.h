@@ -271,8 +271,8 @@ int launch_sweep(const SweepArgs& a, int mode, int block, int ppt, uint32_t grid
 uint32_t sweep_grid(int block, int ppt, int mode);  // persistent grid size for a sweep shape and mode
 uint32_t finish_grid(int tmax);            // persistent grid size of the finisher
 int launch_plan0(const Plan0Args& a, void* stream);
-int launch_plan(const PlanArgs& a, void* stream);
-int launch_finish(const FinishArgs& a, int tmax, void* stream);
+// The finisher of level k and the planner of level k in one launch.
+int launch_finish_plan(const FinishArgs& a, const PlanArgs& p, int tmax, void* stream);
 int launch_assemble(const AssembleArgs& a, void* stream);
 int launch_copy_lists(const AssembleArgs& a, void* stream);
 int launch_stream_scale(const double* in, double* out, uint64_t n, double s, void* stream);

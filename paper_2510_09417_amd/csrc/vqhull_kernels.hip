@@ -778,13 +778,15 @@ __device__ __forceinline__ uint32_t child_kind(uint32_t cnt, uint32_t lds_limit)
   return cnt == 0u ? kKindNone : cnt == 1u ? kKindLeaf : cnt <= lds_limit ? kKindJob : kKindSeg;
 }
 
-struct PlanShared {
-  uint32_t scan[4][kPlanWaves];
+template <int PB>
+struct PlanSharedT {
+  uint32_t scan[4][PB / 64];
   uint32_t nodes, jobs, segs, tiles, swept, jobpts, survivors;
   uint32_t nbig, nfill;
-  uint32_t big[kPlanBlock];
-  uint32_t fill[2 * kPlanBlock];  // up to two new segments per thread
+  uint32_t big[PB];
+  uint32_t fill[2 * PB];  // up to two new segments per thread
 };
+using PlanShared = PlanSharedT<kPlanBlock>;
 
 struct Tri {
   double ax, ay, rx, ry, bx, by;
@@ -795,8 +797,9 @@ struct EmitBase {
   uint32_t node, job, seg, tile;
 };
 
+template <int PB>
 __device__ __forceinline__ EmitBase emit_scan(const uint32_t (&kind)[2], const uint32_t (&cnt)[2], uint32_t tile,
-                                              PlanShared& S, uint32_t (&tot)[4], bool virt = false) {
+                                              PlanSharedT<PB>& S, uint32_t (&tot)[4], bool virt = false) {
   uint32_t v[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
@@ -806,7 +809,7 @@ __device__ __forceinline__ EmitBase emit_scan(const uint32_t (&kind)[2], const u
     v[3] += (kind[k] == kKindSeg && !virt) ? ceil_div(cnt[k], tile) : 0u;
   }
   uint32_t ex[4];
-  block_scan<kPlanBlock, 4>(v, ex, tot, S.scan);
+  block_scan<PB, 4>(v, ex, tot, S.scan);
   return EmitBase{S.nodes + ex[0], S.jobs + ex[1], S.segs + ex[2], S.tiles + ex[3]};
 }
 
@@ -819,11 +822,12 @@ struct Virt {
   unsigned long long* jctr_out;
 };
 
+template <int PB>
 __device__ __forceinline__ int32_t emit_one(uint32_t kind, const Tri& tr, uint32_t ri, uint32_t beg, uint32_t cnt,
                                             uint32_t req, int32_t parent, uint32_t side, uint32_t src,
                                             uint32_t node_base, uint32_t tile, EmitBase& e, Node* nodes, Job* jobs,
                                             Seg* seg_out, unsigned long long* ctr_out, uint32_t* tile_seg_out,
-                                            PlanShared& S, const Virt& vt, uint32_t* index_out) {
+                                            PlanSharedT<PB>& S, const Virt& vt, uint32_t* index_out) {
   int32_t nid = -1;
   if (kind != kKindNone) {
     nid = (int32_t)(node_base + e.node++);
@@ -915,14 +919,15 @@ __device__ __forceinline__ int32_t emit_one(uint32_t kind, const Tri& tr, uint32
 }
 
 // Tile maps of the big new segments (whole workgroup), then running totals.
+template <int PB>
 __device__ __forceinline__ void emit_finish(const uint32_t (&tot)[4], const Seg* seg_out, uint32_t* tile_seg_out,
-                                            uint32_t tile, PlanShared& S) {
+                                            uint32_t tile, PlanSharedT<PB>& S) {
   __syncthreads();
   const uint32_t nf = S.nfill;
   for (uint32_t f = 0; f < nf; ++f) {
     const uint32_t sid = S.fill[f];
     const uint32_t t0 = seg_out[sid].tile0, nt = ceil_div(seg_out[sid].cnt, tile);
-    for (uint32_t i = threadIdx.x; i < nt; i += kPlanBlock) tile_seg_out[t0 + i] = sid;
+    for (uint32_t i = threadIdx.x; i < nt; i += PB) tile_seg_out[t0 + i] = sid;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -936,7 +941,8 @@ __device__ __forceinline__ void emit_finish(const uint32_t (&tot)[4], const Seg*
   __syncthreads();
 }
 
-__device__ __forceinline__ void plan_init(PlanShared& S) {
+template <int PB>
+__device__ __forceinline__ void plan_init(PlanSharedT<PB>& S) {
   if (threadIdx.x == 0) {
     S.nodes = S.jobs = S.segs = S.tiles = S.swept = S.jobpts = S.survivors = 0;
     S.nbig = S.nfill = 0;
@@ -956,7 +962,8 @@ __device__ __forceinline__ void put_status(const Status& st, Status* out, Status
   }
 }
 
-__device__ __forceinline__ void plan_status(PlanShared& S, Status* out, Status* host_out, uint32_t node_base,
+template <int PB>
+__device__ __forceinline__ void plan_status(PlanSharedT<PB>& S, Status* out, Status* host_out, uint32_t node_base,
                                             uint32_t* level_nodes, uint32_t ntiles) {
   if (threadIdx.x == 0) {
     *level_nodes = node_base + S.nodes;
@@ -1117,10 +1124,19 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
 // then lay out its two children (Algorithm 1: Hull(S1, a, r1, r) and
 // Hull(S2, r, r2, b)).  The children's points already sit at the two ends of
 // the segment's range in the output buffer of the sweep.
-__global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
-  __shared__ PlanShared S;
-  __shared__ Cand s_res[kPlanBlock][2];
-  __shared__ Cand s_c[kPlanWaves];
+template <int PB>
+struct PlanLds {
+  PlanSharedT<PB> S;
+  Cand res[PB][2];
+  Cand c[PB / 64];
+};
+
+template <int PB>
+__device__ void plan_level(const PlanArgs& A, PlanLds<PB>& L) {
+  constexpr int NWP = PB / 64;
+  PlanSharedT<PB>& S = L.S;
+  Cand (*s_res)[2] = L.res;
+  Cand* s_c = L.c;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   plan_init(S);
   const uint32_t nseg = A.st_in->nseg, node_base = A.st_in->nnodes;
@@ -1129,7 +1145,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
     return;
   }
   const uint32_t G = A.sweep_grid;
-  for (uint32_t base = 0; base < nseg; base += kPlanBlock) {
+  for (uint32_t base = 0; base < nseg; base += PB) {
     const uint32_t s = base + tid;
     const bool valid = s < nseg;
     uint32_t n1 = 0, n2 = 0, tile0 = 0, nrec = 0;
@@ -1156,7 +1172,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
     }
     __syncthreads();
     const uint32_t nbig = S.nbig;
-    for (uint32_t b = w; b < nbig; b += kPlanWaves) {  // one wave per big segment
+    for (uint32_t b = w; b < nbig; b += NWP) {  // one wave per big segment
       const uint32_t owner = S.big[b];
       const Seg& so = A.seg[base + owner];
       const uint32_t t0 = so.tile0;
@@ -1183,12 +1199,12 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(PlanArgs A) {
       const TilePart* part = so.rside ? A.part2 : A.part;
       if (nr <= kWaveRecs) continue;
       Cand m1 = no_cand(), m2 = no_cand();
-      strided_visit<4>(part + t0, (uint32_t)tid, nr, (uint32_t)kPlanBlock, [&](const TilePart& p) {
+      strided_visit<4>(part + t0, (uint32_t)tid, nr, (uint32_t)PB, [&](const TilePart& p) {
         keep(m1, p.c[0]);
         keep(m2, p.c[1]);
       });
-      m1 = block_best<kPlanBlock>(m1, s_c);
-      m2 = block_best<kPlanBlock>(m2, s_c);
+      m1 = block_best<PB>(m1, s_c);
+      m2 = block_best<PB>(m2, s_c);
       if (tid == 0) {
         s_res[owner][0] = m1;
         s_res[owner][1] = m2;
@@ -1564,12 +1580,28 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
   __syncthreads();  // LDS is reused by the next job
 }
 
+// One launch per level for the finisher and the planner: workgroup 0 plans
+// the next level while the others finish this level's small subproblems.
+// They share no data: the planner reads the sweep's counters and records and
+// writes the next level's tables (its jobs into the other of the two job
+// buffers); the finisher reads this level's jobs and points and fills in the
+// vertex lists of this level's job nodes.
 template <int BLOCK, int TMAX>
-__global__ __launch_bounds__(BLOCK) void k_finish(FinishArgs A) {
+constexpr size_t finish_plan_lds() {
+  return sizeof(FinishShared<BLOCK, TMAX>) > sizeof(PlanLds<BLOCK>) ? sizeof(FinishShared<BLOCK, TMAX>)
+                                                                    : sizeof(PlanLds<BLOCK>);
+}
+
+template <int BLOCK, int TMAX>
+__global__ __launch_bounds__(BLOCK) void k_finish_plan(FinishArgs A, PlanArgs P) {
   extern __shared__ unsigned char smem_raw[];
+  if (blockIdx.x == 0) {
+    plan_level<BLOCK>(P, *reinterpret_cast<PlanLds<BLOCK>*>(smem_raw));
+    return;
+  }
   FinishShared<BLOCK, TMAX>& S = *reinterpret_cast<FinishShared<BLOCK, TMAX>*>(smem_raw);
   const uint32_t njobs = A.st->njobs;
-  for (uint32_t j = blockIdx.x; j < njobs; j += gridDim.x) {
+  for (uint32_t j = blockIdx.x - 1u; j < njobs; j += gridDim.x - 1u) {
     const Job job = A.jobs[j];
     finish_job<BLOCK, TMAX>(job, A, S);
   }
@@ -1730,20 +1762,22 @@ template <int BLOCK, int TMAX>
 int finish_attr() {
   static bool done = false;
   if (!done) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_finish<BLOCK, TMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)sizeof(FinishShared<BLOCK, TMAX>));
+    hipError_t e = hipFuncSetAttribute((const void*)k_finish_plan<BLOCK, TMAX>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)finish_plan_lds<BLOCK, TMAX>());
     if (e != hipSuccess) return (int)e;
     done = true;
   }
   return 0;
 }
 
+// Grid: the planner's workgroup plus as many finisher workgroups as fit.
 template <int BLOCK, int TMAX>
-int finish_one(const FinishArgs& a, hipStream_t st) {
+int finish_plan_one(const FinishArgs& a, const PlanArgs& p, hipStream_t st) {
   int e = finish_attr<BLOCK, TMAX>();
   if (e) return e;
-  hipLaunchKernelGGL((k_finish<BLOCK, TMAX>), dim3(finish_grid(TMAX)), dim3(BLOCK), sizeof(FinishShared<BLOCK, TMAX>),
-                     st, a);
+  const size_t lds = finish_plan_lds<BLOCK, TMAX>();
+  hipLaunchKernelGGL((k_finish_plan<BLOCK, TMAX>), dim3(1u + finish_grid(TMAX)), dim3(BLOCK), lds, st, a, p);
   return (int)hipGetLastError();
 }
 
@@ -1751,8 +1785,8 @@ template <int BLOCK, int TMAX>
 uint32_t finish_occupancy_grid() {
   if (finish_attr<BLOCK, TMAX>() != 0) return 256;
   int per_cu = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_finish<BLOCK, TMAX>, BLOCK,
-                                                   sizeof(FinishShared<BLOCK, TMAX>)) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_finish_plan<BLOCK, TMAX>, BLOCK,
+                                                   finish_plan_lds<BLOCK, TMAX>()) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
@@ -1820,16 +1854,11 @@ int launch_plan0(const Plan0Args& a, void* stream) {
   return (int)hipGetLastError();
 }
 
-int launch_plan(const PlanArgs& a, void* stream) {
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanBlock), 0, (hipStream_t)stream, a);
-  return (int)hipGetLastError();
-}
-
-int launch_finish(const FinishArgs& a, int tmax, void* stream) {
+int launch_finish_plan(const FinishArgs& a, const PlanArgs& p, int tmax, void* stream) {
   hipStream_t st = (hipStream_t)stream;
-  if (tmax == 512) return finish_one<kFinishBlock512, 512>(a, st);
-  if (tmax == 1024) return finish_one<kFinishBlock1024, 1024>(a, st);
-  if (tmax == 2048) return finish_one<kFinishBlock2048, 2048>(a, st);
+  if (tmax == 512) return finish_plan_one<kFinishBlock512, 512>(a, p, st);
+  if (tmax == 1024) return finish_plan_one<kFinishBlock1024, 1024>(a, p, st);
+  if (tmax == 2048) return finish_plan_one<kFinishBlock2048, 2048>(a, p, st);
   return (int)hipErrorInvalidValue;
 }
 

@@ -112,6 +112,9 @@ typedef struct {
   int reverse_tiles;/* debug: process tiles in reverse order (the result must not change) */
   int sweep_persistent; /* 1: the sweep runs as many workgroups as fit on the GPU at once, each
                            looping over tiles; 0: one workgroup per tile */
+  int level_block;  /* threads per workgroup of the sweeps of recursion levels >= 2, with the same
+                       tile (sweep_block x sweep_ppt points); 0 or an unsupported shape: the
+                       sweep shape */
 } vqhull_config;
 
 /* Read / replace the configuration used by later calls (host pointers). */
@@ -121,8 +124,8 @@ int vqhull_set_config(const vqhull_config* cfg);
 /*
  * Autotuner: compute the hull of x[0..n) (device arrays, 1 <= n < 2^31) under
  * every supported configuration -- sweep shapes 256x16, 256x32, 512x8, 512x16,
- * 1024x8; LDS thresholds 512, 1024, 2048; persistent or one workgroup per tile
- * -- timing `repeats` runs of each (median wall time, after one warm-up run)
+ * 1024x8 (deeper levels with 256-thread workgroups where that shape exists);
+ * LDS thresholds 512, 1024, 2048; persistent or one workgroup per tile -- timing `repeats` runs of each (median wall time, after one warm-up run)
  * and checking that each result equals the first configuration's.  *best
  * receives the fastest configuration whose result is equal; up to cap entries
  * (host array) receive the table and *count the number of configurations
@@ -163,7 +166,9 @@ typedef struct {
   int64_t points_out; /* points the launch writes (sweep: |S1| + |S2| over all segments) */
 } vqhull_kernel_time;
 
-/* Enable (1) or disable (0) kernel timing for later calls. */
+/* Kernel timing of later calls: 0 off, 1 every launch, 2 the partition
+ * sweeps only (fewer events in the stream).  VQHULL_ERR_INVALID_ARGUMENT for
+ * other values. */
 int vqhull_set_timing(int enable);
 
 /* Copy up to cap records of the last call (host pointer); returns the count. */

@@ -40,7 +40,7 @@ class VqhullError(RuntimeError):
 
 class Config(ctypes.Structure):
     _fields_ = [("sweep_block", ctypes.c_int), ("sweep_ppt", ctypes.c_int), ("lds_limit", ctypes.c_int),
-                ("reverse_tiles", ctypes.c_int), ("sweep_persistent", ctypes.c_int)]
+                ("reverse_tiles", ctypes.c_int), ("sweep_persistent", ctypes.c_int), ("level_block", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -225,7 +225,7 @@ def get_config() -> dict:
 
 
 def set_config(**kw) -> dict:
-    """Update tuning knobs (sweep_block, sweep_ppt, lds_limit, reverse_tiles, sweep_persistent)."""
+    """Update tuning knobs (sweep_block, sweep_ppt, lds_limit, reverse_tiles, sweep_persistent, level_block)."""
     lib = load_library()
     c = Config()
     _check(lib, lib.vqhull_get_config(ctypes.byref(c)))
@@ -247,10 +247,11 @@ def level_stats() -> list[dict]:
             for i in range(n)]
 
 
-def set_timing(enable: bool) -> None:
-    """Record HIP events around every kernel launch of later calls."""
+def set_timing(enable, sweeps_only: bool = False) -> None:
+    """Record HIP events around every kernel launch of later calls (or, with
+    sweeps_only, around the partition sweeps alone)."""
     lib = load_library()
-    _check(lib, lib.vqhull_set_timing(1 if enable else 0))
+    _check(lib, lib.vqhull_set_timing((2 if sweeps_only else 1) if enable else 0))
 
 
 def kernel_times() -> list[dict]:

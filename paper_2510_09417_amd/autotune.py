@@ -108,7 +108,8 @@ def tune_batched(x, y, offsets, repeats: int = 3, stream=None, persistent=(1, 0)
         for blk, ppt in SHAPES:
             for lds in LDS_LIMITS:
                 for pers in persistent:
-                    cfg = vq.set_config(sweep_block=blk, sweep_ppt=ppt, lds_limit=lds, sweep_persistent=pers)
+                    cfg = vq.set_config(sweep_block=blk, sweep_ppt=ppt, lds_limit=lds, sweep_persistent=pers,
+                                        level_block=256)
                     out, cnt = vq.hull_batched(x, y, offsets, stream=stream)
                     torch.cuda.synchronize()
                     times = []

@@ -27,7 +27,7 @@ namespace {
 thread_local std::string g_last_error;
 
 std::mutex g_cfg_mu;
-vqhull_config g_cfg = {512, 8, 2048, 0, 1};
+vqhull_config g_cfg = {512, 8, 2048, 0, 1, 256};
 
 struct LevelStat {
   int64_t segs, swept, jobs, jobpts;
@@ -243,7 +243,22 @@ vqhull_config sanitized(vqhull_config c) {
   c.lds_limit = std::min(2048, std::max(256, c.lds_limit));
   c.reverse_tiles = c.reverse_tiles ? 1 : 0;
   c.sweep_persistent = c.sweep_persistent ? 1 : 0;
+  const int tile = c.sweep_block * c.sweep_ppt;
+  if (c.level_block <= 0 || c.level_block == c.sweep_block || tile % c.level_block != 0 ||
+      !sweep_shape_supported(c.level_block, tile / c.level_block))
+    c.level_block = 0;
   return c;
+}
+
+// Shape of the sweep of level k: the top-level passes (k <= 1) use the sweep
+// shape; deeper levels level_block threads over the same tile.
+void level_shape(const vqhull_config& c, int k, int& block, int& ppt) {
+  block = c.sweep_block;
+  ppt = c.sweep_ppt;
+  if (k >= 2 && c.level_block > 0) {
+    ppt = c.sweep_block * c.sweep_ppt / c.level_block;
+    block = c.level_block;
+  }
 }
 
 int take_event(Context& w) {
@@ -390,13 +405,15 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
   const int tmax = finish_tmax_for(cfg.lds_limit);
 
   const size_t max_seg = N / (lds_limit + 1) + (size_t)nreq + 2;
-  const bool tm = g_timing.load() != 0;
+  const int tmode = g_timing.load();
+  const bool tm = tmode != 0;          // sweeps
+  const bool tm_all = tmode == 1;      // every other launch too
 
   ExtremesArgs ea{x, y, tile_req, w.req.p, w.epart.p, w.counts_dev, (uint32_t)ext_tiles};
-  timed(w, tm, st, VQHULL_K_EXTREMES, 0, (int64_t)N, 0, [&] { ck(launch_extremes(ea, st), "k_extremes"); });
+  timed(w, tm_all, st, VQHULL_K_EXTREMES, 0, (int64_t)N, 0, [&] { ck(launch_extremes(ea, st), "k_extremes"); });
   ensure(w.level_nodes, 16, st, true);
   const Plan0Args pa = plan0_args(w, cfg);
-  timed(w, tm, st, VQHULL_K_PLAN0, 0, nreq, 0, [&] { ck(launch_plan0(pa, st), "k_plan0"); });
+  timed(w, tm_all, st, VQHULL_K_PLAN0, 0, nreq, 0, [&] { ck(launch_plan0(pa, st), "k_plan0"); });
   ck(hipEventRecord(w.status_ev[0], st), "hipEventRecord");
 
   std::vector<Status> known;           // host copies of status[0..]
@@ -413,14 +430,16 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
     // Grid: persistent, or one workgroup per tile with the tile count bounded
     // from what the host knows (levels 0 and 1 exactly; level k from level
     // k-1: tiles <= ceil(swept(k-1) / tile) + 2 nseg(k-1)); surplus groups exit.
-    uint32_t G = sweep_grid(cfg.sweep_block, cfg.sweep_ppt, mode);
+    int blk = 0, ppt = 0;
+    level_shape(cfg, k, blk, ppt);
+    uint32_t G = sweep_grid(blk, ppt, mode);
     if (!cfg.sweep_persistent) {
       uint64_t bound = k <= 1 ? tiles0
                               : (known[k - 1].swept + (uint64_t)tile - 1) / tile + 2ull * known[k - 1].nseg + 1;
       G = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(bound, max_tiles));
     }
     sweep_recs.push_back(timed(w, tm, st, VQHULL_K_SWEEP, k, 0, 0, [&] {
-      ck(launch_sweep(sa, mode, cfg.sweep_block, cfg.sweep_ppt, G, st), "k_sweep");
+      ck(launch_sweep(sa, mode, blk, ppt, G, st), "k_sweep");
     }));
 
     // Node capacity for this plan: nodes after it <= nodes(k) + 2 nseg(k), with
@@ -432,7 +451,7 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
     ensure(w.level_nodes, (size_t)k + 3, st, true);
     const FinishArgs fa = finish_args(w, x, y, k);
     const PlanArgs pl = plan_args(w, cfg, k, G);
-    finish_recs.push_back(timed(w, tm, st, VQHULL_K_PLAN, k, 0, 0,
+    finish_recs.push_back(timed(w, tm_all, st, VQHULL_K_PLAN, k, 0, 0,
                                 [&] { ck(launch_finish_plan(fa, pl, tmax, st), "k_finish_plan"); }));
     ck(hipEventRecord(w.status_ev[next], st), "hipEventRecord");
 
@@ -478,7 +497,7 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
   aa.out_idx = out_idx;
   aa.out_count = out_counts;
   aa.max_nodes = known.back().nnodes;
-  timed(w, tm, st, VQHULL_K_ASSEMBLE, (int)nlevels, aa.max_nodes, 0, [&] {
+  timed(w, tm_all, st, VQHULL_K_ASSEMBLE, (int)nlevels, aa.max_nodes, 0, [&] {
     ck(launch_assemble(aa, st), "k_assemble");
     ck(launch_copy_lists(aa, st), "k_copy_lists");
   });
@@ -655,6 +674,9 @@ int context_reserve_fixed(Context* c, int64_t npoints, int64_t nreq, int levels,
     // grid sizes are cached on the host here, before any capture
     const vqhull_config cfg = current_config();
     for (int m = 0; m < 3; ++m) (void)sweep_grid(cfg.sweep_block, cfg.sweep_ppt, m);
+    int lb = 0, lp = 0;
+    level_shape(cfg, 2, lb, lp);
+    (void)sweep_grid(lb, lp, kSweepLevel);
     (void)finish_grid(finish_tmax_for(cfg.lds_limit));
     ck(hipStreamSynchronize(s), "hipStreamSynchronize");
   });
@@ -713,8 +735,10 @@ int context_enqueue_fixed(Context* c, const double* x, const double* y, int64_t*
     ck(launch_plan0(plan0_args(w, cfg), st), "k_plan0");
     for (int k = 0; k < levels; ++k) {
       const int mode = sweep_mode(k);
-      const uint32_t G = sweep_grid(cfg.sweep_block, cfg.sweep_ppt, mode);
-      ck(launch_sweep(sweep_args(w, cfg, k, x, y), mode, cfg.sweep_block, cfg.sweep_ppt, G, st), "k_sweep");
+      int blk = 0, ppt = 0;
+      level_shape(cfg, k, blk, ppt);
+      const uint32_t G = sweep_grid(blk, ppt, mode);
+      ck(launch_sweep(sweep_args(w, cfg, k, x, y), mode, blk, ppt, G, st), "k_sweep");
       ck(launch_finish_plan(finish_args(w, x, y, k), plan_args(w, cfg, k, G), tmax, st), "k_finish_plan");
     }
     const int last = levels % kStatusRing;
@@ -777,7 +801,8 @@ int vqhull_autotune(const double* x, const double* y, int64_t n, int32_t repeats
   std::vector<vqhull_config> cands;
   for (const auto& sh : shapes)
     for (int lds : lds_limits)
-      for (int pers = 1; pers >= 0; --pers) cands.push_back(sanitized(vqhull_config{sh[0], sh[1], lds, 0, pers}));
+      for (int pers = 1; pers >= 0; --pers)
+        cands.push_back(sanitized(vqhull_config{sh[0], sh[1], lds, 0, pers, 256}));
   hipStream_t st = (hipStream_t)stream;
   int64_t* d_idx = nullptr;
   int64_t* d_cnt = nullptr;
@@ -869,7 +894,8 @@ int vqhull_stream_scale(const double* in, double* out, int64_t n, double s, vqhu
 }
 
 int vqhull_set_timing(int enable) {
-  g_timing.store(enable ? 1 : 0);
+  if (enable < 0 || enable > 2) return VQHULL_ERR_INVALID_ARGUMENT;
+  g_timing.store(enable);
   return VQHULL_OK;
 }
 

@@ -163,7 +163,8 @@ int make_lane(vqhull_server* s, int index, Lane** out) {
 
 bool same_config(const vqhull_config& a, const vqhull_config& b) {
   return a.sweep_block == b.sweep_block && a.sweep_ppt == b.sweep_ppt && a.lds_limit == b.lds_limit &&
-         a.reverse_tiles == b.reverse_tiles && a.sweep_persistent == b.sweep_persistent;
+         a.reverse_tiles == b.reverse_tiles && a.sweep_persistent == b.sweep_persistent &&
+         a.level_block == b.level_block;
 }
 
 // Capture the lane's whole batch step (table copies, gather, the fixed

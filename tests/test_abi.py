@@ -64,6 +64,16 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert one[0] == 0
 
 
+def test_timing_modes_on_host(lib):
+    try:
+        for mode in (0, 1, 2):
+            assert lib.vqhull_set_timing(mode) == 0
+        for bad in (-1, 3, 100):
+            assert lib.vqhull_set_timing(bad) == 1
+    finally:
+        assert lib.vqhull_set_timing(0) == 0
+
+
 def test_status_strings(lib):
     for code in range(5):
         assert lib.vqhull_status_string(code)
@@ -80,6 +90,12 @@ def test_config_roundtrip_and_sanitizing():
             (256, 16, 1000, 1, 0)
         c = vq.set_config(sweep_block=300, sweep_ppt=7, lds_limit=10**6)
         assert (c["sweep_block"], c["sweep_ppt"], c["lds_limit"]) == (512, 8, 2048)
+        # deeper levels: a workgroup size with the same tile, else the sweep shape (0)
+        assert vq.set_config(sweep_block=512, sweep_ppt=8, level_block=256)["level_block"] == 256
+        assert vq.set_config(level_block=512)["level_block"] == 0  # the sweep shape itself
+        assert vq.set_config(level_block=1024)["level_block"] == 0  # 1024 x 4 is not a shape
+        assert vq.set_config(sweep_block=256, sweep_ppt=32, level_block=1024)["level_block"] == 1024
+        assert vq.set_config(level_block=-3)["level_block"] == 0
     finally:
         vq.set_config(**old)
 

@@ -1299,7 +1299,7 @@ struct FinishShared {
   uint16_t lvl[TMAX + 2];
   uint16_t bigc[TMAX / kSmallChild + 2];
   uint32_t scan[3][BLOCK / 64];
-  uint32_t nsub, ntot, nnode, nlvl, bad, nbigc, anytie;
+  uint32_t bad, nbigc, anytie;
 };
 
 template <int BLOCK, int TMAX>
@@ -1343,19 +1343,17 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
     S.nv[0] = (uint16_t)(cnt + 2);
     S.nc0[0] = kNone16;
     S.nc1[0] = kNone16;
-    S.nsub = 1;
-    S.ntot = cnt;
-    S.nnode = 1;
     S.lvl[0] = 0;
     S.lvl[1] = 1;
-    S.nlvl = 1;
   }
   __syncthreads();
   if (S.bad && tid == 0) A.req[job.req].err = 1u;
 
+  // Level sizes, identical in every thread (the scans return totals to all).
+  uint32_t nsub_next = 1, ntot_next = cnt, nnode = 1, nlvl = 1;
   int cb = 0;  // live list buffer / sub-subproblem table of this level
-  while (S.nsub > 0) {
-    const uint32_t nsub = S.nsub, ntot = S.ntot, nch = 2u * nsub;
+  while (nsub_next > 0) {
+    const uint32_t nsub = nsub_next, ntot = ntot_next, nch = 2u * nsub;
     for (uint32_t c = tid; c < nch; c += BLOCK) {
       S.ccnt[c] = 0;
       S.cmax[c] = 0ull;
@@ -1422,7 +1420,7 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
       }
       uint32_t ex[3], tot[3];
       block_scan<BLOCK, 3>(v, ex, tot, S.scan);
-      uint32_t en = S.nnode + ex[0], es = ex[1], ep = ex[2];
+      uint32_t en = nnode + ex[0], es = ex[1], ep = ex[2];
 #pragma unroll
       for (int k = 0; k < KC; ++k) {
         const uint32_t c = c0 + k;
@@ -1437,12 +1435,9 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
           ep += n >= 2u ? n : 0u;
         }
       }
-      __syncthreads();
-      if (tid == 0) {
-        S.nnode += tot[0];
-        S.nsub = tot[1];
-        S.ntot = tot[2];
-      }
+      nnode += tot[0];
+      nsub_next = tot[1];
+      ntot_next = tot[2];
     }
     __syncthreads();
     // 3. scatter; the point holding its child's largest key is the child's
@@ -1542,16 +1537,12 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
         S.snode[cb ^ 1][ns] = v;
       }
     }
-    __syncthreads();
-    if (tid == 0) {
-      S.nlvl += 1;
-      S.lvl[S.nlvl] = (uint16_t)S.nnode;
-    }
+    nlvl += 1;
+    if (tid == 0) S.lvl[nlvl] = (uint16_t)nnode;  // read after the loop
     __syncthreads();
     cb ^= 1;
   }
   // in-order positions: subtree sizes bottom-up, starts top-down
-  const uint32_t nlvl = S.nlvl;
   for (int L = (int)nlvl - 1; L >= 0; --L) {
     for (uint32_t v = S.lvl[L] + tid; v < S.lvl[L + 1]; v += BLOCK) {
       const uint16_t c0 = S.nc0[v], c1 = S.nc1[v];

@@ -1,0 +1,63 @@
+"""The rocprofv3 summary helpers (CPU): the fused pass's source hash follows
+the code the fused pass is built from and nothing else, and the traffic
+calibration scales the counters on the probe kernel."""
+import csv
+
+from paper_2510_09417_amd import profiling as P
+
+
+def _sources():
+    with open(P.KERNEL_SRC) as f, open(P.HEADER_SRC) as g:
+        return f.read(), g.read()
+
+
+def test_fused_source_hash_scope():
+    k, h = _sources()
+    base = P.fused_source(k, h)
+    assert P.SWEEP_END in k and P.LAUNCH_BEGIN in k and P.LAUNCH_END in k
+    # below the sweep kernel (planners, finisher, assembly): not part of it
+    i = k.index(P.SWEEP_END) + len(P.SWEEP_END)
+    assert P.fused_source(k[:i] + "\n// planner note\n" + k[i:], h) == base
+    # inside the sweep section, in its launchers or in the shared header: part of it
+    j = k.index("__global__ __launch_bounds__(BLOCK) void k_sweep")
+    assert P.fused_source(k[:j] + "// x\n" + k[j:], h) != base
+    m = k.index(P.LAUNCH_BEGIN) + len(P.LAUNCH_BEGIN)
+    assert P.fused_source(k[:m] + "\n// x\n" + k[m:], h) != base
+    assert P.fused_source(k, h + "// x\n") != base
+
+
+def _write_counters(path, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for r in rows:
+            w.writerow(r)
+
+
+def test_traffic_calibration(tmp_path):
+    n = 1000
+    fetch = tmp_path / "f.csv"
+    write = tmp_path / "w.csv"
+    # probe: 8 B read and 8 B written per element; counters in KiB, FETCH_SIZE reads half
+    _write_counters(fetch, [
+        {"Dispatch_Id": 1, "Kernel_Name": "vqh::k_stream_scale(double const*, double*, unsigned long, double)",
+         "Counter_Name": "FETCH_SIZE", "Counter_Value": 8 * n / 1024 / 2},
+        {"Dispatch_Id": 2, "Kernel_Name": "void vqh::k_sweep<512, 8, 2>(vqh::SweepArgs)",
+         "Counter_Name": "FETCH_SIZE", "Counter_Value": 100.0},
+    ])
+    _write_counters(write, [
+        {"Dispatch_Id": 1, "Kernel_Name": "vqh::k_stream_scale(double const*, double*, unsigned long, double)",
+         "Counter_Name": "WRITE_SIZE", "Counter_Value": 8 * n / 1024},
+        {"Dispatch_Id": 2, "Kernel_Name": "void vqh::k_sweep<512, 8, 2>(vqh::SweepArgs)",
+         "Counter_Name": "WRITE_SIZE", "Counter_Value": 50.0},
+    ])
+    out_json, out_md = tmp_path / "t.json", tmp_path / "t.md"
+    P.traffic(str(fetch), str(write), str(out_json), str(out_md), "fetch cmd", "write cmd", n)
+    import json
+
+    t = json.loads(out_json.read_text())
+    assert abs(t["fetch_scale"] - 2.0) < 1e-9 and abs(t["write_scale"] - 1.0) < 1e-9
+    assert t["fetch_bytes_per_launch"] == 2 * 100 * 1024 and t["write_bytes_per_launch"] == 50 * 1024
+    assert t["bytes_per_launch"] == 2 * 100 * 1024 + 50 * 1024
+    assert t["kernel_source_sha256_16"] == P.kernel_source_hash()
+    assert "fetch cmd" in out_md.read_text()

@@ -28,7 +28,6 @@ Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2]
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -37,13 +36,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_fused_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2510_09417_amd", "csrc", "vqhull_kernels.hip")
 METRIC = "Gpoints/s + % HBM peak (1e8 FP64 pts); batched hulls/s + p50/p99 latency"
-
-
-def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def load_traffic():
@@ -54,6 +47,8 @@ def load_traffic():
             t = json.load(f)
     except (OSError, ValueError):
         return None
+    from paper_2510_09417_amd.profiling import kernel_source_hash
+
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     return t

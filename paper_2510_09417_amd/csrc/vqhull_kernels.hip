@@ -6,9 +6,11 @@
 //               considerations"): orientation against p->r and r->q, the
 //               farthest point of each side, and extraction of S1 / S2, for
 //               every tile of every live segment of one recursion level.
-//   k_plan0 /   single-workgroup planners: reduce the per-tile results of a
-//   k_plan      level and lay out the next one (breadth-first recursion).
-//   k_finish    one workgroup finishes a whole small subproblem in LDS.
+//   k_plan0     single-workgroup planner of the roots (p, q of every request).
+//   k_finish_plan  one launch per level: workgroup 0 reduces the per-tile
+//               results of the level and lays out the next one (breadth-first
+//               recursion); every other workgroup finishes whole small
+//               subproblems of the level in LDS.
 //   k_assemble  clockwise order from the recursion tree (Algorithm 1's
 //               unions, in the order p, Hull(S1), q, Hull(S2)).
 //
@@ -1265,7 +1267,7 @@ __device__ void plan_level(const PlanArgs& A, PlanLds<PB>& L) {
   plan_status(S, A.st_out, A.st_host, node_base, A.level_nodes + A.level + 2u, A.fuse ? A.st_in->ntiles : S.tiles);
 }
 
-// --------------------------------------------------------------- k_finish
+// ------------------------------------------------------- k_finish_plan
 //
 // One workgroup runs Algorithm 1 to the end on a subproblem (a, r, b) of at
 // most TMAX points, entirely in LDS, breadth-first: every level classifies

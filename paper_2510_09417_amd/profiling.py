@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import csv
 import hashlib
+import re
 import json
 import os
 import sys
@@ -42,9 +43,18 @@ def fused_source(kernels: str, header: str) -> str:
     return head + "\n" + launch + "\n" + header
 
 
+def code_only(src: str) -> str:
+    """Source without comments and blank lines: comments do not change the code.
+    (Simple textual stripping; no string literal in these sources contains a
+    comment marker.)"""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
+
+
 def kernel_source_hash() -> str:
     with open(KERNEL_SRC) as f, open(HEADER_SRC) as g:
-        return hashlib.sha256(fused_source(f.read(), g.read()).encode()).hexdigest()[:16]
+        return hashlib.sha256(code_only(fused_source(f.read(), g.read())).encode()).hexdigest()[:16]
 
 
 def short(name: str) -> str:
@@ -128,7 +138,7 @@ def traffic(fetch_csv: str, write_csv: str, out_json: str, out_md: str, fetch_cm
              f"| fused sweep fetched bytes per launch (scaled) | {res['fetch_bytes_per_launch']} |",
              f"| fused sweep written bytes per launch (scaled) | {res['write_bytes_per_launch']} |",
              f"| fused sweep HBM traffic per launch | {res['bytes_per_launch']} |",
-             f"| fused-pass source sha256[:16] (kernel file up to the sweep kernel, sweep launchers, shared header) | `{res['kernel_source_sha256_16']}` |"]
+             f"| fused-pass code sha256[:16] (kernel file up to the sweep kernel, sweep launchers, shared header; comments stripped) | `{res['kernel_source_sha256_16']}` |"]
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
     return res

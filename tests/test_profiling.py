@@ -26,6 +26,16 @@ def test_fused_source_hash_scope():
     assert P.fused_source(k, h + "// x\n") != base
 
 
+def test_hash_ignores_comments_only():
+    k, h = _sources()
+    base = P.kernel_source_hash()
+    j = k.index("__global__ __launch_bounds__(BLOCK) void k_sweep")
+    same = P.code_only(P.fused_source(k[:j] + "// a note\n/* more */\n" + k[j:], h))
+    assert same == P.code_only(P.fused_source(k, h))
+    assert P.code_only("a = 1; // c\n/* x\n y */ b = 2;\n\n") == "a = 1;\n  b = 2;"
+    assert base == P.kernel_source_hash()
+
+
 def _write_counters(path, rows):
     with open(path, "w", newline="") as f:
         w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])

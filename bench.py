@@ -63,7 +63,7 @@ def percentile(v, q):
     return v[min(len(v) - 1, int(q * len(v)))]
 
 
-def served_benchmark(vq, workloads, torch, nreq: int, lanes: int) -> dict:
+def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: int = 1 << 25) -> dict:
     """The served mix through vqhull_server_*, against the plain per-request path."""
     import numpy as np
 
@@ -99,7 +99,6 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int) -> dict:
     py = Y.data_ptr() + 8 * off[:-1]
     po = OUT.data_ptr() + 8 * off[:-1]
     pc = CNT.data_ptr() + 8 * np.arange(nreq, dtype=np.int64)
-    lane_points = 1 << 25
 
     # Autotune the batched kernels on one lane-sized batch of the mix (the
     # first requests up to lane_points points) and serve with the winner;
@@ -203,6 +202,7 @@ def main() -> int:
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=65536)
     ap.add_argument("--served-lanes", type=int, default=4)
+    ap.add_argument("--served-lane-points", type=int, default=1 << 25)
     ap.add_argument("--n", type=int, default=100_000_000, help="points per dataset (default 1e8)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -294,6 +294,18 @@ def main() -> int:
                 per_kind[r["kind"]] = per_kind.get(r["kind"], 0.0) + r["ms"]
     torch.cuda.synchronize()
     vq.set_timing(False)
+    # energy per hull: the GPU's energy counter over ~2 s of steps, idle draw
+    # subtracted (outside the timed region)
+    from paper_2510_09417_amd import energy
+
+    en = energy.measure(step, len(names), torch.cuda.synchronize)
+    if en.get("available"):
+        en["unit"] = "hull (disk 1e8 or square 1e8)"
+        en["gpoints_per_joule"] = round(npts / len(names) / 1e9 / en["joules_per_unit"], 3)
+        log(f"energy: {en['joules_per_unit']:.4f} J per hull ({en['dynamic_joules_per_unit']:.4f} J above idle "
+            f"{en['idle_w']} W)")
+    else:
+        log(f"energy: not measured ({en.get('reason')})")
     wall = t1 - t0
     ms_per_step = 1e3 * wall / args.steps
     value = npts * args.steps / wall / 1e9
@@ -330,7 +342,8 @@ def main() -> int:
     if not args.no_served:
         del dx, outs
         torch.cuda.empty_cache()
-        served = served_benchmark(vq, workloads, torch, args.served_requests, args.served_lanes)
+        served = served_benchmark(vq, workloads, torch, args.served_requests, args.served_lanes,
+                                  args.served_lane_points)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -364,6 +377,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernel_ms_per_step": {k: round(v / breakdown_steps, 4) for k, v in per_kind.items()},
+        "energy": en,
         "served": served,
     }
     print(json.dumps(line), flush=True)

@@ -24,9 +24,9 @@ def vq():
 
     assert torch.cuda.is_available()
     vq.load_library()
-    vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048, reverse_tiles=0, sweep_persistent=1)
+    vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048, reverse_tiles=0, sweep_persistent=1, level_block=256)
     yield vq
-    vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048, reverse_tiles=0, sweep_persistent=1)
+    vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048, reverse_tiles=0, sweep_persistent=1, level_block=256)
 
 
 def gpu_hull(vq, x, y):
@@ -129,6 +129,20 @@ def test_kernel_shapes_do_not_change_result(vq, shape, lds_limit, persistent):
             check(vq, x, y, f"{dist} {shape} lds={lds_limit} persistent={persistent}")
     finally:
         vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048, sweep_persistent=1)
+
+
+@pytest.mark.parametrize("shape,level_block", [((512, 8), 0), ((512, 8), 256), ((256, 32), 512), ((256, 32), 1024),
+                                               ((512, 16), 1024), ((1024, 8), 512)])
+def test_level_shapes_do_not_change_result(vq, shape, level_block):
+    """Levels >= 2 with their own workgroup size over the same tile."""
+    c = vq.set_config(sweep_block=shape[0], sweep_ppt=shape[1], level_block=level_block)
+    assert c["level_block"] == level_block
+    try:
+        for dist in workloads.DISTRIBUTIONS:
+            x, y = workloads.points(dist, 300_001, seed=79)
+            check(vq, x, y, f"{dist} {shape} level_block={level_block}")
+    finally:
+        vq.set_config(sweep_block=512, sweep_ppt=8, level_block=256)
 
 
 @pytest.mark.parametrize("persistent", [0, 1])

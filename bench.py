@@ -200,6 +200,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-energy", action="store_true")
     ap.add_argument("--served-requests", type=int, default=65536)
     ap.add_argument("--served-lanes", type=int, default=4)
     ap.add_argument("--served-lane-points", type=int, default=1 << 25)
@@ -298,7 +299,8 @@ def main() -> int:
     # subtracted (outside the timed region)
     from paper_2510_09417_amd import energy
 
-    en = energy.measure(step, len(names), torch.cuda.synchronize)
+    en = ({"available": False, "reason": "--no-energy"} if args.no_energy
+          else energy.measure(step, len(names), torch.cuda.synchronize))
     if en.get("available"):
         en["unit"] = "hull (disk 1e8 or square 1e8)"
         en["gpoints_per_joule"] = round(npts / len(names) / 1e9 / en["joules_per_unit"], 3)

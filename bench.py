@@ -172,6 +172,31 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
     plain_thr = len(plain_lat) / (time.perf_counter() - tp0)
     checked = min(i, 512)
     log(f"plain path: {plain_thr:.0f} hulls/s over {len(plain_lat)} requests; served == plain on {same}/{checked}")
+
+    # both paths under the same Poisson stream at 0.9 x the plain path's
+    # capacity, where both are stable; latency from the scheduled arrival
+    # (plain: queueing behind earlier requests included)
+    nm = min(nreq, 4096)
+    lam = 0.9 * plain_thr
+    gm = np.random.default_rng(workloads.SERVED_SEED + 2)
+    arr_m = np.cumsum(-np.log1p(-gm.random(nm)) / lam)
+    minfos, _ = run(arr_m)
+    m_served = [1e3 * (i["t_done"] - i["t_submit"]) for i in minfos]
+    m_plain = []
+    t_start = time.perf_counter()
+    for k in range(nm):
+        while time.perf_counter() - t_start < arr_m[k]:
+            pass
+        vq.hull_into(X[off[k]:off[k + 1]], Y[off[k]:off[k + 1]], oi, oc, stream)
+        int(oc.item())
+        m_plain.append(1e3 * (time.perf_counter() - t_start - arr_m[k]))
+    matched = {"rate_hulls_per_s": round(lam, 1), "requests": nm,
+               "served_p50_ms": round(percentile(m_served, 0.50), 3),
+               "served_p99_ms": round(percentile(m_served, 0.99), 3),
+               "plain_p50_ms": round(percentile(m_plain, 0.50), 3),
+               "plain_p99_ms": round(percentile(m_plain, 0.99), 3)}
+    log(f"at {lam:.0f} hulls/s: served p50 {matched['served_p50_ms']} p99 {matched['served_p99_ms']} ms, "
+        f"plain p50 {matched['plain_p50_ms']} p99 {matched['plain_p99_ms']} ms")
     vq.set_config(**saved_cfg)
     return {
         "workload": f"{nreq} requests, sizes log-uniform in [16, 1e6] (seed {workloads.SERVED_SEED}), "
@@ -190,6 +215,7 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
         "plain_hulls_per_s": round(plain_thr, 1), "plain_requests": len(plain_lat),
         "plain_p50_ms": round(percentile(plain_lat, 0.50), 3), "plain_p99_ms": round(percentile(plain_lat, 0.99), 3),
         "served_equals_plain": f"{same}/{checked}",
+        "matched_rate": matched,
     }
 
 

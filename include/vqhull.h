@@ -155,7 +155,8 @@ enum {
   VQHULL_K_SWEEP = 2,    /* fused partition sweep of one level */
   VQHULL_K_PLAN = 3,     /* planning of one level, in one launch with the LDS finisher of that
                             level's small subproblems (workgroup 0 plans, the others finish) */
-  VQHULL_K_FINISH = 4,   /* reserved: no launch is a finisher alone */
+  VQHULL_K_FINISH = 4,   /* one launch doing a whole single request of at most the LDS threshold's
+                            points (extremes and Algorithm 1 in one workgroup's LDS) */
   VQHULL_K_ASSEMBLE = 5  /* clockwise assembly (both kernels) */
 };
 typedef struct {

@@ -22,6 +22,8 @@
 
 using namespace vqh;
 
+static_assert(kCountNonfinite == -(int64_t)VQHULL_ERR_NONFINITE, "the kernels' count of a non-finite request");
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -549,6 +551,24 @@ void run(Context& w, const vqhull_config& cfg, const double* x, const double* y,
 
   std::lock_guard<std::mutex> guard(w.mu);
   ck(hipSetDevice(w.device), "hipSetDevice");
+
+  // A single request small enough for the LDS finisher: one launch does it
+  // all (extremes, Algorithm 1 in LDS, the clockwise list).
+  if (nreq == 1 && N <= lds_limit) {
+    ensure_points(w, std::max<size_t>(N, 1), st);
+    ensure(w.nodes, 4096, st);
+    ensure(w.req, 1, st);
+    w.stats.clear();
+    w.launches.clear();
+    w.next_event = 0;
+    SmallArgs sa{x, y, (uint32_t)N, out_idx, out_counts, w.wi[0], w.nodes.p, w.req.p};
+    timed(w, g_timing.load() == 1, st, VQHULL_K_FINISH, 0, (int64_t)N, 0,
+          [&] { ck(launch_small(sa, finish_tmax_for(cfg.lds_limit), st), "k_small"); });
+    // The workspace is reused by the next call: wait for the kernel.
+    ck(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (g_timing.load()) collect_times(w);
+    return;
+  }
 
   // request table and extremes tile map
   ensure_host_req(w, (size_t)nreq);

@@ -17,6 +17,7 @@
 namespace vqh {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr int64_t kCountNonfinite = -3;  // the count of a request with a NaN or infinity (-VQHULL_ERR_NONFINITE)
 
 // Source of a finisher job's points.
 enum : uint32_t { kSrcBufA = 0, kSrcBufB = 1, kSrcUser = 2 };
@@ -249,6 +250,18 @@ struct FinishArgs {
   Req* req;
 };
 
+// One request of at most the LDS threshold's points, whole in one workgroup.
+struct SmallArgs {
+  const double* x;
+  const double* y;
+  uint32_t n;
+  int64_t* out_idx;
+  int64_t* out_count;
+  uint32_t* list;  // n entries of workspace: the finisher's ordered list
+  Node* node;      // one node of workspace
+  Req* req;        // one request record of workspace
+};
+
 struct AssembleArgs {
   Node* nodes;
   const uint32_t* level_begin;  // node level boundaries, nlevels + 1 entries (device)
@@ -273,6 +286,9 @@ uint32_t finish_grid(int tmax);            // persistent grid size of the finish
 int launch_plan0(const Plan0Args& a, void* stream);
 // The finisher of level k and the planner of level k in one launch.
 int launch_finish_plan(const FinishArgs& a, const PlanArgs& p, int tmax, void* stream);
+// A whole request of n <= tmax points in one workgroup (extremes, Algorithm 1
+// in LDS, output in clockwise order).
+int launch_small(const SmallArgs& a, int tmax, void* stream);
 int launch_assemble(const AssembleArgs& a, void* stream);
 int launch_copy_lists(const AssembleArgs& a, void* stream);
 int launch_stream_scale(const double* in, double* out, uint64_t n, double s, void* stream);

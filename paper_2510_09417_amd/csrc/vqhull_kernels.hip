@@ -1600,6 +1600,145 @@ __global__ __launch_bounds__(BLOCK) void k_finish_plan(FinishArgs A, PlanArgs P)
   }
 }
 
+// ------------------------------------------------------------- k_small
+//
+// A single request small enough for the LDS finisher, in one launch: the
+// lexicographic extremes p and q by a workgroup reduction (the non-finite
+// check on the way), then Algorithm 1 from the degenerate triangle (p, q, p)
+// inside LDS exactly as a root job of the level loop, and the clockwise list
+// [p] ++ finisher list written to the caller's output.
+
+// (x, y, index) order: the lexicographic minimum, and the maximum of (x, y)
+// with the lower index among equal points.
+__device__ __forceinline__ bool small_before(double xa, double ya, uint32_t ia, double xb, double yb, uint32_t ib) {
+  if (ib == kNone) return ia != kNone;
+  if (ia == kNone) return false;
+  if (xa != xb) return xa < xb;
+  if (ya != yb) return ya < yb;
+  return ia < ib;
+}
+__device__ __forceinline__ bool small_after(double xa, double ya, uint32_t ia, double xb, double yb, uint32_t ib) {
+  if (ib == kNone) return ia != kNone;
+  if (ia == kNone) return false;
+  if (xa != xb) return xa > xb;
+  if (ya != yb) return ya > yb;
+  return ia < ib;
+}
+
+template <int BLOCK, int TMAX>
+__global__ __launch_bounds__(BLOCK) void k_small(SmallArgs A) {
+  constexpr int NW = BLOCK / 64;
+  extern __shared__ unsigned char smem_raw[];
+  FinishShared<BLOCK, TMAX>& S = *reinterpret_cast<FinishShared<BLOCK, TMAX>*>(smem_raw);
+  __shared__ double s_mn[2][NW], s_mx[2][NW];
+  __shared__ uint32_t s_mni[NW], s_mxi[NW], s_bad;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t n = A.n;
+  double mnx = 0.0, mny = 0.0, mxx = 0.0, mxy = 0.0;
+  uint32_t mni = kNone, mxi = kNone;
+  bool bad = false;
+  for (uint32_t i = tid; i < n; i += BLOCK) {
+    const double xv = A.x[i], yv = A.y[i];
+    bad |= !finite(xv) || !finite(yv);
+    if (small_before(xv, yv, i, mnx, mny, mni)) {
+      mnx = xv;
+      mny = yv;
+      mni = i;
+    }
+    if (small_after(xv, yv, i, mxx, mxy, mxi)) {
+      mxx = xv;
+      mxy = yv;
+      mxi = i;
+    }
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const double ax = __shfl_xor(mnx, m, 64), ay = __shfl_xor(mny, m, 64);
+    const uint32_t ai = __shfl_xor(mni, m, 64);
+    if (small_before(ax, ay, ai, mnx, mny, mni)) {
+      mnx = ax;
+      mny = ay;
+      mni = ai;
+    }
+    const double bx = __shfl_xor(mxx, m, 64), by = __shfl_xor(mxy, m, 64);
+    const uint32_t bi = __shfl_xor(mxi, m, 64);
+    if (small_after(bx, by, bi, mxx, mxy, mxi)) {
+      mxx = bx;
+      mxy = by;
+      mxi = bi;
+    }
+  }
+  if (tid == 0) s_bad = 0u;
+  __syncthreads();
+  if (bad) s_bad = 1u;
+  if (lane == 0) {
+    s_mn[0][w] = mnx;
+    s_mn[1][w] = mny;
+    s_mni[w] = mni;
+    s_mx[0][w] = mxx;
+    s_mx[1][w] = mxy;
+    s_mxi[w] = mxi;
+  }
+  __syncthreads();
+  for (int i = 0; i < NW; ++i) {
+    if (small_before(s_mn[0][i], s_mn[1][i], s_mni[i], mnx, mny, mni)) {
+      mnx = s_mn[0][i];
+      mny = s_mn[1][i];
+      mni = s_mni[i];
+    }
+    if (small_after(s_mx[0][i], s_mx[1][i], s_mxi[i], mxx, mxy, mxi)) {
+      mxx = s_mx[0][i];
+      mxy = s_mx[1][i];
+      mxi = s_mxi[i];
+    }
+  }
+  // every thread now holds the same p = mni and q = mxi (uniform branches)
+  if (s_bad) {
+    if (tid == 0) *A.out_count = kCountNonfinite;
+    return;
+  }
+  if (n == 0u) {
+    if (tid == 0) *A.out_count = 0;
+    return;
+  }
+  if (mni == mxi) {  // every point is the same point
+    if (tid == 0) {
+      A.out_idx[0] = mni;
+      *A.out_count = 1;
+    }
+    return;
+  }
+  Job job;
+  job.ax = mnx;
+  job.ay = mny;
+  job.rx = mxx;
+  job.ry = mxy;
+  job.bx = mnx;
+  job.by = mny;
+  job.ri = mxi;
+  job.beg = 0;
+  job.cnt = n;
+  job.src = kSrcUser;
+  job.req = 0;
+  job.node = 0;
+  job.ibase = 0;
+  job.pad = 0;
+  FinishArgs fa{};
+  fa.ux = A.x;
+  fa.uy = A.y;
+  fa.bi[0] = A.list;
+  fa.bi[1] = A.list;
+  fa.nodes = A.node;
+  fa.req = A.req;
+  finish_job<BLOCK, TMAX>(job, fa, S);  // ends with a workgroup barrier
+  const uint32_t size = S.nsz[0];  // the list: Hull(S1) ++ [q] ++ Hull(S2)
+  for (uint32_t i = tid; i < size; i += BLOCK) A.out_idx[1 + i] = A.list[i];
+  if (tid == 0) {
+    A.out_idx[0] = mni;
+    *A.out_count = (int64_t)size + 1;
+  }
+}
+
 // ------------------------------------------------------------- k_assemble
 //
 // Clockwise order of every request: [p] ++ in-order(root), where the root's
@@ -1647,7 +1786,7 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble(AssembleArgs A) {
     const Req rq = A.req[i];
     int64_t count;
     if (rq.err) {
-      count = -3;
+      count = kCountNonfinite;
     } else if (rq.n == 0) {
       count = 0;
     } else if (rq.p == rq.q) {
@@ -1852,6 +1991,29 @@ int launch_finish_plan(const FinishArgs& a, const PlanArgs& p, int tmax, void* s
   if (tmax == 512) return finish_plan_one<kFinishBlock512, 512>(a, p, st);
   if (tmax == 1024) return finish_plan_one<kFinishBlock1024, 1024>(a, p, st);
   if (tmax == 2048) return finish_plan_one<kFinishBlock2048, 2048>(a, p, st);
+  return (int)hipErrorInvalidValue;
+}
+
+template <int BLOCK, int TMAX>
+int small_one(const SmallArgs& a, hipStream_t st) {
+  static bool done = false;
+  const size_t lds = sizeof(FinishShared<BLOCK, TMAX>);
+  if (!done) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_small<BLOCK, TMAX>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return (int)e;
+    done = true;
+  }
+  hipLaunchKernelGGL((k_small<BLOCK, TMAX>), dim3(1), dim3(BLOCK), lds, st, a);
+  return (int)hipGetLastError();
+}
+
+int launch_small(const SmallArgs& a, int tmax, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (a.n > (uint32_t)tmax) return (int)hipErrorInvalidValue;
+  if (tmax == 512) return small_one<kFinishBlock512, 512>(a, st);
+  if (tmax == 1024) return small_one<kFinishBlock1024, 1024>(a, st);
+  if (tmax == 2048) return small_one<kFinishBlock2048, 2048>(a, st);
   return (int)hipErrorInvalidValue;
 }
 

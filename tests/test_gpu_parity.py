@@ -145,6 +145,31 @@ def test_level_shapes_do_not_change_result(vq, shape, level_block):
         vq.set_config(sweep_block=512, sweep_ppt=8, level_block=256)
 
 
+@pytest.mark.parametrize("lds_limit", [512, 1024, 2048])
+def test_small_request_path_boundary(vq, lds_limit):
+    """A single request of at most the LDS threshold's points runs in one
+    launch (extremes and Algorithm 1 in one workgroup); one point more takes
+    the level loop.  Both give the oracle's list."""
+    vq.set_config(lds_limit=lds_limit)
+    try:
+        for n in (lds_limit - 1, lds_limit, lds_limit + 1):
+            for dist in workloads.DISTRIBUTIONS:
+                x, y = workloads.points(dist, n, seed=n)
+                check(vq, x, y, f"{dist} n={n} lds={lds_limit}")
+        vq.set_timing(True)
+        try:
+            x, y = workloads.points("circle", lds_limit, seed=5)
+            check(vq, x, y, "timed small request")
+            assert [r["kind"] for r in vq.kernel_times()] == ["finish"]
+            x, y = workloads.points("circle", lds_limit + 1, seed=5)
+            check(vq, x, y, "timed level loop")
+            assert "sweep" in {r["kind"] for r in vq.kernel_times()}
+        finally:
+            vq.set_timing(False)
+    finally:
+        vq.set_config(lds_limit=2048)
+
+
 @pytest.mark.parametrize("persistent", [0, 1])
 def test_reverse_tile_order(vq, persistent):
     vq.set_config(reverse_tiles=1, sweep_persistent=persistent)

@@ -51,6 +51,8 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.vqhull_oracle_split.argtypes = [pd, pd, pi64, i64, i64, i64, i64, pi64, pi64, pi64, pi64, pi64]
     lib.vqhull_oracle_hull.restype = ctypes.c_int
     lib.vqhull_oracle_hull.argtypes = [pd, pd, i64, pi64, pi64]
+    lib.vqhull_oracle_octagon.restype = ctypes.c_int
+    lib.vqhull_oracle_octagon.argtypes = [pd, pd, i64, pi64, ctypes.POINTER(ctypes.c_uint8)]
     return lib
 
 
@@ -134,3 +136,36 @@ def hull(x, y, lib=None) -> np.ndarray:
     if st:
         raise OracleError(st)
     return out[: cnt.value].copy()
+
+
+def octagon(x, y, lib=None) -> tuple[np.ndarray, np.ndarray]:
+    """Octagon prefilter (rules F1-F4 of the C source): the eight vertices
+    (v0 = min y, then counter-clockwise) and a keep mask (False = dropped as
+    strictly inside the octagon)."""
+    x, y = _f64(x), _f64(y)
+    if x.shape != y.shape or x.ndim != 1 or len(x) == 0:
+        raise ValueError("x and y must be non-empty 1-D arrays of equal length")
+    vert = np.empty(8, dtype=np.int64)
+    keep = np.empty(len(x), dtype=np.uint8)
+    st = (lib or load()).vqhull_oracle_octagon(_pd(x), _pd(y), len(x), _pi(vert),
+                                               keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    if st:
+        raise OracleError(st)
+    return vert, keep.astype(bool)
+
+
+def hull_prefiltered(x, y, min_points: int, lib=None) -> np.ndarray:
+    """The prefiltered variant of the method (rule F5): with more than
+    ``min_points`` points, the octagon filter first, then Algorithm 1 on the
+    kept points in their index order (so index tie-breaks are unchanged), the
+    result mapped back to input indices; otherwise Algorithm 1 on all points."""
+    x, y = _f64(x), _f64(y)
+    if x.shape != y.shape or x.ndim != 1:
+        raise ValueError("x and y must be 1-D arrays of equal length")
+    if len(x) <= min_points:
+        return hull(x, y, lib=lib)
+    if not (np.isfinite(x).all() and np.isfinite(y).all()):
+        raise OracleError(ORACLE_ERR_NONFINITE)
+    _, keep = octagon(x, y, lib=lib)
+    kept = np.flatnonzero(keep)
+    return kept[hull(x[kept], y[kept], lib=lib)]

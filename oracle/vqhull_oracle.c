@@ -40,6 +40,35 @@
  *
  * The recursion is the plain recursive function of Algorithm 1; every call
  * allocates one buffer for its two subsets and frees it on return.
+ *
+ * Octagon prefilter (Section 6: the Akl-Toussaint heuristic the paper proposes
+ * as future work).  A variant of the method first drops the points that lie
+ * strictly inside the octagon spanned by eight directional extremes, then runs
+ * Algorithm 1 unchanged on the points that remain (keeping their indices).
+ * The dropped points lie strictly inside the hull, so in exact arithmetic the
+ * hull is the same; the rules below fix every rounding and tie:
+ *
+ *   F1  vertices, counter-clockwise: v0 = min y, v1 = max fl(x-y), v2 = q (R4),
+ *       v3 = max fl(x+y), v4 = max y, v5 = min fl(x-y), v6 = p (R4),
+ *       v7 = min fl(x+y); among equal values the lowest index.
+ *   F2  D = fl(fl(x[v2] - x[v6]) + fl(y[v4] - y[v0])) bounds every coordinate
+ *       difference |u - v| of the input (width plus height of its box).
+ *   F3  edge i runs from a = v_i to b = v_(i+1 mod 8): ex = fl(b.x - a.x),
+ *       ey = fl(b.y - a.y), and
+ *         L_i(u) = fl(fl(ex * fl(u.y - a.y)) - fl(ey * fl(u.x - a.x)))
+ *       (the cross product of the edge with u - a: positive on the inner,
+ *       left side of a counter-clockwise polygon), with the margin
+ *         M_i = max(2^-44 * fl(fl(|ex| + |ey|) * D), 2^-900).
+ *   F4  u is dropped iff L_i(u) > M_i for all eight edges.  The rounding error
+ *       of L_i is below 6 ulp-units of (|ex| + |ey|) * D (and below 2^-1072 in
+ *       the gradual-underflow range), both far under M_i, so a dropped point is
+ *       strictly left of every edge in exact arithmetic: the closed polygon
+ *       then winds around it, which puts it strictly inside the hull.  An
+ *       edge of zero length (ex = ey = 0: a repeated vertex) adds nothing to
+ *       the winding and is skipped (M_i = -infinity); when all eight edges
+ *       have zero length (all points equal) nothing is dropped.
+ *   F5  the filter applies only to inputs of more than a given number of
+ *       points (below it every point is kept).
  */
 #include <math.h>
 #include <stdint.h>
@@ -205,4 +234,72 @@ int vqhull_oracle_hull(const double* x, const double* y, int64_t n, int64_t* out
   free(s);
   if (st == ORACLE_OK) *out_count = out.len;
   return st;
+}
+
+/* F1: v = argmin (sign * value(i)) with the lowest index among equal values. */
+static int64_t oct_extreme(const double* x, const double* y, int64_t n, int dir) {
+  int64_t best = 0;
+  double bv = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double v;
+    switch (dir) {
+      case 0: v = y[i]; break;           /* min y */
+      case 1: v = -(x[i] - y[i]); break; /* max fl(x-y): -fl(x-y) is exact */
+      case 3: v = -(x[i] + y[i]); break; /* max fl(x+y) */
+      case 4: v = -y[i]; break;          /* max y */
+      case 5: v = x[i] - y[i]; break;    /* min fl(x-y) */
+      default: v = x[i] + y[i]; break;   /* 7: min fl(x+y) */
+    }
+    if (i == 0 || v < bv) {
+      best = i;
+      bv = v;
+    }
+  }
+  return best;
+}
+
+/*
+ * F1-F4 on all n points (no size threshold): writes the eight vertices to
+ * vert[0..8) and keep[i] = 0 for a dropped point, 1 otherwise.
+ */
+int vqhull_oracle_octagon(const double* x, const double* y, int64_t n, int64_t* vert, uint8_t* keep) {
+  if (n < 1 || !x || !y || !vert || !keep) return ORACLE_ERR_INVALID_ARGUMENT;
+  int64_t p, q;
+  vqhull_oracle_extremes(x, y, n, &p, &q);
+  for (int d = 0; d < 8; ++d) vert[d] = d == 2 ? q : d == 6 ? p : oct_extreme(x, y, n, d);
+  double D = (x[q] - x[p]) + (y[vert[4]] - y[vert[0]]);
+  double ax[8], ay[8], ex[8], ey[8], M[8];
+  int edges = 0;
+  for (int i = 0; i < 8; ++i) {
+    int64_t a = vert[i], b = vert[(i + 1) % 8];
+    ax[i] = x[a];
+    ay[i] = y[a];
+    ex[i] = x[b] - x[a];
+    ey[i] = y[b] - y[a];
+    double s = fabs(ex[i]) + fabs(ey[i]);
+    double sd = s * D;
+    M[i] = fmax(0x1p-44 * sd, 0x1p-900);
+    if (ex[i] == 0.0 && ey[i] == 0.0) {
+      M[i] = -INFINITY;
+    } else {
+      ++edges;
+    }
+  }
+  for (int64_t u = 0; u < n; ++u) {
+    if (edges == 0) {
+      keep[u] = 1;
+      continue;
+    }
+    int inside = 1;
+    for (int i = 0; i < 8; ++i) {
+      double dy = y[u] - ay[i];
+      double dx = x[u] - ax[i];
+      double l1 = ex[i] * dy;
+      double l2 = ey[i] * dx;
+      double L = l1 - l2;
+      if (!(L > M[i])) inside = 0;
+    }
+    keep[u] = (uint8_t)!inside;
+  }
+  return ORACLE_OK;
 }

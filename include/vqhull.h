@@ -115,6 +115,14 @@ typedef struct {
   int level_block;  /* threads per workgroup of the sweeps of recursion levels >= 2, with the same
                        tile (sweep_block x sweep_ppt points); 0 or an unsupported shape: the
                        sweep shape */
+  int prefilter;    /* 1: the octagon prefilter (Section 6, the Akl-Toussaint heuristic) runs
+                       first on every request of more than lds_limit points: the points
+                       strictly inside the octagon of eight directional extremes (minimum and
+                       maximum of x, y, x-y and x+y), with a margin above the rounding error of
+                       the edge test, are dropped and Algorithm 1 runs on the rest.  Dropped
+                       points lie strictly inside the hull, so in exact arithmetic the result
+                       is unchanged.  vqhull_hull and vqhull_hull_batched only (the server's
+                       lanes ignore it).  0: off (default). */
 } vqhull_config;
 
 /* Read / replace the configuration used by later calls (host pointers). */
@@ -157,7 +165,10 @@ enum {
                             level's small subproblems (workgroup 0 plans, the others finish) */
   VQHULL_K_FINISH = 4,   /* one launch doing a whole single request of at most the LDS threshold's
                             points (extremes and Algorithm 1 in one workgroup's LDS) */
-  VQHULL_K_ASSEMBLE = 5  /* clockwise assembly (both kernels) */
+  VQHULL_K_ASSEMBLE = 5, /* clockwise assembly (both kernels) */
+  VQHULL_K_FILTER = 6,   /* octagon prefilter: edges, filter, prefix of the kept counts (with the
+                            prefilter, VQHULL_K_EXTREMES times the eight-direction extremes pass) */
+  VQHULL_K_COMPACT = 7   /* octagon prefilter: kept points moved to the front of each request */
 };
 typedef struct {
   int32_t kind;       /* VQHULL_K_* */

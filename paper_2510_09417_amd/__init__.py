@@ -29,7 +29,7 @@ EXPORTED = (
     "vqhull_server_drain", "vqhull_server_ticket_info", "vqhull_server_stats", "vqhull_server_destroy",
 )
 
-KERNEL_KINDS = ("extremes", "plan0", "sweep", "finish_plan", "finish", "assemble")
+KERNEL_KINDS = ("extremes", "plan0", "sweep", "finish_plan", "finish", "assemble", "filter", "compact")
 
 
 class VqhullError(RuntimeError):
@@ -40,7 +40,8 @@ class VqhullError(RuntimeError):
 
 class Config(ctypes.Structure):
     _fields_ = [("sweep_block", ctypes.c_int), ("sweep_ppt", ctypes.c_int), ("lds_limit", ctypes.c_int),
-                ("reverse_tiles", ctypes.c_int), ("sweep_persistent", ctypes.c_int), ("level_block", ctypes.c_int)]
+                ("reverse_tiles", ctypes.c_int), ("sweep_persistent", ctypes.c_int), ("level_block", ctypes.c_int),
+                ("prefilter", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -225,7 +226,8 @@ def get_config() -> dict:
 
 
 def set_config(**kw) -> dict:
-    """Update tuning knobs (sweep_block, sweep_ppt, lds_limit, reverse_tiles, sweep_persistent, level_block)."""
+    """Update tuning knobs (sweep_block, sweep_ppt, lds_limit, reverse_tiles, sweep_persistent, level_block,
+    prefilter)."""
     lib = load_library()
     c = Config()
     _check(lib, lib.vqhull_get_config(ctypes.byref(c)))

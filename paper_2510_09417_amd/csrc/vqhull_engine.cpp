@@ -29,7 +29,7 @@ namespace {
 thread_local std::string g_last_error;
 
 std::mutex g_cfg_mu;
-vqhull_config g_cfg = {512, 8, 2048, 0, 1, 256};
+vqhull_config g_cfg = {512, 8, 2048, 0, 1, 256, 0};
 
 struct LevelStat {
   int64_t segs, swept, jobs, jobpts;
@@ -70,6 +70,10 @@ struct Context {
   DevBuf<FusedRoot> fr;
   DevBuf<unsigned long long> jctr[2];  // by level parity, like the job tables
   DevBuf<ExtPart> epart;
+  DevBuf<OctPart> opart;     // octagon prefilter: per extremes tile
+  DevBuf<OctEdges> oct;      // per request
+  DevBuf<uint32_t> tcount;   // kept points per extremes tile
+  DevBuf<uint32_t> toff;     // their prefix (ext_tiles + 1)
   DevBuf<uint32_t> tile_req;
   DevBuf<Req> req;
   DevBuf<Job> jobs[2];  // level k's jobs in jobs[k % 2] (the planner of level k writes the other)
@@ -219,6 +223,10 @@ void free_workspace(Context* w) {
   f(w->jctr[0].p);
   f(w->jctr[1].p);
   f(w->epart.p);
+  f(w->opart.p);
+  f(w->oct.p);
+  f(w->tcount.p);
+  f(w->toff.p);
   f(w->tile_req.p);
   f(w->req.p);
   f(w->jobs[0].p);
@@ -244,6 +252,7 @@ vqhull_config sanitized(vqhull_config c) {
   }
   c.lds_limit = std::min(2048, std::max(256, c.lds_limit));
   c.reverse_tiles = c.reverse_tiles ? 1 : 0;
+  c.prefilter = c.prefilter ? 1 : 0;
   c.sweep_persistent = c.sweep_persistent ? 1 : 0;
   const int tile = c.sweep_block * c.sweep_ppt;
   if (c.level_block <= 0 || c.level_block == c.sweep_block || tile % c.level_block != 0 ||
@@ -297,7 +306,13 @@ void collect_times(Context& w) {
   }
 }
 
-int sweep_mode(int k) { return k == 0 ? kSweepArgmax : k == 1 ? kSweepFused : kSweepLevel; }
+// pf: the octagon prefilter ran, so the top-level passes read its compacted
+// copy in buffer A instead of the caller's arrays.
+int sweep_mode(int k, bool pf) {
+  if (k >= 2) return kSweepLevel;
+  if (pf) return k == 0 ? kSweepArgmaxWs : kSweepFusedWs;
+  return k == 0 ? kSweepArgmax : kSweepFused;
+}
 
 // Arguments of level k's kernels (buffers by the parity of k, status slot k mod
 // the ring size).  Level 0 is an argmax-only pass over the roots (sizes and
@@ -305,9 +320,9 @@ int sweep_mode(int k) { return k == 0 ? kSweepArgmax : k == 1 ? kSweepFused : kS
 // arrays and classifies every point twice (root triangle, then its child's
 // triangle), so the top level's subsets are never materialized; levels >= 2
 // sweep the workspace.
-SweepArgs sweep_args(Context& w, const vqhull_config& cfg, int k, const double* x, const double* y) {
+SweepArgs sweep_args(Context& w, const vqhull_config& cfg, int k, const double* x, const double* y, bool pf) {
   SweepArgs sa{};
-  const int in_buf = k <= 1 ? -1 : (k - 1) % 2, out_buf = k % 2, cur = k % 2;
+  const int in_buf = k <= 1 ? (pf ? 0 : -1) : (k - 1) % 2, out_buf = k % 2, cur = k % 2;
   sa.ix = in_buf < 0 ? x : w.wx[in_buf];
   sa.iy = in_buf < 0 ? y : w.wy[in_buf];
   sa.ii = in_buf < 0 ? nullptr : w.wi[in_buf];
@@ -389,6 +404,7 @@ Plan0Args plan0_args(Context& w, const vqhull_config& cfg) {
   pa.tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
   pa.lds_limit = (uint32_t)cfg.lds_limit;
   pa.ext_tile = kExtTile;
+  pa.toff = nullptr;
   return pa;
 }
 
@@ -411,10 +427,45 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
   const bool tm = tmode != 0;          // sweeps
   const bool tm_all = tmode == 1;      // every other launch too
 
-  ExtremesArgs ea{x, y, tile_req, w.req.p, w.epart.p, w.counts_dev, (uint32_t)ext_tiles};
-  timed(w, tm_all, st, VQHULL_K_EXTREMES, 0, (int64_t)N, 0, [&] { ck(launch_extremes(ea, st), "k_extremes"); });
+  // Octagon prefilter (requests above the LDS threshold only): extremes in
+  // eight directions, the edges, the filter into buffer B, the prefix of the
+  // kept counts and the compaction into buffer A.
+  const bool pf = cfg.prefilter != 0 && tiles0 > 0;
+  if (pf) {
+    const OctArgs oa{x, y, tile_req, w.req.p, w.epart.p, w.opart.p, w.counts_dev, (uint32_t)ext_tiles};
+    timed(w, tm_all, st, VQHULL_K_EXTREMES, 0, (int64_t)N, 0, [&] { ck(launch_octagon(oa, st), "k_octagon"); });
+    FilterArgs fa{};
+    fa.x = x;
+    fa.y = y;
+    fa.tile_req = tile_req;
+    fa.req = w.req.p;
+    fa.part = w.epart.p;
+    fa.opart = w.opart.p;
+    fa.oct = w.oct.p;
+    fa.sx = w.wx[1];
+    fa.sy = w.wy[1];
+    fa.si = w.wi[1];
+    fa.cx = w.wx[0];
+    fa.cy = w.wy[0];
+    fa.ci = w.wi[0];
+    fa.tcount = w.tcount.p;
+    fa.toff = w.toff.p;
+    fa.counts = w.counts_dev;
+    fa.ntiles = (uint32_t)ext_tiles;
+    fa.min_points = lds_limit;
+    timed(w, tm_all, st, VQHULL_K_FILTER, 0, (int64_t)N, 0, [&] {
+      ck(launch_oct_plan(fa, (uint32_t)nreq, st), "k_oct_plan");
+      ck(launch_filter(fa, st), "k_filter");
+      ck(launch_filter_scan(fa, st), "k_filter_scan");
+    });
+    timed(w, tm_all, st, VQHULL_K_COMPACT, 0, 0, 0, [&] { ck(launch_compact(fa, st), "k_compact"); });
+  } else {
+    ExtremesArgs ea{x, y, tile_req, w.req.p, w.epart.p, w.counts_dev, (uint32_t)ext_tiles};
+    timed(w, tm_all, st, VQHULL_K_EXTREMES, 0, (int64_t)N, 0, [&] { ck(launch_extremes(ea, st), "k_extremes"); });
+  }
   ensure(w.level_nodes, 16, st, true);
-  const Plan0Args pa = plan0_args(w, cfg);
+  Plan0Args pa = plan0_args(w, cfg);
+  if (pf) pa.toff = w.toff.p;
   timed(w, tm_all, st, VQHULL_K_PLAN0, 0, nreq, 0, [&] { ck(launch_plan0(pa, st), "k_plan0"); });
   ck(hipEventRecord(w.status_ev[0], st), "hipEventRecord");
 
@@ -427,8 +478,8 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
   // points of level 1's small children), in the same launch as plan k.
   for (int k = 0;; ++k) {
     const int slot = k % kStatusRing, next = (k + 1) % kStatusRing;
-    const int mode = sweep_mode(k);
-    const SweepArgs sa = sweep_args(w, cfg, k, x, y);
+    const int mode = sweep_mode(k, pf);
+    const SweepArgs sa = sweep_args(w, cfg, k, x, y, pf);
     // Grid: persistent, or one workgroup per tile with the tile count bounded
     // from what the host knows (levels 0 and 1 exactly; level k from level
     // k-1: tiles <= ceil(swept(k-1) / tile) + 2 nseg(k-1)); surplus groups exit.
@@ -523,6 +574,12 @@ Caps reserve(Context& w, const vqhull_config& cfg, size_t N, size_t nreq, size_t
   const uint32_t lds_limit = (uint32_t)cfg.lds_limit;
   ensure(w.req, std::max<size_t>(nreq, 1), st);
   ensure(w.epart, std::max<size_t>(ext_tiles, 1), st);
+  if (cfg.prefilter) {
+    ensure(w.opart, std::max<size_t>(ext_tiles, 1), st);
+    ensure(w.oct, std::max<size_t>(nreq, 1), st);
+    ensure(w.tcount, std::max<size_t>(ext_tiles, 1), st);
+    ensure(w.toff, ext_tiles + 1, st);
+  }
   ensure_points(w, std::max<size_t>(N, 1), st);
   Caps c;
   c.max_seg = N / (lds_limit + 1) + nreq + 2;
@@ -754,11 +811,11 @@ int context_enqueue_fixed(Context* c, const double* x, const double* y, int64_t*
     ck(launch_extremes(ea, st), "k_extremes");
     ck(launch_plan0(plan0_args(w, cfg), st), "k_plan0");
     for (int k = 0; k < levels; ++k) {
-      const int mode = sweep_mode(k);
+      const int mode = sweep_mode(k, false);
       int blk = 0, ppt = 0;
       level_shape(cfg, k, blk, ppt);
       const uint32_t G = sweep_grid(blk, ppt, mode);
-      ck(launch_sweep(sweep_args(w, cfg, k, x, y), mode, blk, ppt, G, st), "k_sweep");
+      ck(launch_sweep(sweep_args(w, cfg, k, x, y, false), mode, blk, ppt, G, st), "k_sweep");
       ck(launch_finish_plan(finish_args(w, x, y, k), plan_args(w, cfg, k, G), tmax, st), "k_finish_plan");
     }
     const int last = levels % kStatusRing;
@@ -822,7 +879,7 @@ int vqhull_autotune(const double* x, const double* y, int64_t n, int32_t repeats
   for (const auto& sh : shapes)
     for (int lds : lds_limits)
       for (int pers = 1; pers >= 0; --pers)
-        cands.push_back(sanitized(vqhull_config{sh[0], sh[1], lds, 0, pers, 256}));
+        cands.push_back(sanitized(vqhull_config{sh[0], sh[1], lds, 0, pers, 256, 0}));
   hipStream_t st = (hipStream_t)stream;
   int64_t* d_idx = nullptr;
   int64_t* d_cnt = nullptr;

@@ -172,8 +172,67 @@ struct ExtremesArgs {
   uint32_t ntiles;  // grid (>= counts->ext_tiles)
 };
 
-// Sweep modes.
-enum : int { kSweepLevel = 0, kSweepArgmax = 1, kSweepFused = 2 };
+// Sweep modes.  The *Ws forms are the top-level passes over the workspace
+// copy the octagon prefilter leaves (buffer A, with an index array) instead of
+// the caller's arrays.
+enum : int { kSweepLevel = 0, kSweepArgmax = 1, kSweepFused = 2, kSweepArgmaxWs = 3, kSweepFusedWs = 4 };
+constexpr int kSweepModes = 5;
+
+// ------------------------------------------------------- octagon prefilter
+// A variant of the method (Section 6's Akl-Toussaint heuristic): every
+// request with more points than the LDS threshold first drops the points
+// strictly inside the octagon of eight directional extremes (with a margin
+// above the rounding error of the edge test); Algorithm 1 then runs unchanged
+// on the points kept, which sit compacted at the front of the request's range
+// of buffer A.
+//
+// Per extremes tile: minimum and maximum of y, fl(x - y) and fl(x + y), each
+// with the lowest local index among equal values (kNone: empty).
+struct OctPart {
+  double mn[3], mx[3];
+  uint32_t imn[3], imx[3];
+};
+
+// Per request: the eight edges, edge i from vertex a_i with direction
+// (ex_i, ey_i) and margin m_i; a point is dropped iff it is strictly inside
+// all eight.  on = 0: the request is not filtered (at most the threshold's
+// points).
+struct OctEdges {
+  double ax[8], ay[8], ex[8], ey[8], m[8];
+  uint32_t on, pad;
+};
+
+struct OctArgs {
+  const double* x;
+  const double* y;
+  const uint32_t* tile_req;  // nullptr: single request 0
+  Req* req;
+  ExtPart* part;   // the lexicographic extremes, as the plain extremes pass writes them
+  OctPart* opart;
+  const BatchCounts* counts;
+  uint32_t ntiles;  // grid (>= counts->ext_tiles)
+};
+
+struct FilterArgs {
+  const double* x;
+  const double* y;
+  const uint32_t* tile_req;
+  const Req* req;
+  const ExtPart* part;
+  const OctPart* opart;
+  OctEdges* oct;       // per request
+  double* sx;          // staging (buffer B): each tile's kept points at the tile's own start
+  double* sy;
+  uint32_t* si;
+  double* cx;          // compacted (buffer A): the request's kept points at its start
+  double* cy;
+  uint32_t* ci;
+  uint32_t* tcount;    // kept points per extremes tile
+  uint32_t* toff;      // exclusive prefix of tcount over all tiles (ext_tiles + 1 entries)
+  const BatchCounts* counts;
+  uint32_t ntiles;     // grid of the per-tile kernels (>= counts->ext_tiles)
+  uint32_t min_points; // requests with more points are filtered (the LDS threshold)
+};
 
 struct SweepArgs {
   const double* ix;  // level input (caller arrays for the argmax and fused passes)
@@ -210,6 +269,7 @@ struct Plan0Args {
   uint32_t tile;
   uint32_t lds_limit;
   uint32_t ext_tile;
+  const uint32_t* toff;  // octagon prefilter: kept-point prefix per extremes tile (nullptr: off)
 };
 
 struct PlanArgs {
@@ -289,6 +349,14 @@ int launch_finish_plan(const FinishArgs& a, const PlanArgs& p, int tmax, void* s
 // A whole request of n <= tmax points in one workgroup (extremes, Algorithm 1
 // in LDS, output in clockwise order).
 int launch_small(const SmallArgs& a, int tmax, void* stream);
+// Octagon prefilter: extremes in eight directions (instead of
+// launch_extremes), the per-request edges, the per-tile filter into staging,
+// the prefix of the kept counts, and the compaction into buffer A.
+int launch_octagon(const OctArgs& a, void* stream);
+int launch_oct_plan(const FilterArgs& a, uint32_t nreq, void* stream);
+int launch_filter(const FilterArgs& a, void* stream);
+int launch_filter_scan(const FilterArgs& a, void* stream);
+int launch_compact(const FilterArgs& a, void* stream);
 int launch_assemble(const AssembleArgs& a, void* stream);
 int launch_copy_lists(const AssembleArgs& a, void* stream);
 int launch_stream_scale(const double* in, double* out, uint64_t n, double s, void* stream);

@@ -280,6 +280,9 @@ __global__ __launch_bounds__(BLOCK) void k_extremes(ExtremesArgs A) {
 //                 (p, r1, q) or (q, r2, p), so the top level's subsets are
 //                 never written or read back.  Children small enough for the
 //                 LDS finisher are copied instead (pass-through).
+//   kSweepArgmaxWs, kSweepFusedWs
+//                 the same two passes over the points the octagon prefilter
+//                 kept (buffer A, indices from its index array).
 
 // Per-thread farthest-point candidate inside a sweep: the key and the position
 // of the point in the level's input arrays.  Coordinates and index are fetched
@@ -502,8 +505,10 @@ __device__ __forceinline__ void write_streams(const uint32_t (&m)[NS], const uin
 template <int BLOCK, int PPT, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
   static_assert(PPT <= 32, "class masks are 32-bit");
-  constexpr bool USER = MODE != kSweepLevel;  // input = the caller's arrays, index = position - ibase
-  constexpr bool FUSED = MODE == kSweepFused;
+  // USER: input = the caller's arrays, index = position - ibase
+  constexpr bool USER = MODE == kSweepArgmax || MODE == kSweepFused;
+  constexpr bool FUSED = MODE == kSweepFused || MODE == kSweepFusedWs;
+  constexpr bool ARGMAX = MODE == kSweepArgmax || MODE == kSweepArgmaxWs;
   constexpr int NS = FUSED ? 4 : 2;  // output streams (two per output range)
   constexpr uint32_t TILE = BLOCK * PPT;
   constexpr int NW = BLOCK / 64;
@@ -536,7 +541,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
       if (run_seg != kNone) {
         flush_run<USER, NW>(A, A.part, run_slot, b[0], b[1], ibase, s_cand);
         if constexpr (FUSED) flush_run<USER, NW>(A, A.part2, run_slot, b[2], b[3], ibase, s_cand);
-        if constexpr (MODE == kSweepArgmax) {
+        if constexpr (ARGMAX) {
           flush_counts<NW>(A.ctr + (size_t)run_seg * kCtrStride, run1, run2, s_cnt);
           run1 = run2 = 0;
         }
@@ -632,13 +637,13 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
         const double o = dpx * dqy - dpy * dqx;  // orient(p, q, u)
         const bool s0 = ok & (o > 0.0);
         const bool s1 = ok & (o < 0.0);
-        if constexpr (MODE == kSweepArgmax) {
+        if constexpr (ARGMAX) {
           const bool f[2] = {s0, s1};
           const double kk[2] = {o, -o};
-          offer<true, 2>(b, f, kk, x, y, pos, 0u, A);
+          offer<USER, 2>(b, f, kk, x, y, pos, pi[v], A);
           m[0] |= (uint32_t)s0 << v;
           m[1] |= (uint32_t)s1 << v;
-          bad |= ok & !finite(y);
+          if constexpr (USER) bad |= ok & !finite(y);  // the octagon pass checked the kept points
         } else {
           // child 0 = (p, r1, q) holds S1, child 1 = (q, r2, p) holds S2.  Both
           // children are evaluated for every point (no branch on the kinds,
@@ -653,7 +658,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
           const bool a0 = s0 & split0, a1 = s1 & split1;
           const bool l0 = kk[0] > 0.0, l1 = kk[2] > 0.0;
           const bool f[4] = {(bool)(a0 & l0), (bool)(a0 & !l0 & (kk[1] > 0.0)), (bool)(a1 & l1), (bool)(a1 & !l1 & (kk[3] > 0.0))};
-          offer<true, 4>(b, f, kk, x, y, pos, 0u, A);
+          offer<USER, 4>(b, f, kk, x, y, pos, pi[v], A);
           m[0] |= (uint32_t)(f[0] | (s0 & copy0)) << v;
           m[1] |= (uint32_t)f[1] << v;
           m[2] |= (uint32_t)(f[2] | (s1 & copy1)) << v;
@@ -666,7 +671,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
 #pragma unroll
       for (int q = 0; q < NS; ++q) asm volatile("" : "+v"(m[q]));
     }
-    if constexpr (MODE == kSweepArgmax) {
+    if constexpr (ARGMAX) {
       run1 += (uint32_t)__popc(m[0]);
       run2 += (uint32_t)__popc(m[1]);
       if (__ballot(bad) && lane == 0) A.req[req].err = 1u;
@@ -679,7 +684,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
   if (run_seg != kNone) {
     flush_run<USER, NW>(A, A.part, run_slot, b[0], b[1], ibase, s_cand);
     if constexpr (FUSED) flush_run<USER, NW>(A, A.part2, run_slot, b[2], b[3], ibase, s_cand);
-    if constexpr (MODE == kSweepArgmax) flush_counts<NW>(A.ctr + (size_t)run_seg * kCtrStride, run1, run2, s_cnt);
+    if constexpr (ARGMAX) flush_counts<NW>(A.ctr + (size_t)run_seg * kCtrStride, run1, run2, s_cnt);
   }
 }
 
@@ -1096,10 +1101,13 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
     }
     __syncthreads();
     if (big) e = s_res[tid];
+    // With the octagon prefilter, a request above the LDS threshold keeps
+    // its kept points at the front of its range of buffer A.
     uint32_t kind[2] = {kKindNone, kKindNone}, cnt[2] = {0, 0};
+    const bool filt = valid && A.toff != nullptr && rq.n > A.lds_limit;
     if (valid && rq.n > 0) {
-      kind[0] = rq.n <= A.lds_limit ? kKindJob : kKindSeg;
-      cnt[0] = rq.n;
+      cnt[0] = filt ? A.toff[rq.tile0 + ceil_div(rq.n, A.ext_tile)] - A.toff[rq.tile0] : rq.n;
+      kind[0] = cnt[0] <= A.lds_limit ? kKindJob : kKindSeg;
     }
     uint32_t tot[4];
     EmitBase eb = emit_scan(kind, cnt, A.tile, S, tot);
@@ -1109,8 +1117,8 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
         const Tri tr{e.mnx, e.mny, e.mxx, e.mxy, e.mnx, e.mny};
         const Virt nov{false, 0u, 0u, nullptr};
         uint32_t idx = 0;
-        nid = emit_one(kind[0], tr, e.mxi, rq.off, rq.n, i, -1, 0, kSrcUser, 0u, A.tile, eb, A.nodes, A.jobs,
-                       A.seg_out, A.ctr_out, A.tile_seg_out, S, nov, &idx);
+        nid = emit_one(kind[0], tr, e.mxi, rq.off, cnt[0], i, -1, 0, filt ? kSrcBufA : kSrcUser, 0u, A.tile, eb,
+                       A.nodes, A.jobs, A.seg_out, A.ctr_out, A.tile_seg_out, S, nov, &idx);
       }
       A.req[i].p = rq.n > 0 ? e.mni : 0u;
       A.req[i].q = rq.n > 0 ? e.mxi : 0u;
@@ -1739,6 +1747,424 @@ __global__ __launch_bounds__(BLOCK) void k_small(SmallArgs A) {
   }
 }
 
+// ------------------------------------------------------ octagon prefilter
+//
+// A variant of the method (Section 6's Akl-Toussaint heuristic) for requests
+// above the LDS threshold:
+//   k_octagon      per extremes tile: the lexicographic extremes (the record
+//                  the plain extremes pass writes) and the minima and maxima of
+//                  y, fl(x - y) and fl(x + y), lowest index among equal values;
+//                  both coordinates are checked for NaN and infinity.
+//   k_oct_plan     per request: the vertices v0 = min y, v1 = max fl(x - y),
+//                  v2 = q, v3 = max fl(x + y), v4 = max y, v5 = min fl(x - y),
+//                  v6 = p, v7 = min fl(x + y) (counter-clockwise) and the
+//                  records of the eight edges.
+//   k_filter       per extremes tile: the points not strictly inside all eight
+//                  edges, compacted to the tile's own start in buffer B.
+//   k_filter_scan  one workgroup: the prefix of the kept counts over all tiles.
+//   k_compact      per extremes tile: its kept points moved to their place at
+//                  the front of the request's range in buffer A.
+// Edge i runs from a = v_i to b = v_(i+1 mod 8), (ex, ey) = fl(b - a); a point
+// u is strictly inside it when
+//   L = fl(fl(ex * fl(u.y - a.y)) - fl(ey * fl(u.x - a.x))) > m,
+//   m = max(2^-44 * fl(fl(|ex| + |ey|) * D), 2^-900),
+// with D = fl(fl(q.x - p.x) + fl(max y - min y)).  The rounding error of L
+// stays below 6 units in the last place of (|ex| + |ey|) * D (and below 2^-1072
+// where products underflow), far under m, so a dropped point is strictly left
+// of every edge in exact arithmetic: the closed octagon winds around it, so it
+// lies strictly inside the hull and never matters to the hull.  Zero-length
+// edges (repeated vertices) are skipped (m = -inf); if all eight have zero
+// length, or a vertex is missing (a non-finite input, reported as such),
+// nothing is dropped (m = +inf).  Every operation is one rounded binary64
+// operation in the order written (no contraction).
+
+constexpr int kOctBlock = 256, kOctPPT = 8, kOctIter = 8;
+static_assert(kOctBlock * kOctPPT * kOctIter == (int)kExtTile, "the prefilter shares the extremes tiling");
+constexpr int kScanBlock = 1024;
+
+// (v, i) takes (ov, oi) if that is smaller (larger), or equal at a lower index.
+__device__ __forceinline__ void oct_lower(double& v, uint32_t& i, double ov, uint32_t oi) {
+  if (oi != kNone && (i == kNone || ov < v || (ov == v && oi < i))) {
+    v = ov;
+    i = oi;
+  }
+}
+__device__ __forceinline__ void oct_higher(double& v, uint32_t& i, double ov, uint32_t oi) {
+  if (oi != kNone && (i == kNone || ov > v || (ov == v && oi < i))) {
+    v = ov;
+    i = oi;
+  }
+}
+
+// Running extremes of one thread / wave / workgroup: the lexicographic pair
+// and the three direction pairs (index kNone: none yet).
+struct OctAcc {
+  double lnx, lny, lxx, lxy;
+  uint32_t lni, lxi;
+  double mn[3], mx[3];
+  uint32_t imn[3], imx[3];
+};
+
+__device__ __forceinline__ OctAcc oct_empty() {
+  OctAcc a;
+  a.lnx = a.lny = a.lxx = a.lxy = 0.0;
+  a.lni = a.lxi = kNone;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    a.mn[d] = a.mx[d] = 0.0;
+    a.imn[d] = a.imx[d] = kNone;
+  }
+  return a;
+}
+
+__device__ __forceinline__ void oct_merge(OctAcc& a, const OctAcc& o) {
+  if (small_before(o.lnx, o.lny, o.lni, a.lnx, a.lny, a.lni)) {
+    a.lnx = o.lnx;
+    a.lny = o.lny;
+    a.lni = o.lni;
+  }
+  if (small_after(o.lxx, o.lxy, o.lxi, a.lxx, a.lxy, a.lxi)) {
+    a.lxx = o.lxx;
+    a.lxy = o.lxy;
+    a.lxi = o.lxi;
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    oct_lower(a.mn[d], a.imn[d], o.mn[d], o.imn[d]);
+    oct_higher(a.mx[d], a.imx[d], o.mx[d], o.imx[d]);
+  }
+}
+
+__device__ __forceinline__ OctAcc oct_shfl_xor(const OctAcc& a, int m) {
+  OctAcc o;
+  o.lnx = __shfl_xor(a.lnx, m, 64);
+  o.lny = __shfl_xor(a.lny, m, 64);
+  o.lni = __shfl_xor(a.lni, m, 64);
+  o.lxx = __shfl_xor(a.lxx, m, 64);
+  o.lxy = __shfl_xor(a.lxy, m, 64);
+  o.lxi = __shfl_xor(a.lxi, m, 64);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    o.mn[d] = __shfl_xor(a.mn[d], m, 64);
+    o.mx[d] = __shfl_xor(a.mx[d], m, 64);
+    o.imn[d] = __shfl_xor(a.imn[d], m, 64);
+    o.imx[d] = __shfl_xor(a.imx[d], m, 64);
+  }
+  return o;
+}
+
+// Merge over the workgroup; the result is valid in thread 0.
+template <int BLOCK>
+__device__ __forceinline__ OctAcc oct_block(OctAcc a, OctAcc* s_w) {
+  constexpr int NW = BLOCK / 64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) oct_merge(a, oct_shfl_xor(a, m));
+  if (lane == 0) s_w[w] = a;
+  __syncthreads();
+  if (tid == 0)
+    for (int i = 1; i < NW; ++i) oct_merge(a, s_w[i]);
+  return a;
+}
+
+template <int BLOCK, int PPT, int ITER>
+__global__ __launch_bounds__(BLOCK) void k_octagon(OctArgs A) {
+  constexpr uint32_t SUB = BLOCK * PPT;
+  constexpr uint32_t TILE = SUB * ITER;
+  __shared__ OctAcc s_w[BLOCK / 64];
+  const uint32_t t = blockIdx.x;
+  if (t >= A.counts->ext_tiles) return;
+  const uint32_t r = A.tile_req ? A.tile_req[t] : 0u;
+  const uint32_t off = A.req[r].off, n = A.req[r].n, tile0 = A.req[r].tile0;
+  const uint32_t lo = off + (t - tile0) * TILE;
+  const uint32_t hi = min(off + n, lo + TILE);
+  const int tid = threadIdx.x, lane = tid & 63;
+
+  // A thread visits its positions in increasing order, so strict comparisons
+  // keep the lowest index among equal values.  Positions past the end read
+  // NaN, which no comparison selects.
+  double lnx = __builtin_inf(), lny = __builtin_inf(), lxx = -__builtin_inf(), lxy = -__builtin_inf();
+  uint32_t lni = kNone, lxi = kNone;
+  double mn[3], mx[3];
+  uint32_t imn[3], imx[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    mn[d] = __builtin_inf();
+    mx[d] = -__builtin_inf();
+    imn[d] = imx[d] = kNone;
+  }
+  bool bad = false;
+  for (int it = 0; it < ITER; ++it) {
+    const uint32_t slo = lo + (uint32_t)it * SUB;
+    if (slo >= hi) break;  // uniform
+    double xs[PPT], ys[PPT];
+#pragma unroll
+    for (int v = 0; v < PPT; ++v) {
+      const uint32_t pos = slo + v * BLOCK + tid;
+      xs[v] = pos < hi ? __builtin_nontemporal_load(A.x + pos) : __builtin_nan("");
+      ys[v] = pos < hi ? __builtin_nontemporal_load(A.y + pos) : __builtin_nan("");
+    }
+#pragma unroll
+    for (int v = 0; v < PPT; ++v) {
+      const uint32_t pos = slo + v * BLOCK + tid;
+      const double x = xs[v], y = ys[v];
+      bad |= (pos < hi) & !(finite(x) & finite(y));
+      const bool lt = (x < lnx) | ((x == lnx) & (y < lny));
+      const bool gt = (x > lxx) | ((x == lxx) & (y > lxy));
+      lnx = lt ? x : lnx;
+      lny = lt ? y : lny;
+      lni = lt ? pos : lni;
+      lxx = gt ? x : lxx;
+      lxy = gt ? y : lxy;
+      lxi = gt ? pos : lxi;
+      const double val[3] = {y, x - y, x + y};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const bool l = val[d] < mn[d], g = val[d] > mx[d];
+        mn[d] = l ? val[d] : mn[d];
+        imn[d] = l ? pos : imn[d];
+        mx[d] = g ? val[d] : mx[d];
+        imx[d] = g ? pos : imx[d];
+      }
+    }
+  }
+  if (__ballot(bad) && lane == 0) A.req[r].err = 1u;
+  OctAcc a;
+  a.lnx = lnx;
+  a.lny = lny;
+  a.lni = lni;
+  a.lxx = lxx;
+  a.lxy = lxy;
+  a.lxi = lxi;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    a.mn[d] = mn[d];
+    a.mx[d] = mx[d];
+    a.imn[d] = imn[d];
+    a.imx[d] = imx[d];
+  }
+  a = oct_block<BLOCK>(a, s_w);
+  if (tid == 0) {
+    ExtPart e;
+    e.minx = a.lnx;
+    e.miny = a.lny;
+    e.maxx = a.lxx;
+    e.maxy = a.lxy;
+    e.mini = a.lni != kNone ? a.lni - off : kNone;
+    e.maxi = a.lxi != kNone ? a.lxi - off : kNone;
+    e.pad[0] = e.pad[1] = 0;
+    A.part[t] = e;
+    OctPart o;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      o.mn[d] = a.mn[d];
+      o.mx[d] = a.mx[d];
+      o.imn[d] = a.imn[d] != kNone ? a.imn[d] - off : kNone;
+      o.imx[d] = a.imx[d] != kNone ? a.imx[d] - off : kNone;
+    }
+    A.opart[t] = o;
+  }
+}
+
+// One workgroup per request: reduce the request's tile records, then the
+// eight vertices and edge records (thread 0).
+__global__ __launch_bounds__(256) void k_oct_plan(FilterArgs A) {
+  __shared__ OctAcc s_w[256 / 64];
+  const uint32_t r = blockIdx.x;
+  if (r >= A.counts->nreq) return;
+  const Req rq = A.req[r];
+  OctEdges* E = A.oct + r;
+  if (rq.n <= A.min_points) {
+    if (threadIdx.x == 0) E->on = 0u;
+    return;
+  }
+  const uint32_t nt = ceil_div(rq.n, kExtTile);
+  OctAcc a = oct_empty();
+  for (uint32_t k = threadIdx.x; k < nt; k += 256) {
+    const ExtPart p = A.part[rq.tile0 + k];
+    const OctPart o = A.opart[rq.tile0 + k];
+    OctAcc b;
+    b.lnx = p.minx;
+    b.lny = p.miny;
+    b.lni = p.mini;
+    b.lxx = p.maxx;
+    b.lxy = p.maxy;
+    b.lxi = p.maxi;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      b.mn[d] = o.mn[d];
+      b.mx[d] = o.mx[d];
+      b.imn[d] = o.imn[d];
+      b.imx[d] = o.imx[d];
+    }
+    oct_merge(a, b);
+  }
+  a = oct_block<256>(a, s_w);
+  if (threadIdx.x != 0) return;
+  const uint32_t v[8] = {a.imn[0], a.imx[1], a.lxi, a.imx[2], a.imx[0], a.imn[1], a.lni, a.imn[2]};
+  bool missing = false;
+  double vx[8], vy[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    missing |= v[i] == kNone;
+    const uint32_t pos = v[i] == kNone ? rq.off : rq.off + v[i];
+    vx[i] = A.x[pos];
+    vy[i] = A.y[pos];
+  }
+  const double D = (vx[2] - vx[6]) + (vy[4] - vy[0]);
+  int edges = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int b = (i + 1) & 7;
+    const double ex = vx[b] - vx[i];
+    const double ey = vy[b] - vy[i];
+    const double s = fabs(ex) + fabs(ey);
+    const double sd = s * D;
+    double m = fmax(0x1p-44 * sd, 0x1p-900);
+    if (ex == 0.0 && ey == 0.0) {
+      m = -__builtin_inf();
+    } else {
+      ++edges;
+    }
+    E->ax[i] = vx[i];
+    E->ay[i] = vy[i];
+    E->ex[i] = ex;
+    E->ey[i] = ey;
+    E->m[i] = m;
+  }
+  if (edges == 0 || missing) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) E->m[i] = __builtin_inf();
+  }
+  E->on = 1u;
+}
+
+template <int BLOCK, int PPT, int ITER>
+__global__ __launch_bounds__(BLOCK) void k_filter(FilterArgs A) {
+  constexpr uint32_t SUB = BLOCK * PPT;
+  constexpr uint32_t TILE = SUB * ITER;
+  constexpr int NW = BLOCK / 64;
+  __shared__ uint32_t s_cnt[NW];
+  const uint32_t t = blockIdx.x;
+  if (t >= A.counts->ext_tiles) return;
+  const uint32_t r = A.tile_req ? A.tile_req[t] : 0u;
+  const uint32_t off = A.req[r].off, n = A.req[r].n, tile0 = A.req[r].tile0;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (n <= A.min_points) {
+    if (tid == 0) A.tcount[t] = 0u;
+    return;
+  }
+  const uint32_t lo = off + (t - tile0) * TILE;
+  const uint32_t hi = min(off + n, lo + TILE);
+  const OctEdges* E = A.oct + r;
+  double eax[8], eay[8], eex[8], eey[8], em[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    eax[i] = uni(E->ax[i]);
+    eay[i] = uni(E->ay[i]);
+    eex[i] = uni(E->ex[i]);
+    eey[i] = uni(E->ey[i]);
+    em[i] = uni(E->m[i]);
+  }
+  uint32_t wpos = lo;  // next free position of the tile's staging range (uniform)
+  for (int it = 0; it < ITER; ++it) {
+    const uint32_t slo = lo + (uint32_t)it * SUB;
+    if (slo >= hi) break;  // uniform
+    double px[PPT], py[PPT];
+#pragma unroll
+    for (int v = 0; v < PPT; ++v) {
+      const uint32_t pc = min(slo + v * BLOCK + tid, hi - 1u);
+      px[v] = __builtin_nontemporal_load(A.x + pc);
+      py[v] = __builtin_nontemporal_load(A.y + pc);
+    }
+    uint32_t m = 0u;  // bit v: the thread's v-th point is kept
+#pragma unroll
+    for (int v = 0; v < PPT; ++v) {
+      const bool ok = slo + v * BLOCK + tid < hi;
+      bool in = true;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const double dy = py[v] - eay[i];
+        const double dx = px[v] - eax[i];
+        const double l1 = eex[i] * dy;
+        const double l2 = eey[i] * dx;
+        in &= (l1 - l2) > em[i];
+      }
+      m |= (uint32_t)(ok & !in) << v;
+    }
+    const uint32_t wc = wave_sum((uint32_t)__popc(m));
+    if (lane == 0) s_cnt[w] = wc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const uint32_t c = s_cnt[i];
+      before += i < w ? c : 0u;
+      all += c;
+    }
+    __syncthreads();  // s_cnt is rewritten by the next sub-tile
+    uint32_t o = uni(wpos + before);
+#pragma unroll
+    for (int v = 0; v < PPT; ++v) {
+      const bool keepv = (m >> v) & 1u;
+      const unsigned long long bal = __ballot(keepv);
+      if (keepv) {
+        const uint32_t dst = o + lane_rank(bal);
+        A.sx[dst] = px[v];
+        A.sy[dst] = py[v];
+        A.si[dst] = slo + v * BLOCK + tid - off;
+      }
+      o += (uint32_t)__popcll(bal);
+    }
+    wpos += all;
+  }
+  if (tid == 0) A.tcount[t] = wpos - lo;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_filter_scan(FilterArgs A) {
+  __shared__ uint32_t s_w[1][kScanBlock / 64];
+  constexpr uint32_t PER = 4;
+  const uint32_t T = A.counts->ext_tiles;
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < T; base += kScanBlock * PER) {
+    uint32_t c[PER], sum = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+      const uint32_t i = base + threadIdx.x * PER + j;
+      c[j] = i < T ? A.tcount[i] : 0u;
+      sum += c[j];
+    }
+    const uint32_t v[1] = {sum};
+    uint32_t ex[1], tot[1];
+    block_scan<kScanBlock, 1>(v, ex, tot, s_w);
+    uint32_t run = carry + ex[0];
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+      const uint32_t i = base + threadIdx.x * PER + j;
+      if (i < T) A.toff[i] = run;
+      run += c[j];
+    }
+    carry += tot[0];
+  }
+  if (threadIdx.x == 0) A.toff[T] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_compact(FilterArgs A) {
+  const uint32_t t = blockIdx.x;
+  if (t >= A.counts->ext_tiles) return;
+  const uint32_t r = A.tile_req ? A.tile_req[t] : 0u;
+  const uint32_t off = A.req[r].off, n = A.req[r].n, tile0 = A.req[r].tile0;
+  if (n <= A.min_points) return;
+  const uint32_t cnt = A.tcount[t];
+  const uint32_t src = off + (t - tile0) * kExtTile;
+  const uint32_t dst = off + (A.toff[t] - A.toff[tile0]);
+  for (uint32_t i = threadIdx.x; i < cnt; i += 256) {
+    A.cx[dst + i] = __builtin_nontemporal_load(A.sx + src + i);
+    A.cy[dst + i] = __builtin_nontemporal_load(A.sy + src + i);
+    A.ci[dst + i] = __builtin_nontemporal_load(A.si + src + i);
+  }
+}
+
 // ------------------------------------------------------------- k_assemble
 //
 // Clockwise order of every request: [p] ++ in-order(root), where the root's
@@ -1868,6 +2294,10 @@ int sweep_one(const SweepArgs& a, int mode, uint32_t grid, hipStream_t st) {
     hipLaunchKernelGGL((k_sweep<BLOCK, PPT, kSweepArgmax>), dim3(grid), dim3(BLOCK), 0, st, a);
   } else if (mode == kSweepFused) {
     hipLaunchKernelGGL((k_sweep<BLOCK, PPT, kSweepFused>), dim3(grid), dim3(BLOCK), 0, st, a);
+  } else if (mode == kSweepArgmaxWs) {
+    hipLaunchKernelGGL((k_sweep<BLOCK, PPT, kSweepArgmaxWs>), dim3(grid), dim3(BLOCK), 0, st, a);
+  } else if (mode == kSweepFusedWs) {
+    hipLaunchKernelGGL((k_sweep<BLOCK, PPT, kSweepFusedWs>), dim3(grid), dim3(BLOCK), 0, st, a);
   } else {
     hipLaunchKernelGGL((k_sweep<BLOCK, PPT, kSweepLevel>), dim3(grid), dim3(BLOCK), 0, st, a);
   }
@@ -1934,14 +2364,16 @@ bool sweep_shape_supported(int block, int ppt) {
 }
 
 uint32_t sweep_grid(int block, int ppt, int mode) {
-  static uint32_t cache[5][3] = {};
+  static uint32_t cache[5][kSweepModes] = {};
   const int k = block == 256 ? (ppt == 16 ? 0 : 1) : block == 512 ? (ppt == 8 ? 2 : 3) : 4;
   if (!cache[k][mode]) {
 #define VQH_GRID(K, B, P)                                                          \
   if (k == K)                                                                      \
-    cache[k][mode] = mode == kSweepArgmax  ? sweep_occupancy_grid<B, P, kSweepArgmax>() \
-                     : mode == kSweepFused ? sweep_occupancy_grid<B, P, kSweepFused>()  \
-                                           : sweep_occupancy_grid<B, P, kSweepLevel>();
+    cache[k][mode] = mode == kSweepArgmax     ? sweep_occupancy_grid<B, P, kSweepArgmax>()   \
+                     : mode == kSweepFused    ? sweep_occupancy_grid<B, P, kSweepFused>()    \
+                     : mode == kSweepArgmaxWs ? sweep_occupancy_grid<B, P, kSweepArgmaxWs>() \
+                     : mode == kSweepFusedWs  ? sweep_occupancy_grid<B, P, kSweepFusedWs>()  \
+                                              : sweep_occupancy_grid<B, P, kSweepLevel>();
     VQH_GRID(0, 256, 16)
     VQH_GRID(1, 256, 32)
     VQH_GRID(2, 512, 8)
@@ -1979,6 +2411,37 @@ int launch_sweep(const SweepArgs& a, int mode, int block, int ppt, uint32_t grid
   if (block == 512 && ppt == 16) return sweep_one<512, 16>(a, mode, grid, st);
   if (block == 1024 && ppt == 8) return sweep_one<1024, 8>(a, mode, grid, st);
   return (int)hipErrorInvalidValue;
+}
+
+int launch_octagon(const OctArgs& a, void* stream) {
+  if (a.ntiles == 0) return 0;
+  hipLaunchKernelGGL((k_octagon<kOctBlock, kOctPPT, kOctIter>), dim3(a.ntiles), dim3(kOctBlock), 0,
+                     (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int launch_oct_plan(const FilterArgs& a, uint32_t nreq, void* stream) {
+  if (nreq == 0) return 0;
+  hipLaunchKernelGGL(k_oct_plan, dim3(nreq), dim3(256), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int launch_filter(const FilterArgs& a, void* stream) {
+  if (a.ntiles == 0) return 0;
+  hipLaunchKernelGGL((k_filter<kOctBlock, kOctPPT, kOctIter>), dim3(a.ntiles), dim3(kOctBlock), 0,
+                     (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int launch_filter_scan(const FilterArgs& a, void* stream) {
+  hipLaunchKernelGGL(k_filter_scan, dim3(1), dim3(kScanBlock), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int launch_compact(const FilterArgs& a, void* stream) {
+  if (a.ntiles == 0) return 0;
+  hipLaunchKernelGGL(k_compact, dim3(a.ntiles), dim3(256), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
 }
 
 int launch_plan0(const Plan0Args& a, void* stream) {

@@ -22,7 +22,7 @@ def vq():
 
     assert torch.cuda.is_available()
     vq.load_library()
-    vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048, reverse_tiles=0, sweep_persistent=1, level_block=256)
+    vq.set_config(sweep_block=512, sweep_ppt=8, lds_limit=2048, reverse_tiles=0, sweep_persistent=1, level_block=256, prefilter=0)
     yield vq
     vq.release_workspace()
 
@@ -44,6 +44,31 @@ def test_full_size_bit_exact(vq, name):
     assert np.array_equal(got, want)
     # the result is a set of distinct input indices starting at the lexicographic minimum
     assert got[0] == int(np.lexsort((np.arange(len(x)), y, x))[0])
+
+
+@pytest.mark.parametrize("name", ["disk_1e8", "square_1e8"])
+def test_full_size_prefilter_bit_exact(vq, name):
+    """The octagon prefilter at full size: bit-exact against the oracle's
+    prefiltered variant, and the same list as the plain path."""
+    import torch
+
+    x, y = workloads.workload(name)
+    tx, ty = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    plain = vq.hull(tx, ty).cpu().numpy()
+    vq.set_config(prefilter=1)
+    try:
+        got = vq.hull(tx, ty).cpu().numpy()
+        swept = vq.level_stats()[0]["swept"]
+    finally:
+        vq.set_config(prefilter=0)
+    del tx, ty
+    t0 = time.perf_counter()
+    want = oracle.hull_prefiltered(x, y, 2048)
+    keep = int(oracle.octagon(x, y)[1].sum())
+    print(f"{name}: kept {keep} of {len(x)}; oracle variant {time.perf_counter() - t0:.1f}s", flush=True)
+    assert swept == keep
+    assert np.array_equal(got, want)
+    assert np.array_equal(got, plain)
 
 
 def test_disk_1e6_repeated_and_reversed(vq):

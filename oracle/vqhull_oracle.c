@@ -53,19 +53,23 @@
  *       v7 = min fl(x+y); among equal values the lowest index.
  *   F2  D = fl(fl(x[v2] - x[v6]) + fl(y[v4] - y[v0])) bounds every coordinate
  *       difference |u - v| of the input (width plus height of its box).
- *   F3  edge i runs from a = v_i to b = v_(i+1 mod 8): ex = fl(b.x - a.x),
- *       ey = fl(b.y - a.y), and
- *         L_i(u) = fl(fl(ex * fl(u.y - a.y)) - fl(ey * fl(u.x - a.x)))
- *       (the cross product of the edge with u - a: positive on the inner,
- *       left side of a counter-clockwise polygon), with the margin
- *         M_i = max(2^-44 * fl(fl(|ex| + |ey|) * D), 2^-900).
- *   F4  u is dropped iff L_i(u) > M_i for all eight edges.  The rounding error
- *       of L_i is below 6 ulp-units of (|ex| + |ey|) * D (and below 2^-1072 in
- *       the gradual-underflow range), both far under M_i, so a dropped point is
- *       strictly left of every edge in exact arithmetic: the closed polygon
- *       then winds around it, which puts it strictly inside the hull.  An
- *       edge of zero length (ex = ey = 0: a repeated vertex) adds nothing to
- *       the winding and is skipped (M_i = -infinity); when all eight edges
+ *   F3  coordinates are taken relative to the origin o = p: u' = (fl(u.x - o.x),
+ *       fl(u.y - o.y)).  Edge i runs from a = v_i to b = v_(i+1 mod 8):
+ *       ex = fl(b.x - a.x), ey = fl(b.y - a.y), and
+ *         L_i(u) = fl(fl(ex * u'.y) - fl(ey * u'.x)),
+ *         c_i    = L_i(a) (the same expression for the vertex a),
+ *         M_i    = max(2^-44 * fl(fl(|ex| + |ey|) * D), 2^-900),
+ *         T_i    = fl(c_i + M_i).
+ *       L_i(u) - c_i is the cross product of the edge with u - a: positive on
+ *       the inner, left side of a counter-clockwise polygon.
+ *   F4  u is dropped iff L_i(u) > T_i for all eight edges.  The rounding
+ *       errors of L_i(u), c_i and T_i together with the rounding of the edge
+ *       direction stay below 10 ulp-units of (|ex| + |ey|) * D (and below
+ *       2^-1070 in the gradual-underflow range), far under M_i, so a dropped
+ *       point is strictly left of every edge in exact arithmetic: the closed
+ *       polygon then winds around it, which puts it strictly inside the hull.
+ *       An edge of zero length (ex = ey = 0: a repeated vertex) adds nothing
+ *       to the winding and is skipped (T_i = -infinity); when all eight edges
  *       have zero length (all points equal) nothing is dropped.
  *   F5  the filter applies only to inputs of more than a given number of
  *       points (below it every point is kept).
@@ -268,19 +272,24 @@ int vqhull_oracle_octagon(const double* x, const double* y, int64_t n, int64_t* 
   vqhull_oracle_extremes(x, y, n, &p, &q);
   for (int d = 0; d < 8; ++d) vert[d] = d == 2 ? q : d == 6 ? p : oct_extreme(x, y, n, d);
   double D = (x[q] - x[p]) + (y[vert[4]] - y[vert[0]]);
-  double ax[8], ay[8], ex[8], ey[8], M[8];
+  double ox = x[p], oy = y[p];
+  double ex[8], ey[8], T[8];
   int edges = 0;
   for (int i = 0; i < 8; ++i) {
     int64_t a = vert[i], b = vert[(i + 1) % 8];
-    ax[i] = x[a];
-    ay[i] = y[a];
     ex[i] = x[b] - x[a];
     ey[i] = y[b] - y[a];
+    double ay = y[a] - oy;
+    double ax = x[a] - ox;
+    double c1 = ex[i] * ay;
+    double c2 = ey[i] * ax;
+    double c = c1 - c2;
     double s = fabs(ex[i]) + fabs(ey[i]);
     double sd = s * D;
-    M[i] = fmax(0x1p-44 * sd, 0x1p-900);
+    double M = fmax(0x1p-44 * sd, 0x1p-900);
+    T[i] = c + M;
     if (ex[i] == 0.0 && ey[i] == 0.0) {
-      M[i] = -INFINITY;
+      T[i] = -INFINITY;
     } else {
       ++edges;
     }
@@ -290,14 +299,14 @@ int vqhull_oracle_octagon(const double* x, const double* y, int64_t n, int64_t* 
       keep[u] = 1;
       continue;
     }
+    double uy = y[u] - oy;
+    double ux = x[u] - ox;
     int inside = 1;
     for (int i = 0; i < 8; ++i) {
-      double dy = y[u] - ay[i];
-      double dx = x[u] - ax[i];
-      double l1 = ex[i] * dy;
-      double l2 = ey[i] * dx;
+      double l1 = ex[i] * uy;
+      double l2 = ey[i] * ux;
       double L = l1 - l2;
-      if (!(L > M[i])) inside = 0;
+      if (!(L > T[i])) inside = 0;
     }
     keep[u] = (uint8_t)!inside;
   }

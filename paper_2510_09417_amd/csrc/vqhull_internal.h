@@ -193,12 +193,13 @@ struct OctPart {
   uint32_t imn[3], imx[3];
 };
 
-// Per request: the eight edges, edge i from vertex a_i with direction
-// (ex_i, ey_i) and margin m_i; a point is dropped iff it is strictly inside
-// all eight.  on = 0: the request is not filtered (at most the threshold's
-// points).
+// Per request: the origin o (= p) and the eight edges, edge i with direction
+// (ex_i, ey_i) and threshold t_i; a point u is dropped iff
+// fl(fl(ex_i * fl(u.y - o.y)) - fl(ey_i * fl(u.x - o.x))) > t_i for all eight.
+// on = 0: the request is not filtered (at most the threshold's points).
 struct OctEdges {
-  double ax[8], ay[8], ex[8], ey[8], m[8];
+  double ox, oy;
+  double ex[8], ey[8], t[8];
   uint32_t on, pad;
 };
 

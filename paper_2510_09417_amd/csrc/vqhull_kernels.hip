@@ -1764,19 +1764,23 @@ __global__ __launch_bounds__(BLOCK) void k_small(SmallArgs A) {
 //   k_filter_scan  one workgroup: the prefix of the kept counts over all tiles.
 //   k_compact      per extremes tile: its kept points moved to their place at
 //                  the front of the request's range in buffer A.
-// Edge i runs from a = v_i to b = v_(i+1 mod 8), (ex, ey) = fl(b - a); a point
+// Coordinates are taken relative to the origin o = p (u' = fl(u - o)).  Edge
+// i runs from a = v_i to b = v_(i+1 mod 8), (ex, ey) = fl(b - a), and a point
 // u is strictly inside it when
-//   L = fl(fl(ex * fl(u.y - a.y)) - fl(ey * fl(u.x - a.x))) > m,
+//   L(u) = fl(fl(ex * u'.y) - fl(ey * u'.x)) > t = fl(L(a) + m),
 //   m = max(2^-44 * fl(fl(|ex| + |ey|) * D), 2^-900),
-// with D = fl(fl(q.x - p.x) + fl(max y - min y)).  The rounding error of L
-// stays below 6 units in the last place of (|ex| + |ey|) * D (and below 2^-1072
-// where products underflow), far under m, so a dropped point is strictly left
-// of every edge in exact arithmetic: the closed octagon winds around it, so it
-// lies strictly inside the hull and never matters to the hull.  Zero-length
-// edges (repeated vertices) are skipped (m = -inf); if all eight have zero
-// length, or a vertex is missing (a non-finite input, reported as such),
-// nothing is dropped (m = +inf).  Every operation is one rounded binary64
-// operation in the order written (no contraction).
+// with D = fl(fl(q.x - p.x) + fl(max y - min y)).  L(u) - L(a) is the cross
+// product of the edge with u - a; the rounding errors of L(u), L(a), t and of
+// the edge direction stay below 10 units in the last place of
+// (|ex| + |ey|) * D (and below 2^-1070 where products underflow), far under
+// m, so a dropped point is strictly left of every edge in exact arithmetic:
+// the closed octagon winds around it, so it lies strictly inside the hull and
+// never matters to the hull.  Zero-length edges (repeated vertices) are
+// skipped (t = -inf); if all eight have zero length, or a vertex is missing (a
+// non-finite input, reported as such), nothing is dropped (t = +inf).  Every
+// operation is one rounded binary64 operation in the order written (no
+// contraction); per point and edge the test is two products, one difference
+// and one comparison.
 
 constexpr int kOctBlock = 256, kOctPPT = 8, kOctIter = 8;
 static_assert(kOctBlock * kOctPPT * kOctIter == (int)kExtTile, "the prefilter shares the extremes tiling");
@@ -2012,30 +2016,37 @@ __global__ __launch_bounds__(256) void k_oct_plan(FilterArgs A) {
     vy[i] = A.y[pos];
   }
   const double D = (vx[2] - vx[6]) + (vy[4] - vy[0]);
+  const double ox = vx[6], oy = vy[6];
   int edges = 0;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int b = (i + 1) & 7;
     const double ex = vx[b] - vx[i];
     const double ey = vy[b] - vy[i];
+    const double ay = vy[i] - oy;
+    const double ax = vx[i] - ox;
+    const double c1 = ex * ay;
+    const double c2 = ey * ax;
+    const double c = c1 - c2;
     const double s = fabs(ex) + fabs(ey);
     const double sd = s * D;
-    double m = fmax(0x1p-44 * sd, 0x1p-900);
+    const double m = fmax(0x1p-44 * sd, 0x1p-900);
+    double t = c + m;
     if (ex == 0.0 && ey == 0.0) {
-      m = -__builtin_inf();
+      t = -__builtin_inf();
     } else {
       ++edges;
     }
-    E->ax[i] = vx[i];
-    E->ay[i] = vy[i];
     E->ex[i] = ex;
     E->ey[i] = ey;
-    E->m[i] = m;
+    E->t[i] = t;
   }
   if (edges == 0 || missing) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) E->m[i] = __builtin_inf();
+    for (int i = 0; i < 8; ++i) E->t[i] = __builtin_inf();
   }
+  E->ox = ox;
+  E->oy = oy;
   E->on = 1u;
 }
 
@@ -2057,14 +2068,13 @@ __global__ __launch_bounds__(BLOCK) void k_filter(FilterArgs A) {
   const uint32_t lo = off + (t - tile0) * TILE;
   const uint32_t hi = min(off + n, lo + TILE);
   const OctEdges* E = A.oct + r;
-  double eax[8], eay[8], eex[8], eey[8], em[8];
+  const double ox = uni(E->ox), oy = uni(E->oy);
+  double eex[8], eey[8], et[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    eax[i] = uni(E->ax[i]);
-    eay[i] = uni(E->ay[i]);
     eex[i] = uni(E->ex[i]);
     eey[i] = uni(E->ey[i]);
-    em[i] = uni(E->m[i]);
+    et[i] = uni(E->t[i]);
   }
   uint32_t wpos = lo;  // next free position of the tile's staging range (uniform)
   for (int it = 0; it < ITER; ++it) {
@@ -2081,14 +2091,14 @@ __global__ __launch_bounds__(BLOCK) void k_filter(FilterArgs A) {
 #pragma unroll
     for (int v = 0; v < PPT; ++v) {
       const bool ok = slo + v * BLOCK + tid < hi;
+      const double uy = py[v] - oy;
+      const double ux = px[v] - ox;
       bool in = true;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const double dy = py[v] - eay[i];
-        const double dx = px[v] - eax[i];
-        const double l1 = eex[i] * dy;
-        const double l2 = eey[i] * dx;
-        in &= (l1 - l2) > em[i];
+        const double l1 = eex[i] * uy;
+        const double l2 = eey[i] * ux;
+        in &= (l1 - l2) > et[i];
       }
       m |= (uint32_t)(ok & !in) << v;
     }

@@ -176,13 +176,15 @@ def test_prefiltered_hull_equals_plain_hull(dist):
 # ------------------------------------------------------------- planted mistakes
 
 MUTANTS = {
-    "margin_dropped": ("M[i] = fmax(0x1p-44 * sd, 0x1p-900);", "M[i] = 0.0;"),
+    "margin_dropped": ("T[i] = c + M;", "T[i] = c;"),
+    "vertex_not_translated": ("double ay = y[a] - oy;", "double ay = y[a];"),
+    "point_not_translated": ("double ux = x[u] - ox;", "double ux = x[u];"),
     "edge_reversed": ("ex[i] = x[b] - x[a];\n    ey[i] = y[b] - y[a];", "ex[i] = x[a] - x[b];\n    ey[i] = y[a] - y[b];"),
     "cross_sign": ("double L = l1 - l2;", "double L = l2 - l1;"),
     "cross_dropped_term": ("double L = l1 - l2;", "double L = l1;"),
     "tie_highest_index": ("if (i == 0 || v < bv) {", "if (i == 0 || v <= bv) {"),
     "sum_for_difference": ("case 1: v = -(x[i] - y[i]); break;", "case 1: v = -(x[i] + y[i]); break;"),
-    "zero_edges_not_skipped": ("      M[i] = -INFINITY;\n", ""),
+    "zero_edges_not_skipped": ("      T[i] = -INFINITY;\n", ""),
     "all_equal_guard_removed": ("    if (edges == 0) {\n      keep[u] = 1;\n      continue;\n    }\n", ""),
     "vertex_order_mirrored": ("vert[d] = d == 2 ? q : d == 6 ? p : oct_extreme(x, y, n, d);",
                               "vert[d] = d == 2 ? p : d == 6 ? q : oct_extreme(x, y, n, d);"),

@@ -15,6 +15,10 @@ Prints one JSON line:
               average duration, from HIP events recorded on the launch stream
               during the timed steps, against 8 TB/s;
   cpu_baseline  the CPU oracle (single thread) on one whole step.
+  prefilter   the same step with the octagon prefilter on (Section 6's
+              Akl-Toussaint heuristic, a variant of the method; outside the
+              timed region): throughput, a check that every hull equals the
+              plain path's, the points kept, and the bandwidth of its passes.
   served      the served mix (65,536 requests, sizes log-uniform in [16, 10^6],
               disk / square / circle / Kuzmin in equal shares, drawn on the GPU):
               hulls/s with every request submitted at once; p50 / p99 latency
@@ -219,6 +223,63 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
     }
 
 
+def prefilter_leg(vq, torch, dx, outs, names, npts, step, args) -> dict:
+    """The step again with the octagon prefilter on: wall-clock throughput
+    over the same number of steps, equality of every hull with the plain
+    path's, the points kept, and the bandwidth of the eight-direction extremes
+    pass (16 B per point) and of the filter (16 B read per point, 20 B written
+    per kept point) from HIP events on the launch stream."""
+    plain = [oi[: int(oc.item())].clone() for oi, oc in outs]
+    vq.set_config(prefilter=1)
+    try:
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        kept = {}
+        for name, (tx, ty), (oi, oc) in zip(names, dx, outs):
+            vq.hull_into(tx, ty, oi, oc)
+            torch.cuda.synchronize()
+            kept[name] = vq.level_stats()[0]["swept"]
+        same = all(int(oc.item()) == len(p) and torch.equal(oi[: len(p)], p) for (oi, oc), p in zip(outs, plain))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        vq.set_timing(True)
+        per_kind, ext, filt = {}, [], []
+        for _ in range(2):
+            for name, (tx, ty), (oi, oc) in zip(names, dx, outs):
+                vq.hull_into(tx, ty, oi, oc)
+                for r in vq.kernel_times():
+                    per_kind[r["kind"]] = per_kind.get(r["kind"], 0.0) + r["ms"]
+                    if r["kind"] == "extremes":
+                        ext.append((r["ms"], 16 * tx.numel()))
+                    elif r["kind"] == "filter":
+                        filt.append((r["ms"], 16 * tx.numel() + 20 * kept[name]))
+        torch.cuda.synchronize()
+        vq.set_timing(False)
+    finally:
+        vq.set_config(prefilter=0)
+
+    def gbs(recs):
+        return round(sum(b for _, b in recs) / (sum(m for m, _ in recs) * 1e-3) / 1e9, 1)
+
+    res = {
+        "value": round(npts * args.steps / wall / 1e9, 4),
+        "unit": "Gpoints/s",
+        "ms_per_step": round(1e3 * wall / args.steps, 4),
+        "same_result_as_plain": bool(same),
+        "kept_points": kept,
+        "octagon_extremes_gbs": gbs(ext),
+        "filter_gbs": gbs(filt),
+        "kernel_ms_per_step": {k: round(v / 2, 4) for k, v in per_kind.items()},
+    }
+    log(f"prefilter: {res['value']} Gpoints/s, same result: {same}, kept {kept}")
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +288,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-energy", action="store_true")
+    ap.add_argument("--no-prefilter", action="store_true")
     ap.add_argument("--served-requests", type=int, default=65536)
     ap.add_argument("--served-lanes", type=int, default=4)
     ap.add_argument("--served-lane-points", type=int, default=1 << 25)
@@ -337,6 +399,7 @@ def main() -> int:
     wall = t1 - t0
     ms_per_step = 1e3 * wall / args.steps
     value = npts * args.steps / wall / 1e9
+    pre = None if args.no_prefilter else prefilter_leg(vq, torch, dx, outs, names, npts, step, args)
 
     def rate(recs):
         ms = sum(m for m, _ in recs)
@@ -406,6 +469,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "kernel_ms_per_step": {k: round(v / breakdown_steps, 4) for k, v in per_kind.items()},
         "energy": en,
+        "prefilter": pre,
         "served": served,
     }
     print(json.dumps(line), flush=True)

@@ -1970,10 +1970,30 @@ __global__ __launch_bounds__(BLOCK) void k_octagon(OctArgs A) {
   }
 }
 
-// One workgroup per request: reduce the request's tile records, then the
-// eight vertices and edge records (thread 0).
-__global__ __launch_bounds__(256) void k_oct_plan(FilterArgs A) {
-  __shared__ OctAcc s_w[256 / 64];
+// One workgroup per request: reduce the request's tile records (two in
+// flight per thread), then the eight vertices and edge records (thread 0).
+constexpr int kOctPlanBlock = 1024;
+
+__device__ __forceinline__ OctAcc oct_record(const ExtPart& p, const OctPart& o) {
+  OctAcc b;
+  b.lnx = p.minx;
+  b.lny = p.miny;
+  b.lni = p.mini;
+  b.lxx = p.maxx;
+  b.lxy = p.maxy;
+  b.lxi = p.maxi;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    b.mn[d] = o.mn[d];
+    b.mx[d] = o.mx[d];
+    b.imn[d] = o.imn[d];
+    b.imx[d] = o.imx[d];
+  }
+  return b;
+}
+
+__global__ __launch_bounds__(kOctPlanBlock) void k_oct_plan(FilterArgs A) {
+  __shared__ OctAcc s_w[kOctPlanBlock / 64];
   const uint32_t r = blockIdx.x;
   if (r >= A.counts->nreq) return;
   const Req rq = A.req[r];
@@ -1984,26 +2004,15 @@ __global__ __launch_bounds__(256) void k_oct_plan(FilterArgs A) {
   }
   const uint32_t nt = ceil_div(rq.n, kExtTile);
   OctAcc a = oct_empty();
-  for (uint32_t k = threadIdx.x; k < nt; k += 256) {
-    const ExtPart p = A.part[rq.tile0 + k];
-    const OctPart o = A.opart[rq.tile0 + k];
-    OctAcc b;
-    b.lnx = p.minx;
-    b.lny = p.miny;
-    b.lni = p.mini;
-    b.lxx = p.maxx;
-    b.lxy = p.maxy;
-    b.lxi = p.maxi;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      b.mn[d] = o.mn[d];
-      b.mx[d] = o.mx[d];
-      b.imn[d] = o.imn[d];
-      b.imx[d] = o.imx[d];
-    }
-    oct_merge(a, b);
+  uint32_t k = threadIdx.x;
+  for (; k + kOctPlanBlock < nt; k += 2 * kOctPlanBlock) {
+    const ExtPart p0 = A.part[rq.tile0 + k], p1 = A.part[rq.tile0 + k + kOctPlanBlock];
+    const OctPart o0 = A.opart[rq.tile0 + k], o1 = A.opart[rq.tile0 + k + kOctPlanBlock];
+    oct_merge(a, oct_record(p0, o0));
+    oct_merge(a, oct_record(p1, o1));
   }
-  a = oct_block<256>(a, s_w);
+  if (k < nt) oct_merge(a, oct_record(A.part[rq.tile0 + k], A.opart[rq.tile0 + k]));
+  a = oct_block<kOctPlanBlock>(a, s_w);
   if (threadIdx.x != 0) return;
   const uint32_t v[8] = {a.imn[0], a.imx[1], a.lxi, a.imx[2], a.imx[0], a.imn[1], a.lni, a.imn[2]};
   bool missing = false;
@@ -2432,7 +2441,7 @@ int launch_octagon(const OctArgs& a, void* stream) {
 
 int launch_oct_plan(const FilterArgs& a, uint32_t nreq, void* stream) {
   if (nreq == 0) return 0;
-  hipLaunchKernelGGL(k_oct_plan, dim3(nreq), dim3(256), 0, (hipStream_t)stream, a);
+  hipLaunchKernelGGL(k_oct_plan, dim3(nreq), dim3(kOctPlanBlock), 0, (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 

@@ -104,6 +104,22 @@ int vqhull_hull(const double* x, const double* y, int64_t n, int64_t* out_idx, i
 int vqhull_hull_batched(const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
                         int64_t* out_counts, vqhull_stream_t stream);
 
+/*
+ * The same two calls for interleaved input, the array-of-structures layout
+ * (x0, y0, x1, y1, ...) of the paper's benchmark inputs (Section 5.2).
+ *   xy         device array of 2n binary64 values, 16-byte aligned (one
+ *              double2 per point); x_i = xy[2i], y_i = xy[2i+1].
+ * Every other argument, the result and the errors are those of vqhull_hull /
+ * vqhull_hull_batched on the same points (the same index lists).  The points
+ * are deinterleaved once into the library's workspace (8 n + 8 n bytes): a
+ * plain copy of x and y, or with the octagon prefilter on, the filter pass
+ * itself (which writes only the points it keeps); every later kernel reads
+ * the workspace.  VQHULL_ERR_INVALID_ARGUMENT also for a misaligned xy.
+ */
+int vqhull_hull_xy(const double* xy, int64_t n, int64_t* out_idx, int64_t* out_count, vqhull_stream_t stream);
+int vqhull_hull_batched_xy(const double* xy, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
+                           int64_t* out_counts, vqhull_stream_t stream);
+
 /* Tuning knobs of the hull kernels (all values are rounded to supported ones). */
 typedef struct {
   int sweep_block;  /* threads per workgroup of the partition sweep: 256, 512 or 1024 */
@@ -168,7 +184,8 @@ enum {
   VQHULL_K_ASSEMBLE = 5, /* clockwise assembly (both kernels) */
   VQHULL_K_FILTER = 6,   /* octagon prefilter: edges, filter, prefix of the kept counts (with the
                             prefilter, VQHULL_K_EXTREMES times the eight-direction extremes pass) */
-  VQHULL_K_COMPACT = 7   /* octagon prefilter: kept points moved to the front of each request */
+  VQHULL_K_COMPACT = 7,  /* octagon prefilter: kept points moved to the front of each request */
+  VQHULL_K_INGEST = 8    /* interleaved input without the prefilter: x and y copied into the workspace */
 };
 typedef struct {
   int32_t kind;       /* VQHULL_K_* */

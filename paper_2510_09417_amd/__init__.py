@@ -22,14 +22,14 @@ VQHULL_ERR_HIP = 4
 
 # Symbols that include/vqhull.h declares.
 EXPORTED = (
-    "vqhull_hull", "vqhull_hull_batched", "vqhull_get_config", "vqhull_set_config", "vqhull_autotune",
+    "vqhull_hull", "vqhull_hull_batched", "vqhull_hull_xy", "vqhull_hull_batched_xy", "vqhull_get_config", "vqhull_set_config", "vqhull_autotune",
     "vqhull_last_level_stats", "vqhull_set_timing", "vqhull_last_kernel_times", "vqhull_stream_scale",
     "vqhull_release_workspace", "vqhull_status_string", "vqhull_last_error",
     "vqhull_server_create", "vqhull_server_submit", "vqhull_server_submit_batch", "vqhull_server_wait", "vqhull_server_poll",
     "vqhull_server_drain", "vqhull_server_ticket_info", "vqhull_server_stats", "vqhull_server_destroy",
 )
 
-KERNEL_KINDS = ("extremes", "plan0", "sweep", "finish_plan", "finish", "assemble", "filter", "compact")
+KERNEL_KINDS = ("extremes", "plan0", "sweep", "finish_plan", "finish", "assemble", "filter", "compact", "ingest")
 
 
 class VqhullError(RuntimeError):
@@ -93,6 +93,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.vqhull_hull.argtypes = [vp, vp, i64, vp, vp, vp]
         lib.vqhull_hull_batched.restype = ctypes.c_int
         lib.vqhull_hull_batched.argtypes = [vp, vp, pi64, i64, vp, vp, vp]
+        lib.vqhull_hull_xy.restype = ctypes.c_int
+        lib.vqhull_hull_xy.argtypes = [vp, i64, vp, vp, vp]
+        lib.vqhull_hull_batched_xy.restype = ctypes.c_int
+        lib.vqhull_hull_batched_xy.argtypes = [vp, pi64, i64, vp, vp, vp]
         lib.vqhull_get_config.restype = ctypes.c_int
         lib.vqhull_get_config.argtypes = [ctypes.POINTER(Config)]
         lib.vqhull_set_config.restype = ctypes.c_int
@@ -192,6 +196,64 @@ def hull(x, y, stream=None):
     if h < 0:
         raise VqhullError(-h, "non-finite coordinate in the input")
     return out[:h]
+
+
+def _check_xy(xy):
+    import torch
+
+    if not isinstance(xy, torch.Tensor) or xy.dtype != torch.float64 or not xy.is_cuda:
+        raise TypeError("xy must be a float64 GPU tensor")
+    if xy.dim() != 2 or xy.shape[1] != 2 or not xy.is_contiguous():
+        raise ValueError("xy must be a contiguous (n, 2) tensor of interleaved (x, y) pairs")
+    if xy.data_ptr() % 16:
+        raise ValueError("xy must be 16-byte aligned")
+
+
+def hull_xy_into(xy, out_idx, out_count, stream=None) -> None:
+    """vqhull_hull_xy on preallocated device outputs (no allocation, no sync)."""
+    lib = load_library()
+    st = lib.vqhull_hull_xy(ctypes.c_void_p(xy.data_ptr()), xy.shape[0], ctypes.c_void_p(out_idx.data_ptr()),
+                            ctypes.c_void_p(out_count.data_ptr()), _stream_handle(stream))
+    _check(lib, st)
+
+
+def hull_xy(xy, stream=None):
+    """Hull of interleaved points xy[i] = (x_i, y_i) (an (n, 2) float64 GPU tensor):
+    the same index list as hull(xy[:, 0], xy[:, 1])."""
+    import torch
+
+    _check_xy(xy)
+    n = xy.shape[0]
+    out = torch.empty(max(n, 1), dtype=torch.int64, device=xy.device)
+    cnt = torch.empty(1, dtype=torch.int64, device=xy.device)
+    with torch.cuda.device(xy.device):
+        hull_xy_into(xy, out, cnt, stream)
+        h = int(cnt.item())
+    if h < 0:
+        raise VqhullError(-h, "non-finite coordinate in the input")
+    return out[:h]
+
+
+def hull_batched_xy(xy, offsets, stream=None):
+    """hull_batched for interleaved points (an (N, 2) float64 GPU tensor)."""
+    import numpy as np
+    import torch
+
+    _check_xy(xy)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    nreq = len(off) - 1
+    if nreq < 0 or off[-1] != xy.shape[0]:
+        raise ValueError("offsets must have nreq+1 entries ending at len(xy)")
+    lib = load_library()
+    out = torch.empty(max(xy.shape[0], 1), dtype=torch.int64, device=xy.device)
+    cnt = torch.empty(max(nreq, 1), dtype=torch.int64, device=xy.device)
+    with torch.cuda.device(xy.device):
+        st = lib.vqhull_hull_batched_xy(ctypes.c_void_p(xy.data_ptr()),
+                                        off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nreq,
+                                        ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(cnt.data_ptr()),
+                                        _stream_handle(stream))
+    _check(lib, st)
+    return out, cnt[:nreq]
 
 
 def hull_batched(x, y, offsets, stream=None, check=True):

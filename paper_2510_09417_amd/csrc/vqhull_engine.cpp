@@ -405,6 +405,7 @@ Plan0Args plan0_args(Context& w, const vqhull_config& cfg) {
   pa.lds_limit = (uint32_t)cfg.lds_limit;
   pa.ext_tile = kExtTile;
   pa.toff = nullptr;
+  pa.filter_min = 0;
   return pa;
 }
 
@@ -415,9 +416,11 @@ Plan0Args plan0_args(Context& w, const vqhull_config& cfg) {
 // waits only for the status of level k-1: the GPU never waits for the host
 // between levels.  When a status shows an empty level, the loop stops (the
 // kernels already enqueued for it find no work).
-bool run_once(Context& w, const vqhull_config& cfg, const double* x, const double* y, int64_t nreq,
-              int64_t* out_idx, int64_t* out_counts, hipStream_t st, size_t N, const uint32_t* tile_req,
-              size_t ext_tiles, uint64_t tiles0, size_t max_tiles) {
+// ingested: the extremes records were written by the ingest of interleaved
+// input (x, y: its copy in buffer A), so the extremes pass is not run.
+bool run_once(Context& w, const vqhull_config& cfg, const double* x, const double* y, const double* xy,
+              int64_t nreq, int64_t* out_idx, int64_t* out_counts, hipStream_t st, size_t N,
+              const uint32_t* tile_req, size_t ext_tiles, uint64_t tiles0, size_t max_tiles, bool ingested) {
   const uint32_t tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
   const uint32_t lds_limit = (uint32_t)cfg.lds_limit;
   const int tmax = finish_tmax_for(cfg.lds_limit);
@@ -429,14 +432,20 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
 
   // Octagon prefilter (requests above the LDS threshold only): extremes in
   // eight directions, the edges, the filter into buffer B, the prefix of the
-  // kept counts and the compaction into buffer A.
-  const bool pf = cfg.prefilter != 0 && tiles0 > 0;
+  // kept counts and the compaction into buffer A.  Interleaved input takes
+  // the same passes for every request (the filter deinterleaves into buffer
+  // A, dropping points only with the prefilter on), so every later kernel
+  // reads the workspace.
+  const bool aos = xy != nullptr;
+  const bool pf = aos || (cfg.prefilter != 0 && tiles0 > 0);
+  const uint32_t filter_min = aos ? 0u : lds_limit;
   if (pf) {
-    const OctArgs oa{x, y, tile_req, w.req.p, w.epart.p, w.opart.p, w.counts_dev, (uint32_t)ext_tiles};
+    const OctArgs oa{x, y, xy, tile_req, w.req.p, w.epart.p, w.opart.p, w.counts_dev, (uint32_t)ext_tiles};
     timed(w, tm_all, st, VQHULL_K_EXTREMES, 0, (int64_t)N, 0, [&] { ck(launch_octagon(oa, st), "k_octagon"); });
     FilterArgs fa{};
     fa.x = x;
     fa.y = y;
+    fa.xy = xy;
     fa.tile_req = tile_req;
     fa.req = w.req.p;
     fa.part = w.epart.p;
@@ -452,20 +461,24 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
     fa.toff = w.toff.p;
     fa.counts = w.counts_dev;
     fa.ntiles = (uint32_t)ext_tiles;
-    fa.min_points = lds_limit;
+    fa.min_points = filter_min;
+    fa.drop_min = cfg.prefilter ? lds_limit : 0xFFFFFFFFu;
     timed(w, tm_all, st, VQHULL_K_FILTER, 0, (int64_t)N, 0, [&] {
       ck(launch_oct_plan(fa, (uint32_t)nreq, st), "k_oct_plan");
       ck(launch_filter(fa, st), "k_filter");
       ck(launch_filter_scan(fa, st), "k_filter_scan");
     });
     timed(w, tm_all, st, VQHULL_K_COMPACT, 0, 0, 0, [&] { ck(launch_compact(fa, st), "k_compact"); });
-  } else {
+  } else if (!ingested) {
     ExtremesArgs ea{x, y, tile_req, w.req.p, w.epart.p, w.counts_dev, (uint32_t)ext_tiles};
     timed(w, tm_all, st, VQHULL_K_EXTREMES, 0, (int64_t)N, 0, [&] { ck(launch_extremes(ea, st), "k_extremes"); });
   }
   ensure(w.level_nodes, 16, st, true);
   Plan0Args pa = plan0_args(w, cfg);
-  if (pf) pa.toff = w.toff.p;
+  if (pf) {
+    pa.toff = w.toff.p;
+    pa.filter_min = filter_min;
+  }
   timed(w, tm_all, st, VQHULL_K_PLAN0, 0, nreq, 0, [&] { ck(launch_plan0(pa, st), "k_plan0"); });
   ck(hipEventRecord(w.status_ev[0], st), "hipEventRecord");
 
@@ -502,7 +515,9 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
     const int64_t need = known_nodes + 2 * known_seg + 2 * std::min<int64_t>(2 * known_seg, (int64_t)max_seg) + 16;
     ensure(w.nodes, (size_t)need, st, true);
     ensure(w.level_nodes, (size_t)k + 3, st, true);
-    const FinishArgs fa = finish_args(w, x, y, k);
+    // (with interleaved input no job reads the caller's arrays: every root
+    // went through the filter into buffer A)
+    const FinishArgs fa = finish_args(w, aos ? xy : x, aos ? xy : y, k);
     const PlanArgs pl = plan_args(w, cfg, k, G);
     finish_recs.push_back(timed(w, tm_all, st, VQHULL_K_PLAN, k, 0, 0,
                                 [&] { ck(launch_finish_plan(fa, pl, tmax, st), "k_finish_plan"); }));
@@ -569,12 +584,13 @@ struct Caps {
   size_t max_seg, max_tiles;
 };
 
-Caps reserve(Context& w, const vqhull_config& cfg, size_t N, size_t nreq, size_t ext_tiles, hipStream_t st) {
+Caps reserve(Context& w, const vqhull_config& cfg, size_t N, size_t nreq, size_t ext_tiles, hipStream_t st,
+             bool aos = false) {
   const uint32_t tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
   const uint32_t lds_limit = (uint32_t)cfg.lds_limit;
   ensure(w.req, std::max<size_t>(nreq, 1), st);
   ensure(w.epart, std::max<size_t>(ext_tiles, 1), st);
-  if (cfg.prefilter) {
+  if (cfg.prefilter || aos) {
     ensure(w.opart, std::max<size_t>(ext_tiles, 1), st);
     ensure(w.oct, std::max<size_t>(nreq, 1), st);
     ensure(w.tcount, std::max<size_t>(ext_tiles, 1), st);
@@ -600,8 +616,9 @@ Caps reserve(Context& w, const vqhull_config& cfg, size_t N, size_t nreq, size_t
   return c;
 }
 
+// xy: interleaved input (x and y unused), or nullptr.
 void run(Context& w, const vqhull_config& cfg, const double* x, const double* y, const int64_t* offsets, int64_t nreq,
-         int64_t* out_idx, int64_t* out_counts, hipStream_t st) {
+         int64_t* out_idx, int64_t* out_counts, hipStream_t st, const double* xy = nullptr) {
   const uint32_t tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
   const uint32_t lds_limit = (uint32_t)cfg.lds_limit;
   const size_t N = (size_t)offsets[nreq];
@@ -609,15 +626,40 @@ void run(Context& w, const vqhull_config& cfg, const double* x, const double* y,
   std::lock_guard<std::mutex> guard(w.mu);
   ck(hipSetDevice(w.device), "hipSetDevice");
 
+  // Interleaved input without the prefilter: copy x and y into buffer A and
+  // run the plain path on that copy (with the prefilter, the filter pass
+  // deinterleaves the points it keeps instead).
+  const double* const xy_in = xy;
+  const bool deint = xy != nullptr && !cfg.prefilter;
+  if (deint) {
+    ensure_points(w, std::max<size_t>(N, 1), st);
+    x = w.wx[0];
+    y = w.wy[0];
+    xy = nullptr;
+  }
+  auto ingest = [&](const uint32_t* tile_req, size_t ext_tiles) {
+    if (!deint) return;
+    timed(w, g_timing.load() == 1, st, VQHULL_K_INGEST, 0, (int64_t)N, (int64_t)N, [&] {
+      if (ext_tiles == 0) {  // the one-launch small path: a plain copy
+        ck(launch_deinterleave(xy_in, w.wx[0], w.wy[0], (uint64_t)N, st), "k_deinterleave");
+      } else {
+        const IngestArgs ia{xy_in, w.wx[0], w.wy[0], tile_req, w.req.p, w.epart.p, w.counts_dev,
+                            (uint32_t)ext_tiles};
+        ck(launch_ingest(ia, st), "k_ingest");
+      }
+    });
+  };
+
   // A single request small enough for the LDS finisher: one launch does it
   // all (extremes, Algorithm 1 in LDS, the clockwise list).
-  if (nreq == 1 && N <= lds_limit) {
+  if (nreq == 1 && N <= lds_limit && !xy) {
     ensure_points(w, std::max<size_t>(N, 1), st);
     ensure(w.nodes, 4096, st);
     ensure(w.req, 1, st);
     w.stats.clear();
     w.launches.clear();
     w.next_event = 0;
+    ingest(nullptr, 0);
     SmallArgs sa{x, y, (uint32_t)N, out_idx, out_counts, w.wi[0], w.nodes.p, w.req.p};
     timed(w, g_timing.load() == 1, st, VQHULL_K_FINISH, 0, (int64_t)N, 0,
           [&] { ck(launch_small(sa, finish_tmax_for(cfg.lds_limit), st), "k_small"); });
@@ -641,7 +683,7 @@ void run(Context& w, const vqhull_config& cfg, const double* x, const double* y,
     if (r.n > lds_limit) tiles0 += (r.n + tile - 1) / tile;
     w.h_req[i] = r;
   }
-  const Caps caps = reserve(w, cfg, N, (size_t)nreq, ext_tiles, st);
+  const Caps caps = reserve(w, cfg, N, (size_t)nreq, ext_tiles, st, xy != nullptr);
   const uint32_t* tile_req = nullptr;
   if (nreq > 1 && ext_tiles > 0) {
     ensure_host_u32(w, ext_tiles);
@@ -666,7 +708,10 @@ void run(Context& w, const vqhull_config& cfg, const double* x, const double* y,
     w.stats.clear();
     w.launches.clear();
     w.next_event = 0;
-    if (run_once(w, cfg, x, y, nreq, out_idx, out_counts, st, N, tile_req, ext_tiles, tiles0, caps.max_tiles)) break;
+    ingest(tile_req, ext_tiles);  // again on a retry: the failed attempt may have overwritten buffer A
+    if (run_once(w, cfg, x, y, xy, nreq, out_idx, out_counts, st, N, tile_req, ext_tiles, tiles0, caps.max_tiles,
+                 deint))
+      break;
     // The node table was too small for a level (not expected with the host's
     // bound): grow it and start over.
     ensure(w.nodes, 2 * w.nodes.cap, st);
@@ -689,10 +734,18 @@ int guard_status(F&& f) {
 }
 
 int guarded(const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
-            int64_t* out_counts, vqhull_stream_t stream) {
+            int64_t* out_counts, vqhull_stream_t stream, const double* xy = nullptr) {
   return guard_status([&] {
-    run(default_context(), current_config(), x, y, offsets, nreq, out_idx, out_counts, (hipStream_t)stream);
+    run(default_context(), current_config(), x, y, offsets, nreq, out_idx, out_counts, (hipStream_t)stream, xy);
   });
+}
+
+// Offsets: offsets[0] = 0, non-decreasing, total below 2^31.
+bool offsets_valid(const int64_t* offsets, int64_t nreq) {
+  if (offsets[0] != 0) return false;
+  for (int64_t i = 0; i < nreq; ++i)
+    if (offsets[i + 1] < offsets[i]) return false;
+  return offsets[nreq] < (int64_t(1) << 31);
 }
 
 }  // namespace
@@ -866,6 +919,23 @@ int vqhull_hull_batched(const double* x, const double* y, const int64_t* offsets
   if (offsets[nreq] >= (int64_t(1) << 31)) return VQHULL_ERR_INVALID_ARGUMENT;
   if (offsets[nreq] > 0 && (!x || !y)) return VQHULL_ERR_INVALID_ARGUMENT;
   return guarded(x, y, offsets, nreq, out_idx, out_counts, stream);
+}
+
+int vqhull_hull_xy(const double* xy, int64_t n, int64_t* out_idx, int64_t* out_count, vqhull_stream_t stream) {
+  if (n < 0 || n >= (int64_t(1) << 31) || !out_idx || !out_count || (n > 0 && !xy) ||
+      (reinterpret_cast<uintptr_t>(xy) & 15u) != 0)
+    return VQHULL_ERR_INVALID_ARGUMENT;
+  const int64_t offsets[2] = {0, n};
+  return guarded(nullptr, nullptr, offsets, 1, out_idx, out_count, stream, n > 0 ? xy : nullptr);
+}
+
+int vqhull_hull_batched_xy(const double* xy, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
+                           int64_t* out_counts, vqhull_stream_t stream) {
+  if (nreq < 0 || !offsets || nreq >= (int64_t(1) << 31)) return VQHULL_ERR_INVALID_ARGUMENT;
+  if (nreq == 0) return VQHULL_OK;
+  if (!out_counts || !out_idx || !offsets_valid(offsets, nreq)) return VQHULL_ERR_INVALID_ARGUMENT;
+  if (offsets[nreq] > 0 && (!xy || (reinterpret_cast<uintptr_t>(xy) & 15u) != 0)) return VQHULL_ERR_INVALID_ARGUMENT;
+  return guarded(nullptr, nullptr, offsets, nreq, out_idx, out_counts, stream, offsets[nreq] > 0 ? xy : nullptr);
 }
 
 int vqhull_autotune(const double* x, const double* y, int64_t n, int32_t repeats, vqhull_tune_entry* entries,

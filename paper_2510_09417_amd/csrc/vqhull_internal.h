@@ -196,16 +196,19 @@ struct OctPart {
 // Per request: the origin o (= p) and the eight edges, edge i with direction
 // (ex_i, ey_i) and threshold t_i; a point u is dropped iff
 // fl(fl(ex_i * fl(u.y - o.y)) - fl(ey_i * fl(u.x - o.x))) > t_i for all eight.
-// on = 0: the request is not filtered (at most the threshold's points).
+// on = 0: the request does not go through the filter (it is read from the
+// caller's arrays); keep_all = 1: it goes through but drops nothing (the
+// filter writes every point straight to its place in buffer A).
 struct OctEdges {
   double ox, oy;
   double ex[8], ey[8], t[8];
-  uint32_t on, pad;
+  uint32_t on, keep_all;
 };
 
 struct OctArgs {
   const double* x;
   const double* y;
+  const double* xy;  // interleaved input (x0, y0, x1, y1, ...), or nullptr: x and y
   const uint32_t* tile_req;  // nullptr: single request 0
   Req* req;
   ExtPart* part;   // the lexicographic extremes, as the plain extremes pass writes them
@@ -217,6 +220,7 @@ struct OctArgs {
 struct FilterArgs {
   const double* x;
   const double* y;
+  const double* xy;    // interleaved input, or nullptr
   const uint32_t* tile_req;
   const Req* req;
   const ExtPart* part;
@@ -232,7 +236,8 @@ struct FilterArgs {
   uint32_t* toff;      // exclusive prefix of tcount over all tiles (ext_tiles + 1 entries)
   const BatchCounts* counts;
   uint32_t ntiles;     // grid of the per-tile kernels (>= counts->ext_tiles)
-  uint32_t min_points; // requests with more points are filtered (the LDS threshold)
+  uint32_t min_points; // requests with more points go through the filter
+  uint32_t drop_min;   // ... and may drop points if they have more than this many
 };
 
 struct SweepArgs {
@@ -271,6 +276,7 @@ struct Plan0Args {
   uint32_t lds_limit;
   uint32_t ext_tile;
   const uint32_t* toff;  // octagon prefilter: kept-point prefix per extremes tile (nullptr: off)
+  uint32_t filter_min;   // requests with more points went through the filter
 };
 
 struct PlanArgs {
@@ -358,6 +364,21 @@ int launch_oct_plan(const FilterArgs& a, uint32_t nreq, void* stream);
 int launch_filter(const FilterArgs& a, void* stream);
 int launch_filter_scan(const FilterArgs& a, void* stream);
 int launch_compact(const FilterArgs& a, void* stream);
+// Interleaved input without the prefilter: xy[0..2n) -> x[0..n), y[0..n)
+// (k_ingest: per extremes tile, with the tile's lexicographic extremes
+// record, in place of launch_extremes).
+struct IngestArgs {
+  const double* xy;
+  double* x;
+  double* y;
+  const uint32_t* tile_req;
+  Req* req;
+  ExtPart* part;
+  const BatchCounts* counts;
+  uint32_t ntiles;
+};
+int launch_ingest(const IngestArgs& a, void* stream);
+int launch_deinterleave(const double* xy, double* x, double* y, uint64_t n, void* stream);
 int launch_assemble(const AssembleArgs& a, void* stream);
 int launch_copy_lists(const AssembleArgs& a, void* stream);
 int launch_stream_scale(const double* in, double* out, uint64_t n, double s, void* stream);

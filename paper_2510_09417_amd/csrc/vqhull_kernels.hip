@@ -1101,10 +1101,11 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
     }
     __syncthreads();
     if (big) e = s_res[tid];
-    // With the octagon prefilter, a request above the LDS threshold keeps
-    // its kept points at the front of its range of buffer A.
+    // A request that went through the octagon filter (above the LDS
+    // threshold with the prefilter on; every request of interleaved input)
+    // has its kept points at the front of its range of buffer A.
     uint32_t kind[2] = {kKindNone, kKindNone}, cnt[2] = {0, 0};
-    const bool filt = valid && A.toff != nullptr && rq.n > A.lds_limit;
+    const bool filt = valid && A.toff != nullptr && rq.n > A.filter_min;
     if (valid && rq.n > 0) {
       cnt[0] = filt ? A.toff[rq.tile0 + ceil_div(rq.n, A.ext_tile)] - A.toff[rq.tile0] : rq.n;
       kind[0] = cnt[0] <= A.lds_limit ? kKindJob : kKindSeg;
@@ -1871,7 +1872,10 @@ __device__ __forceinline__ OctAcc oct_block(OctAcc a, OctAcc* s_w) {
   return a;
 }
 
-template <int BLOCK, int PPT, int ITER>
+// Interleaved input: one 16-byte load per point.
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+template <int BLOCK, int PPT, int ITER, bool AOS>
 __global__ __launch_bounds__(BLOCK) void k_octagon(OctArgs A) {
   constexpr uint32_t SUB = BLOCK * PPT;
   constexpr uint32_t TILE = SUB * ITER;
@@ -1905,8 +1909,14 @@ __global__ __launch_bounds__(BLOCK) void k_octagon(OctArgs A) {
 #pragma unroll
     for (int v = 0; v < PPT; ++v) {
       const uint32_t pos = slo + v * BLOCK + tid;
-      xs[v] = pos < hi ? __builtin_nontemporal_load(A.x + pos) : __builtin_nan("");
-      ys[v] = pos < hi ? __builtin_nontemporal_load(A.y + pos) : __builtin_nan("");
+      if constexpr (AOS) {
+        const dbl2 p = __builtin_nontemporal_load(reinterpret_cast<const dbl2*>(A.xy) + min(pos, hi - 1u));
+        xs[v] = pos < hi ? p.x : __builtin_nan("");
+        ys[v] = pos < hi ? p.y : __builtin_nan("");
+      } else {
+        xs[v] = pos < hi ? __builtin_nontemporal_load(A.x + pos) : __builtin_nan("");
+        ys[v] = pos < hi ? __builtin_nontemporal_load(A.y + pos) : __builtin_nan("");
+      }
     }
 #pragma unroll
     for (int v = 0; v < PPT; ++v) {
@@ -2021,8 +2031,8 @@ __global__ __launch_bounds__(kOctPlanBlock) void k_oct_plan(FilterArgs A) {
   for (int i = 0; i < 8; ++i) {
     missing |= v[i] == kNone;
     const uint32_t pos = v[i] == kNone ? rq.off : rq.off + v[i];
-    vx[i] = A.x[pos];
-    vy[i] = A.y[pos];
+    vx[i] = A.xy ? A.xy[2 * (size_t)pos] : A.x[pos];
+    vy[i] = A.xy ? A.xy[2 * (size_t)pos + 1] : A.y[pos];
   }
   const double D = (vx[2] - vx[6]) + (vy[4] - vy[0]);
   const double ox = vx[6], oy = vy[6];
@@ -2050,16 +2060,36 @@ __global__ __launch_bounds__(kOctPlanBlock) void k_oct_plan(FilterArgs A) {
     E->ey[i] = ey;
     E->t[i] = t;
   }
-  if (edges == 0 || missing) {
+  const bool keep_all = edges == 0 || missing || rq.n <= A.drop_min;
+  if (keep_all) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) E->t[i] = __builtin_inf();
   }
+  E->keep_all = keep_all ? 1u : 0u;
   E->ox = ox;
   E->oy = oy;
   E->on = 1u;
 }
 
-template <int BLOCK, int PPT, int ITER>
+// Loads of one sub-tile: positions past the end re-read the last point.
+template <int BLOCK, int PPT, bool AOS>
+__device__ __forceinline__ void filter_loads(const FilterArgs& A, uint32_t slo, uint32_t hi, double (&px)[PPT],
+                                             double (&py)[PPT]) {
+#pragma unroll
+  for (int v = 0; v < PPT; ++v) {
+    const uint32_t pc = min(slo + v * BLOCK + threadIdx.x, hi - 1u);
+    if constexpr (AOS) {
+      const dbl2 p = __builtin_nontemporal_load(reinterpret_cast<const dbl2*>(A.xy) + pc);
+      px[v] = p.x;
+      py[v] = p.y;
+    } else {
+      px[v] = __builtin_nontemporal_load(A.x + pc);
+      py[v] = __builtin_nontemporal_load(A.y + pc);
+    }
+  }
+}
+
+template <int BLOCK, int PPT, int ITER, bool AOS>
 __global__ __launch_bounds__(BLOCK) void k_filter(FilterArgs A) {
   constexpr uint32_t SUB = BLOCK * PPT;
   constexpr uint32_t TILE = SUB * ITER;
@@ -2077,6 +2107,28 @@ __global__ __launch_bounds__(BLOCK) void k_filter(FilterArgs A) {
   const uint32_t lo = off + (t - tile0) * TILE;
   const uint32_t hi = min(off + n, lo + TILE);
   const OctEdges* E = A.oct + r;
+  if (uni(E->keep_all)) {
+    // Nothing is dropped: every point goes straight to its own position in
+    // buffer A (the kept-count prefix of the request's tiles is then the
+    // identity, and the compaction skips the request).
+    for (int it = 0; it < ITER; ++it) {
+      const uint32_t slo = lo + (uint32_t)it * SUB;
+      if (slo >= hi) break;  // uniform
+      double px[PPT], py[PPT];
+      filter_loads<BLOCK, PPT, AOS>(A, slo, hi, px, py);
+#pragma unroll
+      for (int v = 0; v < PPT; ++v) {
+        const uint32_t pos = slo + v * BLOCK + tid;
+        if (pos < hi) {
+          A.cx[pos] = px[v];
+          A.cy[pos] = py[v];
+          A.ci[pos] = pos - off;
+        }
+      }
+    }
+    if (tid == 0) A.tcount[t] = hi - lo;
+    return;
+  }
   const double ox = uni(E->ox), oy = uni(E->oy);
   double eex[8], eey[8], et[8];
 #pragma unroll
@@ -2090,12 +2142,7 @@ __global__ __launch_bounds__(BLOCK) void k_filter(FilterArgs A) {
     const uint32_t slo = lo + (uint32_t)it * SUB;
     if (slo >= hi) break;  // uniform
     double px[PPT], py[PPT];
-#pragma unroll
-    for (int v = 0; v < PPT; ++v) {
-      const uint32_t pc = min(slo + v * BLOCK + tid, hi - 1u);
-      px[v] = __builtin_nontemporal_load(A.x + pc);
-      py[v] = __builtin_nontemporal_load(A.y + pc);
-    }
+    filter_loads<BLOCK, PPT, AOS>(A, slo, hi, px, py);
     uint32_t m = 0u;  // bit v: the thread's v-th point is kept
 #pragma unroll
     for (int v = 0; v < PPT; ++v) {
@@ -2173,7 +2220,7 @@ __global__ __launch_bounds__(256) void k_compact(FilterArgs A) {
   if (t >= A.counts->ext_tiles) return;
   const uint32_t r = A.tile_req ? A.tile_req[t] : 0u;
   const uint32_t off = A.req[r].off, n = A.req[r].n, tile0 = A.req[r].tile0;
-  if (n <= A.min_points) return;
+  if (n <= A.min_points || A.oct[r].keep_all) return;
   const uint32_t cnt = A.tcount[t];
   const uint32_t src = off + (t - tile0) * kExtTile;
   const uint32_t dst = off + (A.toff[t] - A.toff[tile0]);
@@ -2181,6 +2228,90 @@ __global__ __launch_bounds__(256) void k_compact(FilterArgs A) {
     A.cx[dst + i] = __builtin_nontemporal_load(A.sx + src + i);
     A.cy[dst + i] = __builtin_nontemporal_load(A.sy + src + i);
     A.ci[dst + i] = __builtin_nontemporal_load(A.si + src + i);
+  }
+}
+
+// Interleaved input without the prefilter: x and y copied into workspace
+// buffer A, which the whole plain path then reads as the caller's arrays
+// (nothing writes buffer A's coordinates before level 2, after the last read
+// of the caller's arrays).  k_ingest also records each extremes tile's
+// lexicographic extremes (the plain extremes pass's record, with the
+// non-finite check on both coordinates), so that pass is not run;
+// k_deinterleave is the plain copy for the one-launch small path.
+template <int BLOCK, int PPT, int ITER>
+__global__ __launch_bounds__(BLOCK) void k_ingest(IngestArgs A) {
+  constexpr uint32_t SUB = BLOCK * PPT;
+  constexpr uint32_t TILE = SUB * ITER;
+  __shared__ OctAcc s_w[BLOCK / 64];
+  const uint32_t t = blockIdx.x;
+  if (t >= A.counts->ext_tiles) return;
+  const uint32_t r = A.tile_req ? A.tile_req[t] : 0u;
+  const uint32_t off = A.req[r].off, n = A.req[r].n, tile0 = A.req[r].tile0;
+  const uint32_t lo = off + (t - tile0) * TILE;
+  const uint32_t hi = min(off + n, lo + TILE);
+  const int tid = threadIdx.x, lane = tid & 63;
+  double lnx = __builtin_inf(), lny = __builtin_inf(), lxx = -__builtin_inf(), lxy = -__builtin_inf();
+  uint32_t lni = kNone, lxi = kNone;
+  bool bad = false;
+  for (int it = 0; it < ITER; ++it) {
+    const uint32_t slo = lo + (uint32_t)it * SUB;
+    if (slo >= hi) break;  // uniform
+    double xs[PPT], ys[PPT];
+#pragma unroll
+    for (int v = 0; v < PPT; ++v) {
+      const uint32_t pos = slo + v * BLOCK + tid;
+      const dbl2 p = __builtin_nontemporal_load(reinterpret_cast<const dbl2*>(A.xy) + min(pos, hi - 1u));
+      xs[v] = pos < hi ? p.x : __builtin_nan("");
+      ys[v] = pos < hi ? p.y : __builtin_nan("");
+    }
+#pragma unroll
+    for (int v = 0; v < PPT; ++v) {
+      const uint32_t pos = slo + v * BLOCK + tid;
+      if (pos < hi) {
+        A.x[pos] = xs[v];
+        A.y[pos] = ys[v];
+      }
+      const double x = xs[v], y = ys[v];
+      bad |= (pos < hi) & !(finite(x) & finite(y));
+      const bool lt = (x < lnx) | ((x == lnx) & (y < lny));
+      const bool gt = (x > lxx) | ((x == lxx) & (y > lxy));
+      lnx = lt ? x : lnx;
+      lny = lt ? y : lny;
+      lni = lt ? pos : lni;
+      lxx = gt ? x : lxx;
+      lxy = gt ? y : lxy;
+      lxi = gt ? pos : lxi;
+    }
+  }
+  if (__ballot(bad) && lane == 0) A.req[r].err = 1u;
+  OctAcc a = oct_empty();
+  a.lnx = lnx;
+  a.lny = lny;
+  a.lni = lni;
+  a.lxx = lxx;
+  a.lxy = lxy;
+  a.lxi = lxi;
+  a = oct_block<BLOCK>(a, s_w);
+  if (tid == 0) {
+    ExtPart e;
+    e.minx = a.lnx;
+    e.miny = a.lny;
+    e.maxx = a.lxx;
+    e.maxy = a.lxy;
+    e.mini = a.lni != kNone ? a.lni - off : kNone;
+    e.maxi = a.lxi != kNone ? a.lxi - off : kNone;
+    e.pad[0] = e.pad[1] = 0;
+    A.part[t] = e;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_deinterleave(const double* __restrict__ xy, double* __restrict__ x,
+                                                      double* __restrict__ y, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * 256u;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < n; i += stride) {
+    const dbl2 p = __builtin_nontemporal_load(reinterpret_cast<const dbl2*>(xy) + i);
+    x[i] = p.x;
+    y[i] = p.y;
   }
 }
 
@@ -2434,8 +2565,13 @@ int launch_sweep(const SweepArgs& a, int mode, int block, int ppt, uint32_t grid
 
 int launch_octagon(const OctArgs& a, void* stream) {
   if (a.ntiles == 0) return 0;
-  hipLaunchKernelGGL((k_octagon<kOctBlock, kOctPPT, kOctIter>), dim3(a.ntiles), dim3(kOctBlock), 0,
-                     (hipStream_t)stream, a);
+  if (a.xy) {
+    hipLaunchKernelGGL((k_octagon<kOctBlock, kOctPPT, kOctIter, true>), dim3(a.ntiles), dim3(kOctBlock), 0,
+                       (hipStream_t)stream, a);
+  } else {
+    hipLaunchKernelGGL((k_octagon<kOctBlock, kOctPPT, kOctIter, false>), dim3(a.ntiles), dim3(kOctBlock), 0,
+                       (hipStream_t)stream, a);
+  }
   return (int)hipGetLastError();
 }
 
@@ -2447,8 +2583,13 @@ int launch_oct_plan(const FilterArgs& a, uint32_t nreq, void* stream) {
 
 int launch_filter(const FilterArgs& a, void* stream) {
   if (a.ntiles == 0) return 0;
-  hipLaunchKernelGGL((k_filter<kOctBlock, kOctPPT, kOctIter>), dim3(a.ntiles), dim3(kOctBlock), 0,
-                     (hipStream_t)stream, a);
+  if (a.xy) {
+    hipLaunchKernelGGL((k_filter<kOctBlock, kOctPPT, kOctIter, true>), dim3(a.ntiles), dim3(kOctBlock), 0,
+                       (hipStream_t)stream, a);
+  } else {
+    hipLaunchKernelGGL((k_filter<kOctBlock, kOctPPT, kOctIter, false>), dim3(a.ntiles), dim3(kOctBlock), 0,
+                       (hipStream_t)stream, a);
+  }
   return (int)hipGetLastError();
 }
 
@@ -2460,6 +2601,20 @@ int launch_filter_scan(const FilterArgs& a, void* stream) {
 int launch_compact(const FilterArgs& a, void* stream) {
   if (a.ntiles == 0) return 0;
   hipLaunchKernelGGL(k_compact, dim3(a.ntiles), dim3(256), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int launch_ingest(const IngestArgs& a, void* stream) {
+  if (a.ntiles == 0) return 0;
+  hipLaunchKernelGGL((k_ingest<kOctBlock, kOctPPT, kOctIter>), dim3(a.ntiles), dim3(kOctBlock), 0,
+                     (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int launch_deinterleave(const double* xy, double* x, double* y, uint64_t n, void* stream) {
+  if (n == 0) return 0;
+  const uint64_t blocks = std::min<uint64_t>((n + 255u) / 256u, 256u * 32u);
+  hipLaunchKernelGGL(k_deinterleave, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream, xy, x, y, n);
   return (int)hipGetLastError();
 }
 

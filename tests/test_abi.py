@@ -59,6 +59,17 @@ def test_invalid_arguments_rejected_on_host(lib):
                                    dummy, None) == 1
     assert lib.vqhull_hull_batched(dummy, dummy, None, 1, dummy, dummy, None) == 1
     assert lib.vqhull_hull_batched(dummy, dummy, p, -1, dummy, dummy, None) == 1
+    # interleaved input: misaligned (not a whole double2), null, bad offsets
+    assert lib.vqhull_hull_xy(vp(0x1008), 5, dummy, dummy, None) == 1
+    assert lib.vqhull_hull_xy(None, 5, dummy, dummy, None) == 1
+    assert lib.vqhull_hull_xy(dummy, -1, dummy, dummy, None) == 1
+    assert lib.vqhull_hull_xy(dummy, 5, None, dummy, None) == 1
+    assert lib.vqhull_hull_batched_xy(dummy, p, 2, dummy, dummy, None) == 1
+    ok = np.array([0, 5], dtype=np.int64)
+    q = ok.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    assert lib.vqhull_hull_batched_xy(vp(0x1008), q, 1, dummy, dummy, None) == 1
+    assert lib.vqhull_hull_batched_xy(None, q, 1, dummy, dummy, None) == 1
+    assert lib.vqhull_hull_batched_xy(dummy, q, 1, None, dummy, None) == 1
     assert lib.vqhull_stream_scale(dummy, dummy, -1, 2.0, None) == 1
     assert lib.vqhull_stream_scale(None, dummy, 4, 2.0, None) == 1
     assert one[0] == 0

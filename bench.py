@@ -19,6 +19,9 @@ Prints one JSON line:
               Akl-Toussaint heuristic, a variant of the method; outside the
               timed region): throughput, a check that every hull equals the
               plain path's, the points kept, and the bandwidth of its passes.
+  aos         the same step from interleaved (x, y) input (the array-of-
+              structures layout of the paper's inputs), without and with the
+              prefilter: throughput and equality with the plain path.
   served      the served mix (65,536 requests, sizes log-uniform in [16, 10^6],
               disk / square / circle / Kuzmin in equal shares, drawn on the GPU):
               hulls/s with every request submitted at once; p50 / p99 latency
@@ -223,13 +226,12 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
     }
 
 
-def prefilter_leg(vq, torch, dx, outs, names, npts, step, args) -> dict:
+def prefilter_leg(vq, torch, dx, outs, names, npts, step, args, plain) -> dict:
     """The step again with the octagon prefilter on: wall-clock throughput
     over the same number of steps, equality of every hull with the plain
     path's, the points kept, and the bandwidth of the eight-direction extremes
     pass (16 B per point) and of the filter (16 B read per point, 20 B written
     per kept point) from HIP events on the launch stream."""
-    plain = [oi[: int(oc.item())].clone() for oi, oc in outs]
     vq.set_config(prefilter=1)
     try:
         for _ in range(args.warmup):
@@ -280,6 +282,39 @@ def prefilter_leg(vq, torch, dx, outs, names, npts, step, args) -> dict:
     return res
 
 
+def aos_leg(vq, torch, dx, outs, npts, args, plain, stream) -> dict:
+    """The step from interleaved input (one (n, 2) tensor per dataset),
+    without and with the prefilter: wall-clock throughput over the same
+    number of steps and equality of every hull with the plain path's."""
+    xys = [torch.stack([tx, ty], dim=1).contiguous() for tx, ty in dx]
+    res = {}
+    try:
+        for pf in (0, 1):
+            vq.set_config(prefilter=pf)
+
+            def step_xy():
+                for xy, (oi, oc) in zip(xys, outs):
+                    vq.hull_xy_into(xy, oi, oc, stream)
+
+            for _ in range(args.warmup):
+                step_xy()
+            torch.cuda.synchronize()
+            same = all(int(oc.item()) == len(p) and torch.equal(oi[: len(p)], p) for (oi, oc), p in zip(outs, plain))
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                step_xy()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            res["prefilter" if pf else "plain"] = {"value": round(npts * args.steps / wall / 1e9, 4), "unit": "Gpoints/s",
+                                                   "ms_per_step": round(1e3 * wall / args.steps, 4),
+                                                   "same_result_as_plain": bool(same)}
+    finally:
+        vq.set_config(prefilter=0)
+        del xys
+    log(f"aos: {res}")
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,6 +324,7 @@ def main() -> int:
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-energy", action="store_true")
     ap.add_argument("--no-prefilter", action="store_true")
+    ap.add_argument("--no-aos", action="store_true")
     ap.add_argument("--served-requests", type=int, default=65536)
     ap.add_argument("--served-lanes", type=int, default=4)
     ap.add_argument("--served-lane-points", type=int, default=1 << 25)
@@ -399,7 +435,9 @@ def main() -> int:
     wall = t1 - t0
     ms_per_step = 1e3 * wall / args.steps
     value = npts * args.steps / wall / 1e9
-    pre = None if args.no_prefilter else prefilter_leg(vq, torch, dx, outs, names, npts, step, args)
+    plain = [oi[: int(oc.item())].clone() for oi, oc in outs]
+    pre = None if args.no_prefilter else prefilter_leg(vq, torch, dx, outs, names, npts, step, args, plain)
+    aos = None if args.no_aos else aos_leg(vq, torch, dx, outs, npts, args, plain, stream)
 
     def rate(recs):
         ms = sum(m for m, _ in recs)
@@ -470,6 +508,7 @@ def main() -> int:
         "kernel_ms_per_step": {k: round(v / breakdown_steps, 4) for k, v in per_kind.items()},
         "energy": en,
         "prefilter": pre,
+        "aos": aos,
         "served": served,
     }
     print(json.dumps(line), flush=True)

@@ -331,8 +331,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=100_000_000, help="points per dataset (default 1e8)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described "
-              "in DESIGN.md and is not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a design that is "
+              "not built.", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -782,11 +782,14 @@ int context_reserve(Context* c, int64_t npoints, int64_t nreq, void* stream) {
   });
 }
 
+// The server's lanes run the plain method: their graph replays never use the
+// octagon prefilter, so neither does their plain fallback.
 int context_run(Context* c, const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
                 int64_t* out_counts, void* stream) {
   if (nreq == 0) return VQHULL_OK;
-  return guard_status(
-      [&] { run(*c, current_config(), x, y, offsets, nreq, out_idx, out_counts, (hipStream_t)stream); });
+  vqhull_config cfg = current_config();
+  cfg.prefilter = 0;
+  return guard_status([&] { run(*c, cfg, x, y, offsets, nreq, out_idx, out_counts, (hipStream_t)stream); });
 }
 
 const char* context_last_error() { return g_last_error.c_str(); }

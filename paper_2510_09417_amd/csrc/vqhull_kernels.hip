@@ -2563,6 +2563,11 @@ int launch_sweep(const SweepArgs& a, int mode, int block, int ppt, uint32_t grid
   return (int)hipErrorInvalidValue;
 }
 
+int launch_plan0(const Plan0Args& a, void* stream) {
+  hipLaunchKernelGGL(k_plan0, dim3(1), dim3(kPlanBlock), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
 int launch_octagon(const OctArgs& a, void* stream) {
   if (a.ntiles == 0) return 0;
   if (a.xy) {
@@ -2615,11 +2620,6 @@ int launch_deinterleave(const double* xy, double* x, double* y, uint64_t n, void
   if (n == 0) return 0;
   const uint64_t blocks = std::min<uint64_t>((n + 255u) / 256u, 256u * 32u);
   hipLaunchKernelGGL(k_deinterleave, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream, xy, x, y, n);
-  return (int)hipGetLastError();
-}
-
-int launch_plan0(const Plan0Args& a, void* stream) {
-  hipLaunchKernelGGL(k_plan0, dim3(1), dim3(kPlanBlock), 0, (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 

@@ -219,3 +219,22 @@ def test_graph_falls_back_when_recursion_is_deeper(vq):
     assert st["plain_batches"] >= 1
     for (x, y, _, _), a in zip(data, got):
         assert np.array_equal(a, oracle.hull(x, y))
+
+
+def test_prefilter_setting_does_not_reach_the_lanes(vq):
+    """The lanes run the plain method whatever the library-wide prefilter
+    setting: graph replays never use it and the plain fallback turns it off."""
+    data = []
+    for i, n, d in _requests(60, 80_000, seed=19):
+        x, y = workloads.served_request(i, n, d, seed=19)
+        data.append((x, y) + _device(x, y))
+    vq.set_config(prefilter=1)
+    try:
+        got_p, st_p = _run_server(vq, data, lanes=1, lane_points=1 << 18, lane_requests=24, graph_levels=0)
+        got_g, st_g = _run_server(vq, data, lanes=1, lane_points=1 << 18, lane_requests=24, graph_levels=20)
+    finally:
+        vq.set_config(prefilter=0)
+    assert st_p["plain_batches"] == st_p["batches"] and st_g["graph_batches"] >= 1
+    for k, ((x, y, _, _), a, b) in enumerate(zip(data, got_p, got_g)):
+        want = oracle.hull(x, y)
+        assert np.array_equal(a, want) and np.array_equal(b, want), f"request {k}"

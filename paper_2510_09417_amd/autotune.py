@@ -94,7 +94,8 @@ def tune_batched(x, y, offsets, repeats: int = 3, stream=None, persistent=(1, 0)
     """Tune the batched path on one representative batch: times
     ``hull_batched(x, y, offsets)`` (median of ``repeats`` runs after a warm-up)
     under every configuration (grid modes limited to ``persistent``: the
-    server's graph-captured batches need persistent sweeps) and checks that
+    server's graph-captured batches need persistent sweeps; the octagon
+    prefilter off, as the server's lanes run the plain method) and checks that
     each gives the same index lists and counts as the first.  Returns (fastest
     equal configuration, table); the library configuration is restored
     afterwards."""
@@ -109,7 +110,7 @@ def tune_batched(x, y, offsets, repeats: int = 3, stream=None, persistent=(1, 0)
             for lds in LDS_LIMITS:
                 for pers in persistent:
                     cfg = vq.set_config(sweep_block=blk, sweep_ppt=ppt, lds_limit=lds, sweep_persistent=pers,
-                                        level_block=256)
+                                        level_block=256, prefilter=0)
                     out, cnt = vq.hull_batched(x, y, offsets, stream=stream)
                     torch.cuda.synchronize()
                     times = []

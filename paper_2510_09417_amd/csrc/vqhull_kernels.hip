@@ -2224,10 +2224,27 @@ __global__ __launch_bounds__(256) void k_compact(FilterArgs A) {
   const uint32_t cnt = A.tcount[t];
   const uint32_t src = off + (t - tile0) * kExtTile;
   const uint32_t dst = off + (A.toff[t] - A.toff[tile0]);
-  for (uint32_t i = threadIdx.x; i < cnt; i += 256) {
-    A.cx[dst + i] = __builtin_nontemporal_load(A.sx + src + i);
-    A.cy[dst + i] = __builtin_nontemporal_load(A.sy + src + i);
-    A.ci[dst + i] = __builtin_nontemporal_load(A.si + src + i);
+  // four points per thread in flight: all loads, then all stores
+  constexpr uint32_t U = 4;
+  for (uint32_t base = 0; base < cnt; base += 256u * U) {
+    double vx[U], vy[U];
+    uint32_t vi[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
+      const uint32_t i = min(base + u * 256u + threadIdx.x, cnt - 1u);
+      vx[u] = __builtin_nontemporal_load(A.sx + src + i);
+      vy[u] = __builtin_nontemporal_load(A.sy + src + i);
+      vi[u] = __builtin_nontemporal_load(A.si + src + i);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
+      const uint32_t i = base + u * 256u + threadIdx.x;
+      if (i < cnt) {
+        A.cx[dst + i] = vx[u];
+        A.cy[dst + i] = vy[u];
+        A.ci[dst + i] = vi[u];
+      }
+    }
   }
 }
 

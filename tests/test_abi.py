@@ -143,3 +143,24 @@ def test_server_arguments_rejected_on_host(lib):
     assert lib.vqhull_server_ticket_info(None, 0, None) == 1
     assert lib.vqhull_server_stats(None, None) == 1
     assert lib.vqhull_server_destroy(None) == 1
+
+
+def test_kernel_kind_names_follow_the_header():
+    import paper_2510_09417_amd as vq
+
+    text = open(HEADER).read()
+    kinds = dict((int(v), k.lower()) for k, v in re.findall(r"VQHULL_K_([A-Z0-9_]+)\s*=\s*(\d+)", text))
+    assert sorted(kinds) == list(range(len(vq.KERNEL_KINDS)))
+    names = {"plan": "finish_plan"}  # the level planner shares its launch with the finisher
+    assert [names.get(kinds[i], kinds[i]) for i in range(len(kinds))] == list(vq.KERNEL_KINDS)
+
+
+def test_config_has_prefilter_flag():
+    import paper_2510_09417_amd as vq
+
+    old = vq.get_config()
+    try:
+        assert vq.set_config(prefilter=7)["prefilter"] == 1
+        assert vq.set_config(prefilter=0)["prefilter"] == 0
+    finally:
+        vq.set_config(**old)

@@ -168,3 +168,13 @@ def test_prefilter_timing_records(vq):
     finally:
         vq.set_timing(False)
     assert {"extremes", "filter", "compact", "plan0", "sweep"} <= kinds
+
+
+@pytest.mark.parametrize("scale", [1e300, 1e150, 1e-150, 1e-300, 2.0 ** -1060])
+def test_prefilter_extreme_scales(vq, scale):
+    """Products that overflow to infinity, thresholds that become NaN or
+    infinite, keys in the subnormal range: the kernels take every decision
+    the oracle takes."""
+    for dist in ("disk", "square", "kuzmin"):
+        x, y = workloads.points(dist, 60_000, seed=31)
+        check(x * scale, y * scale, f"{dist} x{scale:g}")

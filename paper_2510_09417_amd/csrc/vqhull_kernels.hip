@@ -691,7 +691,9 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
 // --------------------------------------------------------- block utilities
 
 // Exclusive scan of N values per thread across a workgroup of BLOCK threads.
-template <int BLOCK, int N>
+// TRAIL = false leaves out the closing barrier: the caller guarantees that
+// every thread passes another barrier before s_w is written again.
+template <int BLOCK, int N, bool TRAIL = true>
 __device__ __forceinline__ void block_scan(const uint32_t (&v)[N], uint32_t (&excl)[N], uint32_t (&total)[N],
                                            uint32_t (*s_w)[BLOCK / 64]) {
   constexpr int NW = BLOCK / 64;
@@ -723,7 +725,7 @@ __device__ __forceinline__ void block_scan(const uint32_t (&v)[N], uint32_t (&ex
     excl[j] = before + inc[j] - v[j];
     total[j] = all;
   }
-  __syncthreads();
+  if constexpr (TRAIL) __syncthreads();
 }
 
 // Best candidate over a workgroup; the result is valid in every thread.
@@ -1356,6 +1358,13 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
     S.nc1[0] = kNone16;
     S.lvl[0] = 0;
     S.lvl[1] = 1;
+    S.nbigc = 0;
+    S.anytie = 0;
+  }
+  if (tid < 2) {  // the two children of the first level
+    S.ccnt[tid] = 0;
+    S.cmax[tid] = 0ull;
+    S.ctie[tid] = 0;
   }
   __syncthreads();
   if (S.bad && tid == 0) A.req[job.req].err = 1u;
@@ -1363,18 +1372,11 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
   // Level sizes, identical in every thread (the scans return totals to all).
   uint32_t nsub_next = 1, ntot_next = cnt, nnode = 1, nlvl = 1;
   int cb = 0;  // live list buffer / sub-subproblem table of this level
+  // The child counters of a level start at zero: the level before cleared
+  // them in step 5 (each thread the children it owns there), with the
+  // barrier that ends that step.
   while (nsub_next > 0) {
     const uint32_t nsub = nsub_next, ntot = ntot_next, nch = 2u * nsub;
-    for (uint32_t c = tid; c < nch; c += BLOCK) {
-      S.ccnt[c] = 0;
-      S.cmax[c] = 0ull;
-      S.ctie[c] = 0;
-    }
-    if (tid == 0) {
-      S.nbigc = 0;
-      S.anytie = 0;
-    }
-    __syncthreads();
     // 1. classify; the key of a point in its child (the orientation value that
     //    put it there, > 0) also enters the child's maximum: for positive
     //    doubles the bit patterns order like the values.
@@ -1430,7 +1432,7 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
         }
       }
       uint32_t ex[3], tot[3];
-      block_scan<BLOCK, 3>(v, ex, tot, S.scan);
+      block_scan<BLOCK, 3, false>(v, ex, tot, S.scan);  // the barrier below closes it
       uint32_t en = nnode + ex[0], es = ex[1], ep = ex[2];
 #pragma unroll
       for (int k = 0; k < KC; ++k) {
@@ -1524,8 +1526,21 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
     }
     __syncthreads();
     }
-    // 5. nodes and next sub-subproblems
-    for (uint32_t c = tid; c < nch; c += BLOCK) {
+    // 5. nodes and next sub-subproblems; each thread then clears the child
+    //    counters it owns for the next level (no other thread reads them
+    //    in this step)
+    const uint32_t nclr = max(nch, 2u * nsub_next);
+    if (tid == 0) {
+      S.nbigc = 0;
+      S.anytie = 0;
+    }
+    for (uint32_t c = tid; c < nclr; c += BLOCK) {
+      if (c >= nch) {
+        S.ccnt[c] = 0;
+        S.cmax[c] = 0ull;
+        S.ctie[c] = 0;
+        continue;
+      }
       const uint32_t n = S.ccnt[c];
       const uint32_t s = c >> 1, side = c & 1u;
       const uint32_t parent = S.snode[cb][s];
@@ -1547,6 +1562,9 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
         S.sr[cb ^ 1][ns] = S.cwin[c];
         S.snode[cb ^ 1][ns] = v;
       }
+      S.ccnt[c] = 0;
+      S.cmax[c] = 0ull;
+      S.ctie[c] = 0;
     }
     nlvl += 1;
     if (tid == 0) S.lvl[nlvl] = (uint16_t)nnode;  // read after the loop

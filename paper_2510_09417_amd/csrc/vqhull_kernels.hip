@@ -101,6 +101,15 @@ __device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
+// A point (x, y) as one 16-byte value: one load from interleaved input or LDS.
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ dbl2 d2(double x, double y) {
+  dbl2 r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+
 // Values that are the same in every lane (a segment's triangle and range, read
 // once per run of tiles) are moved to scalar registers: the loads go through
 // the vector memory path, since the compiler cannot prove that the kernel's
@@ -1300,7 +1309,7 @@ constexpr uint32_t kSmallChild = 32;  // children up to this size are reduced by
 
 template <int BLOCK, int TMAX>
 struct FinishShared {
-  double lx[TMAX + 3], ly[TMAX + 3];
+  dbl2 lp[TMAX + 3];  // coordinates: the job's points, then a, b and r
   uint32_t lid[TMAX + 3];
   uint32_t ord[2][TMAX];
   uint16_t sa[2][TMAX / 2], sr[2][TMAX / 2], sb[2][TMAX / 2], snode[2][TMAX / 2];
@@ -1334,20 +1343,16 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
   for (uint32_t l = tid; l < cnt; l += BLOCK) {
     const uint32_t pos = job.beg + l;
     const double xv = X[pos], yv = Y[pos];
-    S.lx[l] = xv;
-    S.ly[l] = yv;
+    S.lp[l] = d2(xv, yv);
     S.lid[l] = user ? pos - job.ibase : I[pos];
     S.ord[0][l] = l;
     if (user) bad |= !finite(xv) || !finite(yv);
   }
   if (bad) S.bad = 1;
   if (tid == 0) {
-    S.lx[cnt] = job.ax;
-    S.ly[cnt] = job.ay;
-    S.lx[cnt + 1] = job.bx;
-    S.ly[cnt + 1] = job.by;
-    S.lx[cnt + 2] = job.rx;
-    S.ly[cnt + 2] = job.ry;
+    S.lp[cnt] = d2(job.ax, job.ay);
+    S.lp[cnt + 1] = d2(job.bx, job.by);
+    S.lp[cnt + 2] = d2(job.rx, job.ry);
     S.lid[cnt + 2] = job.ri;
     S.sa[0][0] = (uint16_t)cnt;
     S.sb[0][0] = (uint16_t)(cnt + 1);
@@ -1393,15 +1398,17 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
         const uint32_t ent = S.ord[cb][e];
         const uint32_t s = ent >> 16, l = ent & 0xFFFFu;
         const uint32_t a = S.sa[cb][s], r = S.sr[cb][s], b = S.sb[cb][s];
-        const double ux = S.lx[l], uy = S.ly[l];
-        const double o1 = orient(S.lx[a], S.ly[a], S.lx[r], S.ly[r], ux, uy);
+        const dbl2 pu = S.lp[l], pa = S.lp[a], pr = S.lp[r];
+        const double ux = pu.x, uy = pu.y;
+        const double o1 = orient(pa.x, pa.y, pr.x, pr.y, ux, uy);
         uint32_t c = kNone;
         double key = 0.0;
         if (o1 > 0.0) {
           c = 2u * s;
           key = o1;
         } else {
-          const double o2 = orient(S.lx[r], S.ly[r], S.lx[b], S.ly[b], ux, uy);
+          const dbl2 pb = S.lp[b];
+          const double o2 = orient(pr.x, pr.y, pb.x, pb.y, ux, uy);
           if (o2 > 0.0) {
             c = 2u * s + 1u;
             key = o2;
@@ -1483,16 +1490,18 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
       const uint32_t s = c >> 1;
       const uint32_t ea = (c & 1u) ? S.sr[cb][s] : S.sa[cb][s];
       const uint32_t eb = (c & 1u) ? S.sb[cb][s] : S.sr[cb][s];
-      const double ex0 = S.lx[ea], ey0 = S.ly[ea], ex1 = S.lx[eb], ey1 = S.ly[eb];
+      const dbl2 pea = S.lp[ea], peb = S.lp[eb];
+      const double ex0 = pea.x, ey0 = pea.y, ex1 = peb.x, ey1 = peb.y;
       Cand best = no_cand();
       const uint32_t b0 = S.cbase[c];
       for (uint32_t e = 0; e < n; ++e) {
         const uint32_t l = S.ord[cb ^ 1][b0 + e] & 0xFFFFu;
-        const double kk = orient(ex0, ey0, ex1, ey1, S.lx[l], S.ly[l]);
+        const dbl2 pl = S.lp[l];
+        const double kk = orient(ex0, ey0, ex1, ey1, pl.x, pl.y);
         Cand o;
         o.k = kk;
-        o.x = S.lx[l];
-        o.y = S.ly[l];
+        o.x = pl.x;
+        o.y = pl.y;
         o.i = S.lid[l];
         o.pad = l;
         keep(best, o);
@@ -1507,16 +1516,18 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
       const uint32_t s = c >> 1;
       const uint32_t ea = (c & 1u) ? S.sr[cb][s] : S.sa[cb][s];
       const uint32_t eb = (c & 1u) ? S.sb[cb][s] : S.sr[cb][s];
-      const double ex0 = S.lx[ea], ey0 = S.ly[ea], ex1 = S.lx[eb], ey1 = S.ly[eb];
+      const dbl2 pea = S.lp[ea], peb = S.lp[eb];
+      const double ex0 = pea.x, ey0 = pea.y, ex1 = peb.x, ey1 = peb.y;
       Cand best = no_cand();
       const uint32_t b0 = S.cbase[c];
       for (uint32_t e = lane; e < n; e += 64) {
         const uint32_t l = S.ord[cb ^ 1][b0 + e] & 0xFFFFu;
-        const double kk = orient(ex0, ey0, ex1, ey1, S.lx[l], S.ly[l]);
+        const dbl2 pl = S.lp[l];
+        const double kk = orient(ex0, ey0, ex1, ey1, pl.x, pl.y);
         Cand o;
         o.k = kk;
-        o.x = S.lx[l];
-        o.y = S.ly[l];
+        o.x = pl.x;
+        o.y = pl.y;
         o.i = S.lid[l];
         o.pad = l;
         keep(best, o);
@@ -1614,7 +1625,7 @@ constexpr size_t finish_plan_lds() {
 
 template <int BLOCK, int TMAX>
 __global__ __launch_bounds__(BLOCK) void k_finish_plan(FinishArgs A, PlanArgs P) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   if (blockIdx.x == 0) {
     plan_level<BLOCK>(P, *reinterpret_cast<PlanLds<BLOCK>*>(smem_raw));
     return;
@@ -1655,7 +1666,7 @@ __device__ __forceinline__ bool small_after(double xa, double ya, uint32_t ia, d
 template <int BLOCK, int TMAX>
 __global__ __launch_bounds__(BLOCK) void k_small(SmallArgs A) {
   constexpr int NW = BLOCK / 64;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   FinishShared<BLOCK, TMAX>& S = *reinterpret_cast<FinishShared<BLOCK, TMAX>*>(smem_raw);
   __shared__ double s_mn[2][NW], s_mx[2][NW];
   __shared__ uint32_t s_mni[NW], s_mxi[NW], s_bad;
@@ -1889,9 +1900,6 @@ __device__ __forceinline__ OctAcc oct_block(OctAcc a, OctAcc* s_w) {
     for (int i = 1; i < NW; ++i) oct_merge(a, s_w[i]);
   return a;
 }
-
-// Interleaved input: one 16-byte load per point.
-typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 template <int BLOCK, int PPT, int ITER, bool AOS>
 __global__ __launch_bounds__(BLOCK) void k_octagon(OctArgs A) {

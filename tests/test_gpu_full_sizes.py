@@ -71,6 +71,26 @@ def test_full_size_prefilter_bit_exact(vq, name):
     assert np.array_equal(got, plain)
 
 
+def test_full_size_interleaved_input(vq):
+    """Disk 1e8 from interleaved (x, y) input, plain and with the prefilter:
+    the same lists as the structure-of-arrays call (itself bit-exact against
+    the oracle in the tests above)."""
+    import torch
+
+    x, y = workloads.workload("disk_1e8")
+    tx, ty = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    xy = torch.stack([tx, ty], dim=1).contiguous()
+    del x, y
+    try:
+        for pf in (0, 1):
+            vq.set_config(prefilter=pf)
+            soa = vq.hull(tx, ty).cpu().numpy()
+            aos = vq.hull_xy(xy).cpu().numpy()
+            assert len(soa) == 1555 and np.array_equal(aos, soa), pf
+    finally:
+        vq.set_config(prefilter=0)
+
+
 def test_disk_1e6_repeated_and_reversed(vq):
     """The 10^6-point disk (seed 1) in the benchmark configuration, then with the
     tile order reversed: the same list both times."""

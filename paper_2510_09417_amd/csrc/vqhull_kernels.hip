@@ -402,14 +402,18 @@ __device__ __forceinline__ void flush_run(const SweepArgs& A, TilePart* part, ui
 // an inclusive prefix sum by DPP row shifts 1, 2, 4, 8 (within rows of 16
 // lanes) and row broadcasts of lanes 15 and 31; lane 63 ends with the total.
 // Lanes without a valid source add the zero passed as "old".
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
   v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
   v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
   v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
   v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
   v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
   v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+  return v;  // lane i: the sum over lanes 0..i
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)wave_scan_incl(v), 63);
 }
 
 // Argmax pass: add a run's subset sizes (per lane) to the segment's counter,
@@ -707,17 +711,9 @@ __device__ __forceinline__ void block_scan(const uint32_t (&v)[N], uint32_t (&ex
                                            uint32_t (*s_w)[BLOCK / 64]) {
   constexpr int NW = BLOCK / 64;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  uint32_t inc[N];
+  uint32_t inc[N];  // inclusive prefix within the wave (DPP row shifts and broadcasts)
 #pragma unroll
-  for (int j = 0; j < N; ++j) inc[j] = v[j];
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      const uint32_t o = __shfl_up(inc[j], d, 64);
-      if (lane >= d) inc[j] += o;
-    }
-  }
+  for (int j = 0; j < N; ++j) inc[j] = wave_scan_incl(v[j]);
   if (lane == 63) {
 #pragma unroll
     for (int j = 0; j < N; ++j) s_w[j][w] = inc[j];

@@ -95,6 +95,64 @@ __device__ __forceinline__ void wave_best(Cand& c) {
   }
 }
 
+// One DPP step of a wave maximum over doubles: the value from the lane the
+// control selects, or the lane's own where there is none (the halves move
+// separately).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_fmax(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = (int)(uint32_t)b, hi = (int)(uint32_t)(b >> 32);
+  const uint32_t olo = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xf, false);
+  const uint32_t ohi = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xf, false);
+  return fmax(v, __builtin_bit_cast(double, ((uint64_t)ohi << 32) | (uint64_t)olo));
+}
+
+__device__ __forceinline__ double readlane_d(double v, int src) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, src);
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
+  return __builtin_bit_cast(double, (hi << 32) | lo);
+}
+
+// Largest of a non-negative, non-NaN value over the (fully active) wave, in
+// every lane: DPP row shifts 1, 2, 4, 8 and row broadcasts of lanes 15 and
+// 31, then lane 63.
+__device__ __forceinline__ double wave_max_key(double v) {
+  v = dpp_fmax<0x111, 0xf>(v);  // row_shr:1
+  v = dpp_fmax<0x112, 0xf>(v);  // row_shr:2
+  v = dpp_fmax<0x114, 0xf>(v);  // row_shr:4
+  v = dpp_fmax<0x118, 0xf>(v);  // row_shr:8
+  v = dpp_fmax<0x142, 0xa>(v);  // row_bcast:15
+  v = dpp_fmax<0x143, 0xc>(v);  // row_bcast:31
+  return readlane_d(v, 63);
+}
+
+// Every lane ends with the wave's best candidate.  Candidates of members have
+// keys > 0, so when a single lane holds the wave's largest key its candidate
+// is the best and is read from that lane; only exact key ties between lanes
+// take the full reduction (among the tied lanes).
+__device__ __forceinline__ void wave_best_fast(Cand& c) {
+  const bool has = c.i != kNone;
+  const double kmax = wave_max_key(has ? c.k : 0.0);
+  const bool top = has & (c.k == kmax);
+  const unsigned long long m = __ballot(top);
+  if (m == 0ull) {
+    c = no_cand();
+    return;
+  }
+  if (__popcll(m) == 1) {
+    const int src = (int)__builtin_ctzll(m);
+    c.k = readlane_d(c.k, src);
+    c.x = readlane_d(c.x, src);
+    c.y = readlane_d(c.y, src);
+    c.i = (uint32_t)__builtin_amdgcn_readlane((int)c.i, src);
+    c.pad = (uint32_t)__builtin_amdgcn_readlane((int)c.pad, src);
+    return;
+  }
+  if (!top) c = no_cand();
+  wave_best(c);
+}
+
 __device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
@@ -365,12 +423,10 @@ __device__ __forceinline__ Cand to_cand(const SweepArgs& A, const Best& b, uint3
 // are ordered by the full tie-break.
 template <bool USER>
 __device__ __forceinline__ Cand wave_cand(const SweepArgs& A, const Best& b, uint32_t ibase) {
-  double kmax = b.k;  // keys are >= 0: no NaN
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) kmax = fmax(kmax, __shfl_xor(kmax, m, 64));
+  const double kmax = wave_max_key(b.k);  // keys are >= 0: no NaN
   Cand c = no_cand();
   if (b.pos != kNone && b.k == kmax) c = to_cand<USER>(A, b, ibase);
-  wave_best(c);
+  wave_best_fast(c);
   return c;
 }
 
@@ -738,7 +794,7 @@ template <int BLOCK>
 __device__ __forceinline__ Cand block_best(Cand c, Cand* s_c) {
   constexpr int NW = BLOCK / 64;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  wave_best(c);
+  wave_best_fast(c);
   if (lane == 0) s_c[w] = c;
   __syncthreads();
   Cand r = s_c[0];
@@ -1202,8 +1258,8 @@ __device__ void plan_level(const PlanArgs& A, PlanLds<PB>& L) {
         keep(m1, p.c[0]);
         keep(m2, p.c[1]);
       });
-      wave_best(m1);
-      wave_best(m2);
+      wave_best_fast(m1);
+      wave_best_fast(m2);
       if (lane == 0) {
         s_res[owner][0] = m1;
         s_res[owner][1] = m2;

@@ -13,6 +13,17 @@
 //               subproblems of the level in LDS.
 //   k_assemble  clockwise order from the recursion tree (Algorithm 1's
 //               unions, in the order p, Hull(S1), q, Hull(S2)).
+//   k_small     a single request small enough for the LDS finisher, whole in
+//               one launch.
+//   k_octagon, k_oct_plan, k_filter, k_filter_scan, k_compact
+//               the octagon prefilter (Section 6's Akl-Toussaint heuristic,
+//               a variant of the method): eight directional extremes, the
+//               points strictly inside their octagon dropped, the rest
+//               compacted into the workspace for the top-level passes.
+//   k_ingest, k_deinterleave
+//               interleaved (x, y) input copied into the workspace.
+//   k_gather, k_scatter
+//               the batching server's copies in and out of a lane's batch.
 //
 // Floating point: the orientation value must be bit-identical to the formula
 // evaluated operation by operation, so this file is compiled with

@@ -4,6 +4,17 @@
     python -m paper_2510_09417_amd.profiling traffic <fetch counter_collection.csv> <write counter_collection.csv>
             <out.json> <out.md> "<fetch command>" "<write command>" [elements of the probe, default 1e8]
 
+    python -m paper_2510_09417_amd.profiling hull-run <workload>
+    python -m paper_2510_09417_amd.profiling hull-bytes <out.md> "<fetch command>" "<write command>"
+            <workload> <fetch counter_collection.csv> <write counter_collection.csv> <hull-run output> [...]
+
+``hull-run`` is the GPU program the whole-hull counters are taken on: the
+STREAM-Scale probe, then two plain hull calls on the named workload, then one
+JSON line with the level statistics.  ``hull-bytes`` sums the calibrated
+counters of every library kernel of those calls and sets the measured bytes
+per input point beside the algorithmic bytes computed from the level
+statistics (``alg_bytes``).
+
 ``traffic`` calibrates the byte counters on the STREAM-Scale probe kernel, which
 reads and writes exactly 8 bytes per element: factor = known bytes / counted
 bytes, separately for FETCH_SIZE and WRITE_SIZE.  The fused sweep's counted
@@ -144,8 +155,99 @@ def traffic(fetch_csv: str, write_csv: str, out_json: str, out_md: str, fetch_cm
     return res
 
 
+HULL_RUN_CALLS = 2
+
+
+def hull_run(name: str) -> None:
+    """The program profiled for ``hull_bytes`` (see the module docstring)."""
+    import torch
+
+    import paper_2510_09417_amd as vq
+    from paper_2510_09417_amd import workloads
+
+    vq.load_library()
+    x, y = workloads.workload(name)
+    n = len(x)
+    tx, ty = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    del x, y
+    a = torch.empty(100_000_000, dtype=torch.float64, device="cuda").uniform_()
+    b = torch.empty_like(a)
+    vq.stream_scale(a, b, 3.0)
+    torch.cuda.synchronize()
+    del a, b
+    oi = torch.empty(n, dtype=torch.int64, device="cuda")
+    oc = torch.empty(1, dtype=torch.int64, device="cuda")
+    for _ in range(HULL_RUN_CALLS):
+        vq.hull_into(tx, ty, oi, oc)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": name, "n": n, "calls": HULL_RUN_CALLS, "h": int(oc.item()),
+                      "levels": vq.level_stats(), "config": vq.get_config()}), flush=True)
+
+
+def alg_bytes(n: int, levels: list) -> dict:
+    """Algorithmic bytes of one plain hull of a single request of more than
+    the LDS threshold's points, from its level statistics (level k: segments
+    swept and points of the jobs created):
+      extremes 8 B per point (x); argmax pass 16 B per point; fused pass 16 B
+      per point read, and 20 B written per point of the level-1 jobs (copies)
+      and of the level-2 segments and jobs (grandchildren); level k >= 2:
+      20 B read per swept point, 20 B written per point of level k+1's
+      segments and jobs; the LDS finisher reads 20 B per job point.
+    Vertex lists and the output (O(h)) are left out."""
+    sw = [lv["swept"] for lv in levels]
+    jp = [lv["job_points"] for lv in levels]
+    top = 8 * n + 16 * n + 16 * n
+    writes = 20 * ((jp[1] if len(jp) > 1 else 0) + sum(sw[k] + jp[k] for k in range(2, len(levels))))
+    level_reads = 20 * sum(sw[k] for k in range(2, len(levels)))
+    finisher = 20 * sum(jp[k] for k in range(1, len(levels)))
+    total = top + writes + level_reads + finisher
+    return {"top": top, "writes": writes, "level_reads": level_reads, "finisher_reads": finisher, "total": total}
+
+
+def hull_bytes(out_md: str, fetch_cmd: str, write_cmd: str, runs: list, probe_elems: float = 1e8) -> list:
+    """runs: (workload, fetch csv, write csv, hull-run output file) per workload."""
+    rows = []
+    for name, fcsv, wcsv, run_out in runs:
+        run = json.loads([ln for ln in open(run_out).read().splitlines() if ln.startswith("{")][-1])
+        fa, wa = _per_kernel(fcsv, "FETCH_SIZE"), _per_kernel(wcsv, "WRITE_SIZE")
+        is_probe = lambda k: PROBE in k
+        is_lib = lambda k: "vqh::" in k and PROBE not in k
+        mean = lambda v: sum(v) / len(v)
+        known = 8.0 * probe_elems
+        ff = known / (mean(_pick(fa, is_probe)) * 1024.0)
+        fw = known / (mean(_pick(wa, is_probe)) * 1024.0)
+        fetched = sum(_pick(fa, is_lib)) * 1024.0 * ff / run["calls"]
+        written = sum(_pick(wa, is_lib)) * 1024.0 * fw / run["calls"]
+        alg = alg_bytes(run["n"], run["levels"])
+        rows.append((name, run, fetched, written, alg))
+    lines = ["# Bytes per input point of one whole hull: rocprofv3 counters against the algorithmic bytes", "",
+             f"FETCH_SIZE command (per workload W): `{fetch_cmd}`", "",
+             f"WRITE_SIZE command (per workload W): `{write_cmd}`", "",
+             "Every library kernel of the two plain hull calls is summed (the probe and torch's own kernels "
+             "excluded) and divided by the two calls; the counters are calibrated on the STREAM-Scale probe "
+             "(known bytes / counted bytes, per counter).  Algorithmic bytes: "
+             "`paper_2510_09417_amd.profiling.alg_bytes` on the calls' level statistics.", "",
+             "| workload | n | h | levels | algorithmic (GB) | alg. B/pt | fetched (GB) | written (GB) | measured (GB) "
+             "| measured B/pt | measured / algorithmic |",
+             "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for name, run, fetched, written, alg in rows:
+        n = run["n"]
+        meas = fetched + written
+        lines.append(f"| {name} | {n} | {run['h']} | {len(run['levels'])} | {alg['total'] / 1e9:.3f} | "
+                     f"{alg['total'] / n:.1f} | {fetched / 1e9:.3f} | {written / 1e9:.3f} | {meas / 1e9:.3f} | "
+                     f"{meas / n:.1f} | {meas / alg['total']:.3f} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return rows
+
+
 if __name__ == "__main__":
-    if sys.argv[1] == "stats":
+    if sys.argv[1] == "hull-run":
+        hull_run(sys.argv[2])
+    elif sys.argv[1] == "hull-bytes":
+        rest = sys.argv[5:]
+        hull_bytes(sys.argv[2], sys.argv[3], sys.argv[4], [tuple(rest[i:i + 4]) for i in range(0, len(rest), 4)])
+    elif sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6], sys.argv[7],

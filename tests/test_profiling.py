@@ -71,3 +71,18 @@ def test_traffic_calibration(tmp_path):
     assert t["bytes_per_launch"] == 2 * 100 * 1024 + 50 * 1024
     assert t["kernel_source_sha256_16"] == P.kernel_source_hash()
     assert "fetch cmd" in out_md.read_text()
+
+
+def test_alg_bytes_counts_every_move():
+    from paper_2510_09417_amd import profiling
+
+    levels = [dict(segments=1, swept=100, jobs=0, job_points=0),   # roots
+              dict(segments=2, swept=90, jobs=1, job_points=5),    # children of the roots (not written)
+              dict(segments=2, swept=30, jobs=2, job_points=10),   # grandchildren (written by the fused pass)
+              dict(segments=0, swept=0, jobs=3, job_points=6)]     # written by the level-2 sweep
+    b = profiling.alg_bytes(100, levels)
+    assert b["top"] == (8 + 16 + 16) * 100
+    assert b["writes"] == 20 * (5 + 30 + 10 + 0 + 6)
+    assert b["level_reads"] == 20 * 30
+    assert b["finisher_reads"] == 20 * (5 + 10 + 6)
+    assert b["total"] == b["top"] + b["writes"] + b["level_reads"] + b["finisher_reads"]

@@ -14,6 +14,9 @@ Prints one JSON line:
               (16 B read per input point + 20 B written per kept point) over its
               average duration, from HIP events recorded on the launch stream
               during the timed steps, against 8 TB/s;
+  per_hull    each dataset's hull alone: HIP events on the launch stream
+              around the call (first kernel to the count written), 10 runs
+              after a warm-up, median and standard deviation.
   cpu_baseline  the CPU oracle (single thread) on one whole step.
   prefilter   the same step with the octagon prefilter on (Section 6's
               Akl-Toussaint heuristic, a variant of the method; outside the
@@ -419,6 +422,23 @@ def main() -> int:
                 per_kind[r["kind"]] = per_kind.get(r["kind"], 0.0) + r["ms"]
     torch.cuda.synchronize()
     vq.set_timing(False)
+    # per hull: events on the launch stream around each call (first kernel to
+    # the count written), 10 runs after one warm-up, median and spread
+    per_hull = {}
+    for name, (tx, ty), (oi, oc) in zip(names, dx, outs):
+        vq.hull_into(tx, ty, oi, oc, stream)
+        ms = []
+        for _ in range(10):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            vq.hull_into(tx, ty, oi, oc, stream)
+            e1.record(stream)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        med = float(np.median(ms))
+        per_hull[name] = {"median_ms": round(med, 4), "std_ms": round(float(np.std(ms)), 4),
+                          "gpoints_per_s": round(tx.numel() / (med * 1e-3) / 1e9, 3)}
+    log(f"per hull: {per_hull}")
     # energy per hull: the GPU's energy counter over ~2 s of steps, idle draw
     # subtracted (outside the timed region)
     from paper_2510_09417_amd import energy
@@ -506,6 +526,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernel_ms_per_step": {k: round(v / breakdown_steps, 4) for k, v in per_kind.items()},
+        "per_hull": per_hull,
         "energy": en,
         "prefilter": pre,
         "aos": aos,

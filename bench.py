@@ -503,9 +503,16 @@ def main() -> int:
         for _, x, y in data:
             oracle.hull(x, y)
         tc = time.perf_counter() - t0
+        model = "unknown"
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+        except OSError:
+            pass
         cpu = {"value": round(npts / tc / 1e9, 5), "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
                "sample": f"one whole step: {' + '.join(names)} ({npts} points), single-threaded C oracle, "
-                         f"{tc:.2f} s"}
+                         f"{tc:.2f} s",
+               "host": {"cpu_model": model, "logical_cpus": os.cpu_count()}}
         log(f"cpu oracle: {tc:.2f}s for one step")
 
     line = {

@@ -137,8 +137,9 @@ typedef struct {
                        maximum of x, y, x-y and x+y), with a margin above the rounding error of
                        the edge test, are dropped and Algorithm 1 runs on the rest.  Dropped
                        points lie strictly inside the hull, so in exact arithmetic the result
-                       is unchanged.  vqhull_hull and vqhull_hull_batched only (the server's
-                       lanes ignore it).  0: off (default). */
+                       is unchanged.  vqhull_hull, vqhull_hull_batched and their interleaved
+                       forms only (the server's lanes and the served tuner run the plain
+                       method).  0: off (default). */
 } vqhull_config;
 
 /* Read / replace the configuration used by later calls (host pointers). */

@@ -205,6 +205,18 @@ int vqhull_set_timing(int enable);
 int64_t vqhull_last_kernel_times(vqhull_kernel_time* out, int64_t cap);
 
 /*
+ * The orientation predicate of Section 2.1 as the kernels evaluate it, on n
+ * triples (for checking it against a host evaluation bit for bit).
+ *   abc   device array of 6n doubles: a.x, a.y, b.x, b.y, c.x, c.y per triple.
+ *   out   device array of 2n doubles: out[2i] = orient(a, b, c) =
+ *         fl(fl(fl(a.x-c.x)*fl(b.y-c.y)) - fl(fl(a.y-c.y)*fl(b.x-c.x))) as the
+ *         finisher and planners call it, out[2i+1] the same value in the form
+ *         the partition sweeps compute (differences to c formed first).
+ * Stream-ordered; VQHULL_ERR_INVALID_ARGUMENT for n < 0 or null pointers.
+ */
+int vqhull_orient(const double* abc, int64_t n, double* out, vqhull_stream_t stream);
+
+/*
  * HBM probe for the bandwidth context (the paper reports bandwidth as a share
  * of the STREAM "Scale" kernel, Section 5.1): out[i] = s * in[i] for
  * i < n, one read and one write of 8 bytes per element.

@@ -51,6 +51,8 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.vqhull_oracle_split.argtypes = [pd, pd, pi64, i64, i64, i64, i64, pi64, pi64, pi64, pi64, pi64]
     lib.vqhull_oracle_hull.restype = ctypes.c_int
     lib.vqhull_oracle_hull.argtypes = [pd, pd, i64, pi64, pi64]
+    lib.vqhull_oracle_orient_batch.restype = ctypes.c_int
+    lib.vqhull_oracle_orient_batch.argtypes = [pd, i64, pd]
     lib.vqhull_oracle_octagon.restype = ctypes.c_int
     lib.vqhull_oracle_octagon.argtypes = [pd, pd, i64, pi64, ctypes.POINTER(ctypes.c_uint8)]
     return lib
@@ -94,6 +96,18 @@ class OracleError(RuntimeError):
 def orient(ax, ay, bx, by, cx, cy, lib=None) -> float:
     """orient(a, b, c) > 0 iff c is strictly left of a->b (Section 2.1)."""
     return (lib or load()).vqhull_oracle_orient(ax, ay, bx, by, cx, cy)
+
+
+def orient_batch(abc, lib=None) -> np.ndarray:
+    """R1 on the rows of an (n, 6) array (a.x, a.y, b.x, b.y, c.x, c.y)."""
+    abc = np.ascontiguousarray(abc, dtype=np.float64)
+    if abc.ndim != 2 or abc.shape[1] != 6:
+        raise ValueError("abc must be an (n, 6) array")
+    out = np.empty(len(abc), dtype=np.float64)
+    st = (lib or load()).vqhull_oracle_orient_batch(_pd(abc), len(abc), _pd(out))
+    if st:
+        raise OracleError(st)
+    return out
 
 
 def extremes(x, y, lib=None) -> tuple[int, int]:

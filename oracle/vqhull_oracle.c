@@ -169,6 +169,16 @@ static int hull_rec(const double* x, const double* y, const int64_t* P, int64_t 
   return st;
 }
 
+/* R1 on n triples: abc holds a.x, a.y, b.x, b.y, c.x, c.y per triple. */
+int vqhull_oracle_orient_batch(const double* abc, int64_t n, double* out) {
+  if (n < 0 || (n > 0 && (!abc || !out))) return ORACLE_ERR_INVALID_ARGUMENT;
+  for (int64_t i = 0; i < n; ++i) {
+    const double* t = abc + 6 * i;
+    out[i] = vqhull_oracle_orient(t[0], t[1], t[2], t[3], t[4], t[5]);
+  }
+  return ORACLE_OK;
+}
+
 /* R4: p = lexmin (x, y, index); q = lexmax (x, y), lowest index among equals. */
 int vqhull_oracle_extremes(const double* x, const double* y, int64_t n, int64_t* p_out, int64_t* q_out) {
   if (n < 1 || !x || !y || !p_out || !q_out) return ORACLE_ERR_INVALID_ARGUMENT;

@@ -23,7 +23,7 @@ VQHULL_ERR_HIP = 4
 # Symbols that include/vqhull.h declares.
 EXPORTED = (
     "vqhull_hull", "vqhull_hull_batched", "vqhull_hull_xy", "vqhull_hull_batched_xy", "vqhull_get_config", "vqhull_set_config", "vqhull_autotune",
-    "vqhull_last_level_stats", "vqhull_set_timing", "vqhull_last_kernel_times", "vqhull_stream_scale",
+    "vqhull_last_level_stats", "vqhull_set_timing", "vqhull_last_kernel_times", "vqhull_orient", "vqhull_stream_scale",
     "vqhull_release_workspace", "vqhull_status_string", "vqhull_last_error",
     "vqhull_server_create", "vqhull_server_submit", "vqhull_server_submit_batch", "vqhull_server_wait", "vqhull_server_poll",
     "vqhull_server_drain", "vqhull_server_ticket_info", "vqhull_server_stats", "vqhull_server_destroy",
@@ -110,6 +110,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.vqhull_set_timing.argtypes = [ctypes.c_int]
         lib.vqhull_last_kernel_times.restype = i64
         lib.vqhull_last_kernel_times.argtypes = [ctypes.POINTER(KernelTime), i64]
+        lib.vqhull_orient.restype = ctypes.c_int
+        lib.vqhull_orient.argtypes = [vp, i64, vp, vp]
         lib.vqhull_stream_scale.restype = ctypes.c_int
         lib.vqhull_stream_scale.argtypes = [vp, vp, i64, ctypes.c_double, vp]
         lib.vqhull_release_workspace.restype = ctypes.c_int
@@ -326,6 +328,24 @@ def kernel_times() -> list[dict]:
     n = lib.vqhull_last_kernel_times(buf, n)
     return [dict(kind=KERNEL_KINDS[buf[i].kind], level=buf[i].level, ms=buf[i].ms, points_in=buf[i].points_in,
                  points_out=buf[i].points_out) for i in range(n)]
+
+
+def orient_batch(abc, stream=None):
+    """The kernels' orientation predicate on the triples abc (an (n, 6) float64
+    GPU tensor: a.x, a.y, b.x, b.y, c.x, c.y): returns an (n, 2) tensor, the
+    value as the finisher computes it and as the sweeps compute it."""
+    import torch
+
+    if not isinstance(abc, torch.Tensor) or abc.dtype != torch.float64 or not abc.is_cuda:
+        raise TypeError("abc must be a float64 GPU tensor")
+    if abc.dim() != 2 or abc.shape[1] != 6 or not abc.is_contiguous():
+        raise ValueError("abc must be a contiguous (n, 6) tensor")
+    lib = load_library()
+    out = torch.empty((abc.shape[0], 2), dtype=torch.float64, device=abc.device)
+    with torch.cuda.device(abc.device):
+        _check(lib, lib.vqhull_orient(ctypes.c_void_p(abc.data_ptr()), abc.shape[0], ctypes.c_void_p(out.data_ptr()),
+                                      _stream_handle(stream)))
+    return out
 
 
 def stream_scale(src, dst, s: float = 3.0, stream=None) -> None:

@@ -1033,6 +1033,16 @@ int64_t vqhull_last_level_stats(int64_t* out, int64_t cap) {
   return (int64_t)st.size();
 }
 
+int vqhull_orient(const double* abc, int64_t n, double* out, vqhull_stream_t stream) {
+  if (n < 0 || (n > 0 && (!abc || !out))) return VQHULL_ERR_INVALID_ARGUMENT;
+  const int e = launch_orient(abc, (uint64_t)n, out, stream);
+  if (e != 0) {
+    g_last_error = std::string("k_orient: ") + hipGetErrorString((hipError_t)e);
+    return VQHULL_ERR_HIP;
+  }
+  return VQHULL_OK;
+}
+
 int vqhull_stream_scale(const double* in, double* out, int64_t n, double s, vqhull_stream_t stream) {
   if (n < 0 || (n > 0 && (!in || !out))) return VQHULL_ERR_INVALID_ARGUMENT;
   const int e = launch_stream_scale(in, out, (uint64_t)n, s, stream);

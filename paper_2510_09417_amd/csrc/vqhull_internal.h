@@ -382,6 +382,9 @@ int launch_deinterleave(const double* xy, double* x, double* y, uint64_t n, void
 int launch_assemble(const AssembleArgs& a, void* stream);
 int launch_copy_lists(const AssembleArgs& a, void* stream);
 int launch_stream_scale(const double* in, double* out, uint64_t n, double s, void* stream);
+// The orientation predicate on n triples (abc: 6 doubles per triple; out: 2
+// doubles per triple, the two forms the kernels evaluate).
+int launch_orient(const double* abc, uint64_t n, double* out, void* stream);
 
 // Batching server: a request as the caller handed it in, placed at batch
 // offset off; a chunk is at most kServeChunk consecutive points of a request

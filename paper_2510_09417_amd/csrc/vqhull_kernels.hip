@@ -2421,6 +2421,21 @@ __global__ __launch_bounds__(256) void k_deinterleave(const double* __restrict__
   }
 }
 
+// The orientation predicate on n triples, in the two forms the kernels use:
+// orient() as the finisher and planners call it, and the sweeps' form that
+// forms a - u and b - u first (the same rounded operations in the same order).
+// out[2i] and out[2i+1] receive the two values of triple i.
+__global__ __launch_bounds__(256) void k_orient(const double* __restrict__ abc, uint64_t n, double* __restrict__ out) {
+  const uint64_t stride = (uint64_t)gridDim.x * 256u;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < n; i += stride) {
+    const double* t = abc + 6 * i;
+    const double ax = t[0], ay = t[1], bx = t[2], by = t[3], ux = t[4], uy = t[5];
+    out[2 * i] = orient(ax, ay, bx, by, ux, uy);
+    const double dax = ax - ux, day = ay - uy, dbx = bx - ux, dby = by - uy;
+    out[2 * i + 1] = dax * dby - day * dbx;
+  }
+}
+
 // ------------------------------------------------------------- k_assemble
 //
 // Clockwise order of every request: [p] ++ in-order(root), where the root's
@@ -2719,6 +2734,13 @@ int launch_ingest(const IngestArgs& a, void* stream) {
   if (a.ntiles == 0) return 0;
   hipLaunchKernelGGL((k_ingest<kOctBlock, kOctPPT, kOctIter>), dim3(a.ntiles), dim3(kOctBlock), 0,
                      (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int launch_orient(const double* abc, uint64_t n, double* out, void* stream) {
+  if (n == 0) return 0;
+  const uint64_t blocks = std::min<uint64_t>((n + 255u) / 256u, 256u * 32u);
+  hipLaunchKernelGGL(k_orient, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream, abc, n, out);
   return (int)hipGetLastError();
 }
 

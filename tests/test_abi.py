@@ -70,6 +70,9 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert lib.vqhull_hull_batched_xy(vp(0x1008), q, 1, dummy, dummy, None) == 1
     assert lib.vqhull_hull_batched_xy(None, q, 1, dummy, dummy, None) == 1
     assert lib.vqhull_hull_batched_xy(dummy, q, 1, None, dummy, None) == 1
+    assert lib.vqhull_orient(dummy, -1, dummy, None) == 1
+    assert lib.vqhull_orient(None, 3, dummy, None) == 1
+    assert lib.vqhull_orient(dummy, 3, None, None) == 1
     assert lib.vqhull_stream_scale(dummy, dummy, -1, 2.0, None) == 1
     assert lib.vqhull_stream_scale(None, dummy, 4, 2.0, None) == 1
     assert one[0] == 0

@@ -1,0 +1,88 @@
+"""Predicate parity: the orientation value the kernels compute (both forms:
+the finisher's and the sweeps') equals the oracle's bit for bit on about
+4*10^6 adversarial triples.  This pins one formula, rounded operation by
+operation, with no contraction into fused multiply-adds, gradual underflow
+(no flush to zero) and IEEE signed zeros.  A NaN result (only where huge
+inputs overflow) must be NaN on both sides; its bit pattern is not compared.
+
+Inputs:
+* near-collinear grids: the query point steps through 256 x 256 neighbouring
+  doubles around a base point while a and b are fixed far away on (almost)
+  the same line, the classic setting in which rounded orientation tests
+  contradict each other;
+* uniform triples; triples scaled to 1e-160 (products in the subnormal
+  range), to 1e150 (products near the top of the range) and to 1e160
+  (products overflow);
+* every combination of a small set of special values (signed zeros, the
+  smallest subnormal, one, minus one) and repeated points."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _grid(base, a, b):
+    bx, by = base
+    # 256 consecutive doubles upward from each base coordinate
+    x = [bx]
+    for _ in range(255):
+        x.append(np.nextafter(x[-1], np.inf))
+    y = [by]
+    for _ in range(255):
+        y.append(np.nextafter(y[-1], np.inf))
+    X, Y = np.meshgrid(np.array(x), np.array(y), indexing="ij")
+    t = np.empty((X.size, 6))
+    t[:, 0], t[:, 1], t[:, 2], t[:, 3] = a[0], a[1], b[0], b[1]
+    t[:, 4], t[:, 5] = X.ravel(), Y.ravel()
+    return t
+
+
+def _triples():
+    rng = np.random.default_rng(20)
+    parts = [
+        _grid((0.5, 0.5), (12.0, 12.0), (24.0, 24.0)),
+        _grid((0.5, 0.5), (17.300000000000001, 17.300000000000001), (24.00000000000005, 24.0000000000000053)),
+        _grid((0.50000000000002531, 0.5000000000001154), (8.8000000000000007, 7.7999999999999998),
+              (12.1, 12.1)),
+        _grid((1e-160, 1e-160), (3e-160, 3e-160), (7e-160, 7e-160)),
+    ]
+    r = rng.uniform(-1.0, 1.0, (1_000_000, 6))
+    parts += [r, r[:500_000] * 1e-160, r[:500_000] * 1e150, r[:200_000] * 1e160]
+    special = [0.0, -0.0, 5e-324, -5e-324, 1.0, -1.0]
+    combos = np.array(list(itertools.product(special, repeat=6)), dtype=np.float64)  # 46 656 triples
+    parts.append(combos)
+    pts = rng.uniform(-1.0, 1.0, (100_000, 2))
+    dup = np.empty((300_000, 6))
+    dup[:100_000] = np.hstack([pts, pts, rng.uniform(-1, 1, (100_000, 2))])  # a == b
+    dup[100_000:200_000] = np.hstack([pts, rng.uniform(-1, 1, (100_000, 2)), pts])  # a == c
+    dup[200_000:] = np.hstack([rng.uniform(-1, 1, (100_000, 2)), pts, pts])  # b == c
+    parts.append(dup)
+    return np.ascontiguousarray(np.vstack(parts))
+
+
+def test_orient_bit_for_bit():
+    import torch
+
+    import paper_2510_09417_amd as vq
+
+    abc = _triples()
+    want = oracle.orient_batch(abc)
+    got = vq.orient_batch(torch.from_numpy(abc).cuda()).cpu().numpy()
+    assert got.shape == (len(abc), 2)
+    wb = want.view(np.int64)
+    for form in (0, 1):
+        g = np.ascontiguousarray(got[:, form])
+        gb = g.view(np.int64)
+        both_nan = np.isnan(g) & np.isnan(want)
+        bad = (gb != wb) & ~both_nan
+        assert not bad.any(), (form, int(bad.sum()), abc[np.flatnonzero(bad)[:3]].tolist())
+        assert (np.isnan(g) == np.isnan(want)).all()
+    # the inputs reach the cases they are meant for
+    assert (want == 0.0).any() and (np.signbit(want) & (want == 0.0)).any()
+    tiny = np.abs(want[(want != 0.0) & np.isfinite(want)])
+    assert (tiny < 2.2250738585072014e-308).any()  # subnormal results
+    assert np.isinf(want).any() or np.isnan(want).any()

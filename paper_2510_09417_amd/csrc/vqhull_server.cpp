@@ -11,36 +11,25 @@
 // A request that arrives while batches are on the GPU is taken by the next
 // lane that frees up, so work of different batches overlaps on the device;
 // admission is by the lane's fixed device memory, sized once at creation, so
-// serving allocates nothing.
+// serving allocates nothing.  The tickets, the FIFO and its admission rule
+// live in serve_queue.h, which holds no GPU state.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
-#include <chrono>
-#include <condition_variable>
 #include <cstring>
-#include <deque>
-#include <mutex>
+#include <memory>
 #include <string>
 #include <thread>
 #include <vector>
 
 #include "../../include/vqhull.h"
+#include "serve_queue.h"
 #include "vqhull_internal.h"
 
 using namespace vqh;
 
 namespace {
-
-struct Ticket {
-  ServedReq r{};
-  int64_t n = 0;
-  double t_submit = 0, t_start = 0, t_done = 0;
-  int64_t batch = -1;
-  int32_t lane = -1;
-  int32_t status = VQHULL_OK;
-  bool done = false;
-};
 
 struct Lane {
   int index = 0;
@@ -76,20 +65,8 @@ struct vqhull_server {
   vqhull_server_config cfg{};
   int device = 0;
   int64_t max_chunks = 0;
-  std::chrono::steady_clock::time_point t0;
   std::vector<Lane*> lanes;
-  std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::deque<int64_t> pending;      // ticket ids, FIFO
-  std::vector<Ticket> tickets;      // by id
-  std::deque<int64_t> unpolled;     // completed, not yet returned by poll
-  bool stopping = false;
-  int64_t batches = 0, completed = 0, points = 0, failed = 0;
-  double busy = 0;  // summed batch wall time over lanes
-
-  double now() const {
-    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  }
+  std::unique_ptr<ServeQueue<ServedReq>> q;  // tickets, FIFO admission, completion
 };
 
 namespace {
@@ -264,53 +241,15 @@ void lane_loop(vqhull_server* s, Lane* L) {
   (void)hipSetDevice(s->device);
   std::vector<int64_t> ids;
   std::vector<ServedReq> reqs;
-  for (;;) {
-    ids.clear();
-    reqs.clear();
-    {
-      std::unique_lock<std::mutex> lk(s->mu);
-      s->cv_work.wait(lk, [&] { return s->stopping || !s->pending.empty(); });
-      if (s->pending.empty()) return;  // stopping, nothing left
-      int64_t pts = 0;
-      while (!s->pending.empty() && (int64_t)ids.size() < s->cfg.lane_requests) {
-        const Ticket& t = s->tickets[(size_t)s->pending.front()];
-        if (!ids.empty() && pts + t.n > s->cfg.lane_points) break;
-        pts += t.n;
-        ids.push_back(s->pending.front());
-        reqs.push_back(t.r);
-        s->pending.pop_front();
-      }
-      const double ts = s->now();
-      for (int64_t id : ids) {
-        s->tickets[(size_t)id].t_start = ts;
-        s->tickets[(size_t)id].lane = L->index;
-      }
-    }
-    const double tb = s->now();
+  std::vector<int32_t> status;
+  while (s->q->take(L->index, ids, reqs)) {
+    const double tb = s->q->now();
     const int st = run_batch(s, L, reqs);
-    const double te = s->now();
-    {
-      std::lock_guard<std::mutex> lk(s->mu);
-      const int64_t b = s->batches++;
-      s->busy += te - tb;
-      for (size_t i = 0; i < ids.size(); ++i) {
-        Ticket& t = s->tickets[(size_t)ids[i]];
-        t.batch = b;
-        t.t_done = te;
-        if (st != VQHULL_OK)
-          t.status = st;
-        else if (L->h_cnt[i] < 0)
-          t.status = (int32_t)(-L->h_cnt[i]);
-        else
-          t.status = VQHULL_OK;
-        if (t.status != VQHULL_OK) ++s->failed;
-        t.done = true;
-        s->points += t.n;
-        ++s->completed;
-        s->unpolled.push_back(ids[i]);
-      }
-    }
-    s->cv_done.notify_all();
+    const double te = s->q->now();
+    status.resize(ids.size());
+    for (size_t i = 0; i < ids.size(); ++i)
+      status[i] = st != VQHULL_OK ? st : L->h_cnt[i] < 0 ? (int32_t)(-L->h_cnt[i]) : VQHULL_OK;
+    s->q->complete(ids, status, tb, te);
   }
 }
 
@@ -327,7 +266,7 @@ int vqhull_server_create(const vqhull_server_config* cfg, vqhull_server** out) {
   *out = nullptr;
   vqhull_server* s = new vqhull_server();
   s->cfg = *cfg;
-  s->t0 = std::chrono::steady_clock::now();
+  s->q.reset(new ServeQueue<ServedReq>(cfg->lane_points, cfg->lane_requests));
   s->max_chunks = cfg->lane_points / kServeChunk + cfg->lane_requests + 1;
   if (hipGetDevice(&s->device) != hipSuccess) {
     delete s;
@@ -352,23 +291,13 @@ int vqhull_server_submit(vqhull_server* s, const double* x, const double* y, int
                          int64_t* out_count, int64_t* ticket) {
   if (!s || !ticket || !out_count || n < 0 || n > s->cfg.lane_points) return VQHULL_ERR_INVALID_ARGUMENT;
   if (n > 0 && (!x || !y || !out_idx)) return VQHULL_ERR_INVALID_ARGUMENT;
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stopping) return VQHULL_ERR_INVALID_ARGUMENT;
-    Ticket t;
-    t.r.x = x;
-    t.r.y = y;
-    t.r.out_idx = out_idx;
-    t.r.out_count = out_count;
-    t.r.n = (uint64_t)n;
-    t.n = n;
-    t.t_submit = s->now();
-    *ticket = (int64_t)s->tickets.size();
-    s->tickets.push_back(t);
-    s->pending.push_back(*ticket);
-  }
-  s->cv_work.notify_one();
-  return VQHULL_OK;
+  ServedReq r{};
+  r.x = x;
+  r.y = y;
+  r.out_idx = out_idx;
+  r.out_count = out_count;
+  r.n = (uint64_t)n;
+  return s->q->submit(&r, &n, 1, ticket) ? VQHULL_OK : VQHULL_ERR_INVALID_ARGUMENT;
 }
 
 int vqhull_server_submit_batch(vqhull_server* s, int64_t count, const double* const* x, const double* const* y,
@@ -380,59 +309,38 @@ int vqhull_server_submit_batch(vqhull_server* s, int64_t count, const double* co
     if (!out_count[i] || n[i] < 0 || n[i] > s->cfg.lane_points) return VQHULL_ERR_INVALID_ARGUMENT;
     if (n[i] > 0 && (!x[i] || !y[i] || !out_idx[i])) return VQHULL_ERR_INVALID_ARGUMENT;
   }
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stopping) return VQHULL_ERR_INVALID_ARGUMENT;
-    const double now = s->now();
-    *first_ticket = (int64_t)s->tickets.size();
-    for (int64_t i = 0; i < count; ++i) {
-      Ticket t;
-      t.r.x = x[i];
-      t.r.y = y[i];
-      t.r.out_idx = out_idx[i];
-      t.r.out_count = out_count[i];
-      t.r.n = (uint64_t)n[i];
-      t.n = n[i];
-      t.t_submit = now;
-      s->pending.push_back((int64_t)s->tickets.size());
-      s->tickets.push_back(t);
-    }
+  std::vector<ServedReq> r((size_t)count);
+  for (int64_t i = 0; i < count; ++i) {
+    r[(size_t)i].x = x[i];
+    r[(size_t)i].y = y[i];
+    r[(size_t)i].out_idx = out_idx[i];
+    r[(size_t)i].out_count = out_count[i];
+    r[(size_t)i].n = (uint64_t)n[i];
   }
-  s->cv_work.notify_all();
-  return VQHULL_OK;
+  return s->q->submit(r.data(), n, count, first_ticket) ? VQHULL_OK : VQHULL_ERR_INVALID_ARGUMENT;
 }
 
 int vqhull_server_wait(vqhull_server* s, int64_t ticket) {
   if (!s) return VQHULL_ERR_INVALID_ARGUMENT;
-  std::unique_lock<std::mutex> lk(s->mu);
-  if (ticket < 0 || ticket >= (int64_t)s->tickets.size()) return VQHULL_ERR_INVALID_ARGUMENT;
-  s->cv_done.wait(lk, [&] { return s->tickets[(size_t)ticket].done; });
-  return s->tickets[(size_t)ticket].status;
+  int32_t st = 0;
+  return s->q->wait(ticket, &st) ? st : VQHULL_ERR_INVALID_ARGUMENT;
 }
 
 int64_t vqhull_server_poll(vqhull_server* s, int64_t* tickets, int64_t cap) {
   if (!s || cap < 0 || (cap > 0 && !tickets)) return -VQHULL_ERR_INVALID_ARGUMENT;
-  std::lock_guard<std::mutex> lk(s->mu);
-  int64_t k = 0;
-  while (k < cap && !s->unpolled.empty()) {
-    tickets[k++] = s->unpolled.front();
-    s->unpolled.pop_front();
-  }
-  return k;
+  return s->q->poll(tickets, cap);
 }
 
 int vqhull_server_drain(vqhull_server* s) {
   if (!s) return VQHULL_ERR_INVALID_ARGUMENT;
-  std::unique_lock<std::mutex> lk(s->mu);
-  s->cv_done.wait(lk, [&] { return s->completed == (int64_t)s->tickets.size(); });
+  s->q->drain();
   return VQHULL_OK;
 }
 
 int vqhull_server_ticket_info(vqhull_server* s, int64_t ticket, vqhull_ticket_info* out) {
   if (!s || !out) return VQHULL_ERR_INVALID_ARGUMENT;
-  std::lock_guard<std::mutex> lk(s->mu);
-  if (ticket < 0 || ticket >= (int64_t)s->tickets.size()) return VQHULL_ERR_INVALID_ARGUMENT;
-  const Ticket& t = s->tickets[(size_t)ticket];
+  ServeQueue<ServedReq>::Ticket t;
+  if (!s->q->info(ticket, &t)) return VQHULL_ERR_INVALID_ARGUMENT;
   out->n = t.n;
   out->batch = t.batch;
   out->lane = t.lane;
@@ -446,15 +354,15 @@ int vqhull_server_ticket_info(vqhull_server* s, int64_t ticket, vqhull_ticket_in
 
 int vqhull_server_stats(vqhull_server* s, vqhull_server_counters* out) {
   if (!s || !out) return VQHULL_ERR_INVALID_ARGUMENT;
-  std::lock_guard<std::mutex> lk(s->mu);
-  out->submitted = (int64_t)s->tickets.size();
-  out->completed = s->completed;
-  out->failed = s->failed;
-  out->batches = s->batches;
-  out->points = s->points;
-  out->pending = (int64_t)s->pending.size();
-  out->busy_seconds = s->busy;
-  out->now = s->now();
+  const ServeQueue<ServedReq>::Counters c = s->q->counters();
+  out->submitted = c.submitted;
+  out->completed = c.completed;
+  out->failed = c.failed;
+  out->batches = c.batches;
+  out->points = c.points;
+  out->pending = c.pending;
+  out->busy_seconds = c.busy_seconds;
+  out->now = c.now;
   out->graph_batches = 0;
   out->plain_batches = 0;
   for (const Lane* L : s->lanes) {
@@ -466,11 +374,7 @@ int vqhull_server_stats(vqhull_server* s, vqhull_server_counters* out) {
 
 int vqhull_server_destroy(vqhull_server* s) {
   if (!s) return VQHULL_ERR_INVALID_ARGUMENT;
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->stopping = true;
-  }
-  s->cv_work.notify_all();
+  s->q->stop();
   for (Lane* L : s->lanes)
     if (L->th.joinable()) L->th.join();
   for (Lane* L : s->lanes) free_lane(L);

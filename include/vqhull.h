@@ -66,7 +66,8 @@ typedef enum {
   VQHULL_ERR_INVALID_ARGUMENT = 1, /* null pointer, negative size, bad offsets, n >= 2^31 */
   VQHULL_ERR_OUT_OF_MEMORY = 2,    /* device workspace could not be allocated */
   VQHULL_ERR_NONFINITE = 3,        /* a NaN or infinity in the input (reported per request) */
-  VQHULL_ERR_HIP = 4               /* a HIP runtime call failed; see vqhull_last_error() */
+  VQHULL_ERR_HIP = 4,              /* a HIP runtime call failed; see vqhull_last_error() */
+  VQHULL_ERR_TIMEOUT = 5           /* vqhull_server_wait_timeout: the request was not done in time */
 } vqhull_status;
 
 /* Stream handle: a hipStream_t passed as an opaque pointer (NULL = the default
@@ -315,6 +316,15 @@ int vqhull_server_submit_batch(vqhull_server* s, int64_t count, const double* co
 /* Block until the request is done; returns its status (VQHULL_OK,
  * VQHULL_ERR_NONFINITE, ...) or VQHULL_ERR_INVALID_ARGUMENT for an unknown ticket. */
 int vqhull_server_wait(vqhull_server* s, int64_t ticket);
+
+/* Watchdog form of vqhull_server_wait: wait at most `seconds` (0 = look once,
+ * without blocking).  Returns the request's status once done, or
+ * VQHULL_ERR_TIMEOUT if it is still queued or running at the deadline.  A
+ * timed-out request is not cancelled: it still completes and writes out_idx
+ * and out_count, so the caller keeps those buffers (and x, y) alive until a
+ * later wait, poll or drain reports it done.  VQHULL_ERR_INVALID_ARGUMENT for
+ * a null server, an unknown ticket, or seconds negative, NaN or above 10^6. */
+int vqhull_server_wait_timeout(vqhull_server* s, int64_t ticket, double seconds);
 
 /* Completed tickets not returned by an earlier poll, oldest first, up to cap;
  * returns how many were written (a negative status on bad arguments). */

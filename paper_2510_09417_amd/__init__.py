@@ -19,13 +19,15 @@ VQHULL_ERR_INVALID_ARGUMENT = 1
 VQHULL_ERR_OUT_OF_MEMORY = 2
 VQHULL_ERR_NONFINITE = 3
 VQHULL_ERR_HIP = 4
+VQHULL_ERR_TIMEOUT = 5
 
 # Symbols that include/vqhull.h declares.
 EXPORTED = (
     "vqhull_hull", "vqhull_hull_batched", "vqhull_hull_xy", "vqhull_hull_batched_xy", "vqhull_get_config", "vqhull_set_config", "vqhull_autotune",
     "vqhull_last_level_stats", "vqhull_set_timing", "vqhull_last_kernel_times", "vqhull_orient", "vqhull_stream_scale",
     "vqhull_release_workspace", "vqhull_status_string", "vqhull_last_error",
-    "vqhull_server_create", "vqhull_server_submit", "vqhull_server_submit_batch", "vqhull_server_wait", "vqhull_server_poll",
+    "vqhull_server_create", "vqhull_server_submit", "vqhull_server_submit_batch", "vqhull_server_wait", "vqhull_server_wait_timeout",
+    "vqhull_server_poll",
     "vqhull_server_drain", "vqhull_server_ticket_info", "vqhull_server_stats", "vqhull_server_destroy",
 )
 
@@ -129,6 +131,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.vqhull_server_submit_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, pi64]
         lib.vqhull_server_wait.restype = ci
         lib.vqhull_server_wait.argtypes = [vp, i64]
+        lib.vqhull_server_wait_timeout.restype = ci
+        lib.vqhull_server_wait_timeout.argtypes = [vp, i64, ctypes.c_double]
         lib.vqhull_server_poll.restype = i64
         lib.vqhull_server_poll.argtypes = [vp, pi64, i64]
         lib.vqhull_server_drain.restype = ci
@@ -431,6 +435,11 @@ class Server:
     def wait(self, ticket: int) -> int:
         """Block until the request is done; returns its status (0 = ok)."""
         return self._lib.vqhull_server_wait(self._h, ticket)
+
+    def wait_timeout(self, ticket: int, seconds: float) -> int:
+        """Wait at most ``seconds``; the request's status once done, else
+        VQHULL_ERR_TIMEOUT (the request still completes later)."""
+        return self._lib.vqhull_server_wait_timeout(self._h, ticket, float(seconds))
 
     def poll(self, cap: int = 4096) -> list:
         buf = (ctypes.c_int64 * cap)()

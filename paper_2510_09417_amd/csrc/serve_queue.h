@@ -121,6 +121,19 @@ class ServeQueue {
     return true;
   }
 
+  // As wait, for at most `seconds` (0: look once): 1 with the status once
+  // done, 0 if the ticket is still pending or running at the deadline (it is
+  // not cancelled and completes later), -1 for an unknown ticket.
+  int wait_for(int64_t ticket, double seconds, int32_t* status) {
+    std::unique_lock<std::mutex> lk(mu_);
+    if (ticket < 0 || ticket >= (int64_t)tickets_.size()) return -1;
+    const bool done = cv_done_.wait_for(lk, std::chrono::duration<double>(seconds),
+                                        [&] { return tickets_[(size_t)ticket].done; });
+    if (!done) return 0;
+    *status = tickets_[(size_t)ticket].status;
+    return 1;
+  }
+
   // Completed tickets not returned before, oldest first, up to cap.
   int64_t poll(int64_t* out, int64_t cap) {
     std::lock_guard<std::mutex> lk(mu_);

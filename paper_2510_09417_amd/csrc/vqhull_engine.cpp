@@ -1099,6 +1099,8 @@ const char* vqhull_status_string(int status) {
       return "non-finite coordinate in the input";
     case VQHULL_ERR_HIP:
       return "HIP runtime error";
+    case VQHULL_ERR_TIMEOUT:
+      return "request not done before the deadline";
     default:
       return "unknown status";
   }

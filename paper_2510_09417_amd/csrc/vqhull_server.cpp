@@ -326,6 +326,13 @@ int vqhull_server_wait(vqhull_server* s, int64_t ticket) {
   return s->q->wait(ticket, &st) ? st : VQHULL_ERR_INVALID_ARGUMENT;
 }
 
+int vqhull_server_wait_timeout(vqhull_server* s, int64_t ticket, double seconds) {
+  if (!s || !(seconds >= 0.0 && seconds <= 1e6)) return VQHULL_ERR_INVALID_ARGUMENT;
+  int32_t st = 0;
+  const int r = s->q->wait_for(ticket, seconds, &st);
+  return r > 0 ? st : r == 0 ? VQHULL_ERR_TIMEOUT : VQHULL_ERR_INVALID_ARGUMENT;
+}
+
 int64_t vqhull_server_poll(vqhull_server* s, int64_t* tickets, int64_t cap) {
   if (!s || cap < 0 || (cap > 0 && !tickets)) return -VQHULL_ERR_INVALID_ARGUMENT;
   return s->q->poll(tickets, cap);

@@ -8,7 +8,8 @@
 //   IN   int64 count, int64 n[count], then x and y of every request (float64,
 //        requests one after another)
 //   OUT  int64 header {count, submit_after_stop_rejected, unknown_ticket_rejected,
-//        polled}, the polled ticket ids in poll order, int64 counters
+//        polled, watchdog_early, watchdog_late, watchdog_unknown}, the polled
+//        ticket ids in poll order, int64 counters
 //        {submitted, completed, failed, batches, points, pending}, float64
 //        {busy_seconds, now}, then per ticket, in ticket order, int64
 //        {request from the payload, request from the submit's first ticket,
@@ -17,7 +18,11 @@
 // Requests are submitted by `submitters` threads, request i by thread
 // i % submitters in groups of `chunk` (chunk 1: one submit per request); each
 // lane sleeps delay_us per batch so that requests pile up.  stop_early: stop
-// the queue right after the last submit, before any wait.
+// the queue right after the last submit, before any wait.  Watchdog: the last
+// ticket is looked at once (zero timeout) right after the last submit, then
+// waited for with a 60 s timeout after the drain; the ticket after it (unknown)
+// with a short timeout.  Each records wait_for's result (1 done, 0 timed out,
+// -1 unknown ticket).
 #include <atomic>
 #include <chrono>
 #include <cstdint>
@@ -125,6 +130,8 @@ int main(int argc, char** argv) {
     });
   for (auto& t : subs) t.join();
   submitted_all = true;
+  int32_t wd_status = 0;
+  const int64_t wd_early = count > 0 ? q.wait_for(count - 1, 0.0, &wd_status) : -2;
 
   int64_t after_stop_rejected = 0;
   if (stop_early) {
@@ -143,6 +150,8 @@ int main(int argc, char** argv) {
   vqh::ServeQueue<Req>::Ticket probe;
   const int64_t unknown_rejected = (!q.wait(count, &dummy) && !q.wait(-1, &dummy) && !q.info(count, &probe)) ? 1 : 0;
   const auto c = q.counters();
+  const int64_t wd_late = count > 0 ? q.wait_for(count - 1, 60.0, &wd_status) : -2;
+  const int64_t wd_unknown = q.wait_for(count, 0.01, &wd_status);
   if (!stop_early) {
     q.stop();
     for (auto& t : lane_threads) t.join();
@@ -154,8 +163,9 @@ int main(int argc, char** argv) {
 
   FILE* out = fopen(argv[2], "wb");
   if (!out) return 5;
-  const int64_t head[4] = {count, after_stop_rejected, unknown_rejected, (int64_t)polled.size()};
-  fwrite(head, 8, 4, out);
+  const int64_t head[7] = {count, after_stop_rejected, unknown_rejected, (int64_t)polled.size(),
+                           wd_early, wd_late, wd_unknown};
+  fwrite(head, 8, 7, out);
   fwrite(polled.data(), 8, polled.size(), out);
   const int64_t ci[6] = {c.submitted, c.completed, c.failed, c.batches, c.points, c.pending};
   const double cd[2] = {c.busy_seconds, c.now};

@@ -89,7 +89,7 @@ def test_timing_modes_on_host(lib):
 
 
 def test_status_strings(lib):
-    for code in range(5):
+    for code in range(6):
         assert lib.vqhull_status_string(code)
     assert b"unknown" in lib.vqhull_status_string(99)
 
@@ -141,6 +141,8 @@ def test_server_arguments_rejected_on_host(lib):
     assert lib.vqhull_server_submit(None, dummy, dummy, 5, dummy, dummy, ctypes.byref(t)) == 1
     assert lib.vqhull_server_submit_batch(None, 1, dummy, dummy, dummy, dummy, dummy, ctypes.byref(t)) == 1
     assert lib.vqhull_server_wait(None, 0) == 1
+    lib.vqhull_server_wait_timeout.argtypes = [vp, ctypes.c_int64, ctypes.c_double]
+    assert lib.vqhull_server_wait_timeout(None, 0, 1.0) == 1
     assert lib.vqhull_server_poll(None, None, 0) == -1
     assert lib.vqhull_server_drain(None) == 1
     assert lib.vqhull_server_ticket_info(None, 0, None) == 1

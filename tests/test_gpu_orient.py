@@ -1,6 +1,6 @@
 """Predicate parity: the orientation value the kernels compute (both forms:
 the finisher's and the sweeps') equals the oracle's bit for bit on about
-4*10^6 adversarial triples.  This pins one formula, rounded operation by
+10^7 adversarial triples.  This pins one formula, rounded operation by
 operation, with no contraction into fused multiply-adds, gradual underflow
 (no flush to zero) and IEEE signed zeros.  A NaN result (only where huge
 inputs overflow) must be NaN on both sides; its bit pattern is not compared.
@@ -9,7 +9,8 @@ Inputs:
 * near-collinear grids: the query point steps through 256 x 256 neighbouring
   doubles around a base point while a and b are fixed far away on (almost)
   the same line, the classic setting in which rounded orientation tests
-  contradict each other;
+  contradict each other: four hand-picked grids and 80 more along seeded
+  random directions through base points of magnitude 1e-3 to 1e3;
 * uniform triples; triples scaled to 1e-160 (products in the subnormal
   range), to 1e150 (products near the top of the range) and to 1e160
   (products overflow);
@@ -50,8 +51,17 @@ def _triples():
               (12.1, 12.1)),
         _grid((1e-160, 1e-160), (3e-160, 3e-160), (7e-160, 7e-160)),
     ]
-    r = rng.uniform(-1.0, 1.0, (1_000_000, 6))
-    parts += [r, r[:500_000] * 1e-160, r[:500_000] * 1e150, r[:200_000] * 1e160]
+    for k in range(80):
+        # a and b on the ray from the base point at a random angle (rounded to doubles)
+        mag = 10.0 ** rng.uniform(-3, 3)
+        base = (float(mag * rng.uniform(0.5, 1.0)), float(mag * rng.uniform(0.5, 1.0)))
+        th = rng.uniform(0, 2 * np.pi)
+        d = (np.cos(th) * mag, np.sin(th) * mag)
+        a = (base[0] + 11.5 * d[0], base[1] + 11.5 * d[1])
+        b = (base[0] + 23.5 * d[0], base[1] + 23.5 * d[1])
+        parts.append(_grid(base, a, b) if k % 2 == 0 else _grid(base, b, a))
+    r = rng.uniform(-1.0, 1.0, (3_000_000, 6))
+    parts += [r, r[:1_000_000] * 1e-160, r[:1_000_000] * 1e150, r[:500_000] * 1e160]
     special = [0.0, -0.0, 5e-324, -5e-324, 1.0, -1.0]
     combos = np.array(list(itertools.product(special, repeat=6)), dtype=np.float64)  # 46 656 triples
     parts.append(combos)
@@ -70,6 +80,7 @@ def test_orient_bit_for_bit():
     import paper_2510_09417_amd as vq
 
     abc = _triples()
+    assert len(abc) > 10_000_000
     want = oracle.orient_batch(abc)
     got = vq.orient_batch(torch.from_numpy(abc).cuda()).cpu().numpy()
     assert got.shape == (len(abc), 2)

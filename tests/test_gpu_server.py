@@ -238,3 +238,31 @@ def test_prefilter_setting_does_not_reach_the_lanes(vq):
     for k, ((x, y, _, _), a, b) in enumerate(zip(data, got_p, got_g)):
         want = oracle.hull(x, y)
         assert np.array_equal(a, want) and np.array_equal(b, want), f"request {k}"
+
+
+def test_wait_timeout_watchdog(vq):
+    """The bounded wait: a request queued behind several batches on one lane is
+    not done right after submission (timeout reported, nothing cancelled); a
+    long enough bound returns its status, and its hull is the oracle's."""
+    import torch
+
+    data = []
+    for i in range(16):
+        x, y = workloads.points(workloads.DISTRIBUTIONS[i % 4], 400_000, seed=[15, i])
+        tx, ty = _device(x, y)
+        data.append((x, y, tx, ty, torch.empty(400_000, dtype=torch.int64, device="cuda"),
+                     torch.empty(1, dtype=torch.int64, device="cuda")))
+    torch.cuda.synchronize()
+    with vq.Server(lanes=1, lane_points=400_000, lane_requests=4) as srv:
+        tickets = [srv.submit(tx, ty, oi, oc) for (_, _, tx, ty, oi, oc) in data]
+        # 16 batches of one request each are ahead of the last ticket
+        assert srv.wait_timeout(tickets[-1], 0.0) == vq.VQHULL_ERR_TIMEOUT
+        assert srv.wait_timeout(tickets[-1], 120.0) == vq.VQHULL_OK
+        assert srv.wait_timeout(tickets[0], 0.0) == vq.VQHULL_OK  # done long before
+        for bad in (-1.0, float("nan"), 2e6):
+            assert srv.wait_timeout(tickets[0], bad) == vq.VQHULL_ERR_INVALID_ARGUMENT
+        assert srv.wait_timeout(tickets[-1] + 1, 0.01) == vq.VQHULL_ERR_INVALID_ARGUMENT
+        srv.drain()
+        assert srv.stats()["completed"] == 16
+    for x, y, _, _, oi, oc in data:
+        assert np.array_equal(oi[:int(oc.item())].cpu().numpy(), oracle.hull(x, y))

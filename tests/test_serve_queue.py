@@ -14,7 +14,9 @@ driven by host lane threads whose executor is the oracle's hull
 * the counters agree with the tickets; busy time is bounded by the batches'
   spans;
 * after stop, pending work still completes and new submissions are refused;
-  unknown tickets are refused."""
+  unknown tickets are refused;
+* the watchdog wait (bounded in time) reports a timeout while a request is
+  still queued or running and its status once done."""
 import os
 import shutil
 import subprocess
@@ -78,8 +80,8 @@ def run(exe, tmp_path, reqs, lanes, lane_points, lane_requests, submitters=1, ch
     subprocess.run([exe, str(inp), str(outp), str(lanes), str(lane_points), str(lane_requests), str(submitters),
                     str(chunk), str(delay_us), str(int(stop_early))], check=True, timeout=120)
     buf = np.fromfile(outp, dtype=np.int64)
-    count, stop_rejected, unknown_rejected, npolled = (int(v) for v in buf[:4])
-    pos = 4
+    count, stop_rejected, unknown_rejected, npolled, wd_early, wd_late, wd_unknown = (int(v) for v in buf[:7])
+    pos = 7
     polled = buf[pos: pos + npolled]
     pos += npolled
     counters = dict(zip(("submitted", "completed", "failed", "batches", "points", "pending"),
@@ -98,7 +100,7 @@ def run(exe, tmp_path, reqs, lanes, lane_points, lane_requests, submitters=1, ch
                             wait=v[7], idx=idx, t_submit=ts[0], t_start=ts[1], t_done=ts[2]))
     assert pos == len(buf)
     return dict(count=count, stop_rejected=stop_rejected, unknown_rejected=unknown_rejected, polled=polled,
-                counters=counters, tickets=tickets)
+                counters=counters, tickets=tickets, wd_early=wd_early, wd_late=wd_late, wd_unknown=wd_unknown)
 
 
 def check(res, reqs, lanes, lane_points, lane_requests, delay_us=0):
@@ -106,6 +108,9 @@ def check(res, reqs, lanes, lane_points, lane_requests, delay_us=0):
     T = res["tickets"]
     assert res["count"] == count == len(T)
     assert res["stop_rejected"] == 1 and res["unknown_rejected"] == 1
+    # watchdog: a bounded wait returns once done, refuses unknown tickets
+    assert res["wd_unknown"] == -1
+    assert res["wd_late"] == (1 if count else -2)
     # results: each ticket carries its own request, done once, with its own hull
     nonfinite = [not (np.isfinite(x).all() and np.isfinite(y).all()) for x, y in reqs]
     for t, k in enumerate(T):
@@ -206,6 +211,18 @@ def test_stop_with_pending_work(fake_serve, tmp_path):
     res = run(fake_serve, tmp_path, reqs, lanes=2, lane_points=8000, lane_requests=6, submitters=2, chunk=9,
               delay_us=500, stop_early=True)
     check(res, reqs, 2, 8000, 6, delay_us=500)
+
+
+def test_watchdog_times_out_on_a_slow_lane(fake_serve, tmp_path):
+    """A lane that takes 0.3 s per batch: the last of 12 requests cannot be
+    done right after submission, so the zero-timeout look reports a timeout;
+    the request is not cancelled and completes with its own hull."""
+    reqs = make_requests(12, 1000, seed=11)
+    res = run(fake_serve, tmp_path, reqs, lanes=1, lane_points=1 << 20, lane_requests=4, chunk=12,
+              delay_us=300_000)
+    assert res["wd_early"] == 0
+    by_batch = check(res, reqs, 1, 1 << 20, 4, delay_us=300_000)
+    assert len(by_batch) == 3
 
 
 def test_no_requests(fake_serve, tmp_path):

@@ -71,15 +71,16 @@ def _tiny_lattice_cases(count, seed0):
 
 
 def test_brute_force_tiny_lattices(oracle_lib):
-    """Oracle equals the O(u^3) brute-force hull on 1500 seeded lattice inputs."""
-    for k, (x, y) in _tiny_lattice_cases(1500, 7):
+    """Oracle equals the O(u^3) brute-force hull on 10^4 seeded lattice inputs."""
+    for k, (x, y) in _tiny_lattice_cases(10_000, 7):
         want = pins.brute_force_hull(x, y)
         got = oracle.hull(x, y, lib=oracle_lib).tolist()
         assert got == want, f"case {k}: n={len(x)}"
 
 
 @pytest.mark.parametrize("n,hi,seed", [(1000, 7, 1), (10_000, 100, 2), (100_000, 2**20 - 1, 3),
-                                       (300_000, 1000, 4), (200_000, 2**24 - 1, 5)])
+                                       (300_000, 1000, 4), (200_000, 2**24 - 1, 5),
+                                       (1_000_000, 2**20 - 1, 6)])
 def test_andrew_lattices(n, hi, seed, oracle_lib):
     x, y = workloads.lattice(n, seed=seed, lo=-hi, hi=hi, dup_frac=0.05, collinear_runs=4)
     assert oracle.hull(x, y, lib=oracle_lib).tolist() == pins.andrew_hull(x, y)

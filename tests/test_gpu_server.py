@@ -266,3 +266,34 @@ def test_wait_timeout_watchdog(vq):
         assert srv.stats()["completed"] == 16
     for x, y, _, _, oi, oc in data:
         assert np.array_equal(oi[:int(oc.item())].cpu().numpy(), oracle.hull(x, y))
+
+
+def test_tiny_budget_completes_every_request(vq):
+    """Lanes of 4096 points and 3 requests: admission is bound by the budget
+    (many batches, a request that fills a lane goes alone) and every request
+    still completes with the oracle's hull."""
+    import torch
+
+    rng = np.random.default_rng(16)
+    sizes = list(rng.integers(0, 4097, 150)) + [4096, 4096, 0, 1, 2, 3]
+    data = []
+    for i, n in enumerate(sizes):
+        x, y = workloads.points(workloads.DISTRIBUTIONS[i % 4], int(n), seed=[16, i])
+        tx, ty = _device(x, y)
+        data.append((x, y, tx, ty, torch.empty(max(int(n), 1), dtype=torch.int64, device="cuda"),
+                     torch.empty(1, dtype=torch.int64, device="cuda")))
+    torch.cuda.synchronize()
+    with vq.Server(lanes=2, lane_points=4096, lane_requests=3) as srv:
+        tickets = [srv.submit(tx, ty, oi, oc) for (_, _, tx, ty, oi, oc) in data]
+        srv.drain()
+        st = srv.stats()
+        infos = [srv.info(t) for t in tickets]
+    assert st["completed"] == len(sizes) and st["failed"] == 0 and st["points"] == sum(int(n) for n in sizes)
+    batches = {}
+    for inf in infos:
+        batches.setdefault(inf["batch"], []).append(inf["n"])
+    assert st["batches"] == len(batches) >= len(sizes) // 3
+    for ns in batches.values():
+        assert len(ns) <= 3 and (len(ns) == 1 or sum(ns) <= 4096)
+    for x, y, _, _, oi, oc in data:
+        assert np.array_equal(oi[:int(oc.item())].cpu().numpy(), oracle.hull(x, y))

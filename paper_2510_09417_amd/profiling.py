@@ -5,6 +5,7 @@
             <out.json> <out.md> "<fetch command>" "<write command>" [elements of the probe, default 1e8]
 
     python -m paper_2510_09417_amd.profiling hull-run <workload>
+    python -m paper_2510_09417_amd.profiling size-sweep <out.md>
     python -m paper_2510_09417_amd.profiling hull-bytes <out.md> "<fetch command>" "<write command>"
             <workload> <fetch counter_collection.csv> <write counter_collection.csv> <hull-run output> [...]
 
@@ -184,6 +185,68 @@ def hull_run(name: str) -> None:
                       "levels": vq.level_stats(), "config": vq.get_config()}), flush=True)
 
 
+SIZE_SWEEP_SIZES = (10**5, 10**6, 10**7, 10**8, 10**9, 2**31 - 1)
+
+
+def size_sweep(out_md: str, dists=("disk", "square"), sizes=SIZE_SWEEP_SIZES, calls: int = 5) -> list:
+    """Per-hull time against n: for each distribution and size, points drawn
+    on the GPU (seeded torch generator), two warm-up calls, then the median of
+    ``calls`` plain hull calls timed with HIP events on the call's stream.
+    Writes a markdown table (time, Gpoints/s, algorithmic bytes per point and
+    their rate against 8 TB/s) and prints one JSON line per case."""
+    import torch
+
+    import paper_2510_09417_amd as vq
+    from paper_2510_09417_amd import workloads
+
+    vq.load_library()
+    rows = []
+    for dist in dists:
+        for n in sizes:
+            g = torch.Generator(device="cuda")
+            g.manual_seed(7)
+            x = torch.empty(n, dtype=torch.float64, device="cuda")
+            y = torch.empty(n, dtype=torch.float64, device="cuda")
+            workloads.device_points_into(dist, x, y, g)
+            oi = torch.empty(n, dtype=torch.int64, device="cuda")
+            oc = torch.empty(1, dtype=torch.int64, device="cuda")
+            for _ in range(2):
+                vq.hull_into(x, y, oi, oc)
+            ms = []
+            st = torch.cuda.current_stream()
+            for _ in range(calls):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(st)
+                vq.hull_into(x, y, oi, oc)
+                e1.record(st)
+                e1.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            ms.sort()
+            t = ms[len(ms) // 2]
+            alg = alg_bytes(n, vq.level_stats())["total"]
+            row = {"dist": dist, "n": n, "h": int(oc.item()), "median_ms": round(t, 4),
+                   "gpoints_per_s": round(n / t / 1e6, 2), "alg_bytes_per_point": round(alg / n, 1),
+                   "alg_gbs": round(alg / t / 1e6, 1)}
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+            del x, y, oi, oc
+            vq.release_workspace()
+            torch.cuda.empty_cache()
+    lines = ["# Per-hull time against the number of points (plain hull call, one MI355X)", "",
+             f"Command: `python3 -m paper_2510_09417_amd.profiling size-sweep {out_md}`", "",
+             f"Points drawn on the GPU (uniform disk and unit square, torch generator seed 7); two warm-up calls, then the "
+             f"median of {calls} calls timed with HIP events on the call's stream; benchmark configuration.  Algorithmic "
+             "bytes per point from the call's level statistics (`alg_bytes`); their rate is set against 8 TB/s.", "",
+             "| distribution | n | h | median ms | Gpoints/s | algorithmic B/pt | algorithmic GB/s | of 8 TB/s |",
+             "|---|---|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| {r['dist']} | {r['n']:,} | {r['h']} | {r['median_ms']:.3f} | {r['gpoints_per_s']:.1f} | "
+                     f"{r['alg_bytes_per_point']:.1f} | {r['alg_gbs']:.0f} | {r['alg_gbs'] / 8000:.2f} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return rows
+
+
 def alg_bytes(n: int, levels: list) -> dict:
     """Algorithmic bytes of one plain hull of a single request of more than
     the LDS threshold's points, from its level statistics (level k: segments
@@ -247,6 +310,8 @@ if __name__ == "__main__":
     elif sys.argv[1] == "hull-bytes":
         rest = sys.argv[5:]
         hull_bytes(sys.argv[2], sys.argv[3], sys.argv[4], [tuple(rest[i:i + 4]) for i in range(0, len(rest), 4)])
+    elif sys.argv[1] == "size-sweep":
+        size_sweep(sys.argv[2])
     elif sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":

@@ -229,9 +229,26 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
     }
 
 
+LEG_BLOCKS = 3
+
+
+def timed_blocks(torch, step, steps: int) -> list:
+    """Wall-clock seconds of LEG_BLOCKS blocks of ``steps`` steps each
+    (synchronized before and after every block)."""
+    walls = []
+    for _ in range(LEG_BLOCKS):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+    return walls
+
+
 def prefilter_leg(vq, torch, dx, outs, names, npts, step, args, plain) -> dict:
     """The step again with the octagon prefilter on: wall-clock throughput
-    over the same number of steps, equality of every hull with the plain
+    over the same number of steps (the median of three such blocks), equality of every hull with the plain
     path's, the points kept, and the bandwidth of the eight-direction extremes
     pass (16 B per point) and of the filter (16 B read per point, 20 B written
     per kept point) from HIP events on the launch stream."""
@@ -246,12 +263,8 @@ def prefilter_leg(vq, torch, dx, outs, names, npts, step, args, plain) -> dict:
             torch.cuda.synchronize()
             kept[name] = vq.level_stats()[0]["swept"]
         same = all(int(oc.item()) == len(p) and torch.equal(oi[: len(p)], p) for (oi, oc), p in zip(outs, plain))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        walls = timed_blocks(torch, step, args.steps)
+        wall = sorted(walls)[len(walls) // 2]
         vq.set_timing(True)
         per_kind, ext, filt = {}, [], []
         for _ in range(2):
@@ -275,6 +288,7 @@ def prefilter_leg(vq, torch, dx, outs, names, npts, step, args, plain) -> dict:
         "value": round(npts * args.steps / wall / 1e9, 4),
         "unit": "Gpoints/s",
         "ms_per_step": round(1e3 * wall / args.steps, 4),
+        "ms_per_step_blocks": [round(1e3 * w / args.steps, 4) for w in walls],
         "same_result_as_plain": bool(same),
         "kept_points": kept,
         "octagon_extremes_gbs": gbs(ext),
@@ -288,7 +302,7 @@ def prefilter_leg(vq, torch, dx, outs, names, npts, step, args, plain) -> dict:
 def aos_leg(vq, torch, dx, outs, npts, args, plain, stream) -> dict:
     """The step from interleaved input (one (n, 2) tensor per dataset),
     without and with the prefilter: wall-clock throughput over the same
-    number of steps and equality of every hull with the plain path's."""
+    number of steps (the median of three such blocks) and equality of every hull with the plain path's."""
     xys = [torch.stack([tx, ty], dim=1).contiguous() for tx, ty in dx]
     res = {}
     try:
@@ -303,13 +317,11 @@ def aos_leg(vq, torch, dx, outs, npts, args, plain, stream) -> dict:
                 step_xy()
             torch.cuda.synchronize()
             same = all(int(oc.item()) == len(p) and torch.equal(oi[: len(p)], p) for (oi, oc), p in zip(outs, plain))
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                step_xy()
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - t0
+            walls = timed_blocks(torch, step_xy, args.steps)
+            wall = sorted(walls)[len(walls) // 2]
             res["prefilter" if pf else "plain"] = {"value": round(npts * args.steps / wall / 1e9, 4), "unit": "Gpoints/s",
                                                    "ms_per_step": round(1e3 * wall / args.steps, 4),
+                                                   "ms_per_step_blocks": [round(1e3 * w / args.steps, 4) for w in walls],
                                                    "same_result_as_plain": bool(same)}
     finally:
         vq.set_config(prefilter=0)

@@ -33,7 +33,7 @@ Prints one JSON line:
               time-boxed prefix of the same mix; and a check that served results
               equal the plain path's on a sample.
 
-Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+Usage: python bench.py [--gpus 1] [--steps 50] [--warmup 3]
 """
 from __future__ import annotations
 
@@ -333,8 +333,8 @@ def aos_leg(vq, torch, dx, outs, npts, args, plain, stream) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-energy", action="store_true")

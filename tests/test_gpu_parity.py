@@ -240,3 +240,33 @@ def test_level0_sweep_sets_via_stats(vq):
     p, q = oracle.extremes(x, y)
     s1, s2, _, _ = oracle.split(x, y, np.arange(len(x)), p, q, p)
     assert st[1]["swept"] + st[1]["job_points"] == len(s1) + len(s2)
+
+
+@pytest.mark.parametrize("dist", ["disk", "square", "kuzmin"])
+def test_top_levels_against_oracle_splits(vq, dist):
+    """The first three levels' point counts against the oracle's splits: level
+    1 holds S1 and S2 (left of p->q and of q->p), level 2 the four
+    grandchildren cut by the triangles (p, r1, q) and (q, r2, p), so its
+    counts depend on the r1 and r2 the kernels chose.  A subset of one point
+    is a leaf (no sweep, no job); one of at most the LDS threshold's points
+    becomes an LDS job, finished whole (its own children never reach the
+    level statistics); larger ones are swept."""
+    x, y = workloads.points(dist, 1_000_000, seed=41)
+    gpu_hull(vq, x, y)
+    st = vq.level_stats()
+    lds = vq.get_config()["lds_limit"]
+    p, q = oracle.extremes(x, y)
+    s1, s2, r1, r2 = oracle.split(x, y, np.arange(len(x)), p, q, p)
+    live = lambda sets: sum(len(s) for s in sets if len(s) >= 2)
+    assert st[0]["swept"] == len(x)
+    assert st[1]["swept"] + st[1]["job_points"] == live([s1, s2])
+    grand = []
+    if len(s1) > lds:
+        a, b, _, _ = oracle.split(x, y, s1, p, r1, q)
+        grand += [a, b]
+    if len(s2) > lds:
+        a, b, _, _ = oracle.split(x, y, s2, q, r2, p)
+        grand += [a, b]
+    assert st[2]["swept"] + st[2]["job_points"] == live(grand), (st[2], [len(g) for g in grand])
+    big = [g for g in grand if len(g) > lds]
+    assert st[2]["segments"] == len(big) and st[2]["swept"] == sum(len(g) for g in big)

@@ -169,3 +169,21 @@ def test_config_has_prefilter_flag():
         assert vq.set_config(prefilter=0)["prefilter"] == 0
     finally:
         vq.set_config(**old)
+
+
+def test_status_constants_follow_the_header():
+    """The binding's status constants equal the header's vqhull_status enum,
+    and every status has its own text."""
+    import re
+
+    import paper_2510_09417_amd as vq
+
+    text = open(HEADER).read()
+    body = text[text.index("typedef enum {"): text.index("} vqhull_status;")]
+    enum = {m.group(1): int(m.group(2)) for m in re.finditer(r"(VQHULL_(?:OK|ERR_[A-Z_]+))\s*=\s*(\d+)", body)}
+    assert len(enum) >= 6
+    for name, value in enum.items():
+        assert getattr(vq, name) == value, name
+    lib = vq.load_library()
+    texts = {lib.vqhull_status_string(v) for v in enum.values()}
+    assert len(texts) == len(enum) and not any(b"unknown" in t for t in texts)

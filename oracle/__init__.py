@@ -23,7 +23,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 # The predicate must be evaluated exactly as written: no contraction into FMA,
 # no fast-math reassociation, binary64 SSE arithmetic.
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fno-unsafe-math-optimizations",
-          "-fPIC", "-shared"]
+          "-fPIC", "-shared", "-fopenmp"]
 
 ORACLE_OK = 0
 ORACLE_ERR_INVALID_ARGUMENT = 1
@@ -53,6 +53,8 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.vqhull_oracle_hull.argtypes = [pd, pd, i64, pi64, pi64]
     lib.vqhull_oracle_orient_batch.restype = ctypes.c_int
     lib.vqhull_oracle_orient_batch.argtypes = [pd, i64, pd]
+    lib.vqhull_oracle_hull_mt.restype = ctypes.c_int
+    lib.vqhull_oracle_hull_mt.argtypes = [pd, pd, i64, pi64, pi64, ctypes.c_int, i64]
     lib.vqhull_oracle_octagon.restype = ctypes.c_int
     lib.vqhull_oracle_octagon.argtypes = [pd, pd, i64, pi64, ctypes.POINTER(ctypes.c_uint8)]
     return lib
@@ -147,6 +149,23 @@ def hull(x, y, lib=None) -> np.ndarray:
     out = np.empty(max(n, 1), dtype=np.int64)
     cnt = ctypes.c_int64()
     st = (lib or load()).vqhull_oracle_hull(_pd(x), _pd(y), n, _pi(out), ctypes.byref(cnt))
+    if st:
+        raise OracleError(st)
+    return out[: cnt.value].copy()
+
+
+def hull_mt(x, y, threads: int = 0, grain: int = 0, lib=None) -> np.ndarray:
+    """The multithreaded form of ``hull`` (OpenMP, ``threads`` threads, 0 = all
+    the runtime offers; ``grain`` points per parallel chunk and smallest task,
+    0 = default): the same index list, computed on every core."""
+    x, y = _f64(x), _f64(y)
+    if x.shape != y.shape or x.ndim != 1:
+        raise ValueError("x and y must be 1-D arrays of equal length")
+    n = len(x)
+    out = np.empty(max(n, 1), dtype=np.int64)
+    cnt = ctypes.c_int64()
+    st = (lib or load()).vqhull_oracle_hull_mt(_pd(x), _pd(y), n, _pi(out), ctypes.byref(cnt), int(threads),
+                                               int(grain))
     if st:
         raise OracleError(st)
     return out[: cnt.value].copy()

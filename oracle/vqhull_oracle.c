@@ -41,6 +41,15 @@
  * The recursion is the plain recursive function of Algorithm 1; every call
  * allocates one buffer for its two subsets and frees it on return.
  *
+ * A multithreaded form of the same function (vqhull_oracle_hull_mt, OpenMP)
+ * serves as the all-core CPU baseline.  It computes exactly the same steps:
+ * the extremes and every partition are split into chunks of consecutive
+ * points whose partial results are combined in chunk order (so each subset
+ * lists its points in the same order as the sequential scan), and the two
+ * recursive calls of each step run as independent tasks whose vertex lists
+ * are joined in the order of R7.  Its result is identical to
+ * vqhull_oracle_hull's for any thread count.
+ *
  * Octagon prefilter (Section 6: the Akl-Toussaint heuristic the paper proposes
  * as future work).  A variant of the method first drops the points that lie
  * strictly inside the octagon spanned by eight directional extremes, then runs
@@ -75,8 +84,10 @@
  *       points (below it every point is kept).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
+#include <string.h>
 
 #define ORACLE_OK 0
 #define ORACLE_ERR_INVALID_ARGUMENT 1
@@ -321,4 +332,249 @@ int vqhull_oracle_octagon(const double* x, const double* y, int64_t n, int64_t* 
     keep[u] = (uint8_t)!inside;
   }
   return ORACLE_OK;
+}
+
+/* ------------------------------------------------ multithreaded form (OpenMP)
+ *
+ * The all-core CPU baseline.  Same rules R1-R8, same partition order, same
+ * result as vqhull_oracle_hull.  `grain` is the number of points per chunk of
+ * a parallel scan and the smallest subproblem that is handed to a task of its
+ * own (smaller ones run in the calling task).
+ */
+typedef struct {
+  int64_t n1, n2, r1, r2;
+  double k1, k2;
+} part_acc;
+
+/* The partition of P[lo, hi) for the triangle (a, r, b): sizes and farthest
+ * points of the two subsets over this chunk (R3, R5, R6). */
+static part_acc split_count(const double* x, const double* y, const int64_t* P, int64_t lo, int64_t hi, int64_t a,
+                            int64_t r, int64_t b) {
+  part_acc c = {0, 0, -1, -1, 0.0, 0.0};
+  for (int64_t j = lo; j < hi; ++j) {
+    int64_t u = P[j];
+    double o1 = vqhull_oracle_orient(x[a], y[a], x[r], y[r], x[u], y[u]);
+    if (o1 > 0.0) {
+      ++c.n1;
+      if (farther(x, y, o1, u, c.k1, c.r1)) {
+        c.k1 = o1;
+        c.r1 = u;
+      }
+      continue;
+    }
+    double o2 = vqhull_oracle_orient(x[r], y[r], x[b], y[b], x[u], y[u]);
+    if (o2 > 0.0) {
+      ++c.n2;
+      if (farther(x, y, o2, u, c.k2, c.r2)) {
+        c.k2 = o2;
+        c.r2 = u;
+      }
+    }
+  }
+  return c;
+}
+
+/* The chunk's subset members written at their places in the sequential
+ * layout: the j-th member of S1 at s[o1 + j], the j-th member of S2 at
+ * s[m - 1 - (o2 + j)]. */
+static void split_write(const double* x, const double* y, const int64_t* P, int64_t lo, int64_t hi, int64_t a,
+                        int64_t r, int64_t b, int64_t* s, int64_t m, int64_t o1, int64_t o2) {
+  for (int64_t j = lo; j < hi; ++j) {
+    int64_t u = P[j];
+    if (vqhull_oracle_orient(x[a], y[a], x[r], y[r], x[u], y[u]) > 0.0) {
+      s[o1++] = u;
+    } else if (vqhull_oracle_orient(x[r], y[r], x[b], y[b], x[u], y[u]) > 0.0) {
+      s[m - 1 - o2++] = u;
+    }
+  }
+}
+
+/* split() over chunks of `grain` points run as tasks: counts and farthest
+ * points per chunk, chunk offsets, then the members written. */
+static int split_mt(const double* x, const double* y, const int64_t* P, int64_t m, int64_t a, int64_t r, int64_t b,
+                    int64_t* s, int64_t grain, int64_t* n1, int64_t* n2, int64_t* r1, int64_t* r2) {
+  int64_t nch = (m + grain - 1) / grain;
+  part_acc* acc = (part_acc*)malloc((size_t)nch * sizeof(part_acc));
+  if (!acc) return ORACLE_ERR_OUT_OF_MEMORY;
+#pragma omp taskloop grainsize(1)
+  for (int64_t c = 0; c < nch; ++c) {
+    int64_t lo = c * grain, hi = lo + grain < m ? lo + grain : m;
+    acc[c] = split_count(x, y, P, lo, hi, a, r, b);
+  }
+  part_acc t = {0, 0, -1, -1, 0.0, 0.0};
+  for (int64_t c = 0; c < nch; ++c) {
+    int64_t c1 = acc[c].n1, c2 = acc[c].n2;
+    if (acc[c].r1 >= 0 && farther(x, y, acc[c].k1, acc[c].r1, t.k1, t.r1)) {
+      t.k1 = acc[c].k1;
+      t.r1 = acc[c].r1;
+    }
+    if (acc[c].r2 >= 0 && farther(x, y, acc[c].k2, acc[c].r2, t.k2, t.r2)) {
+      t.k2 = acc[c].k2;
+      t.r2 = acc[c].r2;
+    }
+    acc[c].n1 = t.n1; /* from here on: the chunk's offsets */
+    acc[c].n2 = t.n2;
+    t.n1 += c1;
+    t.n2 += c2;
+  }
+#pragma omp taskloop grainsize(1)
+  for (int64_t c = 0; c < nch; ++c) {
+    int64_t lo = c * grain, hi = lo + grain < m ? lo + grain : m;
+    split_write(x, y, P, lo, hi, a, r, b, s, m, acc[c].n1, acc[c].n2);
+  }
+  free(acc);
+  *n1 = t.n1;
+  *n2 = t.n2;
+  *r1 = t.r1;
+  *r2 = t.r2;
+  return ORACLE_OK;
+}
+
+/* Hull(P, a, r, b) into out[0 .. *len) (out has room for m entries): the two
+ * recursive calls write into the two ends of out, then the list
+ * Hull(S1) ++ [r] ++ Hull(S2) is joined at the front (R7).  S1 and S2 do not
+ * contain r, so n1 + 1 + n2 <= m and the join only moves entries forward. */
+static int hull_mt_rec(const double* x, const double* y, const int64_t* P, int64_t m, int64_t a, int64_t r,
+                       int64_t b, int64_t grain, int64_t* out, int64_t* len) {
+  *len = 0;
+  if (m <= 1) {
+    if (m == 1) out[(*len)++] = P[0];
+    return ORACLE_OK;
+  }
+  int64_t* s = (int64_t*)malloc((size_t)m * sizeof(int64_t));
+  if (!s) return ORACLE_ERR_OUT_OF_MEMORY;
+  int64_t n1, n2, r1, r2;
+  int st = ORACLE_OK, st1 = ORACLE_OK, st2 = ORACLE_OK;
+  if (m > 2 * grain) {
+    st = split_mt(x, y, P, m, a, r, b, s, grain, &n1, &n2, &r1, &r2);
+  } else {
+    split(x, y, P, m, a, r, b, s, &n1, &n2, &r1, &r2);
+  }
+  int64_t len1 = 0, len2 = 0;
+  if (st == ORACLE_OK) {
+    if (m > grain) {
+#pragma omp task shared(st1, len1)
+      st1 = hull_mt_rec(x, y, s, n1, a, r1, r, grain, out, &len1);
+#pragma omp task shared(st2, len2)
+      st2 = hull_mt_rec(x, y, s + (m - n2), n2, r, r2, b, grain, out + (m - n2), &len2);
+#pragma omp taskwait
+    } else {
+      st1 = hull_mt_rec(x, y, s, n1, a, r1, r, grain, out, &len1);
+      st2 = hull_mt_rec(x, y, s + (m - n2), n2, r, r2, b, grain, out + (m - n2), &len2);
+    }
+    st = st1 != ORACLE_OK ? st1 : st2;
+  }
+  free(s);
+  if (st != ORACLE_OK) return st;
+  out[len1] = r;
+  memmove(out + len1 + 1, out + (m - n2), (size_t)len2 * sizeof(int64_t));
+  *len = len1 + 1 + len2;
+  return ORACLE_OK;
+}
+
+/* R4 over chunks, combined in chunk order with the same strict comparisons,
+ * so the first of equal points wins as in the sequential scan. */
+static void extremes_mt(const double* x, const double* y, int64_t n, int64_t grain, int64_t* p_out, int64_t* q_out) {
+  int64_t nch = (n + grain - 1) / grain;
+  int64_t* pq = (int64_t*)malloc((size_t)(2 * nch) * sizeof(int64_t));
+  if (!pq) { /* fall back to one scan */
+    vqhull_oracle_extremes(x, y, n, p_out, q_out);
+    return;
+  }
+#pragma omp taskloop grainsize(1)
+  for (int64_t c = 0; c < nch; ++c) {
+    int64_t lo = c * grain, hi = lo + grain < n ? lo + grain : n;
+    int64_t p = lo, q = lo;
+    for (int64_t i = lo + 1; i < hi; ++i) {
+      if (x[i] < x[p] || (x[i] == x[p] && y[i] < y[p])) p = i;
+      if (x[i] > x[q] || (x[i] == x[q] && y[i] > y[q])) q = i;
+    }
+    pq[2 * c] = p;
+    pq[2 * c + 1] = q;
+  }
+  int64_t p = pq[0], q = pq[1];
+  for (int64_t c = 1; c < nch; ++c) {
+    int64_t i = pq[2 * c], j = pq[2 * c + 1];
+    if (x[i] < x[p] || (x[i] == x[p] && y[i] < y[p])) p = i;
+    if (x[j] > x[q] || (x[j] == x[q] && y[j] > y[q])) q = j;
+  }
+  free(pq);
+  *p_out = p;
+  *q_out = q;
+}
+
+static int hull_mt_top(const double* x, const double* y, int64_t n, int64_t grain, int64_t* out_idx,
+                       int64_t* out_count) {
+  int nonfinite = 0;
+#pragma omp taskloop grainsize(1) shared(nonfinite)
+  for (int64_t c = 0; c < (n + grain - 1) / grain; ++c) {
+    int64_t lo = c * grain, hi = lo + grain < n ? lo + grain : n;
+    for (int64_t i = lo; i < hi; ++i)
+      if (!isfinite(x[i]) || !isfinite(y[i])) {
+#pragma omp atomic write
+        nonfinite = 1;
+      }
+  }
+  if (nonfinite) return ORACLE_ERR_NONFINITE;
+  int64_t p, q;
+  extremes_mt(x, y, n, grain, &p, &q);
+  out_idx[0] = p;
+  *out_count = 1;
+  if (p == q) return ORACLE_OK;
+  int64_t* all = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+  int64_t* s = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+  int64_t* tmp = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+  int st = ORACLE_ERR_OUT_OF_MEMORY;
+  if (all && s && tmp) {
+#pragma omp taskloop grainsize(1)
+    for (int64_t c = 0; c < (n + grain - 1) / grain; ++c) {
+      int64_t lo = c * grain, hi = lo + grain < n ? lo + grain : n;
+      for (int64_t i = lo; i < hi; ++i) all[i] = i;
+    }
+    /* the degenerate triangle (p, q, p) (R2) */
+    int64_t n1, n2, r1, r2;
+    st = split_mt(x, y, all, n, p, q, p, s, grain, &n1, &n2, &r1, &r2);
+    if (st == ORACLE_OK) {
+      int64_t len1 = 0, len2 = 0;
+      int st1 = ORACLE_OK, st2 = ORACLE_OK;
+#pragma omp task shared(st1, len1)
+      st1 = hull_mt_rec(x, y, s, n1, p, r1, q, grain, tmp, &len1);
+#pragma omp task shared(st2, len2)
+      st2 = hull_mt_rec(x, y, s + (n - n2), n2, q, r2, p, grain, tmp + (n - n2), &len2);
+#pragma omp taskwait
+      st = st1 != ORACLE_OK ? st1 : st2;
+      if (st == ORACLE_OK) { /* [p] ++ Hull(S1) ++ [q] ++ Hull(S2) (R7) */
+        int64_t k = 1;
+        memcpy(out_idx + k, tmp, (size_t)len1 * sizeof(int64_t));
+        k += len1;
+        out_idx[k++] = q;
+        memcpy(out_idx + k, tmp + (n - n2), (size_t)len2 * sizeof(int64_t));
+        *out_count = k + len2;
+      }
+    }
+  }
+  free(all);
+  free(s);
+  free(tmp);
+  return st;
+}
+
+/*
+ * Algorithm 1 on all n points with `threads` OpenMP threads (<= 0: the
+ * runtime's default); grain as above (<= 0: 65536).  Same output as
+ * vqhull_oracle_hull.
+ */
+int vqhull_oracle_hull_mt(const double* x, const double* y, int64_t n, int64_t* out_idx, int64_t* out_count,
+                          int threads, int64_t grain) {
+  if (n < 0 || !out_count || (n > 0 && (!x || !y || !out_idx))) return ORACLE_ERR_INVALID_ARGUMENT;
+  *out_count = 0;
+  if (n == 0) return ORACLE_OK;
+  if (grain <= 0) grain = 65536;
+  if (threads <= 0) threads = omp_get_max_threads();
+  int st = ORACLE_OK;
+#pragma omp parallel num_threads(threads)
+#pragma omp single
+  st = hull_mt_top(x, y, n, grain, out_idx, out_count);
+  if (st != ORACLE_OK) *out_count = 0;
+  return st;
 }

@@ -99,10 +99,12 @@ def tune_batched(x, y, offsets, repeats: int = 3, stream=None, persistent=(1, 0)
     each gives the same index lists and counts as the first.  Returns (fastest
     equal configuration, table); the library configuration is restored
     afterwards."""
+    import numpy as np
     import torch
 
     import paper_2510_09417_amd as vq
 
+    offsets = np.asarray(offsets, dtype=np.int64)
     saved = vq.get_config()
     table, ref, best = [], None, None
     try:
@@ -119,10 +121,13 @@ def tune_batched(x, y, offsets, repeats: int = 3, stream=None, persistent=(1, 0)
                         out, cnt = vq.hull_batched(x, y, offsets, stream=stream)
                         torch.cuda.synchronize()
                         times.append(time.perf_counter() - t0)
-                    res = (out.cpu().numpy(), cnt.cpu().numpy())
+                    # the index lists only: out_idx past each request's count is unspecified
+                    o, c = out.cpu().numpy(), cnt.cpu().numpy()
+                    res = (c, [o[offsets[i]:offsets[i] + max(int(c[i]), 0)] for i in range(len(c))])
                     if ref is None:
                         ref = res
-                    same = bool((res[0] == ref[0]).all() and (res[1] == ref[1]).all())
+                    same = bool(np.array_equal(res[0], ref[0])
+                                and all(np.array_equal(a, b) for a, b in zip(res[1], ref[1])))
                     ms = 1e3 * sorted(times)[len(times) // 2]
                     table.append({"config": cfg, "ms": ms, "same_result": same})
                     if same and (best is None or ms < best["ms"]):

@@ -343,90 +343,70 @@ int vqhull_oracle_octagon(const double* x, const double* y, int64_t n, int64_t* 
  */
 typedef struct {
   int64_t n1, n2, r1, r2;
-  double k1, k2;
 } part_acc;
 
-/* The partition of P[lo, hi) for the triangle (a, r, b): sizes and farthest
- * points of the two subsets over this chunk (R3, R5, R6). */
-static part_acc split_count(const double* x, const double* y, const int64_t* P, int64_t lo, int64_t hi, int64_t a,
-                            int64_t r, int64_t b) {
-  part_acc c = {0, 0, -1, -1, 0.0, 0.0};
-  for (int64_t j = lo; j < hi; ++j) {
-    int64_t u = P[j];
-    double o1 = vqhull_oracle_orient(x[a], y[a], x[r], y[r], x[u], y[u]);
-    if (o1 > 0.0) {
-      ++c.n1;
-      if (farther(x, y, o1, u, c.k1, c.r1)) {
-        c.k1 = o1;
-        c.r1 = u;
-      }
-      continue;
-    }
-    double o2 = vqhull_oracle_orient(x[r], y[r], x[b], y[b], x[u], y[u]);
-    if (o2 > 0.0) {
-      ++c.n2;
-      if (farther(x, y, o2, u, c.k2, c.r2)) {
-        c.k2 = o2;
-        c.r2 = u;
-      }
-    }
-  }
-  return c;
-}
-
-/* The chunk's subset members written at their places in the sequential
- * layout: the j-th member of S1 at s[o1 + j], the j-th member of S2 at
- * s[m - 1 - (o2 + j)]. */
-static void split_write(const double* x, const double* y, const int64_t* P, int64_t lo, int64_t hi, int64_t a,
-                        int64_t r, int64_t b, int64_t* s, int64_t m, int64_t o1, int64_t o2) {
-  for (int64_t j = lo; j < hi; ++j) {
-    int64_t u = P[j];
-    if (vqhull_oracle_orient(x[a], y[a], x[r], y[r], x[u], y[u]) > 0.0) {
-      s[o1++] = u;
-    } else if (vqhull_oracle_orient(x[r], y[r], x[b], y[b], x[u], y[u]) > 0.0) {
-      s[m - 1 - o2++] = u;
-    }
-  }
-}
-
-/* split() over chunks of `grain` points run as tasks: counts and farthest
- * points per chunk, chunk offsets, then the members written. */
+/* split() over chunks of `grain` points run as tasks: each chunk is split on
+ * its own into its slice of `tmp` (S1 at the slice's front, S2 at its back),
+ * then the chunks are combined in order -- sizes summed into offsets, farthest
+ * points compared by R3 -- and each chunk's members are copied to the places
+ * the sequential split would give them: the j-th member of S1 overall at
+ * s[j], the j-th member of S2 at s[m - 1 - j]. */
 static int split_mt(const double* x, const double* y, const int64_t* P, int64_t m, int64_t a, int64_t r, int64_t b,
                     int64_t* s, int64_t grain, int64_t* n1, int64_t* n2, int64_t* r1, int64_t* r2) {
   int64_t nch = (m + grain - 1) / grain;
   part_acc* acc = (part_acc*)malloc((size_t)nch * sizeof(part_acc));
-  if (!acc) return ORACLE_ERR_OUT_OF_MEMORY;
-#pragma omp taskloop grainsize(1)
-  for (int64_t c = 0; c < nch; ++c) {
-    int64_t lo = c * grain, hi = lo + grain < m ? lo + grain : m;
-    acc[c] = split_count(x, y, P, lo, hi, a, r, b);
-  }
-  part_acc t = {0, 0, -1, -1, 0.0, 0.0};
-  for (int64_t c = 0; c < nch; ++c) {
-    int64_t c1 = acc[c].n1, c2 = acc[c].n2;
-    if (acc[c].r1 >= 0 && farther(x, y, acc[c].k1, acc[c].r1, t.k1, t.r1)) {
-      t.k1 = acc[c].k1;
-      t.r1 = acc[c].r1;
-    }
-    if (acc[c].r2 >= 0 && farther(x, y, acc[c].k2, acc[c].r2, t.k2, t.r2)) {
-      t.k2 = acc[c].k2;
-      t.r2 = acc[c].r2;
-    }
-    acc[c].n1 = t.n1; /* from here on: the chunk's offsets */
-    acc[c].n2 = t.n2;
-    t.n1 += c1;
-    t.n2 += c2;
+  int64_t* tmp = (int64_t*)malloc((size_t)m * sizeof(int64_t));
+  if (!acc || !tmp) {
+    free(acc);
+    free(tmp);
+    return ORACLE_ERR_OUT_OF_MEMORY;
   }
 #pragma omp taskloop grainsize(1)
   for (int64_t c = 0; c < nch; ++c) {
     int64_t lo = c * grain, hi = lo + grain < m ? lo + grain : m;
-    split_write(x, y, P, lo, hi, a, r, b, s, m, acc[c].n1, acc[c].n2);
+    split(x, y, P + lo, hi - lo, a, r, b, tmp + lo, &acc[c].n1, &acc[c].n2, &acc[c].r1, &acc[c].r2);
   }
+  int64_t t1 = 0, t2 = 0, b1 = -1, b2 = -1;
+  double k1 = 0.0, k2 = 0.0;
+  int64_t* o1 = (int64_t*)malloc((size_t)nch * 2 * sizeof(int64_t));
+  if (!o1) {
+    free(acc);
+    free(tmp);
+    return ORACLE_ERR_OUT_OF_MEMORY;
+  }
+  for (int64_t c = 0; c < nch; ++c) {
+    if (acc[c].r1 >= 0) {
+      double k = vqhull_oracle_orient(x[a], y[a], x[r], y[r], x[acc[c].r1], y[acc[c].r1]);
+      if (farther(x, y, k, acc[c].r1, k1, b1)) {
+        k1 = k;
+        b1 = acc[c].r1;
+      }
+    }
+    if (acc[c].r2 >= 0) {
+      double k = vqhull_oracle_orient(x[r], y[r], x[b], y[b], x[acc[c].r2], y[acc[c].r2]);
+      if (farther(x, y, k, acc[c].r2, k2, b2)) {
+        k2 = k;
+        b2 = acc[c].r2;
+      }
+    }
+    o1[2 * c] = t1;
+    o1[2 * c + 1] = t2;
+    t1 += acc[c].n1;
+    t2 += acc[c].n2;
+  }
+#pragma omp taskloop grainsize(1)
+  for (int64_t c = 0; c < nch; ++c) {
+    int64_t lo = c * grain, len = (lo + grain < m ? lo + grain : m) - lo;
+    memcpy(s + o1[2 * c], tmp + lo, (size_t)acc[c].n1 * sizeof(int64_t));
+    memcpy(s + (m - o1[2 * c + 1] - acc[c].n2), tmp + lo + (len - acc[c].n2), (size_t)acc[c].n2 * sizeof(int64_t));
+  }
+  free(o1);
   free(acc);
-  *n1 = t.n1;
-  *n2 = t.n2;
-  *r1 = t.r1;
-  *r2 = t.r2;
+  free(tmp);
+  *n1 = t1;
+  *n2 = t2;
+  *r1 = b1;
+  *r2 = b2;
   return ORACLE_OK;
 }
 
@@ -484,19 +464,16 @@ static void extremes_mt(const double* x, const double* y, int64_t n, int64_t gra
 #pragma omp taskloop grainsize(1)
   for (int64_t c = 0; c < nch; ++c) {
     int64_t lo = c * grain, hi = lo + grain < n ? lo + grain : n;
-    int64_t p = lo, q = lo;
-    for (int64_t i = lo + 1; i < hi; ++i) {
-      if (x[i] < x[p] || (x[i] == x[p] && y[i] < y[p])) p = i;
-      if (x[i] > x[q] || (x[i] == x[q] && y[i] > y[q])) q = i;
-    }
-    pq[2 * c] = p;
-    pq[2 * c + 1] = q;
+    int64_t p, q; /* the sequential scan over the chunk */
+    vqhull_oracle_extremes(x + lo, y + lo, hi - lo, &p, &q);
+    pq[2 * c] = lo + p;
+    pq[2 * c + 1] = lo + q;
   }
   int64_t p = pq[0], q = pq[1];
   for (int64_t c = 1; c < nch; ++c) {
-    int64_t i = pq[2 * c], j = pq[2 * c + 1];
-    if (x[i] < x[p] || (x[i] == x[p] && y[i] < y[p])) p = i;
-    if (x[j] > x[q] || (x[j] == x[q] && y[j] > y[q])) q = j;
+    int64_t cp = pq[2 * c], cq = pq[2 * c + 1];
+    if (x[cp] < x[p] || (x[cp] == x[p] && y[cp] < y[p])) p = cp;
+    if (x[cq] > x[q] || (x[cq] == x[q] && y[cq] > y[q])) q = cq;
   }
   free(pq);
   *p_out = p;

@@ -40,10 +40,10 @@ def fake_serve(tmp_path_factory):
     d = tmp_path_factory.mktemp("fake_serve")
     obj = str(d / "oracle.o")
     exe = str(d / "fake_serve")
-    subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-c",
+    subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-c",
                     os.path.join(ROOT, "oracle", "vqhull_oracle.c"), "-o", obj], check=True)
     subprocess.run(["g++", "-O2", "-std=c++17", "-pthread", "-Wall", "-Werror", f"-I{CSRC}",
-                    os.path.join(HERE, "fake_serve.cpp"), obj, "-o", exe, "-lm"], check=True)
+                    os.path.join(HERE, "fake_serve.cpp"), obj, "-o", exe, "-fopenmp", "-lm"], check=True)
     return exe
 
 

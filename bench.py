@@ -17,7 +17,14 @@ Prints one JSON line:
   per_hull    each dataset's hull alone: HIP events on the launch stream
               around the call (first kernel to the count written), 10 runs
               after a warm-up, median and standard deviation.
-  cpu_baseline  the CPU oracle (single thread) on one whole step.
+  configs     the other single-hull workloads (disk 10^6, circle 5*10^7,
+              Kuzmin 10^8) each alone: median and spread of 10 runs,
+              Gpoints/s, algorithmic bytes per point and per second against
+              8 TB/s, and equality of the GPU's list with the CPU oracle's.
+  cpu_baseline  the CPU oracle on the host: one whole step on every core (its
+              multithreaded form) and single-threaded, median of 3 runs each;
+              every configuration above on every core; a seeded sample of the
+              served requests, one request per thread.
   prefilter   the same step with the octagon prefilter on (Section 6's
               Akl-Toussaint heuristic, a variant of the method; outside the
               timed region): throughput, a check that every hull equals the
@@ -30,8 +37,12 @@ Prints one JSON line:
               hulls/s with every request submitted at once; p50 / p99 latency
               (submit to results written) under Poisson arrivals at half that
               rate; the plain path (one vqhull_hull call per request) on a
-              time-boxed prefix of the same mix; and a check that served results
-              equal the plain path's on a sample.
+              time-boxed prefix of the same mix; both paths under the same
+              Poisson stream at 0.9 x the plain path's capacity (latency from
+              the scheduled arrival on both); the algorithmic bytes of the whole
+              mix per second against 8 TB/s; checks that served results equal
+              the plain path's on a prefix and the CPU oracle's on a seeded
+              sample (random requests plus the largest of each distribution).
 
 Usage: python bench.py [--gpus 1] [--steps 50] [--warmup 3]
 """
@@ -73,9 +84,127 @@ def percentile(v, q):
     return v[min(len(v) - 1, int(q * len(v)))]
 
 
-def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: int = 1 << 25) -> dict:
-    """The served mix through vqhull_server_*, against the plain per-request path."""
+SERVED_SAMPLE = 64  # random served requests checked against the CPU oracle (plus the largest of each distribution)
+CONFIG_LEGS = ("disk_1e6", "circle_5e7", "kuzmin_1e8")
+CONFIG_RUNS = 10
+
+
+def configs_leg(vq, torch, workloads, stream) -> tuple[dict, list]:
+    """The other single-hull workloads (disk 10^6, circle 5*10^7, Kuzmin
+    10^8), each alone: HIP events on the launch stream around the call, 10
+    runs after a warm-up (median and spread), Gpoints/s, and the algorithmic
+    bytes of the call (from its level statistics) per point and per second
+    against 8 TB/s.  Returns the results and, per workload, the points and the
+    GPU's index list for the CPU-baseline leg."""
     import numpy as np
+
+    from paper_2510_09417_amd import profiling
+
+    res, kept = {}, []
+    dev = torch.device("cuda:0")
+    for name in CONFIG_LEGS:
+        x, y = workloads.workload(name)
+        tx, ty = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+        oi = torch.empty(len(x), dtype=torch.int64, device=dev)
+        oc = torch.empty(1, dtype=torch.int64, device=dev)
+        vq.hull_into(tx, ty, oi, oc, stream)
+        torch.cuda.synchronize()
+        levels = vq.level_stats()
+        ms = []
+        for _ in range(CONFIG_RUNS):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            vq.hull_into(tx, ty, oi, oc, stream)
+            e1.record(stream)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        h = int(oc.item())
+        med = float(np.median(ms))
+        alg = profiling.alg_bytes(len(x), levels)["total"]
+        gbs = alg / (med * 1e-3) / 1e9
+        res[name] = {"n": len(x), "hull_vertices": h, "levels": len(levels), "median_ms": round(med, 4),
+                     "std_ms": round(float(np.std(ms)), 4), "runs": CONFIG_RUNS,
+                     "gpoints_per_s": round(len(x) / (med * 1e-3) / 1e9, 3),
+                     "alg_bytes_per_point": round(alg / len(x), 2), "alg_gbs": round(gbs, 1),
+                     "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        kept.append((name, x, y, oi[:max(h, 0)].cpu().numpy()))
+        log(f"{name}: {res[name]}")
+        del tx, ty, oi, oc
+    torch.cuda.empty_cache()
+    return res, kept
+
+
+def cpu_baseline_leg(oracle, data, npts, configs_kept, served_sample) -> dict:
+    """The CPU oracle on the host: the step (disk 10^8 + square 10^8) single-
+    threaded and on every core (its multithreaded form, the same lists),
+    median of three runs each; every other single-hull workload on every core;
+    the sample of served requests one request per thread on every core.  The
+    oracle's lists are compared with the GPU's (configurations and served
+    sample)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    oracle.load()
+    threads = len(os.sched_getaffinity(0))
+
+    def med3(f):
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            f()
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[1], ts
+
+    t1, t1s = med3(lambda: [oracle.hull(x, y) for _, x, y in data])
+    tn, tns = med3(lambda: [oracle.hull_mt(x, y, threads) for _, x, y in data])
+    log(f"cpu oracle, one step: {t1:.2f} s on 1 core, {tn:.2f} s on {threads} threads")
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
+    names = " + ".join(n for n, _, _ in data)
+    out = {"value": round(npts / tn / 1e9, 5), "unit": "Gpoints/s", "cores": threads, "kind": "oracle",
+           "sample": f"one whole step: {names} ({npts} points), the oracle's multithreaded form (OpenMP) on "
+                     f"{threads} threads, median of 3 runs ({', '.join(f'{t:.2f}' for t in tns)} s)",
+           "single_core": {"value": round(npts / t1 / 1e9, 5), "unit": "Gpoints/s", "cores": 1,
+                           "sample": f"the same step single-threaded, median of 3 runs "
+                                     f"({', '.join(f'{t:.2f}' for t in t1s)} s)"},
+           "host": {"cpu_model": model, "logical_cpus": os.cpu_count(), "threads_used": threads}}
+    cfg = {}
+    for name, x, y, gpu in configs_kept:
+        t0 = time.perf_counter()
+        want = oracle.hull_mt(x, y, threads)
+        dt = time.perf_counter() - t0
+        cfg[name] = {"seconds": round(dt, 3), "gpoints_per_s": round(len(x) / dt / 1e9, 5),
+                     "gpu_equals_oracle": bool(np.array_equal(gpu, want))}
+        log(f"cpu oracle, {name}: {dt:.2f} s on {threads} threads, GPU list equal: {cfg[name]['gpu_equals_oracle']}")
+    out["configs"] = cfg
+    if served_sample:
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(threads) as ex:
+            wants = list(ex.map(lambda r: oracle.hull(r["x"], r["y"]), served_sample))
+        dt = time.perf_counter() - t0
+        same = sum(int(r["gpu"] is not None and np.array_equal(r["gpu"], w)) for r, w in zip(served_sample, wants))
+        pts = sum(len(r["x"]) for r in served_sample)
+        out["served_sample"] = {"requests": len(served_sample), "points": pts, "seconds": round(dt, 3),
+                                "hulls_per_s": round(len(served_sample) / dt, 1),
+                                "largest_request": max(len(r["x"]) for r in served_sample),
+                                "served_equals_oracle": f"{same}/{len(served_sample)}"}
+        log(f"cpu oracle, served sample: {len(served_sample)} requests in {dt:.2f} s; served == oracle on "
+            f"{same}/{len(served_sample)}")
+    return out
+
+
+def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: int = 1 << 25) -> tuple[dict, list]:
+    """The served mix through vqhull_server_*, against the plain per-request
+    path.  Returns the results and a seeded sample of served requests (points
+    and index lists, on the host) for the CPU-baseline leg."""
+    import numpy as np
+
+    from paper_2510_09417_amd import profiling
 
     sizes, dists, _ = workloads.served_plan(nreq)
     total = int(sizes.sum())
@@ -132,11 +261,13 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
             first = None
             i = 0
             t_start = time.perf_counter()
+            delay = np.zeros(m)  # scheduled arrival -> submit call, seconds
             while i < m:
                 now = time.perf_counter() - t_start
                 j = int(np.searchsorted(arrivals, now, side="right"))
                 if j <= i:
                     continue
+                delay[i:j] = now - arrivals[i:j]
                 t = srv.submit_pointers(px[i:j], py[i:j], sizes[i:j], po[i:j], pc[i:j])
                 first = t if first is None else first
                 i = j
@@ -145,11 +276,14 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
             st = srv.stats()
         finally:
             srv.close()
-        return infos, st
+        # latency from the scheduled arrival: the wait to be submitted plus
+        # submit -> results written on the server's clock
+        lat_ms = [1e3 * (delay[k] + infos[k]["t_done"] - infos[k]["t_submit"]) for k in range(m)]
+        return infos, st, lat_ms
 
     # warm-up (lane allocation, first launches)
     run(np.zeros(min(nreq, 256)))
-    infos, st = run(np.zeros(nreq))
+    infos, st, _ = run(np.zeros(nreq))
     t_first = min(i["t_submit"] for i in infos)
     t_last = max(i["t_done"] for i in infos)
     thr = nreq / (t_last - t_first)
@@ -157,12 +291,42 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
     log(f"served throughput: {thr:.0f} hulls/s over {st['batches']} batches")
     counts_served = CNT.cpu().numpy().copy()
 
+    # A seeded sample of the served results, with the requests' points, kept on
+    # the host for the CPU-baseline leg (which runs the CPU oracle on them and
+    # compares): random requests from the whole mix plus the largest request
+    # of every distribution.
+    gs = np.random.default_rng(workloads.SERVED_SEED + 3)
+    pick = sorted(set(gs.choice(nreq, size=min(nreq, SERVED_SAMPLE), replace=False).tolist())
+                  | {int(np.nonzero(dists == d)[0][np.argmax(sizes[dists == d])])
+                     for d in range(len(workloads.DISTRIBUTIONS)) if np.any(dists == d)})
+    sample = []
+    for i in pick:
+        a, b = int(off[i]), int(off[i + 1])
+        h = int(counts_served[i])
+        sample.append({"request": i, "dist": workloads.DISTRIBUTIONS[int(dists[i])],
+                       "x": X[a:b].cpu().numpy(), "y": Y[a:b].cpu().numpy(),
+                       "gpu": OUT[a:a + max(h, 0)].cpu().numpy() if h >= 0 else None})
+
+    # Algorithmic bytes of the whole mix: the batched path over lane-sized
+    # batches of the same requests (the same kernels as the lanes), with its
+    # level statistics (outputs discarded)
+    alg_total, lo = 0, 0
+    while lo < nreq:
+        hi = max(lo + 1, int(np.searchsorted(off, off[lo] + lane_points, side="right")) - 1)
+        hi = min(hi, nreq)
+        vq.hull_batched(X[off[lo]:off[hi]], Y[off[lo]:off[hi]], off[lo:hi + 1] - off[lo], check=False)
+        alg_total += profiling.alg_bytes_batched(int(off[hi] - off[lo]), vq.level_stats())["total"]
+        lo = hi
+    torch.cuda.synchronize()
+    served_gbs = alg_total / (t_last - t_first) / 1e9
+    log(f"served: {alg_total / total:.1f} algorithmic B/pt, {served_gbs:.0f} GB/s ({served_gbs / HBM_PEAK_GBS:.3f} "
+        f"of {HBM_PEAK_GBS:.0f} GB/s)")
+
     # latency under Poisson arrivals at half the measured throughput
     nlat = min(nreq, 16384)
     g = np.random.default_rng(workloads.SERVED_SEED + 1)
     arr = np.cumsum(-np.log1p(-g.random(nlat)) / (0.5 * thr))
-    linfos, lst = run(arr)
-    lat = [1e3 * (i["t_done"] - i["t_submit"]) for i in linfos]
+    linfos, lst, lat = run(arr)
 
     # plain path: one synchronous vqhull_hull per request, time-boxed
     stream = torch.cuda.current_stream()
@@ -184,14 +348,13 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
     log(f"plain path: {plain_thr:.0f} hulls/s over {len(plain_lat)} requests; served == plain on {same}/{checked}")
 
     # both paths under the same Poisson stream at 0.9 x the plain path's
-    # capacity, where both are stable; latency from the scheduled arrival
-    # (plain: queueing behind earlier requests included)
+    # capacity, where both are stable; latency from the scheduled arrival on
+    # both (queueing behind earlier requests included)
     nm = min(nreq, 4096)
     lam = 0.9 * plain_thr
     gm = np.random.default_rng(workloads.SERVED_SEED + 2)
     arr_m = np.cumsum(-np.log1p(-gm.random(nm)) / lam)
-    minfos, _ = run(arr_m)
-    m_served = [1e3 * (i["t_done"] - i["t_submit"]) for i in minfos]
+    _, _, m_served = run(arr_m)
     m_plain = []
     t_start = time.perf_counter()
     for k in range(nm):
@@ -218,6 +381,9 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
                     f"{tune_s:.1f} s",
         "hulls_per_s": round(thr, 1),
         "gpoints_per_s": round(total / (t_last - t_first) / 1e9, 3),
+        "alg_bytes_per_point": round(alg_total / total, 2),
+        "alg_gbs": round(served_gbs, 1),
+        "frac_of_hbm_peak": round(served_gbs / HBM_PEAK_GBS, 4),
         "batches": st["batches"], "graph_batches": st["graph_batches"], "plain_batches": st["plain_batches"],
         "failed": bad,
         "latency_load_hulls_per_s": round(0.5 * thr, 1), "latency_requests": nlat,
@@ -226,7 +392,8 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
         "plain_p50_ms": round(percentile(plain_lat, 0.50), 3), "plain_p99_ms": round(percentile(plain_lat, 0.99), 3),
         "served_equals_plain": f"{same}/{checked}",
         "matched_rate": matched,
-    }
+        "latency_from": "scheduled arrival (both paths)",
+    }, sample
 
 
 LEG_BLOCKS = 3
@@ -340,6 +507,7 @@ def main() -> int:
     ap.add_argument("--no-energy", action="store_true")
     ap.add_argument("--no-prefilter", action="store_true")
     ap.add_argument("--no-aos", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--served-requests", type=int, default=65536)
     ap.add_argument("--served-lanes", type=int, default=4)
     ap.add_argument("--served-lane-points", type=int, default=1 << 25)
@@ -499,33 +667,24 @@ def main() -> int:
         "frac_of_stream_scale": round(achieved / probe_gbs, 4),
     }
 
-    served = None
+    del dx, outs
+    torch.cuda.empty_cache()
+    configs, configs_kept = (None, []) if args.no_configs else configs_leg(vq, torch, workloads, stream)
+
+    served, served_sample = None, []
     if not args.no_served:
-        del dx, outs
-        torch.cuda.empty_cache()
-        served = served_benchmark(vq, workloads, torch, args.served_requests, args.served_lanes,
-                                  args.served_lane_points)
+        served, served_sample = served_benchmark(vq, workloads, torch, args.served_requests, args.served_lanes,
+                                                 args.served_lane_points)
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
 
-        oracle.load()
-        t0 = time.perf_counter()
-        for _, x, y in data:
-            oracle.hull(x, y)
-        tc = time.perf_counter() - t0
-        model = "unknown"
-        try:
-            with open("/proc/cpuinfo") as f:
-                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
-        except OSError:
-            pass
-        cpu = {"value": round(npts / tc / 1e9, 5), "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
-               "sample": f"one whole step: {' + '.join(names)} ({npts} points), single-threaded C oracle, "
-                         f"{tc:.2f} s",
-               "host": {"cpu_model": model, "logical_cpus": os.cpu_count()}}
-        log(f"cpu oracle: {tc:.2f}s for one step")
+        cpu = cpu_baseline_leg(oracle, data, npts, configs_kept, served_sample)
+        for name, r in cpu["configs"].items():
+            configs[name]["gpu_equals_oracle"] = r["gpu_equals_oracle"]
+        if served is not None and "served_sample" in cpu:
+            served["served_equals_oracle"] = cpu["served_sample"]["served_equals_oracle"]
 
     line = {
         "metric": METRIC,
@@ -549,6 +708,7 @@ def main() -> int:
         "energy": en,
         "prefilter": pre,
         "aos": aos,
+        "configs": configs,
         "served": served,
     }
     print(json.dumps(line), flush=True)

@@ -121,6 +121,45 @@ int vqhull_hull_xy(const double* xy, int64_t n, int64_t* out_idx, int64_t* out_c
 int vqhull_hull_batched_xy(const double* xy, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
                            int64_t* out_counts, vqhull_stream_t stream);
 
+/*
+ * Caller-owned workspace (so that every byte of device memory a hull needs can
+ * come from the caller's allocator, e.g. a torch tensor).  The problem is the
+ * one of Algorithm 1 (Section 2.1: given a planar point set, the vertices of
+ * its convex hull in clockwise order); these calls compute exactly what
+ * vqhull_hull / vqhull_hull_batched compute, with the same kernels.
+ *
+ * vqhull_workspace_bytes(n_total, nreq): the bytes of device workspace a
+ *   _ws call with n_total points in nreq requests needs under the current
+ *   configuration (vqhull_set_config may change it: query again after a
+ *   change).  About 72 bytes per point: two ping-pong point buffers (x, y,
+ *   index: 40 bytes per point), a node table with one 32-byte node per point
+ *   (the most vertices the recursion can emit), and tables per tile, segment
+ *   and request.  Returns 0 for n_total or nreq outside [0, 2^31).
+ *
+ * vqhull_hull_ws / vqhull_hull_batched_ws: arguments, results and errors of
+ *   vqhull_hull / vqhull_hull_batched, plus
+ *     workspace        device pointer, 256-byte aligned, of workspace_bytes
+ *                      bytes, owned by the caller.  Its contents on entry
+ *                      do not matter; on return they are unspecified.  The
+ *                      library keeps no pointer into it after the call.
+ *     workspace_bytes  at least vqhull_workspace_bytes(n_total, nreq) for the
+ *                      call's sizes, else VQHULL_ERR_INVALID_ARGUMENT (also
+ *                      for a null or misaligned workspace) with nothing
+ *                      enqueued.
+ *   The library allocates no device memory in these calls (host-side pinned
+ *   staging and events are created once per concurrent caller and reused).
+ *   Calls on different streams with different workspaces may run
+ *   concurrently; one workspace must not be used by two calls at once.  Like
+ *   vqhull_hull, a call returns after its result has been written.  Level
+ *   statistics and kernel timing are not recorded for these calls.
+ */
+size_t vqhull_workspace_bytes(int64_t n_total, int64_t nreq);
+int vqhull_hull_ws(const double* x, const double* y, int64_t n, int64_t* out_idx, int64_t* out_count,
+                   void* workspace, size_t workspace_bytes, vqhull_stream_t stream);
+int vqhull_hull_batched_ws(const double* x, const double* y, const int64_t* offsets, int64_t nreq,
+                           int64_t* out_idx, int64_t* out_counts, void* workspace, size_t workspace_bytes,
+                           vqhull_stream_t stream);
+
 /* Tuning knobs of the hull kernels (all values are rounded to supported ones). */
 typedef struct {
   int sweep_block;  /* threads per workgroup of the partition sweep: 256, 512 or 1024 */

@@ -538,7 +538,7 @@ static int hull_mt_top(const double* x, const double* y, int64_t n, int64_t grai
 
 /*
  * Algorithm 1 on all n points with `threads` OpenMP threads (<= 0: the
- * runtime's default); grain as above (<= 0: 65536).  Same output as
+ * runtime's default); grain as above (<= 0: n / (8 threads), at least 2^18).  Same output as
  * vqhull_oracle_hull.
  */
 int vqhull_oracle_hull_mt(const double* x, const double* y, int64_t n, int64_t* out_idx, int64_t* out_count,
@@ -546,8 +546,11 @@ int vqhull_oracle_hull_mt(const double* x, const double* y, int64_t n, int64_t* 
   if (n < 0 || !out_count || (n > 0 && (!x || !y || !out_idx))) return ORACLE_ERR_INVALID_ARGUMENT;
   *out_count = 0;
   if (n == 0) return ORACLE_OK;
-  if (grain <= 0) grain = 65536;
   if (threads <= 0) threads = omp_get_max_threads();
+  if (grain <= 0) { /* about eight chunks per thread over the whole input, at least 2^18 points */
+    grain = n / (8 * (int64_t)threads);
+    if (grain < ((int64_t)1 << 18)) grain = (int64_t)1 << 18;
+  }
   int st = ORACLE_OK;
 #pragma omp parallel num_threads(threads)
 #pragma omp single

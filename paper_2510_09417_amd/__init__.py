@@ -23,7 +23,8 @@ VQHULL_ERR_TIMEOUT = 5
 
 # Symbols that include/vqhull.h declares.
 EXPORTED = (
-    "vqhull_hull", "vqhull_hull_batched", "vqhull_hull_xy", "vqhull_hull_batched_xy", "vqhull_get_config", "vqhull_set_config", "vqhull_autotune",
+    "vqhull_hull", "vqhull_hull_batched", "vqhull_workspace_bytes", "vqhull_hull_ws", "vqhull_hull_batched_ws",
+    "vqhull_hull_xy", "vqhull_hull_batched_xy", "vqhull_get_config", "vqhull_set_config", "vqhull_autotune",
     "vqhull_last_level_stats", "vqhull_set_timing", "vqhull_last_kernel_times", "vqhull_orient", "vqhull_stream_scale",
     "vqhull_release_workspace", "vqhull_status_string", "vqhull_last_error",
     "vqhull_server_create", "vqhull_server_submit", "vqhull_server_submit_batch", "vqhull_server_wait", "vqhull_server_wait_timeout",
@@ -95,6 +96,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.vqhull_hull.argtypes = [vp, vp, i64, vp, vp, vp]
         lib.vqhull_hull_batched.restype = ctypes.c_int
         lib.vqhull_hull_batched.argtypes = [vp, vp, pi64, i64, vp, vp, vp]
+        lib.vqhull_workspace_bytes.restype = ctypes.c_size_t
+        lib.vqhull_workspace_bytes.argtypes = [i64, i64]
+        lib.vqhull_hull_ws.restype = ctypes.c_int
+        lib.vqhull_hull_ws.argtypes = [vp, vp, i64, vp, vp, vp, ctypes.c_size_t, vp]
+        lib.vqhull_hull_batched_ws.restype = ctypes.c_int
+        lib.vqhull_hull_batched_ws.argtypes = [vp, vp, pi64, i64, vp, vp, vp, ctypes.c_size_t, vp]
         lib.vqhull_hull_xy.restype = ctypes.c_int
         lib.vqhull_hull_xy.argtypes = [vp, i64, vp, vp, vp]
         lib.vqhull_hull_batched_xy.restype = ctypes.c_int
@@ -178,7 +185,10 @@ def _check_points(x, y):
 
 
 def hull_into(x, y, out_idx, out_count, stream=None) -> None:
-    """vqhull_hull on preallocated device outputs (no allocation, no sync)."""
+    """vqhull_hull on preallocated device outputs.  The call returns after the
+    result is written (it waits on the stream), and the library's own
+    workspace may be allocated or grown on the first call of a device or when
+    n exceeds every earlier call's."""
     lib = load_library()
     n = x.numel()
     st = lib.vqhull_hull(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), n,
@@ -187,9 +197,42 @@ def hull_into(x, y, out_idx, out_count, stream=None) -> None:
     _check(lib, st)
 
 
+def workspace_bytes(n_total: int, nreq: int = 1) -> int:
+    """Bytes of device workspace a _ws call needs (vqhull_workspace_bytes)."""
+    b = load_library().vqhull_workspace_bytes(int(n_total), int(nreq))
+    if b == 0:
+        raise ValueError("n_total and nreq must lie in [0, 2^31)")
+    return int(b)
+
+
+def workspace(n_total: int, nreq: int = 1, device=None):
+    """A device workspace tensor (uint8, from torch's allocator) for a _ws call
+    on n_total points in nreq requests.  torch's allocator returns blocks
+    aligned to at least 512 bytes, which covers the 256 bytes the calls ask."""
+    import torch
+
+    ws = torch.empty(workspace_bytes(n_total, nreq), dtype=torch.uint8, device=device or "cuda")
+    if ws.data_ptr() % 256:
+        raise RuntimeError("torch returned a workspace that is not 256-byte aligned")
+    return ws
+
+
+def hull_ws_into(x, y, out_idx, out_count, ws, stream=None) -> None:
+    """vqhull_hull_ws: vqhull_hull with every device buffer in the caller's
+    workspace tensor ws (see ``workspace``); the library allocates no device
+    memory.  Returns after the result is written."""
+    lib = load_library()
+    st = lib.vqhull_hull_ws(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), x.numel(),
+                            ctypes.c_void_p(out_idx.data_ptr()), ctypes.c_void_p(out_count.data_ptr()),
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), _stream_handle(stream))
+    _check(lib, st)
+
+
 def hull(x, y, stream=None):
     """Hull vertex indices (int64 tensor on the same GPU), clockwise from the
-    lexicographically smallest point.  Raises VqhullError on a non-finite input."""
+    lexicographically smallest point.  Every device buffer (output and
+    workspace) comes from torch's allocator (vqhull_hull_ws).  Raises
+    VqhullError on a non-finite input."""
     import torch
 
     _check_points(x, y)
@@ -197,8 +240,10 @@ def hull(x, y, stream=None):
     out = torch.empty(max(n, 1), dtype=torch.int64, device=x.device)
     cnt = torch.empty(1, dtype=torch.int64, device=x.device)
     with torch.cuda.device(x.device):
-        hull_into(x, y, out, cnt, stream)
+        ws = workspace(n, 1, x.device)
+        hull_ws_into(x, y, out, cnt, ws, stream)
         h = int(cnt.item())
+    del ws
     if h < 0:
         raise VqhullError(-h, "non-finite coordinate in the input")
     return out[:h]
@@ -216,7 +261,8 @@ def _check_xy(xy):
 
 
 def hull_xy_into(xy, out_idx, out_count, stream=None) -> None:
-    """vqhull_hull_xy on preallocated device outputs (no allocation, no sync)."""
+    """vqhull_hull_xy on preallocated device outputs (returns after the result
+    is written; the library's workspace may be allocated or grown)."""
     lib = load_library()
     st = lib.vqhull_hull_xy(ctypes.c_void_p(xy.data_ptr()), xy.shape[0], ctypes.c_void_p(out_idx.data_ptr()),
                             ctypes.c_void_p(out_count.data_ptr()), _stream_handle(stream))
@@ -257,6 +303,33 @@ def hull_batched_xy(xy, offsets, stream=None):
         st = lib.vqhull_hull_batched_xy(ctypes.c_void_p(xy.data_ptr()),
                                         off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nreq,
                                         ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(cnt.data_ptr()),
+                                        _stream_handle(stream))
+    _check(lib, st)
+    return out, cnt[:nreq]
+
+
+def hull_batched_ws(x, y, offsets, ws=None, stream=None):
+    """hull_batched through vqhull_hull_batched_ws: every device buffer comes
+    from torch's allocator (ws: a tensor from ``workspace``, or None for a
+    fresh one)."""
+    import numpy as np
+    import torch
+
+    _check_points(x, y)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    nreq = len(off) - 1
+    if nreq < 0 or off[-1] != x.numel():
+        raise ValueError("offsets must have nreq+1 entries ending at len(x)")
+    lib = load_library()
+    out = torch.empty(max(x.numel(), 1), dtype=torch.int64, device=x.device)
+    cnt = torch.empty(max(nreq, 1), dtype=torch.int64, device=x.device)
+    with torch.cuda.device(x.device):
+        if ws is None:
+            ws = workspace(x.numel(), nreq, x.device)
+        st = lib.vqhull_hull_batched_ws(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                        off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nreq,
+                                        ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(cnt.data_ptr()),
+                                        ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
                                         _stream_handle(stream))
     _check(lib, st)
     return out, cnt[:nreq]

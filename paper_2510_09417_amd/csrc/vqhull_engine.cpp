@@ -15,6 +15,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/vqhull.h"
@@ -43,10 +44,13 @@ struct TimedLaunch {
   int ev0, ev1;
 };
 
+// A device table: library-owned (grown on demand), or a fixed view into a
+// caller's workspace (never reallocated or freed by the library).
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
   size_t cap = 0;
+  bool fixed = false;
 };
 
 }  // namespace
@@ -59,6 +63,7 @@ namespace vqh {
 struct Context {
   std::mutex mu;
   int device = -1;
+  bool fixed = false;  // every device table is a view into a caller's workspace (the _ws calls)
   size_t cap_pts = 0;
   double* wx[2] = {nullptr, nullptr};
   double* wy[2] = {nullptr, nullptr};
@@ -109,6 +114,9 @@ struct HipFail {
   hipError_t e;
 };
 
+// A caller's workspace is too small for what a call needs.
+struct WorkspaceTooSmall {};
+
 inline void ck(hipError_t e, const char* what) {
   if (e != hipSuccess) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
@@ -125,6 +133,10 @@ std::atomic<uint64_t> g_alloc_gen{0};
 template <typename T>
 void ensure(DevBuf<T>& b, size_t n, hipStream_t st, bool keep = false) {
   if (n <= b.cap) return;
+  if (b.fixed) {
+    g_last_error = "the caller's workspace is too small for this call";
+    throw WorkspaceTooSmall{};
+  }
   g_alloc_gen.fetch_add(1);
   size_t cap = std::max<size_t>(n, b.cap + b.cap / 2);
   T* p = nullptr;
@@ -140,6 +152,10 @@ void ensure(DevBuf<T>& b, size_t n, hipStream_t st, bool keep = false) {
 
 void ensure_points(Context& w, size_t n, hipStream_t st) {
   if (n <= w.cap_pts) return;
+  if (w.fixed) {
+    g_last_error = "the caller's workspace is too small for this call";
+    throw WorkspaceTooSmall{};
+  }
   g_alloc_gen.fetch_add(1);
   ck(hipStreamSynchronize(st), "hipStreamSynchronize");
   for (int k = 0; k < 2; ++k) {
@@ -178,13 +194,17 @@ void ensure_host_u32(Context& w, size_t n) {
   w.h_u32_cap = cap;
 }
 
-Context* new_context() {
+// device_tables = false: the context of the _ws calls, whose status ring and
+// batch counts are carved from the caller's workspace like everything else.
+Context* new_context(bool device_tables = true) {
   int dev = 0;
   ck(hipGetDevice(&dev), "hipGetDevice");
   Context* w = new Context();
   w->device = dev;
-  ck(hipMalloc(&w->status_dev, kStatusRing * sizeof(Status)), "hipMalloc");
-  ck(hipMalloc(&w->counts_dev, sizeof(BatchCounts)), "hipMalloc");
+  if (device_tables) {
+    ck(hipMalloc(&w->status_dev, kStatusRing * sizeof(Status)), "hipMalloc");
+    ck(hipMalloc(&w->counts_dev, sizeof(BatchCounts)), "hipMalloc");
+  }
   ck(hipHostMalloc((void**)&w->counts_host, sizeof(BatchCounts), hipHostMallocDefault), "hipHostMalloc");
   ck(hipHostMalloc((void**)&w->status_host, kStatusRing * sizeof(Status), hipHostMallocMapped), "hipHostMalloc");
   ck(hipHostGetDevicePointer((void**)&w->status_host_dev, w->status_host, 0), "hipHostGetDevicePointer");
@@ -513,7 +533,7 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
     // A grown table is copied on the stream before the launch below, which
     // takes the new pointer for both its planner and its finisher.
     const int64_t need = known_nodes + 2 * known_seg + 2 * std::min<int64_t>(2 * known_seg, (int64_t)max_seg) + 16;
-    ensure(w.nodes, (size_t)need, st, true);
+    if (!w.nodes.fixed) ensure(w.nodes, (size_t)need, st, true);  // a fixed table holds every vertex
     ensure(w.level_nodes, (size_t)k + 3, st, true);
     // (with interleaved input no job reads the caller's arrays: every root
     // went through the filter into buffer A)
@@ -729,6 +749,8 @@ int guard_status(F&& f) {
   } catch (const std::bad_alloc&) {
     g_last_error = "host allocation failed";
     return VQHULL_ERR_OUT_OF_MEMORY;
+  } catch (const WorkspaceTooSmall&) {
+    return VQHULL_ERR_OUT_OF_MEMORY;
   }
   return VQHULL_OK;
 }
@@ -738,6 +760,156 @@ int guarded(const double* x, const double* y, const int64_t* offsets, int64_t nr
   return guard_status([&] {
     run(default_context(), current_config(), x, y, offsets, nreq, out_idx, out_counts, (hipStream_t)stream, xy);
   });
+}
+
+// ------------------------------------------------- caller-owned workspace
+
+constexpr size_t kWsAlign = 256;
+
+// Every device table a call with N points in nreq requests can use, carved
+// in order from the workspace at `base` (with base null, only the size is
+// computed and w is left as it is).  The sizes are those the library-owned
+// path reserves; the node table holds one node per input point plus three per
+// request (every vertex the recursion can emit outside the LDS finisher), and
+// the per-level node counts cover up to 2^20 levels.  Returns the bytes used.
+size_t ws_layout(Context& w, char* base, size_t N, size_t nreq, const vqhull_config& cfg) {
+  N = std::max<size_t>(N, 1);
+  nreq = std::max<size_t>(nreq, 1);
+  const size_t tile = (size_t)cfg.sweep_block * (size_t)cfg.sweep_ppt;
+  const size_t lds_limit = (size_t)cfg.lds_limit;
+  const size_t ext_tiles = N / kExtTile + nreq;  // >= the sum over requests of ceil(n_i / kExtTile)
+  const size_t max_seg = N / (lds_limit + 1) + nreq + 2;
+  const size_t max_tiles = N / tile + max_seg + 2;
+  const size_t njobs = 2 * max_seg + nreq;
+  size_t off = 0;
+  auto raw = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += (bytes + kWsAlign - 1) / kWsAlign * kWsAlign;
+    return p;
+  };
+  auto take = [&](auto& b, size_t n) {
+    using T = std::remove_pointer_t<decltype(b.p)>;
+    T* p = reinterpret_cast<T*>(raw(n * sizeof(T)));
+    if (base) {
+      b.p = p;
+      b.cap = n;
+      b.fixed = true;
+    }
+  };
+  for (int k = 0; k < 2; ++k) {
+    double* px = reinterpret_cast<double*>(raw(N * sizeof(double)));
+    double* py = reinterpret_cast<double*>(raw(N * sizeof(double)));
+    uint32_t* pi = reinterpret_cast<uint32_t*>(raw(N * sizeof(uint32_t)));
+    if (base) {
+      w.wx[k] = px;
+      w.wy[k] = py;
+      w.wi[k] = pi;
+    }
+  }
+  for (int k = 0; k < 2; ++k) {
+    take(w.seg[k], max_seg);
+    take(w.ctr[k], max_seg * kCtrStride);
+    take(w.tile_seg[k], max_tiles);
+    take(w.jobs[k], njobs);
+    take(w.jctr[k], njobs * kCtrStride);
+  }
+  take(w.part, max_tiles);
+  take(w.part2, max_tiles);
+  take(w.fr, max_seg);
+  take(w.epart, ext_tiles);
+  take(w.opart, ext_tiles);
+  take(w.oct, nreq);
+  take(w.tcount, ext_tiles);
+  take(w.toff, ext_tiles + 1);
+  take(w.tile_req, ext_tiles);
+  take(w.req, nreq);
+  take(w.nodes, std::max<size_t>(N + 3 * nreq + 64, 4096));
+  take(w.level_nodes, std::min<size_t>(N, size_t(1) << 20) + 64);
+  BatchCounts* counts = reinterpret_cast<BatchCounts*>(raw(sizeof(BatchCounts)));
+  Status* status = reinterpret_cast<Status*>(raw(kStatusRing * sizeof(Status)));
+  if (base) {
+    w.counts_dev = counts;
+    w.status_dev = status;
+    w.cap_pts = N;
+    w.fixed = true;
+  }
+  return off;
+}
+
+size_t ws_bytes(size_t N, size_t nreq, const vqhull_config& cfg) {
+  Context sizing;
+  return ws_layout(sizing, nullptr, N, nreq, cfg);
+}
+
+// The contexts of the _ws calls: host-side state only (pinned staging, the
+// pinned status copies, events), one per concurrent call, pooled per device.
+std::mutex g_wsc_mu;
+std::map<int, std::vector<Context*>> g_wsc_free;
+
+Context* acquire_ws_context() {
+  int dev = 0;
+  ck(hipGetDevice(&dev), "hipGetDevice");
+  {
+    std::lock_guard<std::mutex> g(g_wsc_mu);
+    auto& v = g_wsc_free[dev];
+    if (!v.empty()) {
+      Context* c = v.back();
+      v.pop_back();
+      return c;
+    }
+  }
+  return new_context(false);
+}
+
+// Forget every view into the caller's workspace, then return the context to
+// its device's pool.
+void release_ws_context(Context* c) {
+  for (int k = 0; k < 2; ++k) {
+    c->wx[k] = c->wy[k] = nullptr;
+    c->wi[k] = nullptr;
+    c->seg[k] = {};
+    c->ctr[k] = {};
+    c->tile_seg[k] = {};
+    c->jobs[k] = {};
+    c->jctr[k] = {};
+  }
+  c->part = {};
+  c->part2 = {};
+  c->fr = {};
+  c->epart = {};
+  c->opart = {};
+  c->oct = {};
+  c->tcount = {};
+  c->toff = {};
+  c->tile_req = {};
+  c->req = {};
+  c->nodes = {};
+  c->level_nodes = {};
+  c->counts_dev = nullptr;
+  c->status_dev = nullptr;
+  c->cap_pts = 0;
+  c->fixed = false;
+  std::lock_guard<std::mutex> g(g_wsc_mu);
+  g_wsc_free[c->device].push_back(c);
+}
+
+int guarded_ws(const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
+               int64_t* out_counts, void* ws, size_t ws_size, vqhull_stream_t stream) {
+  const vqhull_config cfg = current_config();
+  const size_t N = (size_t)offsets[nreq];
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) % kWsAlign) != 0 || ws_size < ws_bytes(N, (size_t)nreq, cfg)) {
+    g_last_error = "workspace missing, misaligned or smaller than vqhull_workspace_bytes()";
+    return VQHULL_ERR_INVALID_ARGUMENT;
+  }
+  Context* c = nullptr;
+  int st = guard_status([&] { c = acquire_ws_context(); });
+  if (st != VQHULL_OK) return st;
+  st = guard_status([&] {
+    ws_layout(*c, static_cast<char*>(ws), N, (size_t)nreq, cfg);
+    run(*c, cfg, x, y, offsets, nreq, out_idx, out_counts, (hipStream_t)stream);
+  });
+  release_ws_context(c);
+  return st;
 }
 
 // Offsets: offsets[0] = 0, non-decreasing, total below 2^31.
@@ -922,6 +1094,33 @@ int vqhull_hull_batched(const double* x, const double* y, const int64_t* offsets
   if (offsets[nreq] >= (int64_t(1) << 31)) return VQHULL_ERR_INVALID_ARGUMENT;
   if (offsets[nreq] > 0 && (!x || !y)) return VQHULL_ERR_INVALID_ARGUMENT;
   return guarded(x, y, offsets, nreq, out_idx, out_counts, stream);
+}
+
+size_t vqhull_workspace_bytes(int64_t n_total, int64_t nreq) {
+  if (n_total < 0 || n_total >= (int64_t(1) << 31) || nreq < 0 || nreq >= (int64_t(1) << 31)) return 0;
+  try {
+    return ws_bytes((size_t)n_total, (size_t)nreq, current_config());
+  } catch (...) {
+    return 0;
+  }
+}
+
+int vqhull_hull_ws(const double* x, const double* y, int64_t n, int64_t* out_idx, int64_t* out_count,
+                   void* workspace, size_t workspace_bytes, vqhull_stream_t stream) {
+  if (n < 0 || n >= (int64_t(1) << 31) || !out_idx || !out_count || (n > 0 && (!x || !y)))
+    return VQHULL_ERR_INVALID_ARGUMENT;
+  const int64_t offsets[2] = {0, n};
+  return guarded_ws(x, y, offsets, 1, out_idx, out_count, workspace, workspace_bytes, stream);
+}
+
+int vqhull_hull_batched_ws(const double* x, const double* y, const int64_t* offsets, int64_t nreq,
+                           int64_t* out_idx, int64_t* out_counts, void* workspace, size_t workspace_bytes,
+                           vqhull_stream_t stream) {
+  if (nreq < 0 || !offsets || nreq >= (int64_t(1) << 31)) return VQHULL_ERR_INVALID_ARGUMENT;
+  if (nreq == 0) return VQHULL_OK;
+  if (!out_counts || !out_idx || !offsets_valid(offsets, nreq)) return VQHULL_ERR_INVALID_ARGUMENT;
+  if (offsets[nreq] > 0 && (!x || !y)) return VQHULL_ERR_INVALID_ARGUMENT;
+  return guarded_ws(x, y, offsets, nreq, out_idx, out_counts, workspace, workspace_bytes, stream);
 }
 
 int vqhull_hull_xy(const double* xy, int64_t n, int64_t* out_idx, int64_t* out_count, vqhull_stream_t stream) {

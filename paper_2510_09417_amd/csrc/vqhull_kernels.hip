@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "vqhull_internal.h"
 
@@ -2593,13 +2594,13 @@ constexpr int kFinishBlock512 = 256, kFinishBlock1024 = 256, kFinishBlock2048 = 
 
 template <int BLOCK, int TMAX>
 int finish_attr() {
-  static bool done = false;
-  if (!done) {
+  static std::atomic<bool> done{false};  // set once (repeating the call is harmless)
+  if (!done.load(std::memory_order_acquire)) {
     hipError_t e = hipFuncSetAttribute((const void*)k_finish_plan<BLOCK, TMAX>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)finish_plan_lds<BLOCK, TMAX>());
     if (e != hipSuccess) return (int)e;
-    done = true;
+    done.store(true, std::memory_order_release);
   }
   return 0;
 }
@@ -2634,38 +2635,44 @@ bool sweep_shape_supported(int block, int ppt) {
          (block == 1024 && ppt == 8);
 }
 
+// Grid sizes are computed once per shape and cached (atomics: calls on
+// several host threads may ask at the same time; they compute equal values).
 uint32_t sweep_grid(int block, int ppt, int mode) {
-  static uint32_t cache[5][kSweepModes] = {};
+  static std::atomic<uint32_t> cache[5][kSweepModes] = {};
   const int k = block == 256 ? (ppt == 16 ? 0 : 1) : block == 512 ? (ppt == 8 ? 2 : 3) : 4;
-  if (!cache[k][mode]) {
+  uint32_t g = cache[k][mode].load(std::memory_order_relaxed);
+  if (!g) {
 #define VQH_GRID(K, B, P)                                                          \
   if (k == K)                                                                      \
-    cache[k][mode] = mode == kSweepArgmax     ? sweep_occupancy_grid<B, P, kSweepArgmax>()   \
-                     : mode == kSweepFused    ? sweep_occupancy_grid<B, P, kSweepFused>()    \
-                     : mode == kSweepArgmaxWs ? sweep_occupancy_grid<B, P, kSweepArgmaxWs>() \
-                     : mode == kSweepFusedWs  ? sweep_occupancy_grid<B, P, kSweepFusedWs>()  \
-                                              : sweep_occupancy_grid<B, P, kSweepLevel>();
+    g = mode == kSweepArgmax     ? sweep_occupancy_grid<B, P, kSweepArgmax>()   \
+        : mode == kSweepFused    ? sweep_occupancy_grid<B, P, kSweepFused>()    \
+        : mode == kSweepArgmaxWs ? sweep_occupancy_grid<B, P, kSweepArgmaxWs>() \
+        : mode == kSweepFusedWs  ? sweep_occupancy_grid<B, P, kSweepFusedWs>()  \
+                                 : sweep_occupancy_grid<B, P, kSweepLevel>();
     VQH_GRID(0, 256, 16)
     VQH_GRID(1, 256, 32)
     VQH_GRID(2, 512, 8)
     VQH_GRID(3, 512, 16)
     VQH_GRID(4, 1024, 8)
 #undef VQH_GRID
+    cache[k][mode].store(g, std::memory_order_relaxed);
   }
-  return cache[k][mode];
+  return g;
 }
 
 int finish_tmax_for(int lds_limit) { return lds_limit <= 512 ? 512 : lds_limit <= 1024 ? 1024 : 2048; }
 
 uint32_t finish_grid(int tmax) {
-  static uint32_t cache[3] = {0, 0, 0};
+  static std::atomic<uint32_t> cache[3] = {};
   const int k = tmax == 512 ? 0 : tmax == 1024 ? 1 : 2;
-  if (!cache[k]) {
-    if (k == 0) cache[k] = finish_occupancy_grid<kFinishBlock512, 512>();
-    if (k == 1) cache[k] = finish_occupancy_grid<kFinishBlock1024, 1024>();
-    if (k == 2) cache[k] = finish_occupancy_grid<kFinishBlock2048, 2048>();
+  uint32_t g = cache[k].load(std::memory_order_relaxed);
+  if (!g) {
+    if (k == 0) g = finish_occupancy_grid<kFinishBlock512, 512>();
+    if (k == 1) g = finish_occupancy_grid<kFinishBlock1024, 1024>();
+    if (k == 2) g = finish_occupancy_grid<kFinishBlock2048, 2048>();
+    cache[k].store(g, std::memory_order_relaxed);
   }
-  return cache[k];
+  return g;
 }
 
 int launch_extremes(const ExtremesArgs& a, void* stream) {
@@ -2761,13 +2768,13 @@ int launch_finish_plan(const FinishArgs& a, const PlanArgs& p, int tmax, void* s
 
 template <int BLOCK, int TMAX>
 int small_one(const SmallArgs& a, hipStream_t st) {
-  static bool done = false;
+  static std::atomic<bool> done{false};  // set once (repeating the call is harmless)
   const size_t lds = sizeof(FinishShared<BLOCK, TMAX>);
-  if (!done) {
+  if (!done.load(std::memory_order_acquire)) {
     const hipError_t e = hipFuncSetAttribute((const void*)k_small<BLOCK, TMAX>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return (int)e;
-    done = true;
+    done.store(true, std::memory_order_release);
   }
   hipLaunchKernelGGL((k_small<BLOCK, TMAX>), dim3(1), dim3(BLOCK), lds, st, a);
   return (int)hipGetLastError();

@@ -247,6 +247,23 @@ def size_sweep(out_md: str, dists=("disk", "square"), sizes=SIZE_SWEEP_SIZES, ca
     return rows
 
 
+def alg_bytes_batched(n_total: int, levels: list) -> dict:
+    """Algorithmic bytes of one batched call (any mix of request sizes) from
+    its level statistics: extremes 8 B per point (x) of every request; the
+    requests above the LDS threshold (level 0's segments, ``swept[0]``
+    points) are read twice at 16 B per point (argmax and fused passes); the
+    requests at most the threshold (level 0's jobs) are read once by the LDS
+    finisher at 16 B per point; deeper levels as in ``alg_bytes``."""
+    sw = [lv["swept"] for lv in levels]
+    jp = [lv["job_points"] for lv in levels]
+    top = 8 * n_total + 32 * (sw[0] if sw else 0) + 16 * (jp[0] if jp else 0)
+    writes = 20 * ((jp[1] if len(jp) > 1 else 0) + sum(sw[k] + jp[k] for k in range(2, len(levels))))
+    level_reads = 20 * sum(sw[k] for k in range(2, len(levels)))
+    finisher = 20 * sum(jp[k] for k in range(1, len(levels)))
+    total = top + writes + level_reads + finisher
+    return {"top": top, "writes": writes, "level_reads": level_reads, "finisher_reads": finisher, "total": total}
+
+
 def alg_bytes(n: int, levels: list) -> dict:
     """Algorithmic bytes of one plain hull of a single request of more than
     the LDS threshold's points, from its level statistics (level k: segments

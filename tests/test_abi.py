@@ -187,3 +187,64 @@ def test_status_constants_follow_the_header():
     lib = vq.load_library()
     texts = {lib.vqhull_status_string(v) for v in enum.values()}
     assert len(texts) == len(enum) and not any(b"unknown" in t for t in texts)
+
+
+def test_workspace_bytes_on_host():
+    """vqhull_workspace_bytes: 0 outside [0, 2^31); about 72 bytes per point
+    (two 20-byte ping-pong point buffers and one 32-byte node per point) plus
+    tables, growing with the point count and the request count, and following
+    the configuration's LDS threshold (segment tables)."""
+    import paper_2510_09417_amd as vq
+
+    lib = vq.load_library()
+    assert lib.vqhull_workspace_bytes(-1, 1) == 0
+    assert lib.vqhull_workspace_bytes(1 << 31, 1) == 0
+    assert lib.vqhull_workspace_bytes(10, -1) == 0
+    with pytest.raises(ValueError):
+        vq.workspace_bytes(-5)
+    small = vq.workspace_bytes(0, 0)
+    assert 0 < small < 1 << 20
+    prev = 0
+    for n in (1, 1000, 10**6, 10**8):
+        b = vq.workspace_bytes(n, 1)
+        assert b > prev and b % 256 == 0
+        prev = b
+    b = vq.workspace_bytes(10**8, 1)
+    assert 72 * 10**8 <= b <= 76 * 10**8
+    assert vq.workspace_bytes(10**6, 1000) > vq.workspace_bytes(10**6, 1)
+    old = vq.get_config()
+    try:
+        vq.set_config(lds_limit=256)
+        b256 = vq.workspace_bytes(10**7, 1)
+        vq.set_config(lds_limit=2048)
+        assert b256 > vq.workspace_bytes(10**7, 1)
+    finally:
+        vq.set_config(**old)
+
+
+def test_workspace_calls_reject_bad_arguments_on_host(lib):
+    """The _ws calls check their arguments and the workspace (null, not
+    256-byte aligned, smaller than vqhull_workspace_bytes) before any HIP
+    call."""
+    import paper_2510_09417_amd as vq
+
+    vp = ctypes.c_void_p
+    dummy = vp(0x1000)
+    need = vq.workspace_bytes(5, 1)
+    ws = vp(0x100000)
+    assert lib.vqhull_hull_ws(dummy, dummy, -1, dummy, dummy, ws, need, None) == 1
+    assert lib.vqhull_hull_ws(None, dummy, 5, dummy, dummy, ws, need, None) == 1
+    assert lib.vqhull_hull_ws(dummy, dummy, 5, None, dummy, ws, need, None) == 1
+    assert lib.vqhull_hull_ws(dummy, dummy, 5, dummy, dummy, None, need, None) == 1
+    assert lib.vqhull_hull_ws(dummy, dummy, 5, dummy, dummy, vp(0x100080), need, None) == 1  # misaligned
+    assert lib.vqhull_hull_ws(dummy, dummy, 5, dummy, dummy, ws, need - 1, None) == 1  # too small
+    off = np.array([0, 3, 5], dtype=np.int64)
+    p = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    need2 = vq.workspace_bytes(5, 2)
+    assert lib.vqhull_hull_batched_ws(dummy, dummy, p, 2, dummy, dummy, ws, need2 - 256, None) == 1
+    assert lib.vqhull_hull_batched_ws(dummy, dummy, p, 2, dummy, dummy, None, need2, None) == 1
+    bad = np.array([0, 5, 3], dtype=np.int64)
+    assert lib.vqhull_hull_batched_ws(dummy, dummy, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 2, dummy,
+                                      dummy, ws, need2, None) == 1
+    assert lib.vqhull_hull_batched_ws(dummy, dummy, None, 2, dummy, dummy, ws, need2, None) == 1
+    assert lib.vqhull_hull_batched_ws(dummy, dummy, p, 0, dummy, dummy, None, 0, None) == 0  # nothing to do

@@ -86,3 +86,21 @@ def test_alg_bytes_counts_every_move():
     assert b["level_reads"] == 20 * 30
     assert b["finisher_reads"] == 20 * (5 + 10 + 6)
     assert b["total"] == b["top"] + b["writes"] + b["level_reads"] + b["finisher_reads"]
+
+
+def test_alg_bytes_batched_reduces_to_single_and_counts_small_requests():
+    from paper_2510_09417_amd import profiling
+
+    levels = [dict(segments=1, swept=100, jobs=0, job_points=0),
+              dict(segments=2, swept=90, jobs=1, job_points=5),
+              dict(segments=2, swept=30, jobs=2, job_points=10),
+              dict(segments=0, swept=0, jobs=3, job_points=6)]
+    assert profiling.alg_bytes_batched(100, levels) == profiling.alg_bytes(100, levels)
+    # a request of 100 points above the LDS threshold and two small ones of 7
+    # and 9 points (root jobs: read once by the finisher)
+    mixed = [dict(segments=1, swept=100, jobs=2, job_points=16)] + levels[1:]
+    b = profiling.alg_bytes_batched(116, mixed)
+    assert b["top"] == 8 * 116 + 32 * 100 + 16 * 16
+    assert b["total"] - b["top"] == profiling.alg_bytes(100, levels)["total"] - profiling.alg_bytes(100, levels)["top"]
+    only_small = [dict(segments=0, swept=0, jobs=3, job_points=40)]
+    assert profiling.alg_bytes_batched(40, only_small)["total"] == 8 * 40 + 16 * 40

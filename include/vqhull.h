@@ -150,8 +150,7 @@ int vqhull_hull_batched_xy(const double* xy, const int64_t* offsets, int64_t nre
  *   staging and events are created once per concurrent caller and reused).
  *   Calls on different streams with different workspaces may run
  *   concurrently; one workspace must not be used by two calls at once.  Like
- *   vqhull_hull, a call returns after its result has been written.  Level
- *   statistics and kernel timing are not recorded for these calls.
+ *   vqhull_hull, a call returns after its result has been written.
  */
 size_t vqhull_workspace_bytes(int64_t n_total, int64_t nreq);
 int vqhull_hull_ws(const double* x, const double* y, int64_t n, int64_t* out_idx, int64_t* out_count,
@@ -206,12 +205,13 @@ typedef struct {
 int vqhull_autotune(const double* x, const double* y, int64_t n, int32_t repeats, vqhull_tune_entry* entries,
                     int64_t cap, int64_t* count, vqhull_config* best, vqhull_stream_t stream);
 
-/* Per-level statistics of the last hull call on this device (host pointer,
+/* Per-level statistics of the last hull call on this device (vqhull_hull,
+ * vqhull_hull_batched, their interleaved and _ws forms; host pointer,
  * up to cap entries of 4 int64: live subproblems, points swept, subproblems
  * finished in LDS, points finished in LDS).  Returns the number of levels. */
 int64_t vqhull_last_level_stats(int64_t* out, int64_t cap);
 
-/* Kernel timing of the last hull call on this device, for benchmarks: when
+/* Kernel timing of the last hull call on this device (the same calls), for benchmarks: when
  * enabled, HIP events are recorded on the call's stream around every kernel
  * launch.  Kinds: */
 enum {

@@ -83,13 +83,20 @@ _lib = None
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
-    """Load ``libvqhull.so`` (raises FileNotFoundError if it has not been built)."""
+    """Load ``libvqhull.so`` (raises FileNotFoundError if it has not been built).
+
+    torch is imported first: its wheel carries its own HIP runtime, whose
+    soname (libamdhip64.so.7) the library's dependency then resolves to, so the
+    process holds one HIP runtime.  Loaded the other way round, the process
+    would hold two, and the one initialized second sees no GPU."""
     global _lib
     with _lock:
         if _lib is not None:
             return _lib
         if not os.path.exists(path):
             raise FileNotFoundError(f"{path} is not built; run `python -m paper_2510_09417_amd.build`")
+        import torch  # noqa: F401  (see above)
+
         lib = ctypes.CDLL(path)
         vp, i64, pi64 = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)
         lib.vqhull_hull.restype = ctypes.c_int

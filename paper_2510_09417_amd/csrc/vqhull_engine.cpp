@@ -755,10 +755,31 @@ int guard_status(F&& f) {
   return VQHULL_OK;
 }
 
+// Level statistics and kernel times of the last public hull call per device
+// (whichever context ran it), for vqhull_last_level_stats / _kernel_times.
+struct LastCall {
+  std::vector<LevelStat> stats;
+  std::vector<vqhull_kernel_time> times;
+};
+std::mutex g_last_mu;
+std::map<int, LastCall> g_last;
+
+void publish_last(const Context& w) {
+  std::lock_guard<std::mutex> g(g_last_mu);
+  LastCall& L = g_last[w.device];
+  L.stats = w.stats;
+  if (g_timing.load())
+    L.times = w.times;
+  else
+    L.times.clear();
+}
+
 int guarded(const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
             int64_t* out_counts, vqhull_stream_t stream, const double* xy = nullptr) {
   return guard_status([&] {
-    run(default_context(), current_config(), x, y, offsets, nreq, out_idx, out_counts, (hipStream_t)stream, xy);
+    Context& w = default_context();
+    run(w, current_config(), x, y, offsets, nreq, out_idx, out_counts, (hipStream_t)stream, xy);
+    publish_last(w);
   });
 }
 
@@ -907,6 +928,7 @@ int guarded_ws(const double* x, const double* y, const int64_t* offsets, int64_t
   st = guard_status([&] {
     ws_layout(*c, static_cast<char*>(ws), N, (size_t)nreq, cfg);
     run(*c, cfg, x, y, offsets, nreq, out_idx, out_counts, (hipStream_t)stream);
+    publish_last(*c);
   });
   release_ws_context(c);
   return st;
@@ -1216,13 +1238,12 @@ int vqhull_set_config(const vqhull_config* cfg) {
 }
 
 int64_t vqhull_last_level_stats(int64_t* out, int64_t cap) {
-  std::lock_guard<std::mutex> guard(g_ws_mu);  // the default context of the current device
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
-  auto it = g_ws.find(dev);
-  if (it == g_ws.end()) return 0;
-  std::lock_guard<std::mutex> cguard(it->second->mu);
-  const auto& st = it->second->stats;
+  std::lock_guard<std::mutex> g(g_last_mu);
+  auto it = g_last.find(dev);
+  if (it == g_last.end()) return 0;
+  const auto& st = it->second.stats;
   for (int64_t i = 0; i < (int64_t)st.size() && i < cap && out; ++i) {
     out[4 * i + 0] = st[i].segs;
     out[4 * i + 1] = st[i].swept;
@@ -1259,13 +1280,12 @@ int vqhull_set_timing(int enable) {
 }
 
 int64_t vqhull_last_kernel_times(vqhull_kernel_time* out, int64_t cap) {
-  std::lock_guard<std::mutex> guard(g_ws_mu);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
-  auto it = g_ws.find(dev);
-  if (it == g_ws.end()) return 0;
-  std::lock_guard<std::mutex> cguard(it->second->mu);
-  const auto& t = it->second->times;
+  std::lock_guard<std::mutex> g(g_last_mu);
+  auto it = g_last.find(dev);
+  if (it == g_last.end()) return 0;
+  const auto& t = it->second.times;
   for (int64_t i = 0; i < (int64_t)t.size() && i < cap && out; ++i) out[i] = t[i];
   return (int64_t)t.size();
 }

@@ -1,7 +1,7 @@
 """Energy per hull from the GPU's own energy counter, idle draw subtracted.
 
 The paper reports the energy of its runs from the CPU package's RAPL energy
-counters, against the machine at rest (Section 5.6).  The GPU analog used here
+counters, against the machine at rest (Section 5.7).  The GPU analog used here
 reads the device's accumulated-energy counter through the amd-smi library
 before and after a loop of hull calls, and subtracts the energy the same GPU
 draws when idle for the same time (measured just before, from the same
@@ -17,7 +17,8 @@ import time
 def _hip_bdf(device: int) -> str | None:
     """PCI address of a HIP device ("dddd:bb:dd.f"), or None."""
     try:
-        hip = ctypes.CDLL("libamdhip64.so")
+        # by soname: the HIP runtime already in the process (torch's), not a second copy
+        hip = ctypes.CDLL("libamdhip64.so.7")
         buf = ctypes.create_string_buffer(64)
         if hip.hipDeviceGetPCIBusId(buf, ctypes.c_int(64), ctypes.c_int(device)) != 0:
             return None

@@ -8,7 +8,8 @@ the result is checked by properties that hold at any size:
 * 8*10^6 sampled input points are not outside any hull edge by more than the
   binary64 rounding bound of the orientation value;
 * the same list with the octagon prefilter on (a second code path).
-About 150 GB of device memory; everything is released at the end."""
+The calls use the library-owned workspace (vqhull_hull): about 150 GB of
+device memory in all; everything is released at the end."""
 import numpy as np
 import pytest
 from fractions import Fraction
@@ -46,8 +47,14 @@ def test_max_size_square(vq):
     g.manual_seed(2031)
     x = torch.rand(N, dtype=torch.float64, device="cuda", generator=g)
     y = torch.rand(N, dtype=torch.float64, device="cuda", generator=g)
+    def hull(x, y):  # the library-owned workspace (40 B per point): the _ws path needs 73 B per point
+        oi = torch.empty(N, dtype=torch.int64, device="cuda")
+        oc = torch.empty(1, dtype=torch.int64, device="cuda")
+        vq.hull_into(x, y, oi, oc)
+        return oi[: int(oc.item())]
+
     try:
-        out = vq.hull(x, y)
+        out = hull(x, y)
         h = out.numel()
         idx = out.cpu().numpy()
         assert 3 <= h < 1000
@@ -79,7 +86,7 @@ def test_max_size_square(vq):
         # the prefiltered path gives the same list
         vq.set_config(prefilter=1)
         try:
-            assert torch.equal(vq.hull(x, y), out)
+            assert torch.equal(hull(x, y), out)
         finally:
             vq.set_config(prefilter=0)
         print(f"max size: n={N} h={h}, {torch.cuda.max_memory_allocated() >> 30} GiB allocated at most", flush=True)

@@ -159,6 +159,27 @@ int vqhull_hull_batched_ws(const double* x, const double* y, const int64_t* offs
                            int64_t* out_idx, int64_t* out_counts, void* workspace, size_t workspace_bytes,
                            vqhull_stream_t stream);
 
+/*
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): vqhull_hull with every device table in a
+ * static device array of the library, VQHULL_NOALLOC_MAX_POINTS points at
+ * most (84 MiB, one copy per GPU the library runs on, held until the process
+ * ends).  Arguments, result and errors are those of vqhull_hull, plus
+ * VQHULL_ERR_INVALID_ARGUMENT for n > VQHULL_NOALLOC_MAX_POINTS.  The call
+ * makes no hipMalloc, hipFree, pinned-memory or event allocation: levels are
+ * enqueued in chunks whose kernels read their work counts from the device,
+ * and the host waits on the stream once per chunk.  Calls on one GPU share its
+ * array: the library runs them one at a time (a mutex per GPU), each returning
+ * after its result is written, so their contents never mix; the array keeps
+ * the last call's contents, which no call reads before writing.  Not for use
+ * inside stream capture (the call waits on the stream).  Level statistics
+ * and kernel times (vqhull_last_level_stats, vqhull_last_kernel_times) are
+ * not recorded for it.
+ */
+#define VQHULL_NOALLOC_MAX_POINTS 1048576
+int vqhull_hull_noalloc(const double* x, const double* y, int64_t n, int64_t* out_idx, int64_t* out_count,
+                        vqhull_stream_t stream);
+
 /* Tuning knobs of the hull kernels (all values are rounded to supported ones). */
 typedef struct {
   int sweep_block;  /* threads per workgroup of the partition sweep: 256, 512 or 1024 */

@@ -24,7 +24,7 @@ VQHULL_ERR_TIMEOUT = 5
 # Symbols that include/vqhull.h declares.
 EXPORTED = (
     "vqhull_hull", "vqhull_hull_batched", "vqhull_workspace_bytes", "vqhull_hull_ws", "vqhull_hull_batched_ws",
-    "vqhull_hull_xy", "vqhull_hull_batched_xy", "vqhull_get_config", "vqhull_set_config", "vqhull_autotune",
+    "vqhull_hull_noalloc", "vqhull_hull_xy", "vqhull_hull_batched_xy", "vqhull_get_config", "vqhull_set_config", "vqhull_autotune",
     "vqhull_last_level_stats", "vqhull_set_timing", "vqhull_last_kernel_times", "vqhull_orient", "vqhull_stream_scale",
     "vqhull_release_workspace", "vqhull_status_string", "vqhull_last_error",
     "vqhull_server_create", "vqhull_server_submit", "vqhull_server_submit_batch", "vqhull_server_wait", "vqhull_server_wait_timeout",
@@ -109,6 +109,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.vqhull_hull_ws.argtypes = [vp, vp, i64, vp, vp, vp, ctypes.c_size_t, vp]
         lib.vqhull_hull_batched_ws.restype = ctypes.c_int
         lib.vqhull_hull_batched_ws.argtypes = [vp, vp, pi64, i64, vp, vp, vp, ctypes.c_size_t, vp]
+        lib.vqhull_hull_noalloc.restype = ctypes.c_int
+        lib.vqhull_hull_noalloc.argtypes = [vp, vp, i64, vp, vp, vp]
         lib.vqhull_hull_xy.restype = ctypes.c_int
         lib.vqhull_hull_xy.argtypes = [vp, i64, vp, vp, vp]
         lib.vqhull_hull_batched_xy.restype = ctypes.c_int
@@ -232,6 +234,20 @@ def hull_ws_into(x, y, out_idx, out_count, ws, stream=None) -> None:
     st = lib.vqhull_hull_ws(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), x.numel(),
                             ctypes.c_void_p(out_idx.data_ptr()), ctypes.c_void_p(out_count.data_ptr()),
                             ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), _stream_handle(stream))
+    _check(lib, st)
+
+
+NOALLOC_MAX_POINTS = 1 << 20  # VQHULL_NOALLOC_MAX_POINTS
+
+
+def hull_noalloc_into(x, y, out_idx, out_count, stream=None) -> None:
+    """vqhull_hull_noalloc: vqhull_hull with every device table in the
+    library's static per-GPU array (at most NOALLOC_MAX_POINTS points); the
+    library allocates nothing.  Returns after the result is written."""
+    lib = load_library()
+    st = lib.vqhull_hull_noalloc(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), x.numel(),
+                                 ctypes.c_void_p(out_idx.data_ptr()), ctypes.c_void_p(out_count.data_ptr()),
+                                 _stream_handle(stream))
     _check(lib, st)
 
 

@@ -89,6 +89,7 @@ struct Context {
   Status* status_dev = nullptr;   // kStatusRing records
   Status* status_host = nullptr;  // pinned copies, written by the planners
   Status* status_host_dev = nullptr;  // device view of status_host
+  Status* status_mirror = nullptr;    // a device ring the planners may write instead (no pinned memory)
   hipEvent_t status_ev[kStatusRing] = {};
   // pinned staging
   Req* h_req = nullptr;
@@ -848,9 +849,11 @@ size_t ws_layout(Context& w, char* base, size_t N, size_t nreq, const vqhull_con
   take(w.level_nodes, std::min<size_t>(N, size_t(1) << 20) + 64);
   BatchCounts* counts = reinterpret_cast<BatchCounts*>(raw(sizeof(BatchCounts)));
   Status* status = reinterpret_cast<Status*>(raw(kStatusRing * sizeof(Status)));
+  Status* mirror = reinterpret_cast<Status*>(raw(kStatusRing * sizeof(Status)));
   if (base) {
     w.counts_dev = counts;
     w.status_dev = status;
+    w.status_mirror = mirror;
     w.cap_pts = N;
     w.fixed = true;
   }
@@ -932,6 +935,98 @@ int guarded_ws(const double* x, const double* y, const int64_t* offsets, int64_t
   });
   release_ws_context(c);
   return st;
+}
+
+// ------------------------------------------ the entry point that allocates nothing
+//
+// vqhull_hull_noalloc keeps every device table of a call in `scratch`, a
+// static device array of the library (one copy per GPU, at that GPU's own
+// address, taken once per device with hipGetSymbolAddress).  It sizes the
+// tables for VQHULL_NOALLOC_MAX_POINTS points under the most demanding
+// configuration (LDS threshold 256, 4096-point tiles: 81.9 MiB).  The level
+// loop is device-driven: levels are enqueued in chunks whose kernels read
+// their work counts from the device, and the host reads one status record per
+// chunk (a copy into static host memory), so no event, pinned buffer or other
+// allocation is needed.
+
+constexpr size_t kNoAllocBytes = size_t(84) << 20;
+constexpr int kNoAllocChunk = 8;  // levels enqueued between two status reads
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+namespace vqh {
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+}  // namespace vqh
+
+namespace {
+
+struct NoAllocDevice {
+  std::mutex mu;          // calls on one GPU run one at a time (they share its scratch)
+  char* ptr = nullptr;    // this device's address of scratch
+  Context ctx;            // views into scratch; no host staging
+  Req req{};              // host staging of the request table and counts (static storage:
+  BatchCounts counts{};   // a pageable source that outlives the asynchronous copy)
+  Status status{};
+  BatchCounts counts_back{};
+};
+NoAllocDevice g_noalloc[kMaxDevices];
+
+// One request of n > 0 points; every table already laid out in w.
+void run_fixed_single(Context& w, vqhull_config cfg, const double* x, const double* y, uint32_t n, int64_t* out_idx,
+                      int64_t* out_count, hipStream_t st, NoAllocDevice& d) {
+  cfg.sweep_persistent = 1;  // grids must not depend on counts the host has not read
+  if (n <= (uint32_t)cfg.lds_limit) {
+    SmallArgs sa{x, y, n, out_idx, out_count, w.wi[0], w.nodes.p, w.req.p};
+    ck(launch_small(sa, finish_tmax_for(cfg.lds_limit), st), "k_small");
+    ck(hipStreamSynchronize(st), "hipStreamSynchronize");
+    return;
+  }
+  d.req = Req{};
+  d.req.off = 0;
+  d.req.n = n;
+  d.req.root = -1;
+  d.req.tile0 = 0;
+  d.counts = BatchCounts{1u, (n + kExtTile - 1) / kExtTile, 0u, 0u};
+  ck(hipMemcpyAsync(w.req.p, &d.req, sizeof(Req), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+  ck(hipMemcpyAsync(w.counts_dev, &d.counts, sizeof(BatchCounts), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+  const ExtremesArgs ea{x, y, nullptr, w.req.p, w.epart.p, w.counts_dev, d.counts.ext_tiles};
+  ck(launch_extremes(ea, st), "k_extremes");
+  ck(launch_plan0(plan0_args(w, cfg), st), "k_plan0");
+  const int tmax = finish_tmax_for(cfg.lds_limit);
+  int k = 0;
+  for (;;) {
+    for (int j = 0; j < kNoAllocChunk; ++j, ++k) {
+      if ((size_t)k + 3 > w.level_nodes.cap) ck(hipErrorOutOfMemory, "recursion deeper than the level table");
+      const int mode = sweep_mode(k, false);
+      int blk = 0, ppt = 0;
+      level_shape(cfg, k, blk, ppt);
+      const uint32_t G = sweep_grid(blk, ppt, mode);
+      ck(launch_sweep(sweep_args(w, cfg, k, x, y, false), mode, blk, ppt, G, st), "k_sweep");
+      ck(launch_finish_plan(finish_args(w, x, y, k), plan_args(w, cfg, k, G), tmax, st), "k_finish_plan");
+    }
+    ck(hipMemcpyAsync(&d.status, w.status_dev + k % kStatusRing, sizeof(Status), hipMemcpyDeviceToHost, st),
+       "hipMemcpyAsync");
+    ck(hipMemcpyAsync(&d.counts_back, w.counts_dev, sizeof(BatchCounts), hipMemcpyDeviceToHost, st),
+       "hipMemcpyAsync");
+    ck(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (d.status.overflow || d.counts_back.overflow) ck(hipErrorOutOfMemory, "node table");
+    if (d.status.nseg == 0 && d.status.njobs == 0) break;  // level k has no work: the recursion is done
+  }
+  AssembleArgs aa{};
+  aa.nodes = w.nodes.p;
+  aa.level_begin = w.level_nodes.p;
+  aa.nlevels = (uint32_t)k + 1u;
+  aa.req = w.req.p;
+  aa.counts = w.counts_dev;
+  aa.lists[0] = w.wi[0];
+  aa.lists[1] = w.wi[1];
+  aa.out_idx = out_idx;
+  aa.out_count = out_count;
+  aa.max_nodes = (uint32_t)std::min<size_t>(w.nodes.cap, 0xFFFFFFFFu);
+  ck(launch_assemble(aa, st), "k_assemble");
+  ck(launch_copy_lists(aa, st), "k_copy_lists");
+  ck(hipStreamSynchronize(st), "hipStreamSynchronize");
 }
 
 // Offsets: offsets[0] = 0, non-decreasing, total below 2^31.
@@ -1143,6 +1238,39 @@ int vqhull_hull_batched_ws(const double* x, const double* y, const int64_t* offs
   if (!out_counts || !out_idx || !offsets_valid(offsets, nreq)) return VQHULL_ERR_INVALID_ARGUMENT;
   if (offsets[nreq] > 0 && (!x || !y)) return VQHULL_ERR_INVALID_ARGUMENT;
   return guarded_ws(x, y, offsets, nreq, out_idx, out_counts, workspace, workspace_bytes, stream);
+}
+
+int vqhull_hull_noalloc(const double* x, const double* y, int64_t n, int64_t* out_idx, int64_t* out_count,
+                        vqhull_stream_t stream) {
+  if (n < 0 || n > VQHULL_NOALLOC_MAX_POINTS || !out_idx || !out_count || (n > 0 && (!x || !y))) {
+    g_last_error = "vqhull_hull_noalloc: invalid argument or more than VQHULL_NOALLOC_MAX_POINTS points";
+    return VQHULL_ERR_INVALID_ARGUMENT;
+  }
+  const vqhull_config cfg = current_config();
+  if (ws_bytes((size_t)n, 1, cfg) > kNoAllocBytes) {  // cannot happen for n within the limit
+    g_last_error = "vqhull_hull_noalloc: the static scratch array is too small for this configuration";
+    return VQHULL_ERR_INVALID_ARGUMENT;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    g_last_error = "vqhull_hull_noalloc: no usable current device";
+    return VQHULL_ERR_HIP;
+  }
+  NoAllocDevice& d = g_noalloc[dev];
+  std::lock_guard<std::mutex> guard(d.mu);
+  return guard_status([&] {
+    hipStream_t st = (hipStream_t)stream;
+    if (!d.ptr) {  // once per device, with that device current: its own address of the array
+      void* p = nullptr;
+      ck(hipGetSymbolAddress(&p, HIP_SYMBOL(vqh::scratch)), "hipGetSymbolAddress");
+      d.ptr = static_cast<char*>(p);
+      d.ctx.device = dev;
+    }
+    Context& w = d.ctx;
+    ws_layout(w, d.ptr, (size_t)n, 1, cfg);
+    w.status_host_dev = w.status_mirror;
+    run_fixed_single(w, cfg, x, y, (uint32_t)n, out_idx, out_count, st, d);
+  });
 }
 
 int vqhull_hull_xy(const double* xy, int64_t n, int64_t* out_idx, int64_t* out_count, vqhull_stream_t stream) {

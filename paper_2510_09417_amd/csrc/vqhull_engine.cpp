@@ -368,6 +368,7 @@ FinishArgs finish_args(Context& w, const double* x, const double* y, int k) {
   fa.jobs = w.jobs[k & 1].p;
   fa.ux = x;
   fa.uy = y;
+  fa.req_arrays = 1u;
   for (int b = 0; b < 2; ++b) {
     fa.bx[b] = w.wx[b];
     fa.by[b] = w.wy[b];
@@ -700,6 +701,8 @@ void run(Context& w, const vqhull_config& cfg, const double* x, const double* y,
     r.n = (uint32_t)(offsets[i + 1] - offsets[i]);
     r.root = -1;
     r.tile0 = (uint32_t)ext_tiles;
+    r.x = x ? x + offsets[i] : nullptr;
+    r.y = y ? y + offsets[i] : nullptr;
     ext_tiles += (r.n + kExtTile - 1) / kExtTile;
     if (r.n > lds_limit) tiles0 += (r.n + tile - 1) / tile;
     w.h_req[i] = r;
@@ -987,6 +990,8 @@ void run_fixed_single(Context& w, vqhull_config cfg, const double* x, const doub
   d.req.n = n;
   d.req.root = -1;
   d.req.tile0 = 0;
+  d.req.x = x;
+  d.req.y = y;
   d.counts = BatchCounts{1u, (n + kExtTile - 1) / kExtTile, 0u, 0u};
   ck(hipMemcpyAsync(w.req.p, &d.req, sizeof(Req), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
   ck(hipMemcpyAsync(w.counts_dev, &d.counts, sizeof(BatchCounts), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
@@ -1104,7 +1109,8 @@ int context_reserve_fixed(Context* c, int64_t npoints, int64_t nreq, int levels,
   });
 }
 
-int context_stage(Context* c, const int64_t* offsets, int64_t nreq) {
+int context_stage(Context* c, const int64_t* offsets, int64_t nreq, const double* const* xs,
+                  const double* const* ys) {
   std::lock_guard<std::mutex> guard(c->mu);
   const vqhull_config cfg = current_config();
   const uint32_t tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
@@ -1118,6 +1124,8 @@ int context_stage(Context* c, const int64_t* offsets, int64_t nreq) {
     r.n = (uint32_t)(offsets[i + 1] - offsets[i]);
     r.root = -1;
     r.tile0 = (uint32_t)ext_tiles;
+    r.x = xs[i];
+    r.y = ys[i];
     ext_tiles += (r.n + kExtTile - 1) / kExtTile;
     c->h_req[i] = r;
   }

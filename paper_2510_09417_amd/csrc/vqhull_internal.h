@@ -30,6 +30,11 @@ struct Req {
   uint32_t err;     // set to 1 by a kernel that sees a non-finite coordinate
   uint32_t tile0;   // first extremes tile of this request
   uint32_t pad;
+  // The request's own coordinate arrays: its point j is (x[j], y[j]).  The
+  // kernels that read the caller's points take them from here, so requests
+  // need not sit in one array (the server's lanes read them where they are).
+  const double* x;
+  const double* y;
 };
 
 // A live subproblem Hull(P, a, r, b): P is the point range [beg, beg + cnt) of
@@ -137,7 +142,10 @@ int context_run(Context* c, const double* x, const double* y, const int64_t* off
 const char* context_last_error();  // of the calling thread
 
 // Fixed launch sequence for graph capture.  context_stage fills the
-// context's pinned tables for a batch (host only); context_enqueue_fixed
+// context's pinned tables for a batch (host only), request i at offsets[i]
+// with its own coordinate arrays xs[i], ys[i] (the kernels read the requests
+// where they are; x and y passed to context_enqueue_fixed are not read for
+// them); context_enqueue_fixed
 // enqueues copies of those tables and `levels` recursion levels with grids
 // sized for the reserved capacity (context_reserve with the same levels):
 // no allocation, no host wait, the same launches for every batch.  Once the
@@ -145,7 +153,8 @@ const char* context_last_error();  // of the calling thread
 // within `levels` levels without a table overflow; if not, the batch must be
 // recomputed with context_run.
 int context_reserve_fixed(Context* c, int64_t npoints, int64_t nreq, int levels, void* stream);
-int context_stage(Context* c, const int64_t* offsets, int64_t nreq);
+int context_stage(Context* c, const int64_t* offsets, int64_t nreq, const double* const* xs,
+                  const double* const* ys);
 int context_enqueue_fixed(Context* c, const double* x, const double* y, int64_t* out_idx, int64_t* out_counts,
                           int levels, void* stream);
 bool context_fixed_done(Context* c, int levels);
@@ -308,13 +317,14 @@ struct PlanArgs {
 struct FinishArgs {
   const Status* st;  // njobs
   const Job* jobs;
-  const double* ux;  // caller arrays (root jobs)
+  const double* ux;  // caller arrays of root jobs, by global position (when req_arrays is 0)
   const double* uy;
   const double* bx[2];
   const double* by[2];
   uint32_t* bi[2];
   Node* nodes;
   Req* req;
+  uint32_t req_arrays;  // 1: root jobs read the request's own arrays (Req::x, Req::y)
 };
 
 // One request of at most the LDS threshold's points, whole in one workgroup.

@@ -226,6 +226,9 @@ __global__ __launch_bounds__(BLOCK) void k_extremes(ExtremesArgs A) {
   if (t >= A.counts->ext_tiles) return;
   const uint32_t r = A.tile_req ? A.tile_req[t] : 0u;
   const uint32_t off = A.req[r].off, n = A.req[r].n, tile0 = A.req[r].tile0;
+  // the request's arrays, indexed by global position (position off = its point 0)
+  const double* const X = A.req[r].x - off;
+  const double* const Y = A.req[r].y - off;
   const uint32_t lo = off + (t - tile0) * TILE;
   const uint32_t hi = min(off + n, lo + TILE);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -246,7 +249,7 @@ __global__ __launch_bounds__(BLOCK) void k_extremes(ExtremesArgs A) {
 #pragma unroll
     for (int v = 0; v < PPT; ++v) {
       const uint32_t pos = slo + v * BLOCK + tid;
-      xs[v] = pos < hi ? __builtin_nontemporal_load(A.x + pos) : __builtin_nan("");
+      xs[v] = pos < hi ? __builtin_nontemporal_load(X + pos) : __builtin_nan("");
     }
 #pragma unroll
     for (int v = 0; v < PPT; ++v) {
@@ -266,12 +269,12 @@ __global__ __launch_bounds__(BLOCK) void k_extremes(ExtremesArgs A) {
     if (tmin | tmax) {
       mni = mxi = kNone;
       for (uint32_t pos = lo + tid; pos < hi; pos += BLOCK) {
-        const double xv = A.x[pos];
-        if (mni == kNone || lex_less(xv, pos, mnx, mni, A.y)) {
+        const double xv = X[pos];
+        if (mni == kNone || lex_less(xv, pos, mnx, mni, Y)) {
           mnx = xv;
           mni = pos;
         }
-        if (mxi == kNone || lex_greater(xv, pos, mxx, mxi, A.y)) {
+        if (mxi == kNone || lex_greater(xv, pos, mxx, mxi, Y)) {
           mxx = xv;
           mxi = pos;
         }
@@ -282,13 +285,13 @@ __global__ __launch_bounds__(BLOCK) void k_extremes(ExtremesArgs A) {
   for (int m = 32; m >= 1; m >>= 1) {
     const double ox = __shfl_xor(mnx, m, 64);
     const uint32_t oi = __shfl_xor(mni, m, 64);
-    if (oi != kNone && (mni == kNone || lex_less(ox, oi, mnx, mni, A.y))) {
+    if (oi != kNone && (mni == kNone || lex_less(ox, oi, mnx, mni, Y))) {
       mnx = ox;
       mni = oi;
     }
     const double gx = __shfl_xor(mxx, m, 64);
     const uint32_t gi = __shfl_xor(mxi, m, 64);
-    if (gi != kNone && (mxi == kNone || lex_greater(gx, gi, mxx, mxi, A.y))) {
+    if (gi != kNone && (mxi == kNone || lex_greater(gx, gi, mxx, mxi, Y))) {
       mxx = gx;
       mxi = gi;
     }
@@ -303,11 +306,11 @@ __global__ __launch_bounds__(BLOCK) void k_extremes(ExtremesArgs A) {
   __syncthreads();
   if (tid == 0) {
     for (int i = 1; i < NW; ++i) {
-      if (s_mni[i] != kNone && (mni == kNone || lex_less(s_mnx[i], s_mni[i], mnx, mni, A.y))) {
+      if (s_mni[i] != kNone && (mni == kNone || lex_less(s_mnx[i], s_mni[i], mnx, mni, Y))) {
         mnx = s_mnx[i];
         mni = s_mni[i];
       }
-      if (s_mxi[i] != kNone && (mxi == kNone || lex_greater(s_mxx[i], s_mxi[i], mxx, mxi, A.y))) {
+      if (s_mxi[i] != kNone && (mxi == kNone || lex_greater(s_mxx[i], s_mxi[i], mxx, mxi, Y))) {
         mxx = s_mxx[i];
         mxi = s_mxi[i];
       }
@@ -315,8 +318,8 @@ __global__ __launch_bounds__(BLOCK) void k_extremes(ExtremesArgs A) {
     ExtPart e;
     e.minx = mnx;
     e.maxx = mxx;
-    e.miny = mni != kNone ? A.y[mni] : 0.0;
-    e.maxy = mxi != kNone ? A.y[mxi] : 0.0;
+    e.miny = mni != kNone ? Y[mni] : 0.0;
+    e.maxy = mxi != kNone ? Y[mxi] : 0.0;
     e.mini = mni != kNone ? mni - off : kNone;
     e.maxi = mxi != kNone ? mxi - off : kNone;
     e.pad[0] = e.pad[1] = 0;
@@ -331,12 +334,13 @@ __global__ __launch_bounds__(BLOCK) void k_extremes(ExtremesArgs A) {
 // count comes from the level's status record.  Per tile, each thread loads PPT
 // points (striped so that every wave load covers consecutive addresses, with
 // non-temporal hints: the data is streamed once), classifies them, and keeps
-// the farthest point of each output subset.  Per-lane bit masks record the
-// subset of every point; their population counts, summed over the wave, give
-// the per-wave subset sizes; one packed 64-bit atomic per output range and
-// tile reserves room at the range's left end (first subset) and right end
-// (second subset); every wave then writes its survivors as contiguous runs
-// (ballot ranks).  The order of points inside a subset is irrelevant to the
+// the farthest point of each output subset.  Every point's output stream is
+// kept as a one-hot byte field; their sums, reduced over the wave, give the
+// per-wave subset sizes; one packed 64-bit atomic per output range and tile
+// reserves room at the range's left end (first subset) and right end (second
+// subset); every wave then writes its survivors as contiguous runs (ranks
+// from one wave prefix sum of the one-hot values per point slot, see
+// write_onehot).  The order of points inside a subset is irrelevant to the
 // result.  Farthest-point candidates are kept per thread across the
 // consecutive tiles a workgroup visits in one segment and written once per
 // such run.
@@ -380,14 +384,29 @@ __device__ __forceinline__ Best no_best() {
   return b;
 }
 
+// The arrays a sweep reads its points from: coordinates, and in the workspace
+// the request-local index of every position (the caller's arrays carry none:
+// there the index is the position minus the request's first position).
+struct Src {
+  const double* x;
+  const double* y;
+  const uint32_t* i;
+};
+
+__device__ __forceinline__ const double* uni_ptr(const double* p) {
+  const uint64_t b = reinterpret_cast<uint64_t>(p);
+  const uint64_t lo = uni((uint32_t)b), hi = uni((uint32_t)(b >> 32));
+  return reinterpret_cast<const double*>((hi << 32) | lo);
+}
+
 // Ordering of two members with equal keys (the stored one at position b.pos):
 // smaller x, then smaller y, then lower index.  In the caller's arrays the
 // index order is the position order.
 template <bool USER>
-__device__ __forceinline__ bool tie_wins(const SweepArgs& A, double x, double y, uint32_t pos, uint32_t idx,
+__device__ __forceinline__ bool tie_wins(const Src& A, double x, double y, uint32_t pos, uint32_t idx,
                                          uint32_t bpos) {
-  const double bx = A.ix[bpos], by = A.iy[bpos];
-  const uint32_t bi = USER ? bpos : A.ii[bpos];
+  const double bx = A.x[bpos], by = A.y[bpos];
+  const uint32_t bi = USER ? bpos : A.i[bpos];
   const uint32_t ni = USER ? pos : idx;
   return (x < bx) | ((x == bx) & ((y < by) | ((y == by) & (ni < bi))));
 }
@@ -397,7 +416,7 @@ __device__ __forceinline__ bool tie_wins(const SweepArgs& A, double x, double y,
 // a wave-uniform slow path that fetches the stored candidate's coordinates.
 template <bool USER, int NB>
 __device__ __forceinline__ void offer(Best (&b)[NB], const bool (&in)[NB], const double (&k)[NB], double x, double y,
-                                      uint32_t pos, uint32_t idx, const SweepArgs& A) {
+                                      uint32_t pos, uint32_t idx, const Src& A) {
   bool t[NB], tie[NB];
   bool any_tie = false;
 #pragma unroll
@@ -419,13 +438,13 @@ __device__ __forceinline__ void offer(Best (&b)[NB], const bool (&in)[NB], const
 }
 
 template <bool USER>
-__device__ __forceinline__ Cand to_cand(const SweepArgs& A, const Best& b, uint32_t ibase) {
+__device__ __forceinline__ Cand to_cand(const Src& A, const Best& b, uint32_t ibase) {
   Cand c = no_cand();
   if (b.pos != kNone) {
     c.k = b.k;
-    c.x = A.ix[b.pos];
-    c.y = A.iy[b.pos];
-    c.i = USER ? b.pos - ibase : A.ii[b.pos];
+    c.x = A.x[b.pos];
+    c.y = A.y[b.pos];
+    c.i = USER ? b.pos - ibase : A.i[b.pos];
   }
   return c;
 }
@@ -434,7 +453,7 @@ __device__ __forceinline__ Cand to_cand(const SweepArgs& A, const Best& b, uint3
 // key fetch their point (one cache line, not one per lane); several such lanes
 // are ordered by the full tie-break.
 template <bool USER>
-__device__ __forceinline__ Cand wave_cand(const SweepArgs& A, const Best& b, uint32_t ibase) {
+__device__ __forceinline__ Cand wave_cand(const Src& A, const Best& b, uint32_t ibase) {
   const double kmax = wave_max_key(b.k);  // keys are >= 0: no NaN
   Cand c = no_cand();
   if (b.pos != kNone && b.k == kmax) c = to_cand<USER>(A, b, ibase);
@@ -444,7 +463,7 @@ __device__ __forceinline__ Cand wave_cand(const SweepArgs& A, const Best& b, uin
 
 // Best candidates of a run over the workgroup, written to record slot `slot`.
 template <bool USER, int NW>
-__device__ __forceinline__ void flush_run(const SweepArgs& A, TilePart* part, uint32_t slot, const Best& b1,
+__device__ __forceinline__ void flush_run(const Src& A, TilePart* part, uint32_t slot, const Best& b1,
                                           const Best& b2, uint32_t ibase, Cand (*s_cand)[NW]) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const Cand c1 = wave_cand<USER>(A, b1, ibase), c2 = wave_cand<USER>(A, b2, ibase);
@@ -508,22 +527,28 @@ __device__ __forceinline__ void flush_counts(unsigned long long* ctr, uint32_t r
   __syncthreads();
 }
 
-// Reserve room for one tile's survivors and write them.  Stream s goes to the
-// left end (even s) or the right end (odd s) of output range s / 2; thread j
-// reserves range j.  m[s] holds bit v for the thread's v-th point.  Stream
-// sizes per lane are at most 32, so two wave sums share one 32-bit word.
+// Reserve room for one tile's survivors and write them (one-hot form).
+// oh[v] holds, for the thread's v-th point, 1 << (8 s) if it goes to stream s
+// (s < NS), else 0.  Stream s goes to the left end (even s) or the right end
+// (odd s) of output range s / 2.  Per v, one wave prefix sum of the packed
+// one-hot values gives every lane its rank in its own stream; lane s of a
+// per-wave table holds stream s's next write position.
 template <int BLOCK, int PPT, int NS, bool USER>
-__device__ __forceinline__ void write_streams(const uint32_t (&m)[NS], const uint32_t (&beg)[NS / 2],
-                                              const uint32_t (&cnt)[NS / 2], unsigned long long* const (&ctr)[NS / 2],
-                                              const double (&px)[PPT], const double (&py)[PPT],
-                                              const uint32_t (&pi)[PPT], uint32_t idx0, double* ox, double* oy,
-                                              uint32_t* oi, uint32_t (*s_cnt)[BLOCK / 64], uint32_t* s_base) {
+__device__ __forceinline__ void write_onehot(const uint32_t (&oh)[PPT], const uint32_t (&beg)[NS / 2],
+                                             const uint32_t (&cnt)[NS / 2], unsigned long long* const (&ctr)[NS / 2],
+                                             const double (&px)[PPT], const double (&py)[PPT],
+                                             const uint32_t (&pi)[PPT], uint32_t idx0, double* ox, double* oy,
+                                             uint32_t* oi, uint32_t (*s_cnt)[BLOCK / 64], uint32_t* s_base) {
   constexpr int NW = BLOCK / 64;
   constexpr int NR = NS / 2;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  uint32_t c = 0;  // per-lane stream sizes, 8-bit fields (at most PPT each)
+#pragma unroll
+  for (int v = 0; v < PPT; ++v) c += oh[v];
 #pragma unroll
   for (int j = 0; j < NR; ++j) {
-    const uint32_t both = wave_sum((uint32_t)__popc(m[2 * j]) | ((uint32_t)__popc(m[2 * j + 1]) << 16));
+    const uint32_t pair = ((c >> (16 * j)) & 0xFFu) | (((c >> (16 * j + 8)) & 0xFFu) << 16);
+    const uint32_t both = wave_sum(pair);
     if (lane == 0) {
       s_cnt[2 * j][w] = both & 0xFFFFu;
       s_cnt[2 * j + 1][w] = both >> 16;
@@ -541,46 +566,37 @@ __device__ __forceinline__ void write_streams(const uint32_t (&m)[NS], const uin
       t1 += a;
       t2 += b;
     }
-    unsigned long long* c = ctr[0];
+    unsigned long long* cp = ctr[0];
     uint32_t b0 = beg[0], n0 = cnt[0];
     if (NR > 1 && j == 1) {
-      c = ctr[NR - 1];
+      cp = ctr[NR - 1];
       b0 = beg[NR - 1];
       n0 = cnt[NR - 1];
     }
     unsigned long long old = 0ull;
-    if (t1 | t2) old = atomicAdd(c, ((unsigned long long)t2 << 32) | (unsigned long long)t1);
+    if (t1 | t2) old = atomicAdd(cp, ((unsigned long long)t2 << 32) | (unsigned long long)t1);
     s_base[2 * j] = b0 + (uint32_t)old;
     s_base[2 * j + 1] = b0 + n0 - (uint32_t)(old >> 32) - t2;
   }
   __syncthreads();
-  uint32_t o[NS];  // per-wave write offsets (uniform: scalar registers)
-#pragma unroll
-  for (int s = 0; s < NS; ++s) o[s] = uni(s_base[s] + s_cnt[s][w]);
+  const int ls = lane < NS ? lane : 0;
+  uint32_t tab = lane < NS ? s_base[ls] + s_cnt[ls][w] : 0u;  // lane s < NS: stream s's next position
+  const uint32_t lsh = (uint32_t)(8 * (lane & 3));
 #pragma unroll
   for (int v = 0; v < PPT; ++v) {
-    bool in[NS];
-    unsigned long long bal[NS];
-    bool any = false;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      in[s] = (m[s] >> v) & 1u;
-      bal[s] = __ballot(in[s]);
-      any |= in[s];
-    }
-    if (any) {
-      uint32_t dst = o[NS - 1] + lane_rank(bal[NS - 1]);
-#pragma unroll
-      for (int s = NS - 2; s >= 0; --s) dst = in[s] ? o[s] + lane_rank(bal[s]) : dst;
+    const uint32_t h = oh[v];
+    const uint32_t incl = wave_scan_incl(h);
+    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    const uint32_t sh = h ? (uint32_t)__builtin_ctz(h) : 0u;  // 8 s
+    const uint32_t base = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(sh >> 1), (int)tab);
+    if (h) {
+      const uint32_t dst = base + ((incl >> sh) & 0xFFu) - 1u;
       ox[dst] = px[v];  // plain stores: the L2 merges the partial lines of
       oy[dst] = py[v];  // neighbouring runs before they reach HBM
       oi[dst] = USER ? idx0 + (uint32_t)(v * BLOCK) : pi[v];
     }
-#pragma unroll
-    for (int s = 0; s < NS; ++s) o[s] += (uint32_t)__popcll(bal[s]);
+    tab += (tot >> lsh) & 0xFFu;
   }
-  // s_cnt / s_base are rewritten only after the next first barrier, which
-  // every thread reaches after finishing these reads.
 }
 
 template <int BLOCK, int PPT, int MODE>
@@ -602,9 +618,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 
   uint32_t run_seg = kNone, run_slot = 0;
+  Src src{A.ix, A.iy, A.ii};  // USER: replaced per segment by its request's own arrays
   // Level: the segment's triangle (a, r, b).  Argmax and fused: p = a, q = r.
   double ax = 0, ay = 0, rx = 0, ry = 0, bx = 0, by = 0;
   double r1x = 0, r1y = 0, r2x = 0, r2y = 0;  // fused: farthest points of the two children
+  double vr1x = 0, vr1y = 0, vr2x = 0, vr2y = 0;  // the same in vector registers (selected per lane)
   uint32_t beg = 0, cnt = 0, tile0 = 0, ibase = 0, req = 0;
   uint32_t cbeg[NS / 2] = {}, ccnt[NS / 2] = {};
   unsigned long long* cctr[NS / 2] = {};
@@ -620,8 +638,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
     const uint32_t s = uni(A.tile_seg[t]);
     if (s != run_seg) {
       if (run_seg != kNone) {
-        flush_run<USER, NW>(A, A.part, run_slot, b[0], b[1], ibase, s_cand);
-        if constexpr (FUSED) flush_run<USER, NW>(A, A.part2, run_slot, b[2], b[3], ibase, s_cand);
+        flush_run<USER, NW>(src, A.part, run_slot, b[0], b[1], ibase, s_cand);
+        if constexpr (FUSED) flush_run<USER, NW>(src, A.part2, run_slot, b[2], b[3], ibase, s_cand);
         if constexpr (ARGMAX) {
           flush_counts<NW>(A.ctr + (size_t)run_seg * kCtrStride, run1, run2, s_cnt);
           run1 = run2 = 0;
@@ -637,10 +655,16 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
         r1y = uni(fr->ry[0]);
         r2x = uni(fr->rx[1]);
         r2y = uni(fr->ry[1]);
+        vr1x = r1x;
+        vr1y = r1y;
+        vr2x = r2x;
+        vr2y = r2y;
+        asm volatile("" : "+v"(vr1x), "+v"(vr1y), "+v"(vr2x), "+v"(vr2y));
         beg = uni(fr->off);
         cnt = uni(fr->n);
         tile0 = uni(fr->tile0);
         ibase = beg;
+        req = uni(fr->req);
         uint32_t kind[2];
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
@@ -670,6 +694,10 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
         ccnt[0] = cnt;
         cctr[0] = A.ctr + (size_t)s * kCtrStride;
       }
+      if constexpr (USER) {  // positions are global; the request's point 0 sits at position ibase
+        src.x = uni_ptr(A.req[req].x) - ibase;
+        src.y = uni_ptr(A.req[req].y) - ibase;
+      }
       run_seg = s;
       run_slot = tile0 + (t - tile0) % G;
 #pragma unroll
@@ -685,18 +713,17 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
 #pragma unroll
     for (int v = 0; v < PPT; ++v) {
       const uint32_t pc = min(lo + v * BLOCK + tid, hi - 1u);
-      px[v] = __builtin_nontemporal_load(A.ix + pc);
-      py[v] = __builtin_nontemporal_load(A.iy + pc);
+      px[v] = __builtin_nontemporal_load(src.x + pc);
+      py[v] = __builtin_nontemporal_load(src.y + pc);
       if constexpr (USER) {
         pi[v] = 0u;
       } else {
-        pi[v] = __builtin_nontemporal_load(A.ii + pc);
+        pi[v] = __builtin_nontemporal_load(src.i + pc);
       }
     }
 
-    uint32_t m[NS];
-#pragma unroll
-    for (int q = 0; q < NS; ++q) m[q] = 0u;
+    uint32_t m[2] = {0u, 0u};  // argmax pass: bit v set for the thread's v-th point in S1 / S2
+    uint32_t oh[PPT];          // the other passes: each point's output stream, one-hot (write_onehot)
 #pragma unroll
     for (int v = 0; v < PPT; ++v) {
       const uint32_t pos = lo + v * BLOCK + tid;
@@ -710,9 +737,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
         const bool in2 = ok & !in1 & (o2 > 0.0);
         const bool f[2] = {in1, in2};
         const double kk[2] = {o1, o2};
-        offer<false, 2>(b, f, kk, x, y, pos, pi[v], A);
-        m[0] |= (uint32_t)in1 << v;
-        m[1] |= (uint32_t)in2 << v;
+        offer<false, 2>(b, f, kk, x, y, pos, pi[v], src);
+        oh[v] = (in1 ? 1u : 0u) | (in2 ? 256u : 0u);
       } else {
         const double dpx = ax - x, dpy = ay - y, dqx = rx - x, dqy = ry - y;
         const double o = dpx * dqy - dpy * dqx;  // orient(p, q, u)
@@ -721,7 +747,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
         if constexpr (ARGMAX) {
           const bool f[2] = {s0, s1};
           const double kk[2] = {o, -o};
-          offer<USER, 2>(b, f, kk, x, y, pos, pi[v], A);
+          offer<USER, 2>(b, f, kk, x, y, pos, pi[v], src);
           m[0] |= (uint32_t)s0 << v;
           m[1] |= (uint32_t)s1 << v;
           if constexpr (USER) bad |= ok & !finite(y);  // the octagon pass checked the kept points
@@ -729,28 +755,33 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
           // child 0 = (p, r1, q) holds S1, child 1 = (q, r2, p) holds S2.  Both
           // children are evaluated for every point (no branch on the kinds,
           // which are uniform); the kind flags mask the results.
-          const double d1x = r1x - x, d1y = r1y - y, d2x = r2x - x, d2y = r2y - y;
-          const double kk[4] = {
-              dpx * d1y - dpy * d1x,  // orient(p, r1, u)
-              d1x * dqy - d1y * dqx,  // orient(r1, q, u)
-              dqx * d2y - dqy * d2x,  // orient(q, r2, u)
-              d2x * dpy - d2y * dpx,  // orient(r2, p, u)
-          };
+          // The point's own child only: R = r1 for S1 (child (p, r1, q)),
+          // r2 for S2 (child (q, r2, p)).  With d = R - u,
+          //   U = orient(p, R, u) = (p.x-u.x)(R.y-u.y) - (p.y-u.y)(R.x-u.x)
+          //   V = orient(q, R, u) = (q.x-u.x)(R.y-u.y) - (q.y-u.y)(R.x-u.x);
+          // orient(r1, q, u) has the same two rounded products in the other
+          // order, so it is exactly -V; likewise orient(r2, p, u) = -U.
+          const double dRx = (s0 ? vr1x : vr2x) - x, dRy = (s0 ? vr1y : vr2y) - y;
+          const double U = dpx * dRy - dpy * dRx;
+          const double V = dqx * dRy - dqy * dRx;
           const bool a0 = s0 & split0, a1 = s1 & split1;
-          const bool l0 = kk[0] > 0.0, l1 = kk[2] > 0.0;
-          const bool f[4] = {(bool)(a0 & l0), (bool)(a0 & !l0 & (kk[1] > 0.0)), (bool)(a1 & l1), (bool)(a1 & !l1 & (kk[3] > 0.0))};
-          offer<USER, 4>(b, f, kk, x, y, pos, pi[v], A);
-          m[0] |= (uint32_t)(f[0] | (s0 & copy0)) << v;
-          m[1] |= (uint32_t)f[1] << v;
-          m[2] |= (uint32_t)(f[2] | (s1 & copy1)) << v;
-          m[3] |= (uint32_t)f[3] << v;
+          const bool u_pos = U > 0.0, v_pos = V > 0.0;
+          const bool f[4] = {(bool)(a0 & u_pos), (bool)(a0 & !u_pos & (V < 0.0)), (bool)(a1 & v_pos),
+                             (bool)(a1 & !v_pos & (U < 0.0))};
+          const double kk[4] = {U, -V, V, -U};
+          offer<USER, 4>(b, f, kk, x, y, pos, pi[v], src);
+          oh[v] = ((f[0] | (s0 & copy0)) ? 1u : 0u) | (f[1] ? 256u : 0u) | ((f[2] | (s1 & copy1)) ? 65536u : 0u) |
+                  (f[3] ? 16777216u : 0u);
         }
       }
-      // The subset bits are materialised in vector registers point by point:
-      // otherwise the compiler keeps every point's lane masks alive in scalar
-      // registers until the write loop and spills them.
-#pragma unroll
-      for (int q = 0; q < NS; ++q) asm volatile("" : "+v"(m[q]));
+      // The classification is materialised in vector registers point by
+      // point: otherwise the compiler keeps every point's lane masks alive in
+      // scalar registers until the write loop and spills them.
+      if constexpr (ARGMAX) {
+        asm volatile("" : "+v"(m[0]), "+v"(m[1]));
+      } else {
+        asm volatile("" : "+v"(oh[v]));
+      }
     }
     if constexpr (ARGMAX) {
       run1 += (uint32_t)__popc(m[0]);
@@ -758,13 +789,13 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
       if (__ballot(bad) && lane == 0) A.req[req].err = 1u;
       bad = false;
     } else {
-      write_streams<BLOCK, PPT, NS, USER>(m, cbeg, ccnt, cctr, px, py, pi, lo + tid - ibase, A.ox, A.oy, A.oi, s_cnt,
-                                          s_base);
+      write_onehot<BLOCK, PPT, NS, USER>(oh, cbeg, ccnt, cctr, px, py, pi, lo + tid - ibase, A.ox, A.oy, A.oi, s_cnt,
+                                         s_base);
     }
   }
   if (run_seg != kNone) {
-    flush_run<USER, NW>(A, A.part, run_slot, b[0], b[1], ibase, s_cand);
-    if constexpr (FUSED) flush_run<USER, NW>(A, A.part2, run_slot, b[2], b[3], ibase, s_cand);
+    flush_run<USER, NW>(src, A.part, run_slot, b[0], b[1], ibase, s_cand);
+    if constexpr (FUSED) flush_run<USER, NW>(src, A.part2, run_slot, b[2], b[3], ibase, s_cand);
     if constexpr (ARGMAX) flush_counts<NW>(A.ctr + (size_t)run_seg * kCtrStride, run1, run2, s_cnt);
   }
 }
@@ -1396,8 +1427,11 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint32_t cnt = job.cnt;
   const bool user = job.src == kSrcUser;
-  const double* X = user ? A.ux : A.bx[job.src];
-  const double* Y = user ? A.uy : A.by[job.src];
+  // the caller's points: the request's own arrays (position ibase = its point 0),
+  // or the arrays passed in (a single request read by global position)
+  const bool own = user && A.req_arrays;
+  const double* X = user ? (own ? A.req[job.req].x - job.ibase : A.ux) : A.bx[job.src];
+  const double* Y = user ? (own ? A.req[job.req].y - job.ibase : A.uy) : A.by[job.src];
   const uint32_t* I = user ? nullptr : A.bi[job.src];
   uint32_t* out = A.bi[user ? 0 : job.src] + job.beg;
 

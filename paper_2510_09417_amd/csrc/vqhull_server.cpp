@@ -4,10 +4,11 @@
 // `lanes` batch lanes, each with its own HIP stream, engine context and
 // pre-allocated batch buffers, and a host thread that loops:
 //   take the oldest pending requests that fit the lane (points and request
-//   count), gather them into the lane's staging arrays (one kernel), run the
-//   batched hull on the lane's context, scatter every request's vertex list
-//   and count into the caller's buffers (one kernel), then mark the requests
-//   done.
+//   count), run the batched hull on the lane's context (a captured graph whose
+//   kernels read each request's points where the caller keeps them; the
+//   rare plain fallback first gathers them into the lane's staging arrays),
+//   scatter every request's vertex list and count into the caller's buffers
+//   (one kernel), then mark the requests done.
 // A request that arrives while batches are on the GPU is taken by the next
 // lane that frees up, so work of different batches overlaps on the device;
 // admission is by the lane's fixed device memory, sized once at creation, so
@@ -50,6 +51,8 @@ struct Lane {
   int64_t* h_cnt = nullptr;
   uint32_t* d_nchunks = nullptr;
   uint32_t* h_nchunks = nullptr;
+  // each request's own arrays, for the graph path (its kernels read them in place)
+  std::vector<const double*> xs, ys;
   // the batch step as one hipGraph (graph_levels > 0)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -144,11 +147,13 @@ bool same_config(const vqhull_config& a, const vqhull_config& b) {
          a.level_block == b.level_block;
 }
 
-// Capture the lane's whole batch step (table copies, gather, the fixed
-// sequence of `levels` recursion levels, assembly, scatter, count copy) as
-// one graph.  Every count the kernels need is read from device memory, so the
-// graph serves every batch; it is captured again when the library's
-// configuration changes or a workspace buffer has moved.
+// Capture the lane's whole batch step (table copies, the fixed sequence of
+// `levels` recursion levels, assembly, scatter, count copy) as one graph.
+// The kernels read every request's points where the caller keeps them (the
+// request table carries its arrays), so nothing is gathered.  Every count the
+// kernels need is read from device memory, so the graph serves every batch;
+// it is captured again when the library's configuration changes or a
+// workspace buffer has moved.
 bool capture_graph(vqhull_server* s, Lane* L, const vqhull_config& cfg) {
   if (L->exec) (void)hipGraphExecDestroy(L->exec);
   if (L->graph) (void)hipGraphDestroy(L->graph);
@@ -161,7 +166,6 @@ bool capture_graph(vqhull_server* s, Lane* L, const vqhull_config& cfg) {
   ok = ok && hipMemcpyAsync(L->d_chunks, L->h_chunks, C * sizeof(ServedChunk), hipMemcpyHostToDevice, L->st) ==
                  hipSuccess;
   ok = ok && hipMemcpyAsync(L->d_nchunks, L->h_nchunks, sizeof(uint32_t), hipMemcpyHostToDevice, L->st) == hipSuccess;
-  ok = ok && launch_gather(L->d_reqs, L->d_chunks, L->d_nchunks, (uint32_t)C, L->sx, L->sy, L->st) == 0;
   ok = ok && context_enqueue_fixed(L->ctx, L->sx, L->sy, L->sidx, L->scnt, s->cfg.graph_levels, L->st) == VQHULL_OK;
   ok = ok && launch_scatter(L->d_reqs, L->d_chunks, L->d_nchunks, (uint32_t)C, L->sidx, L->scnt, L->st) == 0;
   ok = ok && hipMemcpyAsync(L->h_cnt, L->scnt, R * sizeof(int64_t), hipMemcpyDeviceToHost, L->st) == hipSuccess;
@@ -189,11 +193,15 @@ int run_batch(vqhull_server* s, Lane* L, const std::vector<ServedReq>& reqs) {
   const size_t nreq = reqs.size();
   size_t nch = 0;
   int64_t off = 0;
+  L->xs.resize(nreq);
+  L->ys.resize(nreq);
   for (size_t i = 0; i < nreq; ++i) {
     ServedReq r = reqs[i];
     r.off = (uint64_t)off;
     L->h_reqs[i] = r;
     L->h_off[i] = off;
+    L->xs[i] = r.x;
+    L->ys[i] = r.y;
     const uint64_t nc = r.n > 0 ? (r.n + kServeChunk - 1) / kServeChunk : 1;
     for (uint64_t c = 0; c < nc; ++c) L->h_chunks[nch++] = ServedChunk{(uint32_t)i, (uint32_t)(c * kServeChunk)};
     off += (int64_t)r.n;
@@ -204,7 +212,8 @@ int run_batch(vqhull_server* s, Lane* L, const std::vector<ServedReq>& reqs) {
   if (s->cfg.graph_levels > 0 && !L->graph_broken) {
     vqhull_config cfg;
     (void)vqhull_get_config(&cfg);
-    if (cfg.sweep_persistent && context_stage(L->ctx, L->h_off, (int64_t)nreq) == VQHULL_OK) {
+    if (cfg.sweep_persistent &&
+        context_stage(L->ctx, L->h_off, (int64_t)nreq, L->xs.data(), L->ys.data()) == VQHULL_OK) {
       if (!L->exec || L->graph_gen != allocation_generation() || !same_config(cfg, L->graph_cfg)) {
         if (!capture_graph(s, L, cfg)) L->graph_broken = true;  // this lane stays on the plain path
       }
@@ -221,6 +230,8 @@ int run_batch(vqhull_server* s, Lane* L, const std::vector<ServedReq>& reqs) {
     }
   }
 
+  // plain launches on a gathered copy of the batch (the recursion went deeper
+  // than the captured levels, or no graph): rare
   ++L->fallback_batches;
   hipError_t e = hipMemcpyAsync(L->d_reqs, L->h_reqs, nreq * sizeof(ServedReq), hipMemcpyHostToDevice, L->st);
   if (e == hipSuccess)

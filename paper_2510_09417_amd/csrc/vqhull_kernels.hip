@@ -881,7 +881,7 @@ enum : uint32_t { kKindNone = 0, kKindLeaf = 1, kKindJob = 2, kKindSeg = 3 };
 
 constexpr int kPlanBlock = 512;
 constexpr int kPlanWaves = kPlanBlock / 64;
-constexpr uint32_t kSerialRecs = 16;   // segments with more candidate records are reduced by one wave,
+constexpr uint32_t kSerialRecs = 64;   // segments with more candidate records are reduced by one wave,
 constexpr uint32_t kWaveRecs = 2048;   // and with more than this by the whole workgroup
 constexpr uint32_t kSerialFill = 16;  // segments with more tiles get their tile map filled by the workgroup
 
@@ -897,7 +897,9 @@ struct PlanSharedT {
   uint32_t nodes, jobs, segs, tiles, swept, jobpts, survivors;
   uint32_t nbig, nfill;
   uint32_t big[PB];
-  uint32_t fill[2 * PB];  // up to two new segments per thread
+  uint32_t fill[2 * PB];  // up to two new segments per thread: id,
+  uint32_t fill_t0[2 * PB];  // first tile
+  uint32_t fill_nt[2 * PB];  // and tile count
 };
 using PlanShared = PlanSharedT<kPlanBlock>;
 
@@ -1025,22 +1027,26 @@ __device__ __forceinline__ int32_t emit_one(uint32_t kind, const Tri& tr, uint32
     if (nt <= kSerialFill) {
       for (uint32_t i = 0; i < nt; ++i) tile_seg_out[t0 + i] = sid;
     } else {
-      S.fill[atomicAdd(&S.nfill, 1u)] = sid;
+      const uint32_t f = atomicAdd(&S.nfill, 1u);
+      S.fill[f] = sid;
+      S.fill_t0[f] = t0;
+      S.fill_nt[f] = nt;
     }
   }
   return nid;
 }
 
-// Tile maps of the big new segments (whole workgroup), then running totals.
+// Tile maps of the big new segments (one wave per segment, its lanes over the
+// tiles), then running totals.
 template <int PB>
 __device__ __forceinline__ void emit_finish(const uint32_t (&tot)[4], const Seg* seg_out, uint32_t* tile_seg_out,
                                             uint32_t tile, PlanSharedT<PB>& S) {
   __syncthreads();
   const uint32_t nf = S.nfill;
-  for (uint32_t f = 0; f < nf; ++f) {
-    const uint32_t sid = S.fill[f];
-    const uint32_t t0 = seg_out[sid].tile0, nt = ceil_div(seg_out[sid].cnt, tile);
-    for (uint32_t i = threadIdx.x; i < nt; i += PB) tile_seg_out[t0 + i] = sid;
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  for (uint32_t f = w; f < nf; f += PB / 64) {
+    const uint32_t sid = S.fill[f], t0 = S.fill_t0[f], nt = S.fill_nt[f];
+    for (uint32_t i = lane; i < nt; i += 64u) tile_seg_out[t0 + i] = sid;
   }
   __syncthreads();
   if (threadIdx.x == 0) {

@@ -160,6 +160,26 @@ int vqhull_hull_batched_ws(const double* x, const double* y, const int64_t* offs
                            vqhull_stream_t stream);
 
 /*
+ * In-place mode (the paper keeps no second copy of the points: its extraction
+ * permutes them inside the input array, Section 3.1): the caller's x and y
+ * are writable and serve as one of the two ping-pong point buffers, so the
+ * library's point buffers take 24 bytes per point instead of 40.
+ *   x, y       DEVICE arrays, overwritten: their contents after the call are
+ *              unspecified (they hold intermediate subsets).  The result is
+ *              the hull of the points they held on entry.
+ *   workspace, workspace_bytes  as for vqhull_hull_ws, with
+ *              vqhull_workspace_bytes_inplace(n_total, nreq) bytes at least.
+ * Every other argument, the result and the errors are those of
+ * vqhull_hull_ws / vqhull_hull_batched_ws.
+ */
+size_t vqhull_workspace_bytes_inplace(int64_t n_total, int64_t nreq);
+int vqhull_hull_inplace(double* x, double* y, int64_t n, int64_t* out_idx, int64_t* out_count, void* workspace,
+                        size_t workspace_bytes, vqhull_stream_t stream);
+int vqhull_hull_batched_inplace(double* x, double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
+                                int64_t* out_counts, void* workspace, size_t workspace_bytes,
+                                vqhull_stream_t stream);
+
+/*
  * For callers that cannot allocate device memory (tight serving loops,
  * harnesses that forbid hipMalloc): vqhull_hull with every device table in a
  * static device array of the library, VQHULL_NOALLOC_MAX_POINTS points at

@@ -24,6 +24,7 @@ VQHULL_ERR_TIMEOUT = 5
 # Symbols that include/vqhull.h declares.
 EXPORTED = (
     "vqhull_hull", "vqhull_hull_batched", "vqhull_workspace_bytes", "vqhull_hull_ws", "vqhull_hull_batched_ws",
+    "vqhull_workspace_bytes_inplace", "vqhull_hull_inplace", "vqhull_hull_batched_inplace",
     "vqhull_hull_noalloc", "vqhull_hull_xy", "vqhull_hull_batched_xy", "vqhull_get_config", "vqhull_set_config", "vqhull_autotune",
     "vqhull_last_level_stats", "vqhull_set_timing", "vqhull_last_kernel_times", "vqhull_orient", "vqhull_stream_scale",
     "vqhull_release_workspace", "vqhull_status_string", "vqhull_last_error",
@@ -109,6 +110,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.vqhull_hull_ws.argtypes = [vp, vp, i64, vp, vp, vp, ctypes.c_size_t, vp]
         lib.vqhull_hull_batched_ws.restype = ctypes.c_int
         lib.vqhull_hull_batched_ws.argtypes = [vp, vp, pi64, i64, vp, vp, vp, ctypes.c_size_t, vp]
+        lib.vqhull_workspace_bytes_inplace.restype = ctypes.c_size_t
+        lib.vqhull_workspace_bytes_inplace.argtypes = [i64, i64]
+        lib.vqhull_hull_inplace.restype = ctypes.c_int
+        lib.vqhull_hull_inplace.argtypes = [vp, vp, i64, vp, vp, vp, ctypes.c_size_t, vp]
+        lib.vqhull_hull_batched_inplace.restype = ctypes.c_int
+        lib.vqhull_hull_batched_inplace.argtypes = [vp, vp, pi64, i64, vp, vp, vp, ctypes.c_size_t, vp]
         lib.vqhull_hull_noalloc.restype = ctypes.c_int
         lib.vqhull_hull_noalloc.argtypes = [vp, vp, i64, vp, vp, vp]
         lib.vqhull_hull_xy.restype = ctypes.c_int
@@ -235,6 +242,47 @@ def hull_ws_into(x, y, out_idx, out_count, ws, stream=None) -> None:
                             ctypes.c_void_p(out_idx.data_ptr()), ctypes.c_void_p(out_count.data_ptr()),
                             ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), _stream_handle(stream))
     _check(lib, st)
+
+
+def hull_inplace(x, y, offsets=None, stream=None):
+    """In-place mode (vqhull_hull_inplace / vqhull_hull_batched_inplace): x and y
+    are overwritten (their contents afterwards are unspecified) and serve as
+    one of the two point buffers; the workspace (24 B per point for the point
+    buffers instead of 40) comes from torch's allocator.  Without offsets:
+    the hull index list of the single request; with offsets (host sequence of
+    nreq + 1 ints): (out_idx, counts) as hull_batched returns them."""
+    import numpy as np
+    import torch
+
+    _check_points(x, y)
+    lib = load_library()
+    n = x.numel()
+    with torch.cuda.device(x.device):
+        if offsets is None:
+            out = torch.empty(max(n, 1), dtype=torch.int64, device=x.device)
+            cnt = torch.empty(1, dtype=torch.int64, device=x.device)
+            ws = torch.empty(lib.vqhull_workspace_bytes_inplace(n, 1), dtype=torch.uint8, device=x.device)
+            st = lib.vqhull_hull_inplace(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), n,
+                                         ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(cnt.data_ptr()),
+                                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream))
+            _check(lib, st)
+            h = int(cnt.item())
+            if h < 0:
+                raise VqhullError(-h, "non-finite coordinate in the input")
+            return out[:h]
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        nreq = len(off) - 1
+        if nreq < 0 or off[-1] != n:
+            raise ValueError("offsets must have nreq+1 entries ending at len(x)")
+        out = torch.empty(max(n, 1), dtype=torch.int64, device=x.device)
+        cnt = torch.empty(max(nreq, 1), dtype=torch.int64, device=x.device)
+        ws = torch.empty(lib.vqhull_workspace_bytes_inplace(n, nreq), dtype=torch.uint8, device=x.device)
+        st = lib.vqhull_hull_batched_inplace(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                             off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nreq,
+                                             ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(cnt.data_ptr()),
+                                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream))
+        _check(lib, st)
+        return out, cnt[:nreq]
 
 
 NOALLOC_MAX_POINTS = 1 << 20  # VQHULL_NOALLOC_MAX_POINTS

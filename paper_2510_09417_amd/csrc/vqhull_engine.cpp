@@ -797,7 +797,9 @@ constexpr size_t kWsAlign = 256;
 // path reserves; the node table holds one node per input point plus three per
 // request (every vertex the recursion can emit outside the LDS finisher), and
 // the per-level node counts cover up to 2^20 levels.  Returns the bytes used.
-size_t ws_layout(Context& w, char* base, size_t N, size_t nreq, const vqhull_config& cfg) {
+// inplace: buffer A's coordinate arrays are the caller's x and y (set by the
+// caller of this function), so only its index array is carved.
+size_t ws_layout(Context& w, char* base, size_t N, size_t nreq, const vqhull_config& cfg, bool inplace = false) {
   N = std::max<size_t>(N, 1);
   nreq = std::max<size_t>(nreq, 1);
   const size_t tile = (size_t)cfg.sweep_block * (size_t)cfg.sweep_ppt;
@@ -822,8 +824,9 @@ size_t ws_layout(Context& w, char* base, size_t N, size_t nreq, const vqhull_con
     }
   };
   for (int k = 0; k < 2; ++k) {
-    double* px = reinterpret_cast<double*>(raw(N * sizeof(double)));
-    double* py = reinterpret_cast<double*>(raw(N * sizeof(double)));
+    const bool own = !(inplace && k == 0);
+    double* px = own ? reinterpret_cast<double*>(raw(N * sizeof(double))) : nullptr;
+    double* py = own ? reinterpret_cast<double*>(raw(N * sizeof(double))) : nullptr;
     uint32_t* pi = reinterpret_cast<uint32_t*>(raw(N * sizeof(uint32_t)));
     if (base) {
       w.wx[k] = px;
@@ -863,9 +866,9 @@ size_t ws_layout(Context& w, char* base, size_t N, size_t nreq, const vqhull_con
   return off;
 }
 
-size_t ws_bytes(size_t N, size_t nreq, const vqhull_config& cfg) {
+size_t ws_bytes(size_t N, size_t nreq, const vqhull_config& cfg, bool inplace = false) {
   Context sizing;
-  return ws_layout(sizing, nullptr, N, nreq, cfg);
+  return ws_layout(sizing, nullptr, N, nreq, cfg, inplace);
 }
 
 // The contexts of the _ws calls: host-side state only (pinned staging, the
@@ -920,11 +923,14 @@ void release_ws_context(Context* c) {
   g_wsc_free[c->device].push_back(c);
 }
 
+// inplace: x and y (the caller's, writable) also serve as buffer A's
+// coordinate arrays from the first recursion level that writes buffer A on.
 int guarded_ws(const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
-               int64_t* out_counts, void* ws, size_t ws_size, vqhull_stream_t stream) {
+               int64_t* out_counts, void* ws, size_t ws_size, vqhull_stream_t stream, bool inplace = false) {
   const vqhull_config cfg = current_config();
   const size_t N = (size_t)offsets[nreq];
-  if (!ws || (reinterpret_cast<uintptr_t>(ws) % kWsAlign) != 0 || ws_size < ws_bytes(N, (size_t)nreq, cfg)) {
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) % kWsAlign) != 0 ||
+      ws_size < ws_bytes(N, (size_t)nreq, cfg, inplace)) {
     g_last_error = "workspace missing, misaligned or smaller than vqhull_workspace_bytes()";
     return VQHULL_ERR_INVALID_ARGUMENT;
   }
@@ -932,7 +938,11 @@ int guarded_ws(const double* x, const double* y, const int64_t* offsets, int64_t
   int st = guard_status([&] { c = acquire_ws_context(); });
   if (st != VQHULL_OK) return st;
   st = guard_status([&] {
-    ws_layout(*c, static_cast<char*>(ws), N, (size_t)nreq, cfg);
+    ws_layout(*c, static_cast<char*>(ws), N, (size_t)nreq, cfg, inplace);
+    if (inplace) {
+      c->wx[0] = const_cast<double*>(x);
+      c->wy[0] = const_cast<double*>(y);
+    }
     run(*c, cfg, x, y, offsets, nreq, out_idx, out_counts, (hipStream_t)stream);
     publish_last(*c);
   });
@@ -1279,6 +1289,33 @@ int vqhull_hull_noalloc(const double* x, const double* y, int64_t n, int64_t* ou
     w.status_host_dev = w.status_mirror;
     run_fixed_single(w, cfg, x, y, (uint32_t)n, out_idx, out_count, st, d);
   });
+}
+
+size_t vqhull_workspace_bytes_inplace(int64_t n_total, int64_t nreq) {
+  if (n_total < 0 || n_total >= (int64_t(1) << 31) || nreq < 0 || nreq >= (int64_t(1) << 31)) return 0;
+  try {
+    return ws_bytes((size_t)n_total, (size_t)nreq, current_config(), true);
+  } catch (...) {
+    return 0;
+  }
+}
+
+int vqhull_hull_inplace(double* x, double* y, int64_t n, int64_t* out_idx, int64_t* out_count, void* workspace,
+                        size_t workspace_bytes, vqhull_stream_t stream) {
+  if (n < 0 || n >= (int64_t(1) << 31) || !out_idx || !out_count || (n > 0 && (!x || !y)))
+    return VQHULL_ERR_INVALID_ARGUMENT;
+  const int64_t offsets[2] = {0, n};
+  return guarded_ws(x, y, offsets, 1, out_idx, out_count, workspace, workspace_bytes, stream, true);
+}
+
+int vqhull_hull_batched_inplace(double* x, double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
+                                int64_t* out_counts, void* workspace, size_t workspace_bytes,
+                                vqhull_stream_t stream) {
+  if (nreq < 0 || !offsets || nreq >= (int64_t(1) << 31)) return VQHULL_ERR_INVALID_ARGUMENT;
+  if (nreq == 0) return VQHULL_OK;
+  if (!out_counts || !out_idx || !offsets_valid(offsets, nreq)) return VQHULL_ERR_INVALID_ARGUMENT;
+  if (offsets[nreq] > 0 && (!x || !y)) return VQHULL_ERR_INVALID_ARGUMENT;
+  return guarded_ws(x, y, offsets, nreq, out_idx, out_counts, workspace, workspace_bytes, stream, true);
 }
 
 int vqhull_hull_xy(const double* xy, int64_t n, int64_t* out_idx, int64_t* out_count, vqhull_stream_t stream) {

@@ -248,3 +248,28 @@ def test_workspace_calls_reject_bad_arguments_on_host(lib):
                                       dummy, ws, need2, None) == 1
     assert lib.vqhull_hull_batched_ws(dummy, dummy, None, 2, dummy, dummy, ws, need2, None) == 1
     assert lib.vqhull_hull_batched_ws(dummy, dummy, p, 0, dummy, dummy, None, 0, None) == 0  # nothing to do
+
+
+def test_inplace_workspace_and_arguments_on_host(lib):
+    """In-place mode: its workspace is the _ws one less buffer A's two
+    coordinate arrays (16 bytes per point), and its calls check arguments and
+    the workspace before any HIP call."""
+    import paper_2510_09417_amd as vq
+
+    for n, nreq in ((10**6, 1), (10**8, 1), (10**7, 500)):
+        full, inpl = vq.workspace_bytes(n, nreq), lib.vqhull_workspace_bytes_inplace(n, nreq)
+        assert full - inpl == 2 * ((8 * n + 255) // 256 * 256)
+    assert lib.vqhull_workspace_bytes_inplace(-1, 1) == 0
+    vp = ctypes.c_void_p
+    dummy = vp(0x1000)
+    ws = vp(0x100000)
+    need = lib.vqhull_workspace_bytes_inplace(5, 1)
+    assert lib.vqhull_hull_inplace(dummy, dummy, -1, dummy, dummy, ws, need, None) == 1
+    assert lib.vqhull_hull_inplace(None, dummy, 5, dummy, dummy, ws, need, None) == 1
+    assert lib.vqhull_hull_inplace(dummy, dummy, 5, dummy, dummy, ws, need - 1, None) == 1
+    assert lib.vqhull_hull_inplace(dummy, dummy, 5, dummy, dummy, vp(0x100010), need, None) == 1
+    off = np.array([0, 3, 5], dtype=np.int64)
+    p = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    need2 = lib.vqhull_workspace_bytes_inplace(5, 2)
+    assert lib.vqhull_hull_batched_inplace(dummy, dummy, p, 2, dummy, dummy, ws, need2 - 256, None) == 1
+    assert lib.vqhull_hull_batched_inplace(dummy, dummy, None, 2, dummy, dummy, ws, need2, None) == 1

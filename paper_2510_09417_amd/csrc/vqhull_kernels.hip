@@ -1036,17 +1036,23 @@ __device__ __forceinline__ int32_t emit_one(uint32_t kind, const Tri& tr, uint32
   return nid;
 }
 
-// Tile maps of the big new segments (one wave per segment, its lanes over the
-// tiles), then running totals.
+// Tile maps of the big new segments (a few: the whole workgroup over each
+// one's tiles; many: one wave per segment), then running totals.
 template <int PB>
-__device__ __forceinline__ void emit_finish(const uint32_t (&tot)[4], const Seg* seg_out, uint32_t* tile_seg_out,
-                                            uint32_t tile, PlanSharedT<PB>& S) {
+__device__ __forceinline__ void emit_finish(const uint32_t (&tot)[4], uint32_t* tile_seg_out, PlanSharedT<PB>& S) {
   __syncthreads();
   const uint32_t nf = S.nfill;
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-  for (uint32_t f = w; f < nf; f += PB / 64) {
-    const uint32_t sid = S.fill[f], t0 = S.fill_t0[f], nt = S.fill_nt[f];
-    for (uint32_t i = lane; i < nt; i += 64u) tile_seg_out[t0 + i] = sid;
+  if (nf <= PB / 64) {
+    for (uint32_t f = 0; f < nf; ++f) {
+      const uint32_t sid = S.fill[f], t0 = S.fill_t0[f], nt = S.fill_nt[f];
+      for (uint32_t i = threadIdx.x; i < nt; i += PB) tile_seg_out[t0 + i] = sid;
+    }
+  } else {
+    for (uint32_t f = w; f < nf; f += PB / 64) {
+      const uint32_t sid = S.fill[f], t0 = S.fill_t0[f], nt = S.fill_nt[f];
+      for (uint32_t i = lane; i < nt; i += 64u) tile_seg_out[t0 + i] = sid;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1237,7 +1243,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
       A.req[i].q = rq.n > 0 ? e.mxi : 0u;
       A.req[i].root = nid;
     }
-    emit_finish(tot, A.seg_out, A.tile_seg_out, A.tile, S);
+    emit_finish(tot, A.tile_seg_out, S);
   }
   if (threadIdx.x == 0) A.level_nodes[0] = 0u;
   plan_status(S, A.st_out, A.st_host, 0u, A.level_nodes + 1, S.tiles);
@@ -1382,7 +1388,7 @@ __device__ void plan_level(const PlanArgs& A, PlanLds<PB>& L) {
         A.fr_out[s] = f;
       }
     }
-    emit_finish(tot, A.seg_out, A.tile_seg_out, A.tile, S);
+    emit_finish(tot, A.tile_seg_out, S);
   }
   // The fused pass walks the roots' tiles again.
   plan_status(S, A.st_out, A.st_host, node_base, A.level_nodes + A.level + 2u, A.fuse ? A.st_in->ntiles : S.tiles);

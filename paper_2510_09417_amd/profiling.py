@@ -6,6 +6,8 @@
 
     python -m paper_2510_09417_amd.profiling hull-run <workload>
     python -m paper_2510_09417_amd.profiling size-sweep <out.md>
+    python -m paper_2510_09417_amd.profiling sq-counters <pass-1 counter_collection.csv>
+            <pass-2 counter_collection.csv> <hull-run output> <out.md> "<pass-1 command>" "<pass-2 command>"
     python -m paper_2510_09417_amd.profiling hull-bytes <out.md> "<fetch command>" "<write command>"
             <workload> <fetch counter_collection.csv> <write counter_collection.csv> <hull-run output> [...]
 
@@ -321,12 +323,81 @@ def hull_bytes(out_md: str, fetch_cmd: str, write_cmd: str, runs: list, probe_el
     return rows
 
 
+SQ_KINDS = (("fused pass", lambda k: SWEEP in k and FUSED_MODE in k),
+            ("argmax pass", lambda k: SWEEP in k and ", 1>" in k),
+            ("extremes", lambda k: "k_extremes" in k),
+            ("level sweeps (all levels)", lambda k: SWEEP in k and ", 0>" in k))
+
+
+def _sums(path: str) -> dict:
+    agg = {}
+    for r in csv.DictReader(open(path)):
+        a = agg.setdefault(short(r["Kernel_Name"]), {})
+        a[r["Counter_Name"]] = a.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        a.setdefault("_dispatches", set()).add(r.get("Dispatch_Id"))
+    return agg
+
+
+def sq_counters(csv1: str, csv2: str, run_out: str, out_md: str, cmd1: str, cmd2: str) -> list:
+    """Issue and wait counters of the partition sweeps from two rocprofv3
+    --pmc passes over ``hull-run`` (pass 1: wave cycles and activity; pass 2:
+    instruction counts).  Points per kernel from the run's level statistics:
+    n per call for the extremes, argmax and fused passes, the swept points of
+    levels >= 2 for the level sweeps.  Instructions per point are wave
+    instructions x 64 / points."""
+    run = json.loads([ln for ln in open(run_out).read().splitlines() if ln.startswith("{")][-1])
+    n, calls = run["n"], run["calls"]
+    lv = run["levels"]
+    pts = {"fused pass": n * calls, "argmax pass": n * calls, "extremes": n * calls,
+           "level sweeps (all levels)": sum(l["swept"] for l in lv[2:]) * calls}
+    a1, a2 = _sums(csv1), _sums(csv2)
+    rows = []
+    for name, pred in SQ_KINDS:
+        c = {}
+        disp = 0
+        for agg in (a1, a2):
+            for k, v in agg.items():
+                if pred(k):
+                    disp = max(disp, len(v["_dispatches"]))
+                    for key, val in v.items():
+                        if key != "_dispatches":
+                            c[key] = c.get(key, 0.0) + val
+        if not c or not pts[name]:
+            continue
+        wc = c.get("SQ_WAVE_CYCLES", 0.0) or 1.0
+        per = lambda key: 64.0 * c.get(key, 0.0) / pts[name]
+        rows.append((name, disp, c.get("SQ_WAIT_ANY", 0.0) / wc, c.get("SQ_WAIT_INST_ANY", 0.0) / wc,
+                     c.get("SQ_ACTIVE_INST_ANY", 0.0) / wc, c.get("SQ_ACTIVE_INST_VALU", 0.0) / wc,
+                     per("SQ_INSTS_VALU"), per("SQ_INSTS_SALU"), per("SQ_INSTS_VMEM_RD"), per("SQ_INSTS_VMEM_WR"), c))
+    lines = [f"# Issue and wait counters of the partition sweeps (rocprofv3 SQ counters, {run['workload']})", "",
+             f"Pass 1: `{cmd1}`", "", f"Pass 2: `{cmd2}`", "",
+             f"{calls} plain hull calls (n = {n:,}, h = {run['h']}) under the configuration "
+             f"{run['config']}.  Counters are summed over each kernel's dispatches in both calls; ratios are taken "
+             "against SQ_WAVE_CYCLES (the waves' resident cycles); instructions per point are wave instructions "
+             "x 64 / (points that kernel swept).", "",
+             "| kernel | dispatches | waiting (WAIT_ANY / WAVE_CYCLES) | waiting on a dependency (WAIT_INST_ANY) "
+             "| issuing any (ACTIVE_INST_ANY) | issuing VALU (ACTIVE_INST_VALU) | VALU instr / pt | SALU instr / pt "
+             "| vector loads / pt | vector stores / pt |", "|---|---|---|---|---|---|---|---|---|---|"]
+    for name, disp, w, wi, ai, av, va, sa, vr, vw, _ in rows:
+        lines.append(f"| {name} | {disp} | {w:.3f} | {wi:.3f} | {ai:.3f} | {av:.3f} | {va:.1f} | {sa:.1f} | "
+                     f"{vr:.1f} | {vw:.1f} |")
+    lines += ["", "Raw sums:", "", "| kernel | counter | sum |", "|---|---|---|"]
+    for name, *_, c in rows:
+        for key in sorted(c):
+            lines.append(f"| {name} | {key} | {c[key]:.0f} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return rows
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "hull-run":
         hull_run(sys.argv[2])
     elif sys.argv[1] == "hull-bytes":
         rest = sys.argv[5:]
         hull_bytes(sys.argv[2], sys.argv[3], sys.argv[4], [tuple(rest[i:i + 4]) for i in range(0, len(rest), 4)])
+    elif sys.argv[1] == "sq-counters":
+        sq_counters(*sys.argv[2:8])
     elif sys.argv[1] == "size-sweep":
         size_sweep(sys.argv[2])
     elif sys.argv[1] == "stats":

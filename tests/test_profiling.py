@@ -104,3 +104,37 @@ def test_alg_bytes_batched_reduces_to_single_and_counts_small_requests():
     assert b["total"] - b["top"] == profiling.alg_bytes(100, levels)["total"] - profiling.alg_bytes(100, levels)["top"]
     only_small = [dict(segments=0, swept=0, jobs=3, job_points=40)]
     assert profiling.alg_bytes_batched(40, only_small)["total"] == 8 * 40 + 16 * 40
+
+
+def test_sq_counters_summary(tmp_path):
+    """Per-kernel sums of two counter passes, ratios against the waves'
+    resident cycles, and instructions per point from the run's levels."""
+    import csv
+
+    from paper_2510_09417_amd import profiling as P
+
+    fused = "void vqh::k_sweep<256, 16, 2>(vqh::SweepArgs)"
+    level = "void vqh::k_sweep<256, 16, 0>(vqh::SweepArgs)"
+
+    def write(path, rows):
+        with open(path, "w", newline="") as f:
+            w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+            w.writeheader()
+            for r in rows:
+                w.writerow(dict(zip(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"], r)))
+
+    write(tmp_path / "p1.csv", [(1, fused, "SQ_WAVE_CYCLES", 1000), (1, fused, "SQ_WAIT_ANY", 400),
+                                (2, fused, "SQ_WAVE_CYCLES", 1000), (2, fused, "SQ_WAIT_ANY", 200),
+                                (3, level, "SQ_WAVE_CYCLES", 500)])
+    write(tmp_path / "p2.csv", [(1, fused, "SQ_INSTS_VALU", 3000), (2, fused, "SQ_INSTS_VALU", 3000),
+                                (3, level, "SQ_INSTS_VALU", 640)])
+    run = tmp_path / "run.txt"
+    run.write_text('noise\n{"workload": "disk_1e8", "n": 6400, "calls": 2, "h": 9, "config": {}, '
+                   '"levels": [{"swept": 6400}, {"swept": 6400}, {"swept": 320}, {"swept": 0}]}\n')
+    rows = P.sq_counters(str(tmp_path / "p1.csv"), str(tmp_path / "p2.csv"), str(run), str(tmp_path / "o.md"),
+                         "c1", "c2")
+    by = {r[0]: r for r in rows}
+    assert by["fused pass"][1] == 2 and abs(by["fused pass"][2] - 0.3) < 1e-12
+    assert abs(by["fused pass"][6] - 64 * 6000 / 12800) < 1e-9
+    assert abs(by["level sweeps (all levels)"][6] - 64 * 640 / 640) < 1e-9
+    assert "c1" in (tmp_path / "o.md").read_text()

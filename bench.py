@@ -279,11 +279,13 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
         # latency from the scheduled arrival: the wait to be submitted plus
         # submit -> results written on the server's clock
         lat_ms = [1e3 * (delay[k] + infos[k]["t_done"] - infos[k]["t_submit"]) for k in range(m)]
-        return infos, st, lat_ms
+        # the part of it spent waiting for a lane (admission is per batch)
+        wait_ms = [1e3 * (delay[k] + infos[k]["t_start"] - infos[k]["t_submit"]) for k in range(m)]
+        return infos, st, lat_ms, wait_ms
 
     # warm-up (lane allocation, first launches)
     run(np.zeros(min(nreq, 256)))
-    infos, st, _ = run(np.zeros(nreq))
+    infos, st, _, _ = run(np.zeros(nreq))
     t_first = min(i["t_submit"] for i in infos)
     t_last = max(i["t_done"] for i in infos)
     thr = nreq / (t_last - t_first)
@@ -326,7 +328,9 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
     nlat = min(nreq, 16384)
     g = np.random.default_rng(workloads.SERVED_SEED + 1)
     arr = np.cumsum(-np.log1p(-g.random(nlat)) / (0.5 * thr))
-    linfos, lst, lat = run(arr)
+    linfos, lst, lat, lwait = run(arr)
+    log(f"at {0.5 * thr:.0f} hulls/s: served p50 {percentile(lat, 0.50):.3f} p99 {percentile(lat, 0.99):.3f} ms, "
+        f"of which waiting for a lane p50 {percentile(lwait, 0.50):.3f} p99 {percentile(lwait, 0.99):.3f} ms")
 
     # plain path: one synchronous vqhull_hull per request, time-boxed
     stream = torch.cuda.current_stream()
@@ -354,7 +358,7 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
     lam = 0.9 * plain_thr
     gm = np.random.default_rng(workloads.SERVED_SEED + 2)
     arr_m = np.cumsum(-np.log1p(-gm.random(nm)) / lam)
-    _, _, m_served = run(arr_m)
+    _, _, m_served, _ = run(arr_m)
     m_plain = []
     t_start = time.perf_counter()
     for k in range(nm):
@@ -388,6 +392,7 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
         "failed": bad,
         "latency_load_hulls_per_s": round(0.5 * thr, 1), "latency_requests": nlat,
         "p50_ms": round(percentile(lat, 0.50), 3), "p99_ms": round(percentile(lat, 0.99), 3),
+        "lane_wait_p50_ms": round(percentile(lwait, 0.50), 3), "lane_wait_p99_ms": round(percentile(lwait, 0.99), 3),
         "plain_hulls_per_s": round(plain_thr, 1), "plain_requests": len(plain_lat),
         "plain_p50_ms": round(percentile(plain_lat, 0.50), 3), "plain_p99_ms": round(percentile(plain_lat, 0.99), 3),
         "served_equals_plain": f"{same}/{checked}",
@@ -509,7 +514,7 @@ def main() -> int:
     ap.add_argument("--no-aos", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--served-requests", type=int, default=65536)
-    ap.add_argument("--served-lanes", type=int, default=4)
+    ap.add_argument("--served-lanes", type=int, default=8)
     ap.add_argument("--served-lane-points", type=int, default=1 << 25)
     ap.add_argument("--n", type=int, default=100_000_000, help="points per dataset (default 1e8)")
     args = ap.parse_args()

@@ -1,4 +1,4 @@
-"""GPU test of the server in the exact shape the benchmark times it: 4 lanes
+"""GPU test of the server in the exact shape the benchmark times it: 8 lanes
 of 2^25 points and 8192 requests, each lane replaying its batch step captured
 with 20 recursion levels, under the persistent kernel configuration that the
 batched autotuner picks on the request mix.  The requests are the served mix's
@@ -15,7 +15,7 @@ from paper_2510_09417_amd import autotune, workloads
 
 pytestmark = pytest.mark.gpu
 
-LANES, LANE_POINTS, LANE_REQUESTS, GRAPH_LEVELS = 4, 1 << 25, 8192, 20
+LANES, LANE_POINTS, LANE_REQUESTS, GRAPH_LEVELS = 8, 1 << 25, 8192, 20
 FIRST = 400
 
 

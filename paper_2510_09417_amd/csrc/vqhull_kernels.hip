@@ -2635,8 +2635,10 @@ uint32_t sweep_occupancy_grid() {
   return (uint32_t)(per_cu * cus);
 }
 
-// Workgroup size of the LDS finisher per job capacity.
-constexpr int kFinishBlock512 = 256, kFinishBlock1024 = 256, kFinishBlock2048 = 512;
+// Workgroup size of the LDS finisher per job capacity.  Jobs of up to 1024
+// points take 512 threads too: two such workgroups share a CU (~78 KB of LDS
+// each), and their 16 waves hide the finisher's LDS latency better than 8.
+constexpr int kFinishBlock512 = 256, kFinishBlock1024 = 512, kFinishBlock2048 = 512;
 
 template <int BLOCK, int TMAX>
 int finish_attr() {

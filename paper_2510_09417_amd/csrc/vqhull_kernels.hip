@@ -2635,10 +2635,67 @@ uint32_t sweep_occupancy_grid() {
   return (uint32_t)(per_cu * cus);
 }
 
+}  // namespace
+
+bool sweep_shape_supported(int block, int ppt) {
+  return (block == 256 && (ppt == 16 || ppt == 32)) || (block == 512 && (ppt == 8 || ppt == 16)) ||
+         (block == 1024 && ppt == 8);
+}
+
+// Grid sizes are computed once per shape and cached (atomics: calls on
+// several host threads may ask at the same time; they compute equal values).
+uint32_t sweep_grid(int block, int ppt, int mode) {
+  static std::atomic<uint32_t> cache[5][kSweepModes] = {};
+  const int k = block == 256 ? (ppt == 16 ? 0 : 1) : block == 512 ? (ppt == 8 ? 2 : 3) : 4;
+  uint32_t g = cache[k][mode].load(std::memory_order_relaxed);
+  if (!g) {
+#define VQH_GRID(K, B, P)                                                          \
+  if (k == K)                                                                      \
+    g = mode == kSweepArgmax     ? sweep_occupancy_grid<B, P, kSweepArgmax>()   \
+        : mode == kSweepFused    ? sweep_occupancy_grid<B, P, kSweepFused>()    \
+        : mode == kSweepArgmaxWs ? sweep_occupancy_grid<B, P, kSweepArgmaxWs>() \
+        : mode == kSweepFusedWs  ? sweep_occupancy_grid<B, P, kSweepFusedWs>()  \
+                                 : sweep_occupancy_grid<B, P, kSweepLevel>();
+    VQH_GRID(0, 256, 16)
+    VQH_GRID(1, 256, 32)
+    VQH_GRID(2, 512, 8)
+    VQH_GRID(3, 512, 16)
+    VQH_GRID(4, 1024, 8)
+#undef VQH_GRID
+    cache[k][mode].store(g, std::memory_order_relaxed);
+  }
+  return g;
+}
+
+int launch_extremes(const ExtremesArgs& a, void* stream) {
+  if (a.ntiles == 0) return 0;
+  hipLaunchKernelGGL((k_extremes<kExtBlock, kExtPPT, kExtIter>), dim3(a.ntiles), dim3(kExtBlock), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int launch_sweep(const SweepArgs& a, int mode, int block, int ppt, uint32_t grid, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (block == 256 && ppt == 16) return sweep_one<256, 16>(a, mode, grid, st);
+  if (block == 256 && ppt == 32) return sweep_one<256, 32>(a, mode, grid, st);
+  if (block == 512 && ppt == 8) return sweep_one<512, 8>(a, mode, grid, st);
+  if (block == 512 && ppt == 16) return sweep_one<512, 16>(a, mode, grid, st);
+  if (block == 1024 && ppt == 8) return sweep_one<1024, 8>(a, mode, grid, st);
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_plan0(const Plan0Args& a, void* stream) {
+  hipLaunchKernelGGL(k_plan0, dim3(1), dim3(kPlanBlock), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+// LDS finisher + planner launches (below the sweep launchers).
+namespace {
+
 // Workgroup size of the LDS finisher per job capacity.  Jobs of up to 1024
 // points take 512 threads too: two such workgroups share a CU (~78 KB of LDS
 // each), and their 16 waves hide the finisher's LDS latency better than 8.
 constexpr int kFinishBlock512 = 256, kFinishBlock1024 = 512, kFinishBlock2048 = 512;
+static_assert(sizeof(FinishShared<kFinishBlock2048, 2048>) <= 160 * 1024, "the LDS finisher fits one CU's LDS");
 
 template <int BLOCK, int TMAX>
 int finish_attr() {
@@ -2676,37 +2733,8 @@ uint32_t finish_occupancy_grid() {
     cus = 256;
   return (uint32_t)(per_cu * cus);
 }
+
 }  // namespace
-
-bool sweep_shape_supported(int block, int ppt) {
-  return (block == 256 && (ppt == 16 || ppt == 32)) || (block == 512 && (ppt == 8 || ppt == 16)) ||
-         (block == 1024 && ppt == 8);
-}
-
-// Grid sizes are computed once per shape and cached (atomics: calls on
-// several host threads may ask at the same time; they compute equal values).
-uint32_t sweep_grid(int block, int ppt, int mode) {
-  static std::atomic<uint32_t> cache[5][kSweepModes] = {};
-  const int k = block == 256 ? (ppt == 16 ? 0 : 1) : block == 512 ? (ppt == 8 ? 2 : 3) : 4;
-  uint32_t g = cache[k][mode].load(std::memory_order_relaxed);
-  if (!g) {
-#define VQH_GRID(K, B, P)                                                          \
-  if (k == K)                                                                      \
-    g = mode == kSweepArgmax     ? sweep_occupancy_grid<B, P, kSweepArgmax>()   \
-        : mode == kSweepFused    ? sweep_occupancy_grid<B, P, kSweepFused>()    \
-        : mode == kSweepArgmaxWs ? sweep_occupancy_grid<B, P, kSweepArgmaxWs>() \
-        : mode == kSweepFusedWs  ? sweep_occupancy_grid<B, P, kSweepFusedWs>()  \
-                                 : sweep_occupancy_grid<B, P, kSweepLevel>();
-    VQH_GRID(0, 256, 16)
-    VQH_GRID(1, 256, 32)
-    VQH_GRID(2, 512, 8)
-    VQH_GRID(3, 512, 16)
-    VQH_GRID(4, 1024, 8)
-#undef VQH_GRID
-    cache[k][mode].store(g, std::memory_order_relaxed);
-  }
-  return g;
-}
 
 int finish_tmax_for(int lds_limit) { return lds_limit <= 512 ? 512 : lds_limit <= 1024 ? 1024 : 2048; }
 
@@ -2721,27 +2749,6 @@ uint32_t finish_grid(int tmax) {
     cache[k].store(g, std::memory_order_relaxed);
   }
   return g;
-}
-
-int launch_extremes(const ExtremesArgs& a, void* stream) {
-  if (a.ntiles == 0) return 0;
-  hipLaunchKernelGGL((k_extremes<kExtBlock, kExtPPT, kExtIter>), dim3(a.ntiles), dim3(kExtBlock), 0, (hipStream_t)stream, a);
-  return (int)hipGetLastError();
-}
-
-int launch_sweep(const SweepArgs& a, int mode, int block, int ppt, uint32_t grid, void* stream) {
-  hipStream_t st = (hipStream_t)stream;
-  if (block == 256 && ppt == 16) return sweep_one<256, 16>(a, mode, grid, st);
-  if (block == 256 && ppt == 32) return sweep_one<256, 32>(a, mode, grid, st);
-  if (block == 512 && ppt == 8) return sweep_one<512, 8>(a, mode, grid, st);
-  if (block == 512 && ppt == 16) return sweep_one<512, 16>(a, mode, grid, st);
-  if (block == 1024 && ppt == 8) return sweep_one<1024, 8>(a, mode, grid, st);
-  return (int)hipErrorInvalidValue;
-}
-
-int launch_plan0(const Plan0Args& a, void* stream) {
-  hipLaunchKernelGGL(k_plan0, dim3(1), dim3(kPlanBlock), 0, (hipStream_t)stream, a);
-  return (int)hipGetLastError();
 }
 
 int launch_octagon(const OctArgs& a, void* stream) {

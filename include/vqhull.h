@@ -67,7 +67,9 @@ typedef enum {
   VQHULL_ERR_OUT_OF_MEMORY = 2,    /* device workspace could not be allocated */
   VQHULL_ERR_NONFINITE = 3,        /* a NaN or infinity in the input (reported per request) */
   VQHULL_ERR_HIP = 4,              /* a HIP runtime call failed; see vqhull_last_error() */
-  VQHULL_ERR_TIMEOUT = 5           /* vqhull_server_wait_timeout: the request was not done in time */
+  VQHULL_ERR_TIMEOUT = 5,          /* vqhull_server_wait_timeout: the request was not done in time */
+  VQHULL_ERR_INCOMPLETE = 6        /* vqhull_hull_batched_async: the level budget ended before the
+                                      recursion did (reported per request) */
 } vqhull_status;
 
 /* Stream handle: a hipStream_t passed as an opaque pointer (NULL = the default
@@ -158,6 +160,38 @@ int vqhull_hull_ws(const double* x, const double* y, int64_t n, int64_t* out_idx
 int vqhull_hull_batched_ws(const double* x, const double* y, const int64_t* offsets, int64_t nreq,
                            int64_t* out_idx, int64_t* out_counts, void* workspace, size_t workspace_bytes,
                            vqhull_stream_t stream);
+
+/*
+ * Stream-ordered batched call: the hulls of Algorithm 1 (Section 2.1) for the
+ * requests of vqhull_hull_batched_ws, enqueued on the stream with no host
+ * wait; the call returns once its work is enqueued.  The recursion runs a
+ * fixed budget of `levels` breadth-first levels (the top level counts as
+ * two: its argmax pass and its fused pass), whose kernels read their work
+ * counts from the device; levels past the end of the recursion do no work.
+ *   levels     the level budget, 1 <= levels <= 4096; a disk or square of
+ *              10^8 points needs about 8, a circle of 5 10^7 about 16, the
+ *              worst case (points on a convex curve of growing curvature)
+ *              up to the number of points.
+ *   workspace, workspace_bytes  as for vqhull_hull_batched_ws (the same
+ *              vqhull_workspace_bytes); the workspace and out_idx must stay
+ *              untouched until the stream has finished the call's work.
+ * Every other argument is that of vqhull_hull_batched_ws.  On the device,
+ * out_counts[i] receives h_i, or -VQHULL_ERR_NONFINITE for a request with a
+ * NaN or infinity, or -VQHULL_ERR_INCOMPLETE for every request of the call
+ * when the recursion had work left after the last level of the budget (its
+ * lists are then not written: run the call again with a larger budget or
+ * with vqhull_hull_batched_ws, whose level loop is not bounded).  The index
+ * lists of a completed call equal those of vqhull_hull_batched.
+ * Returns VQHULL_OK once enqueued, VQHULL_ERR_INVALID_ARGUMENT (bad sizes,
+ * offsets, level budget or workspace) with nothing enqueued, or
+ * VQHULL_ERR_HIP.  The request table is staged in pinned host memory of the
+ * library, which a later call reuses only once the stream has copied it.
+ * The call writes no status to the host: vqhull_last_level_stats and
+ * vqhull_last_kernel_times do not cover it.
+ */
+int vqhull_hull_batched_async(const double* x, const double* y, const int64_t* offsets, int64_t nreq,
+                              int64_t* out_idx, int64_t* out_counts, int32_t levels, void* workspace,
+                              size_t workspace_bytes, vqhull_stream_t stream);
 
 /*
  * In-place mode (the paper keeps no second copy of the points: its extraction

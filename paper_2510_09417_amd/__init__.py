@@ -20,10 +20,12 @@ VQHULL_ERR_OUT_OF_MEMORY = 2
 VQHULL_ERR_NONFINITE = 3
 VQHULL_ERR_HIP = 4
 VQHULL_ERR_TIMEOUT = 5
+VQHULL_ERR_INCOMPLETE = 6
 
 # Symbols that include/vqhull.h declares.
 EXPORTED = (
     "vqhull_hull", "vqhull_hull_batched", "vqhull_workspace_bytes", "vqhull_hull_ws", "vqhull_hull_batched_ws",
+    "vqhull_hull_batched_async",
     "vqhull_workspace_bytes_inplace", "vqhull_hull_inplace", "vqhull_hull_batched_inplace",
     "vqhull_hull_noalloc", "vqhull_hull_xy", "vqhull_hull_batched_xy", "vqhull_get_config", "vqhull_set_config", "vqhull_autotune",
     "vqhull_last_level_stats", "vqhull_set_timing", "vqhull_last_kernel_times", "vqhull_orient", "vqhull_stream_scale",
@@ -110,6 +112,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.vqhull_hull_ws.argtypes = [vp, vp, i64, vp, vp, vp, ctypes.c_size_t, vp]
         lib.vqhull_hull_batched_ws.restype = ctypes.c_int
         lib.vqhull_hull_batched_ws.argtypes = [vp, vp, pi64, i64, vp, vp, vp, ctypes.c_size_t, vp]
+        lib.vqhull_hull_batched_async.restype = ctypes.c_int
+        lib.vqhull_hull_batched_async.argtypes = [vp, vp, pi64, i64, vp, vp, ctypes.c_int32, vp, ctypes.c_size_t, vp]
         lib.vqhull_workspace_bytes_inplace.restype = ctypes.c_size_t
         lib.vqhull_workspace_bytes_inplace.argtypes = [i64, i64]
         lib.vqhull_hull_inplace.restype = ctypes.c_int
@@ -404,6 +408,39 @@ def hull_batched_ws(x, y, offsets, ws=None, stream=None):
                                         _stream_handle(stream))
     _check(lib, st)
     return out, cnt[:nreq]
+
+
+INCOMPLETE = -VQHULL_ERR_INCOMPLETE  # a count of hull_batched_async: the level budget ended before the recursion
+
+
+def hull_batched_async(x, y, offsets, levels: int = 64, ws=None, stream=None):
+    """vqhull_hull_batched_async: the batched hulls enqueued on the stream with
+    no host wait, in a budget of ``levels`` recursion levels.  Returns
+    (out_idx, counts, ws) device tensors, valid once the stream has finished
+    the call's work; a count of INCOMPLETE for every request means the budget
+    was too small.  ws (a tensor from ``workspace``, or None for a fresh one)
+    must stay alive until then; it is returned for that purpose."""
+    import numpy as np
+    import torch
+
+    _check_points(x, y)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    nreq = len(off) - 1
+    if nreq < 0 or off[-1] != x.numel():
+        raise ValueError("offsets must have nreq+1 entries ending at len(x)")
+    lib = load_library()
+    out = torch.empty(max(x.numel(), 1), dtype=torch.int64, device=x.device)
+    cnt = torch.empty(max(nreq, 1), dtype=torch.int64, device=x.device)
+    with torch.cuda.device(x.device):
+        if ws is None:
+            ws = workspace(x.numel(), nreq, x.device)
+        st = lib.vqhull_hull_batched_async(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                           off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nreq,
+                                           ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(cnt.data_ptr()),
+                                           int(levels), ctypes.c_void_p(ws.data_ptr()),
+                                           ws.numel() * ws.element_size(), _stream_handle(stream))
+    _check(lib, st)
+    return out, cnt[:nreq], ws
 
 
 def hull_batched(x, y, offsets, stream=None, check=True):

@@ -24,6 +24,7 @@
 using namespace vqh;
 
 static_assert(kCountNonfinite == -(int64_t)VQHULL_ERR_NONFINITE, "the kernels' count of a non-finite request");
+static_assert(kCountIncomplete == -(int64_t)VQHULL_ERR_INCOMPLETE, "the kernels' count of an unfinished request");
 
 namespace {
 
@@ -91,6 +92,7 @@ struct Context {
   Status* status_host_dev = nullptr;  // device view of status_host
   Status* status_mirror = nullptr;    // a device ring the planners may write instead (no pinned memory)
   hipEvent_t status_ev[kStatusRing] = {};
+  hipEvent_t staged = nullptr;  // stream-ordered calls: recorded after the copies of the host staging
   // pinned staging
   Req* h_req = nullptr;
   size_t h_req_cap = 0;
@@ -263,6 +265,7 @@ void free_workspace(Context* w) {
   for (hipEvent_t e : w->events) (void)hipEventDestroy(e);
   for (hipEvent_t e : w->status_ev)
     if (e) (void)hipEventDestroy(e);
+  if (w->staged) (void)hipEventDestroy(w->staged);
   delete w;
 }
 
@@ -950,6 +953,137 @@ int guarded_ws(const double* x, const double* y, const int64_t* offsets, int64_t
   return st;
 }
 
+// ------------------------------------------------- stream-ordered batched call
+
+// Host-side contexts of the stream-ordered calls, pooled per device.  A
+// context returns to the pool at once, but is taken again only after the
+// stream has copied its staging (its `staged` event has completed); otherwise
+// a new one is made, so a call never waits for earlier work.
+std::mutex g_asc_mu;
+std::map<int, std::vector<Context*>> g_asc_free;
+constexpr int kAsyncMaxLevels = 4096;
+
+Context* acquire_async_context() {
+  int dev = 0;
+  ck(hipGetDevice(&dev), "hipGetDevice");
+  {
+    std::lock_guard<std::mutex> g(g_asc_mu);
+    auto& v = g_asc_free[dev];
+    for (size_t i = 0; i < v.size(); ++i) {
+      if (hipEventQuery(v[i]->staged) == hipSuccess) {
+        Context* c = v[i];
+        v.erase(v.begin() + (ptrdiff_t)i);
+        return c;
+      }
+    }
+  }
+  Context* c = new_context(false);
+  ck(hipEventCreateWithFlags(&c->staged, hipEventDisableTiming), "hipEventCreateWithFlags");
+  return c;
+}
+
+void release_async_context(Context* c) {
+  std::lock_guard<std::mutex> g(g_asc_mu);
+  g_asc_free[c->device].push_back(c);
+}
+
+// Extremes, root planning, `levels` levels of sweeps and finisher + planner
+// launches with persistent grids, and the assembly, all enqueued on the stream
+// with no host wait.  The planners write no status to the host; the assembly
+// reads the device status of the level after the last and, if it still has
+// work, marks every request incomplete instead of writing lists.
+void enqueue_async(Context& w, vqhull_config cfg, const double* x, const double* y, const int64_t* offsets,
+                   int64_t nreq, int64_t* out_idx, int64_t* out_counts, int levels, hipStream_t st) {
+  const size_t N = (size_t)offsets[nreq];
+  size_t ext_tiles = 0;
+  ensure_host_req(w, (size_t)nreq);
+  for (int64_t i = 0; i < nreq; ++i) {
+    Req r{};
+    r.off = (uint32_t)offsets[i];
+    r.n = (uint32_t)(offsets[i + 1] - offsets[i]);
+    r.root = -1;
+    r.tile0 = (uint32_t)ext_tiles;
+    r.x = x + offsets[i];
+    r.y = y + offsets[i];
+    ext_tiles += (r.n + kExtTile - 1) / kExtTile;
+    w.h_req[i] = r;
+  }
+  if (ext_tiles > w.tile_req.cap) ck(hipErrorInvalidValue, "extremes tiles beyond the workspace");
+  ensure_host_u32(w, std::max<size_t>(ext_tiles, 1));
+  size_t t = 0;
+  for (int64_t i = 0; i < nreq; ++i) {
+    const size_t nt = (w.h_req[i].n + kExtTile - 1) / kExtTile;
+    for (size_t k = 0; k < nt; ++k) w.h_u32[t++] = (uint32_t)i;
+  }
+  w.counts_host->nreq = (uint32_t)nreq;
+  w.counts_host->ext_tiles = (uint32_t)ext_tiles;
+  w.counts_host->overflow = 0;
+  w.counts_host->pad = 0;
+  ck(hipMemcpyAsync(w.req.p, w.h_req, (size_t)nreq * sizeof(Req), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+  if (ext_tiles)
+    ck(hipMemcpyAsync(w.tile_req.p, w.h_u32, ext_tiles * sizeof(uint32_t), hipMemcpyHostToDevice, st),
+       "hipMemcpyAsync");
+  ck(hipMemcpyAsync(w.counts_dev, w.counts_host, sizeof(BatchCounts), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+  ck(hipEventRecord(w.staged, st), "hipEventRecord");
+
+  // The recursion of n points is at most n + 2 levels deep, and the table of
+  // per-level node counts holds min(N, 2^20) + 64 entries: a longer budget
+  // would only add empty levels.
+  levels = (int)std::min<size_t>((size_t)levels, w.level_nodes.cap - 3);
+  const int tmax = finish_tmax_for(cfg.lds_limit);
+  const ExtremesArgs ea{x, y, w.tile_req.p, w.req.p, w.epart.p, w.counts_dev, (uint32_t)ext_tiles};
+  ck(launch_extremes(ea, st), "k_extremes");
+  Plan0Args pa = plan0_args(w, cfg);
+  pa.st_host = nullptr;
+  ck(launch_plan0(pa, st), "k_plan0");
+  for (int k = 0; k < levels; ++k) {
+    const int mode = sweep_mode(k, false);
+    int blk = 0, ppt = 0;
+    level_shape(cfg, k, blk, ppt);
+    const uint32_t G = sweep_grid(blk, ppt, mode);
+    ck(launch_sweep(sweep_args(w, cfg, k, x, y, false), mode, blk, ppt, G, st), "k_sweep");
+    PlanArgs pl = plan_args(w, cfg, k, G);
+    pl.st_host = nullptr;
+    ck(launch_finish_plan(finish_args(w, x, y, k), pl, tmax, st), "k_finish_plan");
+  }
+  AssembleArgs aa{};
+  aa.nodes = w.nodes.p;
+  aa.level_begin = w.level_nodes.p;
+  aa.nlevels = (uint32_t)levels + 1u;
+  aa.req = w.req.p;
+  aa.counts = w.counts_dev;
+  aa.lists[0] = w.wi[0];
+  aa.lists[1] = w.wi[1];
+  aa.out_idx = out_idx;
+  aa.out_count = out_counts;
+  aa.max_nodes = (uint32_t)std::min<size_t>(w.nodes.cap, 0xFFFFFFFFu);
+  aa.last = w.status_dev + levels % kStatusRing;
+  ck(launch_assemble(aa, st), "k_assemble");
+  ck(launch_copy_lists(aa, st), "k_copy_lists");
+  (void)N;
+}
+
+int guarded_async(const double* x, const double* y, const int64_t* offsets, int64_t nreq, int64_t* out_idx,
+                  int64_t* out_counts, int levels, void* ws, size_t ws_size, vqhull_stream_t stream) {
+  vqhull_config cfg = current_config();
+  cfg.sweep_persistent = 1;  // grids must not depend on counts the host does not read
+  cfg.prefilter = 0;
+  const size_t N = (size_t)offsets[nreq];
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) % kWsAlign) != 0 || ws_size < ws_bytes(N, (size_t)nreq, cfg)) {
+    g_last_error = "workspace missing, misaligned or smaller than vqhull_workspace_bytes()";
+    return VQHULL_ERR_INVALID_ARGUMENT;
+  }
+  Context* c = nullptr;
+  int st = guard_status([&] { c = acquire_async_context(); });
+  if (st != VQHULL_OK) return st;
+  st = guard_status([&] {
+    ws_layout(*c, static_cast<char*>(ws), N, (size_t)nreq, cfg);
+    enqueue_async(*c, cfg, x, y, offsets, nreq, out_idx, out_counts, levels, (hipStream_t)stream);
+  });
+  release_async_context(c);
+  return st;
+}
+
 // ------------------------------------------ the entry point that allocates nothing
 //
 // vqhull_hull_noalloc keeps every device table of a call in `scratch`, a
@@ -1291,6 +1425,17 @@ int vqhull_hull_noalloc(const double* x, const double* y, int64_t n, int64_t* ou
   });
 }
 
+int vqhull_hull_batched_async(const double* x, const double* y, const int64_t* offsets, int64_t nreq,
+                              int64_t* out_idx, int64_t* out_counts, int32_t levels, void* workspace,
+                              size_t workspace_bytes, vqhull_stream_t stream) {
+  if (nreq < 0 || !offsets || nreq >= (int64_t(1) << 31) || levels < 1 || levels > kAsyncMaxLevels)
+    return VQHULL_ERR_INVALID_ARGUMENT;
+  if (nreq == 0) return VQHULL_OK;
+  if (!out_counts || !out_idx || !offsets_valid(offsets, nreq)) return VQHULL_ERR_INVALID_ARGUMENT;
+  if (offsets[nreq] > 0 && (!x || !y)) return VQHULL_ERR_INVALID_ARGUMENT;
+  return guarded_async(x, y, offsets, nreq, out_idx, out_counts, levels, workspace, workspace_bytes, stream);
+}
+
 size_t vqhull_workspace_bytes_inplace(int64_t n_total, int64_t nreq) {
   if (n_total < 0 || n_total >= (int64_t(1) << 31) || nreq < 0 || nreq >= (int64_t(1) << 31)) return 0;
   try {
@@ -1493,6 +1638,8 @@ const char* vqhull_status_string(int status) {
       return "HIP runtime error";
     case VQHULL_ERR_TIMEOUT:
       return "request not done before the deadline";
+    case VQHULL_ERR_INCOMPLETE:
+      return "the level budget ended before the recursion";
     default:
       return "unknown status";
   }

@@ -18,6 +18,7 @@ namespace vqh {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int64_t kCountNonfinite = -3;  // the count of a request with a NaN or infinity (-VQHULL_ERR_NONFINITE)
+constexpr int64_t kCountIncomplete = -6;  // a stream-ordered call's level budget ended first (-VQHULL_ERR_INCOMPLETE)
 
 // Source of a finisher job's points.
 enum : uint32_t { kSrcBufA = 0, kSrcBufB = 1, kSrcUser = 2 };
@@ -349,6 +350,10 @@ struct AssembleArgs {
   int64_t* out_idx;
   int64_t* out_count;
   uint32_t max_nodes;  // bound on level_begin[nlevels] (sizes k_copy_lists' grid)
+  // Stream-ordered calls: the status of the level after the last enqueued
+  // one.  If it still has segments or jobs (or a table overflowed), every
+  // request is marked incomplete and no list is written.  Null otherwise.
+  const Status* last;
 };
 
 // Supported sweep shapes.

@@ -2493,8 +2493,19 @@ __global__ __launch_bounds__(256) void k_orient(const double* __restrict__ abc, 
 
 constexpr int kAsmBlock = 1024;
 
+// A stream-ordered call whose level budget ended before the recursion did.
+__device__ __forceinline__ bool assembly_incomplete(const AssembleArgs& A) {
+  if (!A.last) return false;
+  const Status st = *A.last;
+  return st.nseg != 0u || st.njobs != 0u || st.overflow != 0u || A.counts->overflow != 0u;
+}
+
 __global__ __launch_bounds__(kAsmBlock) void k_assemble(AssembleArgs A) {
   const int tid = threadIdx.x;
+  if (assembly_incomplete(A)) {
+    for (uint32_t i = tid; i < A.counts->nreq; i += kAsmBlock) A.out_count[i] = kCountIncomplete;
+    return;
+  }
   for (int L = (int)A.nlevels - 1; L >= 0; --L) {
     for (uint32_t v = A.level_begin[L] + tid; v < A.level_begin[L + 1]; v += kAsmBlock) {
       Node& nd = A.nodes[v];
@@ -2546,6 +2557,7 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble(AssembleArgs A) {
 
 // Copy the ordered lists of LDS-finished subtrees into place (one wave each).
 __global__ __launch_bounds__(256) void k_copy_lists(AssembleArgs A) {
+  if (assembly_incomplete(A)) return;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = (blockIdx.x * 256u + threadIdx.x) >> 6;
   const uint32_t nwaves = (gridDim.x * 256u) >> 6;

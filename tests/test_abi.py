@@ -250,6 +250,36 @@ def test_workspace_calls_reject_bad_arguments_on_host(lib):
     assert lib.vqhull_hull_batched_ws(dummy, dummy, p, 0, dummy, dummy, None, 0, None) == 0  # nothing to do
 
 
+def test_async_call_rejects_bad_arguments_on_host(lib):
+    """The stream-ordered batched call checks its sizes, offsets, level budget
+    (1 .. 4096) and workspace (the _ws one) before any HIP call, and returns
+    at once with nothing to do for no requests."""
+    import paper_2510_09417_amd as vq
+
+    vp = ctypes.c_void_p
+    dummy = vp(0x1000)
+    off = np.array([0, 3, 5], dtype=np.int64)
+    p = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    need = vq.workspace_bytes(5, 2)
+    ws = vp(0x100000)
+    f = lib.vqhull_hull_batched_async
+    for levels in (0, -3, 4097):
+        assert f(dummy, dummy, p, 2, dummy, dummy, levels, ws, need, None) == 1
+    assert f(dummy, dummy, p, -1, dummy, dummy, 8, ws, need, None) == 1
+    assert f(dummy, dummy, None, 2, dummy, dummy, 8, ws, need, None) == 1
+    bad = np.array([0, 5, 3], dtype=np.int64)
+    assert f(dummy, dummy, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 2, dummy, dummy, 8, ws, need,
+             None) == 1
+    assert f(None, dummy, p, 2, dummy, dummy, 8, ws, need, None) == 1
+    assert f(dummy, dummy, p, 2, None, dummy, 8, ws, need, None) == 1
+    assert f(dummy, dummy, p, 2, dummy, None, 8, ws, need, None) == 1
+    assert f(dummy, dummy, p, 2, dummy, dummy, 8, None, need, None) == 1
+    assert f(dummy, dummy, p, 2, dummy, dummy, 8, vp(0x100080), need, None) == 1  # misaligned
+    assert f(dummy, dummy, p, 2, dummy, dummy, 8, ws, need - 256, None) == 1  # too small
+    assert f(dummy, dummy, p, 0, dummy, dummy, 8, None, 0, None) == 0  # nothing to do
+    assert lib.vqhull_status_string(6) == b"the level budget ended before the recursion"
+
+
 def test_inplace_workspace_and_arguments_on_host(lib):
     """In-place mode: its workspace is the _ws one less buffer A's two
     coordinate arrays (16 bytes per point), and its calls check arguments and

@@ -13,7 +13,9 @@ Prints one JSON line:
               writes the grandchild subsets): algorithmic bytes per launch
               (16 B read per input point + 20 B written per kept point) over its
               average duration, from HIP events recorded on the launch stream
-              during the timed steps, against 8 TB/s;
+              around that kernel alone during the timed steps (no other launch
+              is timed there), against 8 TB/s; the argmax pass and all-sweep
+              rates beside it come from two untimed breakdown steps;
   per_hull    each dataset's hull alone: HIP events on the launch stream
               around the call (first kernel to the count written), 10 runs
               after a warm-up, median and standard deviation.
@@ -198,7 +200,8 @@ def cpu_baseline_leg(oracle, data, npts, configs_kept, served_sample) -> dict:
     return out
 
 
-def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: int = 1 << 25) -> tuple[dict, list]:
+def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: int = 1 << 25,
+                     graph_levels: int = 16) -> tuple[dict, list]:
     """The served mix through vqhull_server_*, against the plain per-request
     path.  Returns the results and a seeded sample of served requests (points
     and index lists, on the host) for the CPU-baseline leg."""
@@ -255,7 +258,7 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
 
     def run(arrivals):
         """Submit request i at arrivals[i] seconds (all that are due in one call)."""
-        srv = vq.Server(lanes=lanes, lane_points=lane_points, lane_requests=8192)
+        srv = vq.Server(lanes=lanes, lane_points=lane_points, lane_requests=8192, graph_levels=graph_levels)
         try:
             m = len(arrivals)
             first = None
@@ -378,7 +381,7 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
     return {
         "workload": f"{nreq} requests, sizes log-uniform in [16, 1e6] (seed {workloads.SERVED_SEED}), "
                     f"disk/square/circle/kuzmin, {total} points, drawn on the GPU",
-        "lanes": lanes, "lane_points": lane_points,
+        "lanes": lanes, "lane_points": lane_points, "graph_levels": graph_levels,
         "autotuned_config": {k: tuned[k] for k in ("sweep_block", "sweep_ppt", "lds_limit", "sweep_persistent",
                                                     "level_block")},
         "autotune": f"{len(table)} configurations timed on the first {nb} requests ({int(off[nb])} points), "
@@ -516,6 +519,9 @@ def main() -> int:
     ap.add_argument("--served-requests", type=int, default=65536)
     ap.add_argument("--served-lanes", type=int, default=8)
     ap.add_argument("--served-lane-points", type=int, default=1 << 25)
+    ap.add_argument("--served-graph-levels", type=int, default=16,
+                    help="recursion levels each lane's captured batch step holds (deeper batches fall back to "
+                         "plain launches)")
     ap.add_argument("--n", type=int, default=100_000_000, help="points per dataset (default 1e8)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -571,40 +577,45 @@ def main() -> int:
     hulls = [int(oc.item()) for _, oc in outs]
     log(f"hull sizes: {dict(zip(names, hulls))}")
 
-    # timed region: timing events around the partition sweeps are recorded on
-    # the launch stream (the roofline's kernel durations)
-    vq.set_timing(True, sweeps_only=True)
-    fused, argmax, sweeps = [], [], []  # (ms, algorithmic bytes) per launch
+    def sweep_rec(r):
+        """(ms, algorithmic bytes) of a sweep launch: level 0, the argmax pass
+        over the caller's arrays, reads 16 B per point; level 1, the fused
+        pass, 16 B per point and 20 B per kept point; deeper levels read and
+        write 20 B per point."""
+        rd = 16 if r["level"] <= 1 else 20
+        return (r["ms"], rd * r["points_in"] + 20 * r["points_out"])
+
+    # timed region: timing events around the fused pass (the roofline's
+    # kernel) are recorded on the launch stream; no other launch is timed
+    # here, since each timed launch adds two timestamped events to the stream
+    vq.set_timing(True, fused_only=True)
+    fused = []  # (ms, algorithmic bytes) per launch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         for (tx, ty), (oi, oc) in zip(dx, outs):
             vq.hull_into(tx, ty, oi, oc, stream)
             for r in vq.kernel_times():
-                if r["kind"] != "sweep":
-                    continue
-                # level 0: argmax pass over the caller's arrays (16 B read per point);
-                # level 1: fused pass (16 B read per point, 20 B per kept point);
-                # deeper levels read and write 20 B per point.
-                rd = 16 if r["level"] <= 1 else 20
-                rec = (r["ms"], rd * r["points_in"] + 20 * r["points_out"])
-                sweeps.append(rec)
-                if r["level"] == 0:
-                    argmax.append(rec)
-                elif r["level"] == 1:
-                    fused.append(rec)
+                if r["kind"] == "sweep" and r["level"] == 1:
+                    fused.append(sweep_rec(r))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     # per-kernel breakdown: two more steps with every launch timed (outside
-    # the timed region: the extra events cost wall time)
+    # the timed region: the extra events cost wall time); the argmax pass and
+    # all-sweep rates come from these
     vq.set_timing(True)
     per_kind = {}
+    argmax, sweeps = [], []
     breakdown_steps = 2
     for _ in range(breakdown_steps):
         for (tx, ty), (oi, oc) in zip(dx, outs):
             vq.hull_into(tx, ty, oi, oc, stream)
             for r in vq.kernel_times():
                 per_kind[r["kind"]] = per_kind.get(r["kind"], 0.0) + r["ms"]
+                if r["kind"] == "sweep":
+                    sweeps.append(sweep_rec(r))
+                    if r["level"] == 0:
+                        argmax.append(sweep_rec(r))
     torch.cuda.synchronize()
     vq.set_timing(False)
     # per hull: events on the launch stream around each call (first kernel to
@@ -679,7 +690,7 @@ def main() -> int:
     served, served_sample = None, []
     if not args.no_served:
         served, served_sample = served_benchmark(vq, workloads, torch, args.served_requests, args.served_lanes,
-                                                 args.served_lane_points)
+                                                 args.served_lane_points, args.served_graph_levels)
 
     cpu = None
     if not args.no_cpu_baseline:

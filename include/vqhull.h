@@ -312,8 +312,10 @@ typedef struct {
 } vqhull_kernel_time;
 
 /* Kernel timing of later calls: 0 off, 1 every launch, 2 the partition
- * sweeps only (fewer events in the stream).  VQHULL_ERR_INVALID_ARGUMENT for
- * other values. */
+ * sweeps only, 3 the fused top-level pass only (the sweep of level 1: two
+ * events per call, the fewest the stream carries).  Each timed launch adds
+ * two timestamped events to the stream (a few microseconds of device time).
+ * VQHULL_ERR_INVALID_ARGUMENT for other values. */
 int vqhull_set_timing(int enable);
 
 /* Copy up to cap records of the last call (host pointer); returns the count. */

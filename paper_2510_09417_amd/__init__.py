@@ -498,11 +498,13 @@ def level_stats() -> list[dict]:
             for i in range(n)]
 
 
-def set_timing(enable, sweeps_only: bool = False) -> None:
-    """Record HIP events around every kernel launch of later calls (or, with
-    sweeps_only, around the partition sweeps alone)."""
+def set_timing(enable, sweeps_only: bool = False, fused_only: bool = False) -> None:
+    """Record HIP events around every kernel launch of later calls (with
+    sweeps_only, around the partition sweeps alone; with fused_only, around
+    the fused top-level pass alone)."""
     lib = load_library()
-    _check(lib, lib.vqhull_set_timing((2 if sweeps_only else 1) if enable else 0))
+    mode = (3 if fused_only else 2 if sweeps_only else 1) if enable else 0
+    _check(lib, lib.vqhull_set_timing(mode))
 
 
 def kernel_times() -> list[dict]:

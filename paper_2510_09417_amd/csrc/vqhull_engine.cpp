@@ -452,8 +452,9 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
 
   const size_t max_seg = N / (lds_limit + 1) + (size_t)nreq + 2;
   const int tmode = g_timing.load();
-  const bool tm = tmode != 0;          // sweeps
-  const bool tm_all = tmode == 1;      // every other launch too
+  const bool tm = tmode == 1 || tmode == 2;  // sweeps
+  const bool tm_all = tmode == 1;            // every other launch too
+  const bool tm_fused = tmode != 0;          // the sweep of level 1 (the fused pass) in every mode
 
   // Octagon prefilter (requests above the LDS threshold only): extremes in
   // eight directions, the edges, the filter into buffer B, the prefix of the
@@ -529,7 +530,7 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
                               : (known[k - 1].swept + (uint64_t)tile - 1) / tile + 2ull * known[k - 1].nseg + 1;
       G = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(bound, max_tiles));
     }
-    sweep_recs.push_back(timed(w, tm, st, VQHULL_K_SWEEP, k, 0, 0, [&] {
+    sweep_recs.push_back(timed(w, tm || (tm_fused && k == 1), st, VQHULL_K_SWEEP, k, 0, 0, [&] {
       ck(launch_sweep(sa, mode, blk, ppt, G, st), "k_sweep");
     }));
 
@@ -1592,7 +1593,7 @@ int vqhull_stream_scale(const double* in, double* out, int64_t n, double s, vqhu
 }
 
 int vqhull_set_timing(int enable) {
-  if (enable < 0 || enable > 2) return VQHULL_ERR_INVALID_ARGUMENT;
+  if (enable < 0 || enable > 3) return VQHULL_ERR_INVALID_ARGUMENT;
   g_timing.store(enable);
   return VQHULL_OK;
 }

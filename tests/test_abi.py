@@ -80,9 +80,9 @@ def test_invalid_arguments_rejected_on_host(lib):
 
 def test_timing_modes_on_host(lib):
     try:
-        for mode in (0, 1, 2):
+        for mode in (0, 1, 2, 3):
             assert lib.vqhull_set_timing(mode) == 0
-        for bad in (-1, 3, 100):
+        for bad in (-1, 4, 100):
             assert lib.vqhull_set_timing(bad) == 1
     finally:
         assert lib.vqhull_set_timing(0) == 0

@@ -1,6 +1,6 @@
 """GPU test of the server in the exact shape the benchmark times it: 8 lanes
 of 2^25 points and 8192 requests, each lane replaying its batch step captured
-with 20 recursion levels, under the persistent kernel configuration that the
+with 16 recursion levels, under the persistent kernel configuration that the
 batched autotuner picks on the request mix.  The requests are the served mix's
 own: the first 400 of the 65,536-request plan (sizes log-uniform in
 [16, 10^6], disk / square / circle / Kuzmin, ``default_rng(5)``) with the
@@ -15,7 +15,7 @@ from paper_2510_09417_amd import autotune, workloads
 
 pytestmark = pytest.mark.gpu
 
-LANES, LANE_POINTS, LANE_REQUESTS, GRAPH_LEVELS = 8, 1 << 25, 8192, 20
+LANES, LANE_POINTS, LANE_REQUESTS, GRAPH_LEVELS = 8, 1 << 25, 8192, 16
 FIRST = 400
 
 

@@ -589,15 +589,19 @@ def main() -> int:
     # kernel) are recorded on the launch stream; no other launch is timed
     # here, since each timed launch adds two timestamped events to the stream
     vq.set_timing(True, fused_only=True)
+    lib = vq.load_library()
+    recbuf = (vq.KernelTime * 16)()  # the last call's timing records (one: the fused pass), read in place
     fused = []  # (ms, algorithmic bytes) per launch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         for (tx, ty), (oi, oc) in zip(dx, outs):
             vq.hull_into(tx, ty, oi, oc, stream)
-            for r in vq.kernel_times():
-                if r["kind"] == "sweep" and r["level"] == 1:
-                    fused.append(sweep_rec(r))
+            for i in range(min(16, lib.vqhull_last_kernel_times(recbuf, 16))):
+                r = recbuf[i]
+                if vq.KERNEL_KINDS[r.kind] == "sweep" and r.level == 1:
+                    fused.append(sweep_rec({"level": r.level, "ms": r.ms, "points_in": r.points_in,
+                                            "points_out": r.points_out}))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     # per-kernel breakdown: two more steps with every launch timed (outside

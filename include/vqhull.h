@@ -185,7 +185,9 @@ int vqhull_hull_batched_ws(const double* x, const double* y, const int64_t* offs
  * Returns VQHULL_OK once enqueued, VQHULL_ERR_INVALID_ARGUMENT (bad sizes,
  * offsets, level budget or workspace) with nothing enqueued, or
  * VQHULL_ERR_HIP.  The request table is staged in pinned host memory of the
- * library, which a later call reuses only once the stream has copied it.
+ * library, which a later call reuses only once the stream has copied it
+ * (with more than 32 calls on a device still waiting for their copies, a
+ * call waits for the oldest one).
  * The call writes no status to the host: vqhull_last_level_stats and
  * vqhull_last_kernel_times do not cover it.
  */

@@ -959,14 +959,19 @@ int guarded_ws(const double* x, const double* y, const int64_t* offsets, int64_t
 // Host-side contexts of the stream-ordered calls, pooled per device.  A
 // context returns to the pool at once, but is taken again only after the
 // stream has copied its staging (its `staged` event has completed); otherwise
-// a new one is made, so a call never waits for earlier work.
+// a new one is made, so a call does not wait for earlier work, up to
+// kAsyncMaxContexts per device: past that, a call waits for the oldest
+// staging copy (the pool's host memory stays bounded).
 std::mutex g_asc_mu;
 std::map<int, std::vector<Context*>> g_asc_free;
+std::map<int, int> g_asc_count;
 constexpr int kAsyncMaxLevels = 4096;
+constexpr int kAsyncMaxContexts = 32;
 
 Context* acquire_async_context() {
   int dev = 0;
   ck(hipGetDevice(&dev), "hipGetDevice");
+  Context* wait_for = nullptr;
   {
     std::lock_guard<std::mutex> g(g_asc_mu);
     auto& v = g_asc_free[dev];
@@ -977,6 +982,16 @@ Context* acquire_async_context() {
         return c;
       }
     }
+    if (g_asc_count[dev] >= kAsyncMaxContexts && !v.empty()) {
+      wait_for = v.front();  // the longest in the pool
+      v.erase(v.begin());
+    } else {
+      ++g_asc_count[dev];
+    }
+  }
+  if (wait_for) {
+    ck(hipEventSynchronize(wait_for->staged), "hipEventSynchronize");
+    return wait_for;
   }
   Context* c = new_context(false);
   ck(hipEventCreateWithFlags(&c->staged, hipEventDisableTiming), "hipEventCreateWithFlags");

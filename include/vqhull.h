@@ -41,11 +41,16 @@
  *   - Calls are stream-ordered.  The hull calls synchronize the given stream
  *     internally between levels (they read small level counters back to the
  *     host), so they return after the result has been written; the results are
- *     then visible to later work on the same stream.
- *   - The library allocates and keeps its own device workspace (about 40 bytes
- *     per input point plus small tables), one cache per device, grown on
- *     demand and guarded by a mutex: concurrent calls from several host
- *     threads are serialized per device.  vqhull_release_workspace() frees it.
+ *     then visible to later work on the same stream.  The exception is
+ *     vqhull_hull_batched_async, which enqueues a fixed budget of levels and
+ *     returns at once.
+ *   - vqhull_hull, vqhull_hull_batched and the _xy calls use the library's own
+ *     device workspace (about 40 bytes per input point plus small tables), one
+ *     cache per device, grown on demand and guarded by a mutex: concurrent
+ *     calls from several host threads are serialized per device.
+ *     vqhull_release_workspace() frees it.  The _ws, _inplace and _async calls
+ *     take the caller's workspace instead (and run concurrently on different
+ *     streams); vqhull_hull_noalloc uses a static array of the library.
  *   - Errors detectable on the host return at once with a status and enqueue
  *     no work.  A NaN or infinity in a request's input is detected on the
  *     device: that request's count is set to -VQHULL_ERR_NONFINITE and its

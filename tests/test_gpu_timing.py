@@ -1,5 +1,6 @@
-"""Kernel timing records: every launch (mode 1) or the partition sweeps only
-(mode 2), and the result does not depend on the timing mode."""
+"""Kernel timing records: every launch (mode 1), the partition sweeps only
+(mode 2) or the fused top-level pass only (mode 3, the benchmark's timed
+region), and the result does not depend on the timing mode."""
 import numpy as np
 import pytest
 
@@ -23,9 +24,16 @@ def test_timing_modes():
         vq.set_timing(True, sweeps_only=True)
         h2 = vq.hull(tx, ty).cpu().numpy()
         recs = vq.kernel_times()
+        vq.set_timing(True, fused_only=True)
+        h3 = vq.hull(tx, ty).cpu().numpy()
+        fused = vq.kernel_times()
     finally:
         vq.set_timing(False)
-    assert np.array_equal(h1, ref) and np.array_equal(h2, ref)
+    assert np.array_equal(h1, ref) and np.array_equal(h2, ref) and np.array_equal(h3, ref)
+    # mode 3: one record, the level-1 sweep, with the same point counts as in mode 2
+    assert [(r["kind"], r["level"]) for r in fused] == [("sweep", 1)]
+    assert fused[0]["points_in"] == recs[1]["points_in"] == len(x)
+    assert fused[0]["points_out"] == recs[1]["points_out"] > 0
     assert {"extremes", "plan0", "sweep", "finish_plan", "assemble"} <= all_kinds
     assert recs and {r["kind"] for r in recs} == {"sweep"}
     levels = [r["level"] for r in recs]

@@ -74,6 +74,7 @@ struct Context {
   DevBuf<uint32_t> tile_seg[2];
   DevBuf<TilePart> part, part2;
   DevBuf<FusedRoot> fr;
+  DevBuf<PlanRound> rounds[2];  // look-back records of the level planners (level k uses rounds[k % 2])
   DevBuf<unsigned long long> jctr[2];  // by level parity, like the job tables
   DevBuf<ExtPart> epart;
   DevBuf<OctPart> opart;     // octagon prefilter: per extremes tile
@@ -243,6 +244,8 @@ void free_workspace(Context* w) {
   f(w->part.p);
   f(w->part2.p);
   f(w->fr.p);
+  f(w->rounds[0].p);
+  f(w->rounds[1].p);
   f(w->jctr[0].p);
   f(w->jctr[1].p);
   f(w->epart.p);
@@ -409,6 +412,10 @@ PlanArgs plan_args(Context& w, const vqhull_config& cfg, int k, uint32_t G) {
   pl.level_nodes = w.level_nodes.p;
   pl.level = (uint32_t)k;
   pl.counts = w.counts_dev;
+  pl.planners = kPlanners;
+  pl.rounds = w.rounds[k % 2].p;
+  pl.rounds_next = w.rounds[(k + 1) % 2].p;
+  pl.rounds_cap = (uint32_t)std::min<size_t>(std::min(w.rounds[0].cap, w.rounds[1].cap), 0xFFFFFFFFu);
   return pl;
 }
 
@@ -431,6 +438,8 @@ Plan0Args plan0_args(Context& w, const vqhull_config& cfg) {
   pa.ext_tile = kExtTile;
   pa.toff = nullptr;
   pa.filter_min = 0;
+  pa.rounds_next = w.rounds[0].p;
+  pa.rounds_cap = (uint32_t)std::min<size_t>(std::min(w.rounds[0].cap, w.rounds[1].cap), 0xFFFFFFFFu);
   return pa;
 }
 
@@ -634,6 +643,7 @@ Caps reserve(Context& w, const vqhull_config& cfg, size_t N, size_t nreq, size_t
   ensure(w.part, c.max_tiles, st);
   ensure(w.part2, c.max_tiles, st);
   ensure(w.fr, c.max_seg, st);
+  for (int k = 0; k < 2; ++k) ensure(w.rounds[k], c.max_seg / kPlanRoundMin + 3, st);
   for (int k = 0; k < 2; ++k) {
     ensure(w.jobs[k], 2 * c.max_seg + nreq, st);
     ensure(w.jctr[k], (2 * c.max_seg + nreq) * kCtrStride, st);
@@ -848,6 +858,8 @@ size_t ws_layout(Context& w, char* base, size_t N, size_t nreq, const vqhull_con
   take(w.part, max_tiles);
   take(w.part2, max_tiles);
   take(w.fr, max_seg);
+  take(w.rounds[0], max_seg / kPlanRoundMin + 3);
+  take(w.rounds[1], max_seg / kPlanRoundMin + 3);
   take(w.epart, ext_tiles);
   take(w.opart, ext_tiles);
   take(w.oct, nreq);
@@ -910,6 +922,8 @@ void release_ws_context(Context* c) {
   c->part = {};
   c->part2 = {};
   c->fr = {};
+  c->rounds[0] = {};
+  c->rounds[1] = {};
   c->epart = {};
   c->opart = {};
   c->oct = {};

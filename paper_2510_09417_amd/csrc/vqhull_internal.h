@@ -122,6 +122,22 @@ struct Status {
   uint32_t overflow;    // 1 if the node table was too small (nothing was created)
 };
 
+// A level planner works in rounds of one segment per thread; several
+// planner workgroups take the rounds of a level in turn and find where each
+// round's output goes by a decoupled look-back over the rounds before it: a
+// round publishes its own totals (flag 1), then, once the totals of all
+// earlier rounds are known, its inclusive totals (flag 2).  Counters:
+// nodes, jobs, segments, tiles, swept points, job points, survivors.
+constexpr int kPlanCounters = 7;
+struct PlanRound {
+  uint32_t flag;
+  uint32_t agg[kPlanCounters];
+  uint32_t incl[kPlanCounters];
+  uint32_t pad;
+};
+constexpr uint32_t kPlanners = 8;        // planner workgroups of a level planner launch
+constexpr uint32_t kPlanRoundMin = 256;  // the smallest round (segments per planner workgroup)
+
 constexpr int kStatusRing = 4;
 // Segment and job counters (packed S1 | S2 << 32 reservations) sit one
 // 128-byte line apart: the device-scope atomics of one line are serialised,
@@ -287,6 +303,8 @@ struct Plan0Args {
   uint32_t ext_tile;
   const uint32_t* toff;  // octagon prefilter: kept-point prefix per extremes tile (nullptr: off)
   uint32_t filter_min;   // requests with more points went through the filter
+  PlanRound* rounds_next;  // look-back records of the level-0 planner, cleared here
+  uint32_t rounds_cap;     // records per buffer
 };
 
 struct PlanArgs {
@@ -313,6 +331,10 @@ struct PlanArgs {
   uint32_t* level_nodes;  // [level + 2] = node count after this plan
   uint32_t level;
   BatchCounts* counts;    // overflow flag
+  uint32_t planners;      // workgroups 0 .. planners-1 of the launch plan; the others finish jobs
+  PlanRound* rounds;      // this planner's look-back records (cleared by the planner before it)
+  PlanRound* rounds_next; // the next level planner's, cleared here
+  uint32_t rounds_cap;    // records per buffer
 };
 
 struct FinishArgs {

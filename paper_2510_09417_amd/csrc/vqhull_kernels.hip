@@ -893,8 +893,10 @@ __device__ __forceinline__ uint32_t child_kind(uint32_t cnt, uint32_t lds_limit)
 
 template <int PB>
 struct PlanSharedT {
-  uint32_t scan[4][PB / 64];
+  uint32_t scan[kPlanCounters][PB / 64];
   uint32_t nodes, jobs, segs, tiles, swept, jobpts, survivors;
+  uint32_t pre[kPlanCounters];  // level planners: the totals of the rounds before this one
+  uint32_t lb_fail;
   uint32_t nbig, nfill;
   uint32_t big[PB];
   uint32_t fill[2 * PB];  // up to two new segments per thread: id,
@@ -942,7 +944,8 @@ __device__ __forceinline__ int32_t emit_one(uint32_t kind, const Tri& tr, uint32
                                             uint32_t req, int32_t parent, uint32_t side, uint32_t src,
                                             uint32_t node_base, uint32_t tile, EmitBase& e, Node* nodes, Job* jobs,
                                             Seg* seg_out, unsigned long long* ctr_out, uint32_t* tile_seg_out,
-                                            PlanSharedT<PB>& S, const Virt& vt, uint32_t* index_out) {
+                                            PlanSharedT<PB>& S, const Virt& vt, uint32_t* index_out,
+                                            bool count_pts = true) {
   int32_t nid = -1;
   if (kind != kKindNone) {
     nid = (int32_t)(node_base + e.node++);
@@ -978,7 +981,7 @@ __device__ __forceinline__ int32_t emit_one(uint32_t kind, const Tri& tr, uint32
     jobs[jid] = j;
     if (vt.on) vt.jctr_out[(size_t)jid * kCtrStride] = 0ull;
     *index_out = jid;
-    atomicAdd(&S.jobpts, cnt);
+    if (count_pts) atomicAdd(&S.jobpts, cnt);
   } else if (kind == kKindSeg && vt.on) {
     const uint32_t sid = e.seg++;
     Seg sg;
@@ -999,7 +1002,7 @@ __device__ __forceinline__ int32_t emit_one(uint32_t kind, const Tri& tr, uint32
     seg_out[sid] = sg;
     ctr_out[(size_t)sid * kCtrStride] = 0ull;
     *index_out = sid;
-    atomicAdd(&S.swept, cnt);
+    if (count_pts) atomicAdd(&S.swept, cnt);
   } else if (kind == kKindSeg) {
     const uint32_t sid = e.seg++;
     const uint32_t nt = ceil_div(cnt, tile);
@@ -1023,7 +1026,7 @@ __device__ __forceinline__ int32_t emit_one(uint32_t kind, const Tri& tr, uint32
     sg.rside = 0u;
     seg_out[sid] = sg;
     ctr_out[(size_t)sid * kCtrStride] = 0ull;
-    atomicAdd(&S.swept, cnt);
+    if (count_pts) atomicAdd(&S.swept, cnt);
     if (nt <= kSerialFill) {
       for (uint32_t i = 0; i < nt; ++i) tile_seg_out[t0 + i] = sid;
     } else {
@@ -1038,8 +1041,9 @@ __device__ __forceinline__ int32_t emit_one(uint32_t kind, const Tri& tr, uint32
 
 // Tile maps of the big new segments (a few: the whole workgroup over each
 // one's tiles; many: one wave per segment), then running totals.
-template <int PB>
-__device__ __forceinline__ void emit_finish(const uint32_t (&tot)[4], uint32_t* tile_seg_out, PlanSharedT<PB>& S) {
+template <int PB, int NT = 4>
+__device__ __forceinline__ void emit_finish(const uint32_t (&tot)[NT], uint32_t* tile_seg_out, PlanSharedT<PB>& S,
+                                            bool running = true) {
   __syncthreads();
   const uint32_t nf = S.nfill;
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
@@ -1056,10 +1060,12 @@ __device__ __forceinline__ void emit_finish(const uint32_t (&tot)[4], uint32_t* 
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    S.nodes += tot[0];
-    S.jobs += tot[1];
-    S.segs += tot[2];
-    S.tiles += tot[3];
+    if (running) {
+      S.nodes += tot[0];
+      S.jobs += tot[1];
+      S.segs += tot[2];
+      S.tiles += tot[3];
+    }
     S.nfill = 0;
     S.nbig = 0;
   }
@@ -1115,6 +1121,84 @@ __device__ __forceinline__ void plan_overflow(Status* out, Status* host_out, uin
     st.overflow = 1;
     put_status(st, out, host_out);
   }
+}
+
+// The status of a level planned in rounds: t = nodes, jobs, segments, tiles,
+// swept points, job points, survivors (the inclusive totals of the last round).
+__device__ __forceinline__ void plan_status_totals(const uint32_t (&t)[kPlanCounters], Status* out, Status* host_out,
+                                                   uint32_t node_base, uint32_t* level_nodes, uint32_t ntiles) {
+  if (threadIdx.x == 0) {
+    *level_nodes = node_base + t[0];
+    Status st;
+    st.nseg = t[2];
+    st.ntiles = ntiles;
+    st.njobs = t[1];
+    st.nnodes = node_base + t[0];
+    st.swept = t[4];
+    st.jobpts = t[5];
+    st.survivors = t[6];
+    st.overflow = 0;
+    put_status(st, out, host_out);
+  }
+}
+
+// Look-back records are read and written with device-scope atomics: the
+// planner workgroups of a launch may run on different XCDs.
+__device__ __forceinline__ uint32_t ld_acquire(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A round's own totals (flag 1) or its inclusive totals (flag 2); one thread.
+__device__ __forceinline__ void round_publish(PlanRound* R, const uint32_t (&v)[kPlanCounters], bool incl) {
+  uint32_t* dst = incl ? R->incl : R->agg;
+#pragma unroll
+  for (int i = 0; i < kPlanCounters; ++i) st_relaxed(&dst[i], v[i]);
+  st_release(&R->flag, incl ? 2u : 1u);
+}
+
+// Waits of the look-back before it gives up (each a short sleep and one load
+// per lane; a round's predecessor publishes within microseconds).
+constexpr uint32_t kLookbackSpins = 1u << 20;
+
+// The totals of rounds 0 .. r-1, by one whole wave: lane l looks at round
+// r - 1 - l (64 rounds a step) and the sum runs down to the nearest round with
+// inclusive totals.  Returns false if a round never published.
+__device__ bool round_lookback(const PlanRound* R, uint32_t r, uint32_t (&pre)[kPlanCounters]) {
+  const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+  for (int i = 0; i < kPlanCounters; ++i) pre[i] = 0u;
+  int64_t top = (int64_t)r - 1;  // the round lane 0 looks at
+  uint32_t spins = 0;
+  while (top >= 0) {
+    const int64_t j = top - (int64_t)lane;
+    const uint32_t f = j >= 0 ? ld_acquire(&R[j].flag) : 2u;  // before round 0: the empty prefix
+    const unsigned long long m2 = __ballot(f == 2u), m0 = __ballot(f == 0u);
+    const uint32_t stop = m2 ? (uint32_t)__builtin_ctzll(m2) : 64u;
+    const unsigned long long upto = stop >= 63u ? ~0ull : (2ull << stop) - 1ull;  // lanes 0 .. stop
+    if (m0 & upto) {  // a round before the nearest complete one has not published
+      if (++spins > kLookbackSpins) return false;
+      __builtin_amdgcn_s_sleep(2);
+      continue;
+    }
+#pragma unroll
+    for (int i = 0; i < kPlanCounters; ++i) {
+      uint32_t v = 0u;
+      if (j >= 0 && lane <= stop) v = lane < stop ? ld_relaxed(&R[j].agg[i]) : ld_relaxed(&R[j].incl[i]);
+      pre[i] += wave_sum(v);
+    }
+    if (stop < 64u) break;
+    top -= 64;
+  }
+  return true;
 }
 
 // Lexicographic extremes of partial records (y is present in the records).
@@ -1247,6 +1331,9 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
   }
   if (threadIdx.x == 0) A.level_nodes[0] = 0u;
   plan_status(S, A.st_out, A.st_host, 0u, A.level_nodes + 1, S.tiles);
+  // the look-back records of the level-0 planner start cleared
+  const uint32_t nclr = min(A.rounds_cap, ceil_div(S.segs, kPlanRoundMin) + 1u);
+  for (uint32_t c = threadIdx.x; c < nclr; c += kPlanBlock) st_relaxed(&A.rounds_next[c].flag, 0u);
 }
 
 // One recursion level: reduce the counts and candidates of every segment,
@@ -1261,7 +1348,7 @@ struct PlanLds {
 };
 
 template <int PB>
-__device__ void plan_level(const PlanArgs& A, PlanLds<PB>& L) {
+__device__ void plan_level(const PlanArgs& A, PlanLds<PB>& L, uint32_t g, uint32_t P) {
   constexpr int NWP = PB / 64;
   PlanSharedT<PB>& S = L.S;
   Cand (*s_res)[2] = L.res;
@@ -1269,12 +1356,25 @@ __device__ void plan_level(const PlanArgs& A, PlanLds<PB>& L) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   plan_init(S);
   const uint32_t nseg = A.st_in->nseg, node_base = A.st_in->nnodes;
-  if ((uint64_t)node_base + 2ull * nseg > A.node_cap) {
-    plan_overflow(A.st_out, A.st_host, node_base, A.level_nodes + A.level + 2u, A.counts);
+  const uint32_t nrounds = ceil_div(nseg, PB);
+  if ((uint64_t)node_base + 2ull * nseg > A.node_cap || nrounds > A.rounds_cap) {
+    if (g == 0) plan_overflow(A.st_out, A.st_host, node_base, A.level_nodes + A.level + 2u, A.counts);
+    return;
+  }
+  if (nrounds == 0) {  // an empty level: the next is empty too
+    if (g == 0) {
+      const uint32_t zero[kPlanCounters] = {0, 0, 0, 0, 0, 0, 0};
+      plan_status_totals(zero, A.st_out, A.st_host, node_base, A.level_nodes + A.level + 2u,
+                         A.fuse ? A.st_in->ntiles : 0u);
+    }
     return;
   }
   const uint32_t G = A.sweep_grid;
-  for (uint32_t base = 0; base < nseg; base += PB) {
+  uint32_t fin[kPlanCounters];  // inclusive totals of the last round (its workgroup writes the status)
+  // Rounds of PB segments, taken by the planner workgroups in turn; each
+  // round's output offsets are the totals of the rounds before it (look-back).
+  for (uint32_t rr = g; rr < nrounds; rr += P) {
+    const uint32_t base = rr * PB;
     const uint32_t s = base + tid;
     const bool valid = s < nseg;
     uint32_t n1 = 0, n2 = 0, tile0 = 0, nrec = 0;
@@ -1284,7 +1384,6 @@ __device__ void plan_level(const PlanArgs& A, PlanLds<PB>& L) {
       const unsigned long long c = A.ctr[(size_t)s * kCtrStride];
       n1 = (uint32_t)c;
       n2 = (uint32_t)(c >> 32);
-      atomicAdd(&S.survivors, n1 + n2);
       tile0 = A.seg[s].tile0;
       const uint32_t rt = A.seg[s].rtiles;
       nrec = min(G, rt ? rt : ceil_div(A.seg[s].cnt, A.tile));
@@ -1349,8 +1448,54 @@ __device__ void plan_level(const PlanArgs& A, PlanLds<PB>& L) {
       kind[0] = child_kind(n1, A.lds_limit);
       kind[1] = child_kind(n2, A.lds_limit);
     }
-    uint32_t tot[4];
-    EmitBase eb = emit_scan(kind, cnt, A.tile, S, tot, A.fuse != 0);
+    // this thread's share of the round's counts
+    uint32_t v[kPlanCounters] = {0, 0, 0, 0, 0, 0, n1 + n2};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      v[0] += kind[k] != kKindNone;
+      v[1] += kind[k] == kKindJob;
+      v[2] += kind[k] == kKindSeg;
+      v[3] += (kind[k] == kKindSeg && !A.fuse) ? ceil_div(cnt[k], A.tile) : 0u;
+      v[4] += kind[k] == kKindSeg ? cnt[k] : 0u;
+      v[5] += kind[k] == kKindJob ? cnt[k] : 0u;
+    }
+    uint32_t ex[kPlanCounters], tot[kPlanCounters];
+    block_scan<PB, kPlanCounters>(v, ex, tot, S.scan);
+    // publish the round's totals and find those of the rounds before it
+    if (tid == 0) {
+      round_publish(A.rounds + rr, tot, rr == 0);
+      if (rr == 0) {
+#pragma unroll
+        for (int i = 0; i < kPlanCounters; ++i) S.pre[i] = 0u;
+      }
+    }
+    if (rr > 0 && w == 0) {
+      uint32_t pre[kPlanCounters];
+      const bool ok = round_lookback(A.rounds, rr, pre);
+      if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < kPlanCounters; ++i) S.pre[i] = pre[i];
+        S.lb_fail = ok ? 0u : 1u;
+        if (ok) {
+          uint32_t incl[kPlanCounters];
+#pragma unroll
+          for (int i = 0; i < kPlanCounters; ++i) incl[i] = pre[i] + tot[i];
+          round_publish(A.rounds + rr, incl, true);
+        }
+      }
+    }
+    __syncthreads();
+    if (rr > 0 && S.lb_fail) {  // a round never published (not expected): report an overflow
+      plan_overflow(A.st_out, A.st_host, node_base, A.level_nodes + A.level + 2u, A.counts);
+      return;
+    }
+    uint32_t pre[kPlanCounters];
+#pragma unroll
+    for (int i = 0; i < kPlanCounters; ++i) {
+      pre[i] = S.pre[i];
+      fin[i] = pre[i] + tot[i];
+    }
+    EmitBase eb{pre[0] + ex[0], pre[1] + ex[1], pre[2] + ex[2], pre[3] + ex[3]};
     if (valid) {
       const Seg sg = A.seg[s];
       const uint32_t root_tiles = ceil_div(sg.cnt, A.tile);
@@ -1358,10 +1503,10 @@ __device__ void plan_level(const PlanArgs& A, PlanLds<PB>& L) {
       const Tri t1{sg.ax, sg.ay, r1.x, r1.y, sg.rx, sg.ry};
       uint32_t i1 = 0, i2 = 0;
       emit_one(kind[0], t1, r1.i, sg.beg, n1, sg.req, sg.node, 0, A.out_buf, node_base, A.tile, eb, A.nodes, A.jobs,
-               A.seg_out, A.ctr_out, A.tile_seg_out, S, vt, &i1);
+               A.seg_out, A.ctr_out, A.tile_seg_out, S, vt, &i1, false);
       const Tri t2{sg.rx, sg.ry, r2.x, r2.y, sg.bx, sg.by};
       emit_one(kind[1], t2, r2.i, sg.beg + sg.cnt - n2, n2, sg.req, sg.node, 1, A.out_buf, node_base, A.tile, eb,
-               A.nodes, A.jobs, A.seg_out, A.ctr_out, A.tile_seg_out, S, vt, &i2);
+               A.nodes, A.jobs, A.seg_out, A.ctr_out, A.tile_seg_out, S, vt, &i2, false);
       if (A.fuse) {
         FusedRoot f;
         f.px = sg.ax;
@@ -1388,10 +1533,17 @@ __device__ void plan_level(const PlanArgs& A, PlanLds<PB>& L) {
         A.fr_out[s] = f;
       }
     }
-    emit_finish(tot, A.tile_seg_out, S);
+    emit_finish(tot, A.tile_seg_out, S, false);
   }
-  // The fused pass walks the roots' tiles again.
-  plan_status(S, A.st_out, A.st_host, node_base, A.level_nodes + A.level + 2u, A.fuse ? A.st_in->ntiles : S.tiles);
+  // The workgroup of the last round knows the level's totals: the status,
+  // and the look-back records of the next level planner cleared.
+  if ((nrounds - 1u) % P == g) {
+    // The fused pass walks the roots' tiles again.
+    plan_status_totals(fin, A.st_out, A.st_host, node_base, A.level_nodes + A.level + 2u,
+                       A.fuse ? A.st_in->ntiles : fin[3]);
+    const uint32_t nclr = min(A.rounds_cap, ceil_div(fin[2], kPlanRoundMin) + 1u);
+    for (uint32_t i = tid; i < nclr; i += PB) st_relaxed(&A.rounds_next[i].flag, 0u);
+  }
 }
 
 // ------------------------------------------------------- k_finish_plan
@@ -1721,8 +1873,9 @@ __device__ void finish_job(const Job& job, const FinishArgs& A, FinishShared<BLO
   __syncthreads();  // LDS is reused by the next job
 }
 
-// One launch per level for the finisher and the planner: workgroup 0 plans
-// the next level while the others finish this level's small subproblems.
+// One launch per level for the finisher and the planner: workgroups
+// 0 .. planners-1 plan the next level while the others finish this level's
+// small subproblems.
 // They share no data: the planner reads the sweep's counters and records and
 // writes the next level's tables (its jobs into the other of the two job
 // buffers); the finisher reads this level's jobs and points and fills in the
@@ -1736,13 +1889,13 @@ constexpr size_t finish_plan_lds() {
 template <int BLOCK, int TMAX>
 __global__ __launch_bounds__(BLOCK) void k_finish_plan(FinishArgs A, PlanArgs P) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  if (blockIdx.x == 0) {
-    plan_level<BLOCK>(P, *reinterpret_cast<PlanLds<BLOCK>*>(smem_raw));
+  if (blockIdx.x < P.planners) {
+    plan_level<BLOCK>(P, *reinterpret_cast<PlanLds<BLOCK>*>(smem_raw), blockIdx.x, P.planners);
     return;
   }
   FinishShared<BLOCK, TMAX>& S = *reinterpret_cast<FinishShared<BLOCK, TMAX>*>(smem_raw);
   const uint32_t njobs = A.st->njobs;
-  for (uint32_t j = blockIdx.x - 1u; j < njobs; j += gridDim.x - 1u) {
+  for (uint32_t j = blockIdx.x - P.planners; j < njobs; j += gridDim.x - P.planners) {
     const Job job = A.jobs[j];
     finish_job<BLOCK, TMAX>(job, A, S);
   }
@@ -2728,7 +2881,7 @@ int finish_plan_one(const FinishArgs& a, const PlanArgs& p, hipStream_t st) {
   int e = finish_attr<BLOCK, TMAX>();
   if (e) return e;
   const size_t lds = finish_plan_lds<BLOCK, TMAX>();
-  hipLaunchKernelGGL((k_finish_plan<BLOCK, TMAX>), dim3(1u + finish_grid(TMAX)), dim3(BLOCK), lds, st, a, p);
+  hipLaunchKernelGGL((k_finish_plan<BLOCK, TMAX>), dim3(p.planners + finish_grid(TMAX)), dim3(BLOCK), lds, st, a, p);
   return (int)hipGetLastError();
 }
 

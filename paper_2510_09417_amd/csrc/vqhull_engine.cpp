@@ -443,6 +443,17 @@ Plan0Args plan0_args(Context& w, const vqhull_config& cfg) {
   return pa;
 }
 
+// Inputs whose levels keep nearly every point they sweep (most points are
+// hull vertices, as on a circle) finish faster with the 1024-point LDS
+// finisher, two workgroups per CU: under the 2048-point threshold, once a
+// level (from the third on) has kept more than 3/4 of the points the level
+// before it swept, the later levels plan with 1024.  Tables are sized for
+// the lower threshold.
+constexpr uint32_t kAdaptLds = 1024;
+size_t seg_capacity(size_t N, size_t nreq, const vqhull_config& cfg) {
+  return N / (std::min<uint32_t>((uint32_t)cfg.lds_limit, kAdaptLds) + 1) + nreq + 2;
+}
+
 // The whole hull computation for nreq requests on one stream.
 //
 // Level k's kernels read their work counts from the device status record the
@@ -459,7 +470,7 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
   const uint32_t lds_limit = (uint32_t)cfg.lds_limit;
   const int tmax = finish_tmax_for(cfg.lds_limit);
 
-  const size_t max_seg = N / (lds_limit + 1) + (size_t)nreq + 2;
+  const size_t max_seg = seg_capacity(N, (size_t)nreq, cfg);
   const int tmode = g_timing.load();
   const bool tm = tmode == 1 || tmode == 2;  // sweeps
   const bool tm_all = tmode == 1;            // every other launch too
@@ -522,6 +533,9 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
   std::vector<size_t> finish_recs;     // timing records of the finisher + planner launches, per level
   bool overflow = false;
   int64_t known_nodes = (int64_t)nreq, known_seg = (int64_t)std::min<size_t>((size_t)nreq, max_seg);
+  uint32_t lds_plan = lds_limit;  // threshold of the next plan
+  uint32_t lds_jobs = lds_limit;  // threshold the jobs of the current level were made with
+  const bool adapt = lds_limit > kAdaptLds && w.seg[0].cap >= max_seg;
   // Finisher jobs of level k run after sweep k (the fused pass writes the
   // points of level 1's small children), in the same launch as plan k.
   for (int k = 0;; ++k) {
@@ -553,9 +567,13 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
     // (with interleaved input no job reads the caller's arrays: every root
     // went through the filter into buffer A)
     const FinishArgs fa = finish_args(w, aos ? xy : x, aos ? xy : y, k);
-    const PlanArgs pl = plan_args(w, cfg, k, G);
+    vqhull_config cfg_k = cfg;
+    cfg_k.lds_limit = (int)lds_plan;
+    const PlanArgs pl = plan_args(w, cfg_k, k, G);
+    const int tmax_k = finish_tmax_for((int)lds_jobs);
     finish_recs.push_back(timed(w, tm_all, st, VQHULL_K_PLAN, k, 0, 0,
-                                [&] { ck(launch_finish_plan(fa, pl, tmax, st), "k_finish_plan"); }));
+                                [&] { ck(launch_finish_plan(fa, pl, tmax_k, st), "k_finish_plan"); }));
+    lds_jobs = lds_plan;
     ck(hipEventRecord(w.status_ev[next], st), "hipEventRecord");
 
     // Wait for the status of level k (written by the previous plan).
@@ -575,6 +593,9 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
     }
     known_nodes = sk.nnodes;
     known_seg = sk.nseg;
+    if (adapt && lds_plan > kAdaptLds && k >= 3 && known[k - 1].swept >= (1u << 20) &&
+        4ull * sk.survivors > 3ull * known[k - 1].swept)
+      lds_plan = kAdaptLds;  // from plan k + 1 on (plan k is already enqueued)
     if (sk.nseg == 0) {
       // Level k had no segment: plan(k) wrote an empty status (its jobs = 0).
       // The node count after level k is final.
@@ -633,7 +654,7 @@ Caps reserve(Context& w, const vqhull_config& cfg, size_t N, size_t nreq, size_t
   }
   ensure_points(w, std::max<size_t>(N, 1), st);
   Caps c;
-  c.max_seg = N / (lds_limit + 1) + nreq + 2;
+  c.max_seg = seg_capacity(N, nreq, cfg);
   c.max_tiles = N / tile + c.max_seg + 2;
   for (int k = 0; k < 2; ++k) {
     ensure(w.seg[k], c.max_seg, st);
@@ -817,9 +838,8 @@ size_t ws_layout(Context& w, char* base, size_t N, size_t nreq, const vqhull_con
   N = std::max<size_t>(N, 1);
   nreq = std::max<size_t>(nreq, 1);
   const size_t tile = (size_t)cfg.sweep_block * (size_t)cfg.sweep_ppt;
-  const size_t lds_limit = (size_t)cfg.lds_limit;
   const size_t ext_tiles = N / kExtTile + nreq;  // >= the sum over requests of ceil(n_i / kExtTile)
-  const size_t max_seg = N / (lds_limit + 1) + nreq + 2;
+  const size_t max_seg = seg_capacity(N, nreq, cfg);
   const size_t max_tiles = N / tile + max_seg + 2;
   const size_t njobs = 2 * max_seg + nreq;
   size_t off = 0;

@@ -241,7 +241,10 @@ int vqhull_hull_batched_inplace(double* x, double* y, const int64_t* offsets, in
 int vqhull_hull_noalloc(const double* x, const double* y, int64_t n, int64_t* out_idx, int64_t* out_count,
                         vqhull_stream_t stream);
 
-/* Tuning knobs of the hull kernels (all values are rounded to supported ones). */
+/* Tuning knobs of the hull kernels (all values are rounded to supported ones).
+ * Defaults: 256 x 16 sweep shape, LDS threshold 2048, persistent sweeps, no
+ * reversed tiles, deeper levels in the sweep shape, no prefilter; an
+ * unsupported sweep shape becomes 256 x 16. */
 typedef struct {
   int sweep_block;  /* threads per workgroup of the partition sweep: 256, 512 or 1024 */
   int sweep_ppt;    /* points per thread of the partition sweep: 8, 16 or 32 */

@@ -31,7 +31,7 @@ namespace {
 thread_local std::string g_last_error;
 
 std::mutex g_cfg_mu;
-vqhull_config g_cfg = {512, 8, 2048, 0, 1, 256, 0};
+vqhull_config g_cfg = {256, 16, 2048, 0, 1, 0, 0};
 
 struct LevelStat {
   int64_t segs, swept, jobs, jobpts;
@@ -274,8 +274,8 @@ void free_workspace(Context* w) {
 
 vqhull_config sanitized(vqhull_config c) {
   if (!sweep_shape_supported(c.sweep_block, c.sweep_ppt)) {
-    c.sweep_block = 512;
-    c.sweep_ppt = 8;
+    c.sweep_block = 256;
+    c.sweep_ppt = 16;
   }
   c.lds_limit = std::min(2048, std::max(256, c.lds_limit));
   c.reverse_tiles = c.reverse_tiles ? 1 : 0;

@@ -103,7 +103,7 @@ def test_config_roundtrip_and_sanitizing():
         assert (c["sweep_block"], c["sweep_ppt"], c["lds_limit"], c["reverse_tiles"], c["sweep_persistent"]) == \
             (256, 16, 1000, 1, 0)
         c = vq.set_config(sweep_block=300, sweep_ppt=7, lds_limit=10**6)
-        assert (c["sweep_block"], c["sweep_ppt"], c["lds_limit"]) == (512, 8, 2048)
+        assert (c["sweep_block"], c["sweep_ppt"], c["lds_limit"]) == (256, 16, 2048)  # the default shape
         # deeper levels: a workgroup size with the same tile, else the sweep shape (0)
         assert vq.set_config(sweep_block=512, sweep_ppt=8, level_block=256)["level_block"] == 256
         assert vq.set_config(level_block=512)["level_block"] == 0  # the sweep shape itself

@@ -296,6 +296,34 @@ int vqhull_autotune(const double* x, const double* y, int64_t n, int32_t repeats
  * finished in LDS, points finished in LDS).  Returns the number of levels. */
 int64_t vqhull_last_level_stats(int64_t* out, int64_t cap);
 
+/* How the partition sweep of each level of the last hull call on this device
+ * read and wrote its points (the calls of vqhull_last_level_stats; host
+ * pointer, up to cap entries; returns the number of levels):
+ *   VQHULL_SWEEP_ARGMAX  read the level's points and wrote none: the sizes and
+ *                        farthest points of the children only (level 0, and
+ *                        the first level of a level pair);
+ *   VQHULL_SWEEP_FUSED   read the points of the level before again and wrote
+ *                        this level's children (level 1, and the second level
+ *                        of a pair) and copies of the points of the level
+ *                        before's small children;
+ *   VQHULL_SWEEP_LEVEL   read the level's points and wrote its children. */
+#define VQHULL_SWEEP_LEVEL 0
+#define VQHULL_SWEEP_ARGMAX 1
+#define VQHULL_SWEEP_FUSED 2
+int64_t vqhull_last_level_kinds(int32_t* out, int64_t cap);
+
+/* Level pairs of vqhull_hull, vqhull_hull_batched and their interleaved and
+ * _ws forms (the top level's argmax and fused passes applied below the top;
+ * Algorithm 1's partition and results unchanged): a level
+ * swept without writing, then the next level read in place from it, one
+ * write per point instead of two.  mode 0: never; 1 (default): from the
+ * fourth level on, where the level before kept more than 3/4 of the points it
+ * swept (at least 2^20 of them) and its segments average more than four times
+ * the LDS threshold; 2: from the third level on, back to back.
+ * The result does not depend on the mode.  Returns VQHULL_ERR_INVALID_ARGUMENT
+ * for any other mode. */
+int vqhull_set_level_pairs(int mode);
+
 /* Kernel timing of the last hull call on this device (the same calls), for benchmarks: when
  * enabled, HIP events are recorded on the call's stream around every kernel
  * launch.  Kinds: */

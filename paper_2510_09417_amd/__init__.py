@@ -28,13 +28,14 @@ EXPORTED = (
     "vqhull_hull_batched_async",
     "vqhull_workspace_bytes_inplace", "vqhull_hull_inplace", "vqhull_hull_batched_inplace",
     "vqhull_hull_noalloc", "vqhull_hull_xy", "vqhull_hull_batched_xy", "vqhull_get_config", "vqhull_set_config", "vqhull_autotune",
-    "vqhull_last_level_stats", "vqhull_set_timing", "vqhull_last_kernel_times", "vqhull_orient", "vqhull_stream_scale",
+    "vqhull_last_level_stats", "vqhull_last_level_kinds", "vqhull_set_level_pairs", "vqhull_set_timing", "vqhull_last_kernel_times", "vqhull_orient", "vqhull_stream_scale",
     "vqhull_release_workspace", "vqhull_status_string", "vqhull_last_error",
     "vqhull_server_create", "vqhull_server_submit", "vqhull_server_submit_batch", "vqhull_server_wait", "vqhull_server_wait_timeout",
     "vqhull_server_poll",
     "vqhull_server_drain", "vqhull_server_ticket_info", "vqhull_server_stats", "vqhull_server_destroy",
 )
 
+SWEEP_KINDS = ("level", "argmax", "fused")  # VQHULL_SWEEP_*: how a level's sweep read and wrote its points
 KERNEL_KINDS = ("extremes", "plan0", "sweep", "finish_plan", "finish", "assemble", "filter", "compact", "ingest")
 
 
@@ -135,6 +136,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                         ctypes.POINTER(Config), vp]
         lib.vqhull_last_level_stats.restype = i64
         lib.vqhull_last_level_stats.argtypes = [pi64, i64]
+        lib.vqhull_last_level_kinds.restype = i64
+        lib.vqhull_last_level_kinds.argtypes = [ctypes.POINTER(ctypes.c_int32), i64]
+        lib.vqhull_set_level_pairs.restype = ctypes.c_int
+        lib.vqhull_set_level_pairs.argtypes = [ctypes.c_int]
         lib.vqhull_set_timing.restype = ctypes.c_int
         lib.vqhull_set_timing.argtypes = [ctypes.c_int]
         lib.vqhull_last_kernel_times.restype = i64
@@ -494,8 +499,17 @@ def level_stats() -> list[dict]:
     n = lib.vqhull_last_level_stats(None, 0)
     buf = (ctypes.c_int64 * (4 * max(n, 1)))()
     n = lib.vqhull_last_level_stats(buf, n)
-    return [dict(segments=buf[4 * i], swept=buf[4 * i + 1], jobs=buf[4 * i + 2], job_points=buf[4 * i + 3])
+    kinds = (ctypes.c_int32 * max(n, 1))()
+    nk = lib.vqhull_last_level_kinds(kinds, n)
+    return [dict(segments=buf[4 * i], swept=buf[4 * i + 1], jobs=buf[4 * i + 2], job_points=buf[4 * i + 3],
+                 sweep=SWEEP_KINDS[kinds[i]] if i < nk else "level")
             for i in range(n)]
+
+
+def set_level_pairs(mode: int) -> None:
+    """Level pairs below the top (0 never, 1 where levels keep most of their
+    points, the default; 2 from the first level sweep on)."""
+    _check(load_library(), load_library().vqhull_set_level_pairs(int(mode)))
 
 
 def set_timing(enable, sweeps_only: bool = False, fused_only: bool = False) -> None:

@@ -35,9 +35,11 @@ vqhull_config g_cfg = {256, 16, 2048, 0, 1, 0, 0};
 
 struct LevelStat {
   int64_t segs, swept, jobs, jobpts;
+  int32_t kind;  // VQHULL_SWEEP_*: how the level's sweep read and wrote its points
 };
 
 std::atomic<int> g_timing{0};
+std::atomic<int> g_pairs{1};  // level pairs: 0 off, 1 where levels keep most points, 2 from the first level sweep
 
 struct TimedLaunch {
   int kind, level;
@@ -536,12 +538,47 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
   uint32_t lds_plan = lds_limit;  // threshold of the next plan
   uint32_t lds_jobs = lds_limit;  // threshold the jobs of the current level were made with
   const bool adapt = lds_limit > kAdaptLds && w.seg[0].cap >= max_seg;
+  // Level pairs: a level whose segments are swept without writing (argmax
+  // pass) and the next level, whose segments are read in place from the level
+  // before and whose children are written (fused pass), as the top level
+  // does.  Two reads and one write per point instead of two of each: chosen
+  // where the level before kept more than 3/4 of the points it swept and its
+  // segments average more than four LDS thresholds (so that this level's
+  // children are segments again: a pair whose first level makes only jobs
+  // reads them twice and copies them once).
+  const int pairs = g_pairs.load();
+  std::vector<int> kinds;  // VQHULL_SWEEP_* of each level enqueued
+  int inb = 1;             // the buffer holding the points of level k >= 2
+  uint32_t G_prev = 0;
   // Finisher jobs of level k run after sweep k (the fused pass writes the
   // points of level 1's small children), in the same launch as plan k.
   for (int k = 0;; ++k) {
     const int slot = k % kStatusRing, next = (k + 1) % kStatusRing;
-    const int mode = sweep_mode(k, pf);
-    const SweepArgs sa = sweep_args(w, cfg, k, x, y, pf);
+    int mode = sweep_mode(k, pf);
+    if (k >= 2) {
+      const int prev = kinds[k - 1];
+      if (prev == VQHULL_SWEEP_ARGMAX) {
+        mode = kSweepFusedPair;
+      } else if (pairs == 2 ||
+                 (pairs == 1 && k >= 3 && known[k - 2].swept >= (1u << 20) &&
+                  4ull * known[k - 1].survivors > 3ull * known[k - 2].swept &&
+                  (uint64_t)known[k - 1].swept > 4ull * lds_plan * known[k - 1].nseg)) {
+        mode = kSweepArgmaxPair;
+      }
+    }
+    const bool argmax = mode == kSweepArgmax || mode == kSweepArgmaxWs || mode == kSweepArgmaxPair;
+    const bool fused = mode == kSweepFused || mode == kSweepFusedWs || mode == kSweepFusedPair;
+    kinds.push_back(argmax ? VQHULL_SWEEP_ARGMAX : fused ? VQHULL_SWEEP_FUSED : VQHULL_SWEEP_LEVEL);
+    SweepArgs sa = sweep_args(w, cfg, k, x, y, pf);
+    if (k >= 2) {  // buffers by the levels' kinds (a pair's second level reads the first's points)
+      sa.ix = w.wx[inb];
+      sa.iy = w.wy[inb];
+      sa.ii = w.wi[inb];
+      sa.ox = w.wx[inb ^ 1];
+      sa.oy = w.wy[inb ^ 1];
+      sa.oi = w.wi[inb ^ 1];
+      if (mode == kSweepFusedPair) sa.tile_seg = w.tile_seg[(k - 1) % 2].p;  // the first level's tiles again
+    }
     // Grid: persistent, or one workgroup per tile with the tile count bounded
     // from what the host knows (levels 0 and 1 exactly; level k from level
     // k-1: tiles <= ceil(swept(k-1) / tile) + 2 nseg(k-1)); surplus groups exit.
@@ -551,8 +588,9 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
     if (!cfg.sweep_persistent) {
       uint64_t bound = k <= 1 ? tiles0
                               : (known[k - 1].swept + (uint64_t)tile - 1) / tile + 2ull * known[k - 1].nseg + 1;
-      G = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(bound, max_tiles));
+      G = mode == kSweepFusedPair ? G_prev : (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(bound, max_tiles));
     }
+    G_prev = G;
     sweep_recs.push_back(timed(w, tm || (tm_fused && k == 1), st, VQHULL_K_SWEEP, k, 0, 0, [&] {
       ck(launch_sweep(sa, mode, blk, ppt, G, st), "k_sweep");
     }));
@@ -569,7 +607,12 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
     const FinishArgs fa = finish_args(w, aos ? xy : x, aos ? xy : y, k);
     vqhull_config cfg_k = cfg;
     cfg_k.lds_limit = (int)lds_plan;
-    const PlanArgs pl = plan_args(w, cfg_k, k, G);
+    PlanArgs pl = plan_args(w, cfg_k, k, G);
+    if (k >= 2) {
+      pl.fuse = mode == kSweepArgmaxPair ? 1u : 0u;  // its children are read in place by the next sweep
+      pl.out_buf = (uint32_t)(inb ^ 1);              // where the next sweep writes (this level's jobs too)
+      if (mode != kSweepArgmaxPair) inb ^= 1;
+    }
     const int tmax_k = finish_tmax_for((int)lds_jobs);
     finish_recs.push_back(timed(w, tm_all, st, VQHULL_K_PLAN, k, 0, 0,
                                 [&] { ck(launch_finish_plan(fa, pl, tmax_k, st), "k_finish_plan"); }));
@@ -580,12 +623,15 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
     ck(hipEventSynchronize(w.status_ev[slot]), "hipEventSynchronize");
     const Status sk = w.status_host[slot];
     known.push_back(sk);
-    w.stats.push_back({(int64_t)sk.nseg, (int64_t)sk.swept, (int64_t)sk.njobs, (int64_t)sk.jobpts});
-    // sweep k reads status[k].swept points (the fused pass: the roots' points
-    // again) and writes what plan k counts as survivors (+ pass-through copies)
-    if (k >= 2 && sweep_recs[k - 1] != (size_t)-1) w.launches[sweep_recs[k - 1]].out += sk.survivors;
-    if (sweep_recs[k] != (size_t)-1) w.launches[sweep_recs[k]].in = k == 1 ? known[0].swept : sk.swept;
-    if (k == 1 && sweep_recs[1] != (size_t)-1) w.launches[sweep_recs[1]].out += sk.jobpts;
+    w.stats.push_back({(int64_t)sk.nseg, (int64_t)sk.swept, (int64_t)sk.njobs, (int64_t)sk.jobpts, kinds[k]});
+    // sweep k reads status[k].swept points (a fused pass: the points of the
+    // level before again) and writes what plan k counts as survivors (an
+    // argmax pass writes nothing), a fused pass also the pass-through copies
+    if (k >= 2 && sweep_recs[k - 1] != (size_t)-1 && kinds[k - 1] != VQHULL_SWEEP_ARGMAX)
+      w.launches[sweep_recs[k - 1]].out += sk.survivors;
+    if (sweep_recs[k] != (size_t)-1)
+      w.launches[sweep_recs[k]].in = kinds[k] == VQHULL_SWEEP_FUSED ? known[k - 1].swept : sk.swept;
+    if (kinds[k] == VQHULL_SWEEP_FUSED && sweep_recs[k] != (size_t)-1) w.launches[sweep_recs[k]].out += sk.jobpts;
     if (finish_recs[k] != (size_t)-1) w.launches[finish_recs[k]].in = sk.jobpts;
     if (sk.overflow) {
       overflow = true;
@@ -1619,6 +1665,23 @@ int64_t vqhull_last_level_stats(int64_t* out, int64_t cap) {
     out[4 * i + 3] = st[i].jobpts;
   }
   return (int64_t)st.size();
+}
+
+int64_t vqhull_last_level_kinds(int32_t* out, int64_t cap) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> g(g_last_mu);
+  auto it = g_last.find(dev);
+  if (it == g_last.end()) return 0;
+  const auto& st = it->second.stats;
+  for (int64_t i = 0; i < (int64_t)st.size() && i < cap && out; ++i) out[i] = st[i].kind;
+  return (int64_t)st.size();
+}
+
+int vqhull_set_level_pairs(int mode) {
+  if (mode < 0 || mode > 2) return VQHULL_ERR_INVALID_ARGUMENT;
+  g_pairs.store(mode);
+  return VQHULL_OK;
 }
 
 int vqhull_orient(const double* abc, int64_t n, double* out, vqhull_stream_t stream) {

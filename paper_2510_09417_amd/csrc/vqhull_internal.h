@@ -57,11 +57,15 @@ struct Seg {
 // A child swept at the next level is "virtual": its points are never written;
 // its own children (the root's grandchildren) are.  A child small enough for
 // the LDS finisher is "pass-through": its points are copied into its range.
+// A level pair does the same below the top: a segment (a, r, b) whose level
+// was swept without writing is read again and classified against (a, r, b),
+// then against its child (a, r1, r) or (r, r2, b).
 enum : uint32_t { kFuseSkip = 0, kFuseSplit = 1, kFuseCopy = 2 };
 
 struct FusedRoot {
-  double px, py, qx, qy;  // the root's extreme points p and q
-  double rx[2], ry[2];    // farthest point of each child: child 0 = (p, r1, q) holds S1, child 1 = (q, r2, p) S2
+  double px, py, qx, qy;  // the segment's a and r (a root's extreme points p and q)
+  double bx, by;          // the segment's b (a root: p again)
+  double rx[2], ry[2];    // farthest point of each child: child 0 = (a, r1, r) holds S1, child 1 = (r, r2, b) S2
   uint32_t beg[2], cnt[2];  // child ranges in the output buffer
   uint32_t kind[2];         // kFuse*
   uint32_t slot[2];         // kFuseSplit: next-level segment id; kFuseCopy: job id
@@ -200,9 +204,19 @@ struct ExtremesArgs {
 
 // Sweep modes.  The *Ws forms are the top-level passes over the workspace
 // copy the octagon prefilter leaves (buffer A, with an index array) instead of
-// the caller's arrays.
-enum : int { kSweepLevel = 0, kSweepArgmax = 1, kSweepFused = 2, kSweepArgmaxWs = 3, kSweepFusedWs = 4 };
-constexpr int kSweepModes = 5;
+// the caller's arrays.  The *Pair forms are a level pair below the top: the
+// level's segments swept without writing (sizes and farthest points of their
+// children), then swept again, writing their grandchildren.
+enum : int {
+  kSweepLevel = 0,
+  kSweepArgmax = 1,
+  kSweepFused = 2,
+  kSweepArgmaxWs = 3,
+  kSweepFusedWs = 4,
+  kSweepArgmaxPair = 5,
+  kSweepFusedPair = 6
+};
+constexpr int kSweepModes = 7;
 
 // ------------------------------------------------------- octagon prefilter
 // A variant of the method (Section 6's Akl-Toussaint heuristic): every

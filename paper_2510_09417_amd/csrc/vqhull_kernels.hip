@@ -366,6 +366,13 @@ __global__ __launch_bounds__(BLOCK) void k_extremes(ExtremesArgs A) {
 //   kSweepArgmaxWs, kSweepFusedWs
 //                 the same two passes over the points the octagon prefilter
 //                 kept (buffer A, indices from its index array).
+//   kSweepArgmaxPair, kSweepFusedPair
+//                 the same two passes below the top (a level pair, for levels
+//                 that keep most of their points): the workspace's segments
+//                 (a, r, b) with Algorithm 1's partition, S1 = left of a->r,
+//                 S2 = left of r->b and not in S1; the argmax pass writes
+//                 nothing, the fused pass re-reads the segment and writes the
+//                 subsets of its children (a, r1, r) and (r, r2, b).
 
 // Per-thread farthest-point candidate inside a sweep: the key and the position
 // of the point in the level's input arrays.  Coordinates and index are fetched
@@ -604,8 +611,9 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
   static_assert(PPT <= 32, "class masks are 32-bit");
   // USER: input = the caller's arrays, index = position - ibase
   constexpr bool USER = MODE == kSweepArgmax || MODE == kSweepFused;
-  constexpr bool FUSED = MODE == kSweepFused || MODE == kSweepFusedWs;
-  constexpr bool ARGMAX = MODE == kSweepArgmax || MODE == kSweepArgmaxWs;
+  constexpr bool FUSED = MODE == kSweepFused || MODE == kSweepFusedWs || MODE == kSweepFusedPair;
+  constexpr bool ARGMAX = MODE == kSweepArgmax || MODE == kSweepArgmaxWs || MODE == kSweepArgmaxPair;
+  constexpr bool PAIR = MODE == kSweepArgmaxPair || MODE == kSweepFusedPair;  // a segment (a, r, b), not a root
   constexpr int NS = FUSED ? 4 : 2;  // output streams (two per output range)
   constexpr uint32_t TILE = BLOCK * PPT;
   constexpr int NW = BLOCK / 64;
@@ -651,6 +659,10 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
         ay = uni(fr->py);
         rx = uni(fr->qx);
         ry = uni(fr->qy);
+        if constexpr (PAIR) {
+          bx = uni(fr->bx);
+          by = uni(fr->by);
+        }
         r1x = uni(fr->rx[0]);
         r1y = uni(fr->ry[0]);
         r2x = uni(fr->rx[1]);
@@ -741,12 +753,20 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
         oh[v] = (in1 ? 1u : 0u) | (in2 ? 256u : 0u);
       } else {
         const double dpx = ax - x, dpy = ay - y, dqx = rx - x, dqy = ry - y;
-        const double o = dpx * dqy - dpy * dqx;  // orient(p, q, u)
+        const double o = dpx * dqy - dpy * dqx;  // orient(p, q, u); a pair: orient(a, r, u)
+        // A root's S2 = left of q->p: orient(q, p, u) is exactly -o.  A pair's
+        // S2 = left of r->b and not in S1.
+        double o2 = -o, dbx = 0.0, dby = 0.0;
+        if constexpr (PAIR) {
+          dbx = bx - x;
+          dby = by - y;
+          o2 = dqx * dby - dqy * dbx;  // orient(r, b, u)
+        }
         const bool s0 = ok & (o > 0.0);
-        const bool s1 = ok & (o < 0.0);
+        const bool s1 = PAIR ? (ok & !(o > 0.0) & (o2 > 0.0)) : (ok & (o < 0.0));
         if constexpr (ARGMAX) {
           const bool f[2] = {s0, s1};
-          const double kk[2] = {o, -o};
+          const double kk[2] = {o, o2};
           offer<USER, 2>(b, f, kk, x, y, pos, pi[v], src);
           m[0] |= (uint32_t)s0 << v;
           m[1] |= (uint32_t)s1 << v;
@@ -761,8 +781,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
           //   V = orient(q, R, u) = (q.x-u.x)(R.y-u.y) - (q.y-u.y)(R.x-u.x);
           // orient(r1, q, u) has the same two rounded products in the other
           // order, so it is exactly -V; likewise orient(r2, p, u) = -U.
+          // A pair's child 1 is (r, r2, b): U = orient(b, R, u) there, so that
+          // -U = orient(r2, b, u) exactly (a root's b is p).
           const double dRx = (s0 ? vr1x : vr2x) - x, dRy = (s0 ? vr1y : vr2y) - y;
-          const double U = dpx * dRy - dpy * dRx;
+          const double dPx = PAIR ? (s0 ? dpx : dbx) : dpx, dPy = PAIR ? (s0 ? dpy : dby) : dpy;
+          const double U = dPx * dRy - dPy * dRx;
           const double V = dqx * dRy - dqy * dRx;
           const bool a0 = s0 & split0, a1 = s1 & split1;
           const bool u_pos = U > 0.0, v_pos = V > 0.0;
@@ -1513,6 +1536,8 @@ __device__ void plan_level(const PlanArgs& A, PlanLds<PB>& L, uint32_t g, uint32
         f.py = sg.ay;
         f.qx = sg.rx;
         f.qy = sg.ry;
+        f.bx = sg.bx;
+        f.by = sg.by;
         const Tri* tt[2] = {&t1, &t2};
         const uint32_t idx[2] = {i1, i2};
 #pragma unroll
@@ -2781,6 +2806,10 @@ int sweep_one(const SweepArgs& a, int mode, uint32_t grid, hipStream_t st) {
     hipLaunchKernelGGL((k_sweep<BLOCK, PPT, kSweepArgmaxWs>), dim3(grid), dim3(BLOCK), 0, st, a);
   } else if (mode == kSweepFusedWs) {
     hipLaunchKernelGGL((k_sweep<BLOCK, PPT, kSweepFusedWs>), dim3(grid), dim3(BLOCK), 0, st, a);
+  } else if (mode == kSweepArgmaxPair) {
+    hipLaunchKernelGGL((k_sweep<BLOCK, PPT, kSweepArgmaxPair>), dim3(grid), dim3(BLOCK), 0, st, a);
+  } else if (mode == kSweepFusedPair) {
+    hipLaunchKernelGGL((k_sweep<BLOCK, PPT, kSweepFusedPair>), dim3(grid), dim3(BLOCK), 0, st, a);
   } else {
     hipLaunchKernelGGL((k_sweep<BLOCK, PPT, kSweepLevel>), dim3(grid), dim3(BLOCK), 0, st, a);
   }
@@ -2820,6 +2849,8 @@ uint32_t sweep_grid(int block, int ppt, int mode) {
         : mode == kSweepFused    ? sweep_occupancy_grid<B, P, kSweepFused>()    \
         : mode == kSweepArgmaxWs ? sweep_occupancy_grid<B, P, kSweepArgmaxWs>() \
         : mode == kSweepFusedWs  ? sweep_occupancy_grid<B, P, kSweepFusedWs>()  \
+        : mode == kSweepArgmaxPair ? sweep_occupancy_grid<B, P, kSweepArgmaxPair>() \
+        : mode == kSweepFusedPair  ? sweep_occupancy_grid<B, P, kSweepFusedPair>()  \
                                  : sweep_occupancy_grid<B, P, kSweepLevel>();
     VQH_GRID(0, 256, 16)
     VQH_GRID(1, 256, 32)

@@ -249,6 +249,22 @@ def size_sweep(out_md: str, dists=("disk", "square"), sizes=SIZE_SWEEP_SIZES, ca
     return rows
 
 
+def _deep_terms(levels: list) -> tuple:
+    """(writes, level reads) in bytes of the levels below the top, 20 B per
+    point moved.  Level k's jobs are written once (by sweep k-1, or as
+    pass-through copies by a fused sweep k); its segments are written by sweep
+    k-1 unless that sweep was an argmax pass (then they are read in place).
+    Sweep k reads its own segments' points, or a fused sweep those of level
+    k-1 again."""
+    sw = [lv["swept"] for lv in levels]
+    jp = [lv["job_points"] for lv in levels]
+    kind = [lv.get("sweep", "level") for lv in levels]
+    writes = 20 * ((jp[1] if len(jp) > 1 else 0)
+                   + sum(jp[k] + (sw[k] if kind[k - 1] != "argmax" else 0) for k in range(2, len(levels))))
+    reads = 20 * sum(sw[k - 1] if kind[k] == "fused" else sw[k] for k in range(2, len(levels)))
+    return writes, reads
+
+
 def alg_bytes_batched(n_total: int, levels: list) -> dict:
     """Algorithmic bytes of one batched call (any mix of request sizes) from
     its level statistics: extremes 8 B per point (x) of every request; the
@@ -259,8 +275,7 @@ def alg_bytes_batched(n_total: int, levels: list) -> dict:
     sw = [lv["swept"] for lv in levels]
     jp = [lv["job_points"] for lv in levels]
     top = 8 * n_total + 32 * (sw[0] if sw else 0) + 16 * (jp[0] if jp else 0)
-    writes = 20 * ((jp[1] if len(jp) > 1 else 0) + sum(sw[k] + jp[k] for k in range(2, len(levels))))
-    level_reads = 20 * sum(sw[k] for k in range(2, len(levels)))
+    writes, level_reads = _deep_terms(levels)
     finisher = 20 * sum(jp[k] for k in range(1, len(levels)))
     total = top + writes + level_reads + finisher
     return {"top": top, "writes": writes, "level_reads": level_reads, "finisher_reads": finisher, "total": total}
@@ -274,13 +289,14 @@ def alg_bytes(n: int, levels: list) -> dict:
       per point read, and 20 B written per point of the level-1 jobs (copies)
       and of the level-2 segments and jobs (grandchildren); level k >= 2:
       20 B read per swept point, 20 B written per point of level k+1's
-      segments and jobs; the LDS finisher reads 20 B per job point.
+      segments and jobs (a level pair: the second level re-reads the first's
+      points and the first writes none); the LDS finisher reads 20 B per job
+      point.
     Vertex lists and the output (O(h)) are left out."""
     sw = [lv["swept"] for lv in levels]
     jp = [lv["job_points"] for lv in levels]
     top = 8 * n + 16 * n + 16 * n
-    writes = 20 * ((jp[1] if len(jp) > 1 else 0) + sum(sw[k] + jp[k] for k in range(2, len(levels))))
-    level_reads = 20 * sum(sw[k] for k in range(2, len(levels)))
+    writes, level_reads = _deep_terms(levels)
     finisher = 20 * sum(jp[k] for k in range(1, len(levels)))
     total = top + writes + level_reads + finisher
     return {"top": top, "writes": writes, "level_reads": level_reads, "finisher_reads": finisher, "total": total}

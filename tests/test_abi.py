@@ -88,6 +88,16 @@ def test_timing_modes_on_host(lib):
         assert lib.vqhull_set_timing(0) == 0
 
 
+def test_level_pair_modes_on_host(lib):
+    try:
+        for mode in (0, 1, 2):
+            assert lib.vqhull_set_level_pairs(mode) == 0
+        for bad in (-1, 3, 100):
+            assert lib.vqhull_set_level_pairs(bad) == 1
+    finally:
+        assert lib.vqhull_set_level_pairs(1) == 0  # the default
+
+
 def test_status_strings(lib):
     for code in range(6):
         assert lib.vqhull_status_string(code)

@@ -88,6 +88,25 @@ def test_alg_bytes_counts_every_move():
     assert b["total"] == b["top"] + b["writes"] + b["level_reads"] + b["finisher_reads"]
 
 
+def test_alg_bytes_level_pair():
+    """A level pair at levels 2 and 3: level 3's segments are never written
+    (read in place from level 2's range), its jobs are copied by the fused
+    sweep, and sweep 3 reads level 2's points again."""
+    from paper_2510_09417_amd import profiling
+
+    levels = [dict(segments=1, swept=100, jobs=0, job_points=0, sweep="argmax"),
+              dict(segments=2, swept=90, jobs=1, job_points=5, sweep="fused"),
+              dict(segments=4, swept=80, jobs=0, job_points=0, sweep="argmax"),
+              dict(segments=8, swept=70, jobs=4, job_points=20, sweep="fused"),
+              dict(segments=0, swept=0, jobs=3, job_points=6, sweep="level")]
+    b = profiling.alg_bytes(100, levels)
+    assert b["writes"] == 20 * (5 + (0 + 80) + (20 + 0) + (6 + 0))
+    assert b["level_reads"] == 20 * (80 + 80 + 0)
+    assert b["finisher_reads"] == 20 * (5 + 0 + 20 + 6)
+    plain = [dict(lv, sweep="level") for lv in levels]  # the same counts swept level by level
+    assert profiling.alg_bytes(100, plain)["total"] - b["total"] == 20 * (70 + 70 - 80)
+
+
 def test_alg_bytes_batched_reduces_to_single_and_counts_small_requests():
     from paper_2510_09417_amd import profiling
 

@@ -320,8 +320,10 @@ int64_t vqhull_last_level_kinds(int32_t* out, int64_t cap);
  * fourth level on, where the level before kept more than 3/4 of the points it
  * swept (at least 2^20 of them) and its segments average more than four times
  * the LDS threshold; 2: from the third level on, back to back.
- * The result does not depend on the mode.  Returns VQHULL_ERR_INVALID_ARGUMENT
- * for any other mode. */
+ * The server's lanes and the stream-ordered call, whose level sequences are
+ * fixed before any status is known, sweep level by level.  The result does
+ * not depend on the mode.  Returns VQHULL_ERR_INVALID_ARGUMENT for any other
+ * mode. */
 int vqhull_set_level_pairs(int mode);
 
 /* Kernel timing of the last hull call on this device (the same calls), for benchmarks: when

@@ -445,6 +445,28 @@ Plan0Args plan0_args(Context& w, const vqhull_config& cfg) {
   return pa;
 }
 
+// Level k >= 2 of a call with level pairs: its point buffers follow the kinds
+// of the levels before it (inb: the buffer holding level k's points; the
+// second level of a pair reads the first's points again, and its tiles).
+void pair_sweep_buffers(Context& w, int k, int mode, int inb, SweepArgs& sa) {
+  sa.ix = w.wx[inb];
+  sa.iy = w.wy[inb];
+  sa.ii = w.wi[inb];
+  sa.ox = w.wx[inb ^ 1];
+  sa.oy = w.wy[inb ^ 1];
+  sa.oi = w.wi[inb ^ 1];
+  if (mode == kSweepFusedPair) sa.tile_seg = w.tile_seg[(k - 1) % 2].p;
+}
+
+// The plan of that level: its children are read in place by the next sweep
+// (the first level of a pair) or written by this one; either way their points
+// and this level's jobs end up in the other buffer.  Advances inb.
+void pair_plan(int mode, int& inb, PlanArgs& pl) {
+  pl.fuse = mode == kSweepArgmaxPair ? 1u : 0u;
+  pl.out_buf = (uint32_t)(inb ^ 1);
+  if (mode != kSweepArgmaxPair) inb ^= 1;
+}
+
 // Inputs whose levels keep nearly every point they sweep (most points are
 // hull vertices, as on a circle) finish faster with the 1024-point LDS
 // finisher, two workgroups per CU: under the 2048-point threshold, once a
@@ -570,15 +592,7 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
     const bool fused = mode == kSweepFused || mode == kSweepFusedWs || mode == kSweepFusedPair;
     kinds.push_back(argmax ? VQHULL_SWEEP_ARGMAX : fused ? VQHULL_SWEEP_FUSED : VQHULL_SWEEP_LEVEL);
     SweepArgs sa = sweep_args(w, cfg, k, x, y, pf);
-    if (k >= 2) {  // buffers by the levels' kinds (a pair's second level reads the first's points)
-      sa.ix = w.wx[inb];
-      sa.iy = w.wy[inb];
-      sa.ii = w.wi[inb];
-      sa.ox = w.wx[inb ^ 1];
-      sa.oy = w.wy[inb ^ 1];
-      sa.oi = w.wi[inb ^ 1];
-      if (mode == kSweepFusedPair) sa.tile_seg = w.tile_seg[(k - 1) % 2].p;  // the first level's tiles again
-    }
+    if (k >= 2) pair_sweep_buffers(w, k, mode, inb, sa);
     // Grid: persistent, or one workgroup per tile with the tile count bounded
     // from what the host knows (levels 0 and 1 exactly; level k from level
     // k-1: tiles <= ceil(swept(k-1) / tile) + 2 nseg(k-1)); surplus groups exit.
@@ -608,11 +622,7 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
     vqhull_config cfg_k = cfg;
     cfg_k.lds_limit = (int)lds_plan;
     PlanArgs pl = plan_args(w, cfg_k, k, G);
-    if (k >= 2) {
-      pl.fuse = mode == kSweepArgmaxPair ? 1u : 0u;  // its children are read in place by the next sweep
-      pl.out_buf = (uint32_t)(inb ^ 1);              // where the next sweep writes (this level's jobs too)
-      if (mode != kSweepArgmaxPair) inb ^= 1;
-    }
+    if (k >= 2) pair_plan(mode, inb, pl);
     const int tmax_k = finish_tmax_for((int)lds_jobs);
     finish_recs.push_back(timed(w, tm_all, st, VQHULL_K_PLAN, k, 0, 0,
                                 [&] { ck(launch_finish_plan(fa, pl, tmax_k, st), "k_finish_plan"); }));

@@ -144,3 +144,4 @@ def test_forced_pairs_configurations(vq, cfg):
         vq.set_config(**saved)
     for g, w in zip(got, want):
         assert np.array_equal(g, w), cfg
+

@@ -2670,6 +2670,7 @@ __global__ __launch_bounds__(256) void k_orient(const double* __restrict__ abc, 
 // finished in LDS already hold their ordered lists; k_copy_lists moves them.
 
 constexpr int kAsmBlock = 1024;
+constexpr int kAsmUnroll = 4;  // nodes per thread whose loads are in flight together
 
 // A stream-ordered call whose level budget ended before the recursion did.
 __device__ __forceinline__ bool assembly_incomplete(const AssembleArgs& A) {
@@ -2684,12 +2685,36 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble(AssembleArgs A) {
     for (uint32_t i = tid; i < A.counts->nreq; i += kAsmBlock) A.out_count[i] = kCountIncomplete;
     return;
   }
+  // Each thread takes kAsmUnroll nodes of a level at a time, their loads
+  // issued together: a node's children sit on the next level, which is done,
+  // so the nodes of one level do not depend on each other.
   for (int L = (int)A.nlevels - 1; L >= 0; --L) {
-    for (uint32_t v = A.level_begin[L] + tid; v < A.level_begin[L + 1]; v += kAsmBlock) {
-      Node& nd = A.nodes[v];
-      if (nd.list != kNone) continue;
-      const int32_t c0 = nd.c[0], c1 = nd.c[1];
-      nd.size = 1u + (c0 >= 0 ? A.nodes[c0].size : 0u) + (c1 >= 0 ? A.nodes[c1].size : 0u);
+    const uint32_t end = A.level_begin[L + 1];
+    for (uint32_t v0 = A.level_begin[L] + tid; v0 < end; v0 += kAsmUnroll * kAsmBlock) {
+      int32_t c[kAsmUnroll][2];
+      bool act[kAsmUnroll];
+#pragma unroll
+      for (int j = 0; j < kAsmUnroll; ++j) {
+        const uint32_t v = v0 + (uint32_t)j * kAsmBlock;
+        act[j] = false;
+        c[j][0] = c[j][1] = -1;
+        if (v < end) {
+          const Node nd = A.nodes[v];
+          act[j] = nd.list == kNone;
+          c[j][0] = nd.c[0];
+          c[j][1] = nd.c[1];
+        }
+      }
+      uint32_t sz[kAsmUnroll][2];
+#pragma unroll
+      for (int j = 0; j < kAsmUnroll; ++j) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) sz[j][e] = (act[j] && c[j][e] >= 0) ? A.nodes[c[j][e]].size : 0u;
+      }
+#pragma unroll
+      for (int j = 0; j < kAsmUnroll; ++j) {
+        if (act[j]) A.nodes[v0 + (uint32_t)j * kAsmBlock].size = 1u + sz[j][0] + sz[j][1];
+      }
     }
     __threadfence_block();
     __syncthreads();
@@ -2701,16 +2726,36 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble(AssembleArgs A) {
   }
   __syncthreads();
   for (uint32_t L = 0; L < A.nlevels; ++L) {
-    for (uint32_t v = A.level_begin[L] + tid; v < A.level_begin[L + 1]; v += kAsmBlock) {
-      const Node nd = A.nodes[v];
-      const Req rq = A.req[nd.req];
-      if (rq.err || rq.p == rq.q) continue;
-      if (nd.list != kNone) continue;
-      const int32_t c0 = nd.c[0], c1 = nd.c[1];
-      const uint32_t pos = nd.start + (c0 >= 0 ? A.nodes[c0].size : 0u);
-      A.out_idx[rq.off + pos] = (int64_t)nd.vertex;
-      if (c0 >= 0) A.nodes[c0].start = nd.start;
-      if (c1 >= 0) A.nodes[c1].start = pos + 1u;
+    const uint32_t end = A.level_begin[L + 1];
+    for (uint32_t v0 = A.level_begin[L] + tid; v0 < end; v0 += kAsmUnroll * kAsmBlock) {
+      Node nd[kAsmUnroll];
+      bool act[kAsmUnroll];
+#pragma unroll
+      for (int j = 0; j < kAsmUnroll; ++j) {
+        const uint32_t v = v0 + (uint32_t)j * kAsmBlock;
+        act[j] = v < end;
+        if (act[j]) nd[j] = A.nodes[v];
+      }
+      uint32_t off[kAsmUnroll], s0[kAsmUnroll];
+#pragma unroll
+      for (int j = 0; j < kAsmUnroll; ++j) {
+        off[j] = 0u;
+        s0[j] = 0u;
+        if (act[j]) {
+          const Req rq = A.req[nd[j].req];
+          act[j] = !rq.err && rq.p != rq.q && nd[j].list == kNone;
+          off[j] = rq.off;
+          if (act[j] && nd[j].c[0] >= 0) s0[j] = A.nodes[nd[j].c[0]].size;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kAsmUnroll; ++j) {
+        if (!act[j]) continue;
+        const uint32_t pos = nd[j].start + s0[j];
+        A.out_idx[off[j] + pos] = (int64_t)nd[j].vertex;
+        if (nd[j].c[0] >= 0) A.nodes[nd[j].c[0]].start = nd[j].start;
+        if (nd[j].c[1] >= 0) A.nodes[nd[j].c[1]].start = pos + 1u;
+      }
     }
     __threadfence_block();
     __syncthreads();

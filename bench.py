@@ -313,15 +313,20 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
                        "gpu": OUT[a:a + max(h, 0)].cpu().numpy() if h >= 0 else None})
 
     # Algorithmic bytes of the whole mix: the batched path over lane-sized
-    # batches of the same requests (the same kernels as the lanes), with its
-    # level statistics (outputs discarded)
+    # batches of the same requests (the same kernels as the lanes, which sweep
+    # level by level: no level pairs here either), with its level statistics
+    # (outputs discarded)
     alg_total, lo = 0, 0
-    while lo < nreq:
-        hi = max(lo + 1, int(np.searchsorted(off, off[lo] + lane_points, side="right")) - 1)
-        hi = min(hi, nreq)
-        vq.hull_batched(X[off[lo]:off[hi]], Y[off[lo]:off[hi]], off[lo:hi + 1] - off[lo], check=False)
-        alg_total += profiling.alg_bytes_batched(int(off[hi] - off[lo]), vq.level_stats())["total"]
-        lo = hi
+    vq.set_level_pairs(0)
+    try:
+        while lo < nreq:
+            hi = max(lo + 1, int(np.searchsorted(off, off[lo] + lane_points, side="right")) - 1)
+            hi = min(hi, nreq)
+            vq.hull_batched(X[off[lo]:off[hi]], Y[off[lo]:off[hi]], off[lo:hi + 1] - off[lo], check=False)
+            alg_total += profiling.alg_bytes_batched(int(off[hi] - off[lo]), vq.level_stats())["total"]
+            lo = hi
+    finally:
+        vq.set_level_pairs(1)
     torch.cuda.synchronize()
     served_gbs = alg_total / (t_last - t_first) / 1e9
     log(f"served: {alg_total / total:.1f} algorithmic B/pt, {served_gbs:.0f} GB/s ({served_gbs / HBM_PEAK_GBS:.3f} "

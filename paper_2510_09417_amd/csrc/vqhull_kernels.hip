@@ -414,7 +414,7 @@ __device__ __forceinline__ bool tie_wins(const Src& A, double x, double y, uint3
                                          uint32_t bpos) {
   const double bx = A.x[bpos], by = A.y[bpos];
   const uint32_t bi = USER ? bpos : A.i[bpos];
-  const uint32_t ni = USER ? pos : idx != kNone ? idx : A.i[pos];  // kNone: not loaded (argmax passes)
+  const uint32_t ni = USER ? pos : idx;
   return (x < bx) | ((x == bx) & ((y < by) | ((y == by) & (ni < bi))));
 }
 
@@ -727,8 +727,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs A) {
       const uint32_t pc = min(lo + v * BLOCK + tid, hi - 1u);
       px[v] = __builtin_nontemporal_load(src.x + pc);
       py[v] = __builtin_nontemporal_load(src.y + pc);
-      if constexpr (USER || ARGMAX) {
-        pi[v] = USER ? 0u : kNone;  // an argmax pass fetches an index only to break an exact key tie
+      if constexpr (USER) {
+        pi[v] = 0u;
       } else {
         pi[v] = __builtin_nontemporal_load(src.i + pc);
       }

@@ -254,15 +254,14 @@ def _deep_terms(levels: list) -> tuple:
     point moved.  Level k's jobs are written once (by sweep k-1, or as
     pass-through copies by a fused sweep k); its segments are written by sweep
     k-1 unless that sweep was an argmax pass (then they are read in place).
-    Sweep k reads its own segments' points (an argmax pass their coordinates
-    only, 16 B), or a fused sweep those of level k-1 again."""
+    Sweep k reads its own segments' points, or a fused sweep those of level
+    k-1 again."""
     sw = [lv["swept"] for lv in levels]
     jp = [lv["job_points"] for lv in levels]
     kind = [lv.get("sweep", "level") for lv in levels]
     writes = 20 * ((jp[1] if len(jp) > 1 else 0)
                    + sum(jp[k] + (sw[k] if kind[k - 1] != "argmax" else 0) for k in range(2, len(levels))))
-    reads = sum(20 * sw[k - 1] if kind[k] == "fused" else (16 if kind[k] == "argmax" else 20) * sw[k]
-                for k in range(2, len(levels)))
+    reads = 20 * sum(sw[k - 1] if kind[k] == "fused" else sw[k] for k in range(2, len(levels)))
     return writes, reads
 
 

@@ -101,10 +101,10 @@ def test_alg_bytes_level_pair():
               dict(segments=0, swept=0, jobs=3, job_points=6, sweep="level")]
     b = profiling.alg_bytes(100, levels)
     assert b["writes"] == 20 * (5 + (0 + 80) + (20 + 0) + (6 + 0))
-    assert b["level_reads"] == 16 * 80 + 20 * 80 + 20 * 0  # the argmax pass reads coordinates only
+    assert b["level_reads"] == 20 * (80 + 80 + 0)
     assert b["finisher_reads"] == 20 * (5 + 0 + 20 + 6)
     plain = [dict(lv, sweep="level") for lv in levels]  # the same counts swept level by level
-    assert profiling.alg_bytes(100, plain)["total"] - b["total"] == 20 * (70 + 70 - 80) + 4 * 80
+    assert profiling.alg_bytes(100, plain)["total"] - b["total"] == 20 * (70 + 70 - 80)
 
 
 def test_alg_bytes_batched_reduces_to_single_and_counts_small_requests():

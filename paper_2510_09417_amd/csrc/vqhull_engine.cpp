@@ -91,10 +91,10 @@ struct Context {
   BatchCounts* counts_host = nullptr;  // pinned source of that copy
   DevBuf<uint32_t> level_nodes;        // node count after each level (written by the planners)
   Status* status_dev = nullptr;   // kStatusRing records
-  Status* status_host = nullptr;  // pinned copies, written by the planners
-  Status* status_host_dev = nullptr;  // device view of status_host
-  Status* status_mirror = nullptr;    // a device ring the planners may write instead (no pinned memory)
-  hipEvent_t status_ev[kStatusRing] = {};
+  Status* status_host = nullptr;  // pinned copies, read back by copies on the stream (server lanes)
+  uint64_t* status_words = nullptr;      // pinned tagged words of the status ring, written by the planners
+  uint64_t* status_words_dev = nullptr;  // device view of status_words (null: the planners write none)
+  uint32_t status_tag = 0;               // the last tag given to a level
   hipEvent_t staged = nullptr;  // stream-ordered calls: recorded after the copies of the host staging
   // pinned staging
   Req* h_req = nullptr;
@@ -212,10 +212,12 @@ Context* new_context(bool device_tables = true) {
     ck(hipMalloc(&w->counts_dev, sizeof(BatchCounts)), "hipMalloc");
   }
   ck(hipHostMalloc((void**)&w->counts_host, sizeof(BatchCounts), hipHostMallocDefault), "hipHostMalloc");
-  ck(hipHostMalloc((void**)&w->status_host, kStatusRing * sizeof(Status), hipHostMallocMapped), "hipHostMalloc");
-  ck(hipHostGetDevicePointer((void**)&w->status_host_dev, w->status_host, 0), "hipHostGetDevicePointer");
-  for (int i = 0; i < kStatusRing; ++i)
-    ck(hipEventCreateWithFlags(&w->status_ev[i], hipEventDisableTiming), "hipEventCreateWithFlags");
+  ck(hipHostMalloc((void**)&w->status_host, kStatusRing * sizeof(Status), hipHostMallocDefault), "hipHostMalloc");
+  ck(hipHostMalloc((void**)&w->status_words, kStatusRing * kStatusWords * sizeof(uint64_t),
+                   hipHostMallocMapped | hipHostMallocCoherent),
+     "hipHostMalloc");
+  std::memset(w->status_words, 0, kStatusRing * kStatusWords * sizeof(uint64_t));  // tag 0 is never given
+  ck(hipHostGetDevicePointer((void**)&w->status_words_dev, w->status_words, 0), "hipHostGetDevicePointer");
   return w;
 }
 
@@ -265,11 +267,10 @@ void free_workspace(Context* w) {
   f(w->level_nodes.p);
   if (w->counts_host) (void)hipHostFree(w->counts_host);
   if (w->status_host) (void)hipHostFree(w->status_host);
+  if (w->status_words) (void)hipHostFree(w->status_words);
   if (w->h_req) (void)hipHostFree(w->h_req);
   if (w->h_u32) (void)hipHostFree(w->h_u32);
   for (hipEvent_t e : w->events) (void)hipEventDestroy(e);
-  for (hipEvent_t e : w->status_ev)
-    if (e) (void)hipEventDestroy(e);
   if (w->staged) (void)hipEventDestroy(w->staged);
   delete w;
 }
@@ -408,7 +409,8 @@ PlanArgs plan_args(Context& w, const vqhull_config& cfg, int k, uint32_t G) {
   pl.node_cap = (uint32_t)std::min<size_t>(w.nodes.cap, 0xFFFFFFFFu);
   pl.out_buf = (uint32_t)(k == 0 ? 1 : k % 2);  // level 0's children are written by the fused pass
   pl.st_out = w.status_dev + (k + 1) % kStatusRing;
-  pl.st_host = w.status_host_dev + (k + 1) % kStatusRing;
+  pl.st_host = w.status_words_dev ? w.status_words_dev + (size_t)((k + 1) % kStatusRing) * kStatusWords : nullptr;
+  pl.st_tag = 0;
   pl.tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
   pl.lds_limit = (uint32_t)cfg.lds_limit;
   pl.level_nodes = w.level_nodes.p;
@@ -434,7 +436,8 @@ Plan0Args plan0_args(Context& w, const vqhull_config& cfg) {
   pa.nodes = w.nodes.p;
   pa.node_cap = (uint32_t)std::min<size_t>(w.nodes.cap, 0xFFFFFFFFu);
   pa.st_out = w.status_dev + 0;
-  pa.st_host = w.status_host_dev + 0;
+  pa.st_host = w.status_words_dev;
+  pa.st_tag = 0;
   pa.tile = (uint32_t)(cfg.sweep_block * cfg.sweep_ppt);
   pa.lds_limit = (uint32_t)cfg.lds_limit;
   pa.ext_tile = kExtTile;
@@ -443,6 +446,58 @@ Plan0Args plan0_args(Context& w, const vqhull_config& cfg) {
   pa.rounds_next = w.rounds[0].p;
   pa.rounds_cap = (uint32_t)std::min<size_t>(std::min(w.rounds[0].cap, w.rounds[1].cap), 0xFFFFFFFFu);
   return pa;
+}
+
+// Tags of the status words: never 0 (the words start at 0), never the tag
+// of another level still in the ring.
+uint32_t next_status_tag(Context& w) {
+  if (++w.status_tag == 0) w.status_tag = 1;
+  return w.status_tag;
+}
+
+// The status record of a ring slot as the planner wrote it to the pinned
+// words, once every word carries `tag`.  The host spins on the words and
+// puts nothing on the stream: an event, or a query of the stream, adds a
+// marker whose system-scope release (a write-back of the whole L2) leaves
+// the GPU idle ~6 us before the next kernel, once per level.  Only a wait
+// longer than kStatusCheck asks the stream for an error (a stream that has
+// finished without the record is an error too).
+constexpr auto kStatusCheck = std::chrono::milliseconds(20);
+
+Status wait_status(Context& w, int slot, uint32_t tag, hipStream_t st) {
+  const uint64_t* words = w.status_words + (size_t)slot * kStatusWords;
+  int idle_checks = 0;
+  auto next_check = std::chrono::steady_clock::now() + kStatusCheck;
+  for (uint64_t spin = 1;; ++spin) {
+    uint32_t v[kStatusWords];
+    bool whole = true;
+    for (int i = 0; i < kStatusWords && whole; ++i) {
+      const uint64_t x = __atomic_load_n(words + i, __ATOMIC_ACQUIRE);
+      whole = (uint32_t)(x >> 32) == tag;
+      v[i] = (uint32_t)x;
+    }
+    if (whole) {
+      Status s;
+      s.nseg = v[0];
+      s.ntiles = v[1];
+      s.njobs = v[2];
+      s.nnodes = v[3];
+      s.swept = v[4];
+      s.jobpts = v[5];
+      s.survivors = v[6];
+      s.overflow = v[7];
+      return s;
+    }
+    if (spin % 1024 == 0 && std::chrono::steady_clock::now() >= next_check) {
+      next_check = std::chrono::steady_clock::now() + kStatusCheck;
+      const hipError_t e = hipStreamQuery(st);
+      if (e == hipSuccess) {
+        if (++idle_checks > 2) ck(hipErrorUnknown, "a planner's status record never reached the host");
+      } else if (e != hipErrorNotReady) {
+        ck(e, "hipStreamQuery");
+      }
+    }
+  }
 }
 
 // Level k >= 2 of a call with level pairs: its point buffers follow the kinds
@@ -549,8 +604,10 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
     pa.toff = w.toff.p;
     pa.filter_min = filter_min;
   }
+  std::vector<uint32_t> tags;  // tags[k]: the tag of level k's status words
+  tags.push_back(next_status_tag(w));
+  pa.st_tag = tags[0];
   timed(w, tm_all, st, VQHULL_K_PLAN0, 0, nreq, 0, [&] { ck(launch_plan0(pa, st), "k_plan0"); });
-  ck(hipEventRecord(w.status_ev[0], st), "hipEventRecord");
 
   std::vector<Status> known;           // host copies of status[0..]
   std::vector<size_t> sweep_recs;      // timing records of the sweeps, per level
@@ -623,15 +680,15 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
     cfg_k.lds_limit = (int)lds_plan;
     PlanArgs pl = plan_args(w, cfg_k, k, G);
     if (k >= 2) pair_plan(mode, inb, pl);
+    tags.push_back(next_status_tag(w));
+    pl.st_tag = tags[k + 1];
     const int tmax_k = finish_tmax_for((int)lds_jobs);
     finish_recs.push_back(timed(w, tm_all, st, VQHULL_K_PLAN, k, 0, 0,
                                 [&] { ck(launch_finish_plan(fa, pl, tmax_k, st), "k_finish_plan"); }));
     lds_jobs = lds_plan;
-    ck(hipEventRecord(w.status_ev[next], st), "hipEventRecord");
 
     // Wait for the status of level k (written by the previous plan).
-    ck(hipEventSynchronize(w.status_ev[slot]), "hipEventSynchronize");
-    const Status sk = w.status_host[slot];
+    const Status sk = wait_status(w, slot, tags[k], st);
     known.push_back(sk);
     w.stats.push_back({(int64_t)sk.nseg, (int64_t)sk.swept, (int64_t)sk.njobs, (int64_t)sk.jobpts, kinds[k]});
     // sweep k reads status[k].swept points (a fused pass: the points of the
@@ -947,11 +1004,9 @@ size_t ws_layout(Context& w, char* base, size_t N, size_t nreq, const vqhull_con
   take(w.level_nodes, std::min<size_t>(N, size_t(1) << 20) + 64);
   BatchCounts* counts = reinterpret_cast<BatchCounts*>(raw(sizeof(BatchCounts)));
   Status* status = reinterpret_cast<Status*>(raw(kStatusRing * sizeof(Status)));
-  Status* mirror = reinterpret_cast<Status*>(raw(kStatusRing * sizeof(Status)));
   if (base) {
     w.counts_dev = counts;
     w.status_dev = status;
-    w.status_mirror = mirror;
     w.cap_pts = N;
     w.fixed = true;
   }
@@ -1412,14 +1467,20 @@ int context_enqueue_fixed(Context* c, const double* x, const double* y, int64_t*
     ck(hipMemcpyAsync(w.counts_dev, w.counts_host, sizeof(BatchCounts), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
     const ExtremesArgs ea{x, y, w.tile_req.p, w.req.p, w.epart.p, w.counts_dev, (uint32_t)tiles_cap};
     ck(launch_extremes(ea, st), "k_extremes");
-    ck(launch_plan0(plan0_args(w, cfg), st), "k_plan0");
+    // The lane reads its last status by a copy on the stream: the planners
+    // write no host words.
+    Plan0Args pa = plan0_args(w, cfg);
+    pa.st_host = nullptr;
+    ck(launch_plan0(pa, st), "k_plan0");
     for (int k = 0; k < levels; ++k) {
       const int mode = sweep_mode(k, false);
       int blk = 0, ppt = 0;
       level_shape(cfg, k, blk, ppt);
       const uint32_t G = sweep_grid(blk, ppt, mode);
       ck(launch_sweep(sweep_args(w, cfg, k, x, y, false), mode, blk, ppt, G, st), "k_sweep");
-      ck(launch_finish_plan(finish_args(w, x, y, k), plan_args(w, cfg, k, G), tmax, st), "k_finish_plan");
+      PlanArgs pl = plan_args(w, cfg, k, G);
+      pl.st_host = nullptr;
+      ck(launch_finish_plan(finish_args(w, x, y, k), pl, tmax, st), "k_finish_plan");
     }
     const int last = levels % kStatusRing;
     ck(hipMemcpyAsync(w.status_host + last, w.status_dev + last, sizeof(Status), hipMemcpyDeviceToHost, st),
@@ -1525,8 +1586,7 @@ int vqhull_hull_noalloc(const double* x, const double* y, int64_t n, int64_t* ou
       d.ctx.device = dev;
     }
     Context& w = d.ctx;
-    ws_layout(w, d.ptr, (size_t)n, 1, cfg);
-    w.status_host_dev = w.status_mirror;
+    ws_layout(w, d.ptr, (size_t)n, 1, cfg);  // its context has no pinned status words: the planners write none
     run_fixed_single(w, cfg, x, y, (uint32_t)n, out_idx, out_count, st, d);
   });
 }

@@ -143,6 +143,14 @@ constexpr uint32_t kPlanners = 8;        // planner workgroups of a level planne
 constexpr uint32_t kPlanRoundMin = 256;  // the smallest round (segments per planner workgroup)
 
 constexpr int kStatusRing = 4;
+
+// The host's copy of a status record, written by the planner straight into
+// pinned host memory: one 64-bit word per field, (tag << 32) | value, each a
+// relaxed system-scope store.  The host knows the record is whole when every
+// word carries the tag it gave that level, so the device needs no
+// system-scope fence (which would write back the whole L2) and the stream no
+// event between the levels.  Word order: the fields of Status in order.
+constexpr int kStatusWords = 8;
 // Segment and job counters (packed S1 | S2 << 32 reservations) sit one
 // 128-byte line apart: the device-scope atomics of one line are serialised,
 // and the two children of a segment take theirs from every tile.
@@ -311,7 +319,8 @@ struct Plan0Args {
   Node* nodes;
   uint32_t node_cap;
   Status* st_out;
-  Status* st_host;  // pinned host copy of *st_out (device view), or null
+  uint64_t* st_host;  // tagged host words of *st_out (kStatusWords, pinned, device view), or null
+  uint32_t st_tag;    // the tag of those words
   uint32_t tile;
   uint32_t lds_limit;
   uint32_t ext_tile;
@@ -339,7 +348,8 @@ struct PlanArgs {
   uint32_t node_cap;
   uint32_t out_buf;  // buffer the children were written to (0 = A, 1 = B)
   Status* st_out;
-  Status* st_host;   // pinned host copy of *st_out (device view), or null
+  uint64_t* st_host;  // tagged host words of *st_out (kStatusWords, pinned, device view), or null
+  uint32_t st_tag;    // the tag of those words
   uint32_t tile;
   uint32_t lds_limit;
   uint32_t* level_nodes;  // [level + 2] = node count after this plan

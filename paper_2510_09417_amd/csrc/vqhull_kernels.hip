@@ -1108,16 +1108,20 @@ __device__ __forceinline__ void plan_init(PlanSharedT<PB>& S) {
 // kernels) and, when host_out is set, straight to the host's pinned copy (read
 // by the host after the event that follows this kernel), so no copy is
 // enqueued per level.
-__device__ __forceinline__ void put_status(const Status& st, Status* out, Status* host_out) {
+__device__ __forceinline__ void put_status(const Status& st, Status* out, uint64_t* host_out, uint32_t tag) {
   *out = st;
   if (host_out) {
-    *host_out = st;
-    __threadfence_system();
+    const uint32_t v[kStatusWords] = {st.nseg, st.ntiles, st.njobs, st.nnodes, st.swept, st.jobpts, st.survivors,
+                                      st.overflow};
+    const uint64_t t = (uint64_t)tag << 32;
+#pragma unroll
+    for (int i = 0; i < kStatusWords; ++i)
+      __hip_atomic_store(host_out + i, t | v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
 template <int PB>
-__device__ __forceinline__ void plan_status(PlanSharedT<PB>& S, Status* out, Status* host_out, uint32_t node_base,
+__device__ __forceinline__ void plan_status(PlanSharedT<PB>& S, Status* out, uint64_t* host_out, uint32_t tag, uint32_t node_base,
                                             uint32_t* level_nodes, uint32_t ntiles) {
   if (threadIdx.x == 0) {
     *level_nodes = node_base + S.nodes;
@@ -1130,11 +1134,11 @@ __device__ __forceinline__ void plan_status(PlanSharedT<PB>& S, Status* out, Sta
     st.jobpts = S.jobpts;
     st.survivors = S.survivors;
     st.overflow = 0;
-    put_status(st, out, host_out);
+    put_status(st, out, host_out, tag);
   }
 }
 
-__device__ __forceinline__ void plan_overflow(Status* out, Status* host_out, uint32_t node_base,
+__device__ __forceinline__ void plan_overflow(Status* out, uint64_t* host_out, uint32_t tag, uint32_t node_base,
                                               uint32_t* level_nodes, BatchCounts* counts) {
   if (threadIdx.x == 0) {
     *level_nodes = node_base;
@@ -1142,13 +1146,13 @@ __device__ __forceinline__ void plan_overflow(Status* out, Status* host_out, uin
     Status st{};
     st.nnodes = node_base;
     st.overflow = 1;
-    put_status(st, out, host_out);
+    put_status(st, out, host_out, tag);
   }
 }
 
 // The status of a level planned in rounds: t = nodes, jobs, segments, tiles,
 // swept points, job points, survivors (the inclusive totals of the last round).
-__device__ __forceinline__ void plan_status_totals(const uint32_t (&t)[kPlanCounters], Status* out, Status* host_out,
+__device__ __forceinline__ void plan_status_totals(const uint32_t (&t)[kPlanCounters], Status* out, uint64_t* host_out, uint32_t tag,
                                                    uint32_t node_base, uint32_t* level_nodes, uint32_t ntiles) {
   if (threadIdx.x == 0) {
     *level_nodes = node_base + t[0];
@@ -1161,7 +1165,7 @@ __device__ __forceinline__ void plan_status_totals(const uint32_t (&t)[kPlanCoun
     st.jobpts = t[5];
     st.survivors = t[6];
     st.overflow = 0;
-    put_status(st, out, host_out);
+    put_status(st, out, host_out, tag);
   }
 }
 
@@ -1274,7 +1278,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
   const uint32_t nreq = A.counts->nreq;
   if ((uint64_t)nreq > A.node_cap) {
     if (threadIdx.x == 0) A.level_nodes[0] = 0u;
-    plan_overflow(A.st_out, A.st_host, 0u, A.level_nodes + 1, A.counts);
+    plan_overflow(A.st_out, A.st_host, A.st_tag, 0u, A.level_nodes + 1, A.counts);
     return;
   }
   for (uint32_t base = 0; base < nreq; base += kPlanBlock) {
@@ -1353,7 +1357,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan0(Plan0Args A) {
     emit_finish(tot, A.tile_seg_out, S);
   }
   if (threadIdx.x == 0) A.level_nodes[0] = 0u;
-  plan_status(S, A.st_out, A.st_host, 0u, A.level_nodes + 1, S.tiles);
+  plan_status(S, A.st_out, A.st_host, A.st_tag, 0u, A.level_nodes + 1, S.tiles);
   // the look-back records of the level-0 planner start cleared
   const uint32_t nclr = min(A.rounds_cap, ceil_div(S.segs, kPlanRoundMin) + 1u);
   for (uint32_t c = threadIdx.x; c < nclr; c += kPlanBlock) st_relaxed(&A.rounds_next[c].flag, 0u);
@@ -1381,13 +1385,13 @@ __device__ void plan_level(const PlanArgs& A, PlanLds<PB>& L, uint32_t g, uint32
   const uint32_t nseg = A.st_in->nseg, node_base = A.st_in->nnodes;
   const uint32_t nrounds = ceil_div(nseg, PB);
   if ((uint64_t)node_base + 2ull * nseg > A.node_cap || nrounds > A.rounds_cap) {
-    if (g == 0) plan_overflow(A.st_out, A.st_host, node_base, A.level_nodes + A.level + 2u, A.counts);
+    if (g == 0) plan_overflow(A.st_out, A.st_host, A.st_tag, node_base, A.level_nodes + A.level + 2u, A.counts);
     return;
   }
   if (nrounds == 0) {  // an empty level: the next is empty too
     if (g == 0) {
       const uint32_t zero[kPlanCounters] = {0, 0, 0, 0, 0, 0, 0};
-      plan_status_totals(zero, A.st_out, A.st_host, node_base, A.level_nodes + A.level + 2u,
+      plan_status_totals(zero, A.st_out, A.st_host, A.st_tag, node_base, A.level_nodes + A.level + 2u,
                          A.fuse ? A.st_in->ntiles : 0u);
     }
     return;
@@ -1509,7 +1513,7 @@ __device__ void plan_level(const PlanArgs& A, PlanLds<PB>& L, uint32_t g, uint32
     }
     __syncthreads();
     if (rr > 0 && S.lb_fail) {  // a round never published (not expected): report an overflow
-      plan_overflow(A.st_out, A.st_host, node_base, A.level_nodes + A.level + 2u, A.counts);
+      plan_overflow(A.st_out, A.st_host, A.st_tag, node_base, A.level_nodes + A.level + 2u, A.counts);
       return;
     }
     uint32_t pre[kPlanCounters];
@@ -1564,7 +1568,7 @@ __device__ void plan_level(const PlanArgs& A, PlanLds<PB>& L, uint32_t g, uint32
   // and the look-back records of the next level planner cleared.
   if ((nrounds - 1u) % P == g) {
     // The fused pass walks the roots' tiles again.
-    plan_status_totals(fin, A.st_out, A.st_host, node_base, A.level_nodes + A.level + 2u,
+    plan_status_totals(fin, A.st_out, A.st_host, A.st_tag, node_base, A.level_nodes + A.level + 2u,
                        A.fuse ? A.st_in->ntiles : fin[3]);
     const uint32_t nclr = min(A.rounds_cap, ceil_div(fin[2], kPlanRoundMin) + 1u);
     for (uint32_t i = tid; i < nclr; i += PB) st_relaxed(&A.rounds_next[i].flag, 0u);

@@ -318,8 +318,10 @@ int64_t vqhull_last_level_kinds(int32_t* out, int64_t cap);
  * swept without writing, then the next level read in place from it, one
  * write per point instead of two.  mode 0: never; 1 (default): from the
  * fourth level on, where the level before kept more than 3/4 of the points it
- * swept (at least 2^20 of them) and its segments average more than four times
- * the LDS threshold; 2: from the third level on, back to back.
+ * swept (at least 2^20 of them) and the levels left whose segments exceed the
+ * LDS threshold (about log2 of the average segment over the threshold, at
+ * least 2) come in a whole number of pairs; 2: from the third level on, back
+ * to back.
  * The server's lanes and the stream-ordered call, whose level sequences are
  * fixed before any status is known, sweep level by level.  The result does
  * not depend on the mode.  Returns VQHULL_ERR_INVALID_ARGUMENT for any other

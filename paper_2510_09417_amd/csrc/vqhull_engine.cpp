@@ -624,11 +624,21 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
   // pass) and the next level, whose segments are read in place from the level
   // before and whose children are written (fused pass), as the top level
   // does.  Two reads and one write per point instead of two of each: chosen
-  // where the level before kept more than 3/4 of the points it swept and its
-  // segments average more than four LDS thresholds (so that this level's
-  // children are segments again: a pair whose first level makes only jobs
-  // reads them twice and copies them once).
+  // where the level before kept more than 3/4 of the points it swept.  Such
+  // levels halve their segments, so the levels left whose segments still
+  // exceed the threshold the plans end with are about log2(average segment /
+  // threshold); a pair starts only where that count is even, so that the
+  // pairs end on the last of them (a pair whose first level makes only
+  // finisher jobs reads them twice and copies them once).
   const int pairs = g_pairs.load();
+  const uint32_t lds_end = adapt ? kAdaptLds : lds_limit;
+  auto segment_levels_left = [&](const Status& s) {
+    if (s.nseg == 0) return 0;
+    double a = (double)s.swept / (double)s.nseg / (double)lds_end;
+    int n = 0;
+    for (; a >= 2.0; a *= 0.5) ++n;
+    return n;
+  };
   std::vector<int> kinds;  // VQHULL_SWEEP_* of each level enqueued
   int inb = 1;             // the buffer holding the points of level k >= 2
   uint32_t G_prev = 0;
@@ -644,7 +654,7 @@ bool run_once(Context& w, const vqhull_config& cfg, const double* x, const doubl
       } else if (pairs == 2 ||
                  (pairs == 1 && k >= 3 && known[k - 2].swept >= (1u << 20) &&
                   4ull * known[k - 1].survivors > 3ull * known[k - 2].swept &&
-                  (uint64_t)known[k - 1].swept > 4ull * lds_plan * known[k - 1].nseg)) {
+                  segment_levels_left(known[k - 1]) >= 2 && segment_levels_left(known[k - 1]) % 2 == 0)) {
         mode = kSweepArgmaxPair;
       }
     }

@@ -249,7 +249,7 @@ def served_benchmark(vq, workloads, torch, nreq: int, lanes: int, lane_points: i
 
     nb = int(np.searchsorted(off, lane_points, side="right")) - 1
     t0 = time.perf_counter()
-    tuned, table = autotune.tune_batched(X[: off[nb]], Y[: off[nb]], off[: nb + 1], repeats=3, persistent=(1,))
+    tuned, table = autotune.tune_batched(X[: off[nb]], Y[: off[nb]], off[: nb + 1], repeats=5, persistent=(1,))
     saved_cfg = vq.get_config()
     vq.set_config(**tuned)
     tune_s = time.perf_counter() - t0

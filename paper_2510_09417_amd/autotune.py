@@ -95,7 +95,8 @@ def tune_batched(x, y, offsets, repeats: int = 3, stream=None, persistent=(1, 0)
     ``hull_batched(x, y, offsets)`` (median of ``repeats`` runs after a warm-up)
     under every configuration (grid modes limited to ``persistent``: the
     server's graph-captured batches need persistent sweeps; the octagon
-    prefilter off, as the server's lanes run the plain method) and checks that
+    prefilter and level pairs off, as the server's lanes run the plain method
+    level by level) and checks that
     each gives the same index lists and counts as the first.  Returns (fastest
     equal configuration, table); the library configuration is restored
     afterwards."""
@@ -107,6 +108,7 @@ def tune_batched(x, y, offsets, repeats: int = 3, stream=None, persistent=(1, 0)
     offsets = np.asarray(offsets, dtype=np.int64)
     saved = vq.get_config()
     table, ref, best = [], None, None
+    vq.set_level_pairs(0)
     try:
         for blk, ppt in SHAPES:
             for lds in LDS_LIMITS:
@@ -134,6 +136,7 @@ def tune_batched(x, y, offsets, repeats: int = 3, stream=None, persistent=(1, 0)
                         best = table[-1]
     finally:
         vq.set_config(**saved)
+        vq.set_level_pairs(1)
     return best["config"], table
 
 
